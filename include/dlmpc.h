@@ -1,0 +1,172 @@
+/*
+ * dlmpc.h — C ABI of the MI355X DLMPC-ADMM library (libdlmpc.so).
+ *
+ * The library solves the distributed and localized MPC subproblem of eq. (MPC) in
+ * Section II-A of Amo Alonso & Tseng, "Effective GPU Parallelization of Distributed and
+ * Localized MPC": minimise sum_t x_t'Q x_t + u_t'R u_t subject to x_{t+1} = A x_t + B u_t,
+ * x_0 = x(tau), box bounds on states and inputs, and d-locality over the graph G_(A,B).
+ * It uses the SLS parametrisation of the same section (the matrix Phi with N_x*T + N_u*(T-1)
+ * rows and N_x columns, sparse by locality) and the ADMM of Algorithm 2: Phi-comp row by
+ * row, Psi-comp column by column, the Lambda update and the convergence check, all on one
+ * GPU. Algorithm 1 splits the work into an offline precomputation (dlmpc_setup) and a
+ * per-MPC-step solve from the measured state x(tau) (dlmpc_solve).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an int status: 0 = ok, > 0 = soft status with valid outputs,
+ *     < 0 = error with outputs untouched. dlmpc_last_error() gives a message for the last
+ *     error raised on the calling thread.
+ *   - The caller owns every buffer it passes and keeps ownership; the library deep-copies
+ *     what it needs during dlmpc_setup. A dlmpc_problem is owned by the library until
+ *     dlmpc_destroy.
+ *   - A problem is bound to one device and one HIP stream; it is not thread-safe. Calls on
+ *     different problems may run concurrently.
+ *   - Rows of Phi are in canonical order: state blocks x_0..x_{T-1}, then input blocks
+ *     u_0..u_{T-2}; within a block subsystem-major (subsystem i owns nx consecutive state
+ *     rows, nu consecutive input rows). Columns are the N_x = n_sub*nx components of x0.
+ *   - Phi[r, c] may be nonzero iff hop(sub(r), sub(c)) <= d in G_(A,B) (the locality
+ *     pattern of Section II-A; Lemma 1 counts the nodes within d hops).
+ */
+#ifndef DLMPC_H
+#define DLMPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DLMPC_OK = 0,
+  DLMPC_ENOCONV = 1,              /* max_iter reached: the last iterate is returned */
+  DLMPC_EINVAL = -1,              /* bad argument (sizes, NaN/Inf, d < 0, T < 2, NULL) */
+  DLMPC_ENOMEM = -2,              /* host or device allocation failed */
+  DLMPC_EDEVICE = -3,             /* HIP runtime error, or no device work on a host-only problem */
+  DLMPC_EINFEASIBLE_LOCALITY = -4,/* some column cannot meet Z_AB Psi = I inside its d-hop patch */
+  DLMPC_ENUMERIC = -5             /* NaN/Inf appeared in the iterate */
+};
+
+typedef enum {
+  DLMPC_FP64 = 0, /* state, operators and reductions in double */
+  DLMPC_FP32 = 1  /* state and operators in float; setup and outputs stay double */
+} dlmpc_precision;
+
+/* Setup flags (dlmpc_options.flags). */
+#define DLMPC_FLAG_HOST_ONLY 0x1u /* build host-side data only; no HIP call is made and every
+                                     solve returns DLMPC_EDEVICE. For inspection and tests. */
+
+/* Networked plant. G_(A,B) is read off the block sparsity of A: subsystems i != j are
+ * adjacent iff block A_ij or A_ji is present in the block-CSR with a nonzero entry. Every
+ * subsystem has nx states and nu inputs. B is block diagonal (one nx x nu block per
+ * subsystem). All arrays are host memory. */
+typedef struct {
+  int32_t n_sub;            /* N >= 1 */
+  int32_t nx, nu;           /* states / inputs per subsystem, >= 1 */
+  const int64_t *a_rowptr;  /* [N+1] block-CSR row pointers over subsystems */
+  const int32_t *a_colidx;  /* [nnzb] block column indices (any order, no duplicates) */
+  const double *a_blocks;   /* [nnzb * nx * nx] row-major nx x nx blocks, CSR order */
+  const double *b_blocks;   /* [N * nx * nu] row-major diagonal blocks B_ii */
+} dlmpc_system;
+
+/* Diagonal stage cost and box bounds of eq. (MPC). q_diag weights every state row
+ * x_0..x_{T-1}; r_diag every input row u_0..u_{T-2}. State bounds apply at t = 1..T-1
+ * (x_0 is the measured state), input bounds at t = 0..T-2. A NULL bound array means
+ * unbounded; +-INFINITY entries are allowed; each interval must contain 0. */
+typedef struct {
+  const double *q_diag; /* [N*nx], > 0 */
+  const double *r_diag; /* [N*nu], > 0 */
+  const double *x_lo, *x_hi; /* [N*nx] or NULL */
+  const double *u_lo, *u_hi; /* [N*nu] or NULL */
+} dlmpc_cost;
+
+typedef struct {
+  double rho;          /* ADMM penalty, > 0 (default 5 when 0 is passed) */
+  double eps;          /* convergence tolerance, > 0 (default 1e-4 when 0) */
+  int32_t max_iter;    /* > 0 (default 500 when 0) */
+  int32_t check_every; /* iterations per captured graph launch between host checks (0 = auto) */
+  int32_t precision;   /* dlmpc_precision */
+  int32_t device;      /* HIP device ordinal */
+  void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
+  uint32_t flags;      /* DLMPC_FLAG_* */
+} dlmpc_options;
+
+/* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
+ * canonical CSR pattern of dlmpc_phi_pattern (host arrays of nnz doubles). NULL = cold start
+ * Psi^0 = Lambda^0 = 0. */
+typedef struct {
+  const double *psi0;
+  const double *lambda0;
+} dlmpc_warm;
+
+typedef struct {
+  int32_t iters;        /* ADMM iterations run */
+  int32_t converged;    /* 1 iff both residuals <= eps at the stopping iterate */
+  double r_primal;      /* max over columns of ||Phi[:,c] - Psi[:,c]||_2 at the stopping iterate */
+  double r_dual;        /* max over columns of ||Psi^{k+1}[:,c] - Psi^k[:,c]||_2 */
+  double objective;     /* sum_r w_r (Phi x0)_r^2 at the stopping iterate, FP64 */
+  double t_solve_ms;    /* host wall time of the solve call */
+  double t_iter_ms;     /* device time of the iteration phase (HIP events) */
+  int32_t graph_launches;
+  int32_t reserved;
+} dlmpc_stats;
+
+typedef struct {
+  int64_t R;            /* rows of Phi: N*nx*T + N*nu*(T-1) */
+  int64_t n_cols;       /* N*nx */
+  int64_t nnz;          /* entries of the locality pattern */
+  int64_t n_tiles;      /* (column subsystem, row subsystem) pairs within d hops */
+  int32_t d_row_max;    /* longest row of the pattern (Section III-B, D_row) */
+  int32_t d_col_max;    /* longest column (D_col) */
+  int32_t p_max;        /* largest d-hop patch, in subsystems */
+  int32_t k_max;        /* largest null-space dimension of a column block */
+  int64_t sum_dcol_k;   /* sum over subsystems of D_col(j) * k_j (entries of the null bases) */
+  int64_t sum_dcol2;    /* sum over subsystems of D_col(j)^2 */
+  double setup_ms;      /* host wall time of dlmpc_setup */
+  double factor_ms;     /* of which the FP64 factorisation of the column blocks */
+} dlmpc_info;
+
+/* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the
+ * locality pattern, and for every subsystem j the FP64 factorisation of its column block of
+ * Z_AB (the SLS achievability operator: Phi_x[0] = I, Phi_x[t] = A Phi_x[t-1] + B Phi_u[t-1])
+ * restricted to the support of j's columns: an orthonormal basis N_j of its null space and
+ * the minimum-norm offsets o_c solving the block's equations for each column c of j, so that
+ * the Psi-comp projection is psi = N_j N_j' v + o_c. Uploads the operators and allocates all
+ * solve-time device memory. d >= 0, T >= 2. Returns DLMPC_EINFEASIBLE_LOCALITY when some
+ * column has no localised trajectory. On success *out receives the handle. */
+int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *cost,
+                const dlmpc_options *opts, struct dlmpc_problem **out);
+
+/* Sizes of the problem (fills *info). */
+int dlmpc_query(const struct dlmpc_problem *p, dlmpc_info *info);
+
+/* Canonical CSR pattern of Phi: row_ptr [R+1], col_idx [nnz] (ascending within a row). */
+int dlmpc_phi_pattern(const struct dlmpc_problem *p, int64_t *row_ptr, int32_t *col_idx);
+
+/* Host FP64 setup products of subsystem j (for inspection and tests): rows [D] are the
+ * canonical Phi rows of the support of j's columns in the library's order, P [D*D] the
+ * row-major projector N_j N_j' onto the null space of the column block, O [D*nx] row-major
+ * offsets (column c = o_c). Any output may be NULL. *D_out receives D_col(j). */
+int dlmpc_column_block(const struct dlmpc_problem *p, int32_t j, int32_t *D_out,
+                       int64_t *rows, double *P, double *O);
+
+/* Per-step solve (Algorithm 1 loop body: precompute with x0, ADMM of Algorithm 2, read
+ * u(0) from Phi). x0 [N*nx] host. Outputs (host, may be NULL): u0 [N*nu] = the u_0 block of
+ * Phi x0 at the stopping iterate; phi [nnz] = Phi values on the canonical CSR pattern.
+ * Returns DLMPC_OK, or DLMPC_ENOCONV with outputs from the last iterate. */
+int dlmpc_solve(struct dlmpc_problem *p, const double *x0, const dlmpc_warm *warm, double *u0,
+                double *phi, dlmpc_stats *stats);
+
+/* Same as dlmpc_solve with device buffers on the problem's device: x0_dev [N*nx] double in,
+ * u0_dev [N*nu] double out, phi_dev [nnz] double out or NULL. Cold start. The call returns
+ * after the outputs are written (the problem's stream is synchronised). */
+int dlmpc_solve_device(struct dlmpc_problem *p, const double *x0_dev, double *u0_dev,
+                       double *phi_dev, dlmpc_stats *stats);
+
+void dlmpc_destroy(struct dlmpc_problem *p);
+const char *dlmpc_status_string(int status);
+const char *dlmpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLMPC_H */

@@ -148,28 +148,30 @@ class ColumnBlock:
     feas_resid: float
 
 
-def column_blocks(Z: sp.csr_matrix, mask: np.ndarray, lay: Layout) -> list[ColumnBlock]:
+def column_block(Z: sp.csr_matrix, mask: np.ndarray, lay: Layout, j: int) -> ColumnBlock:
     """H_j = Z_AB restricted to the support rows of subsystem j's columns (zero rows dropped),
     projector P_j = I - H_j^+ H_j and offsets o_c = H_j^+ e_c from an FP64 SVD."""
     Zc = Z.tocsc()
-    rhs = np.zeros((Z.shape[0], lay.Nx))
-    rhs[:lay.Nx, :lay.Nx] = np.eye(lay.Nx)
-    out = []
-    for j in range(lay.n_sub):
-        cols = np.arange(j * lay.nx, (j + 1) * lay.nx)
-        rows = np.flatnonzero(mask[:, cols[0]])
-        H = Zc[:, rows].toarray()
-        keep = np.any(H != 0, axis=1)
-        H, E = H[keep], rhs[keep][:, cols]
-        U, s, Vt = np.linalg.svd(H, full_matrices=False)
-        tol = max(H.shape) * np.finfo(np.float64).eps * (s[0] if s.size else 0.0)
-        r = int(np.sum(s > tol))
-        Ur, sr, Vr = U[:, :r], s[:r], Vt[:r].T
-        Hpinv_E = Vr @ ((Ur.T @ E) / sr[:, None])
-        P = np.eye(len(rows)) - Vr @ Vr.T
-        feas = float(np.abs(H @ Hpinv_E - E).max())
-        out.append(ColumnBlock(rows=rows, P=P, O=Hpinv_E, rank=r, feas_resid=feas))
-    return out
+    cols = np.arange(j * lay.nx, (j + 1) * lay.nx)
+    rows = np.flatnonzero(mask[:, cols[0]])
+    H = Zc[:, rows].toarray()
+    keep = np.any(H != 0, axis=1)
+    rhs = np.zeros((Z.shape[0], lay.nx))
+    rhs[cols, np.arange(lay.nx)] = 1.0  # e_c: the x_0 row of state c (block row 0 of Z_AB)
+    H, E = H[keep], rhs[keep]
+    U, s, Vt = np.linalg.svd(H, full_matrices=False)
+    tol = max(H.shape) * np.finfo(np.float64).eps * (s[0] if s.size else 0.0)
+    r = int(np.sum(s > tol))
+    Ur, sr, Vr = U[:, :r], s[:r], Vt[:r].T
+    Hpinv_E = Vr @ ((Ur.T @ E) / sr[:, None])
+    P = np.eye(len(rows)) - Vr @ Vr.T
+    feas = float(np.abs(H @ Hpinv_E - E).max())
+    return ColumnBlock(rows=rows, P=P, O=Hpinv_E, rank=r, feas_resid=feas)
+
+
+def column_blocks(Z: sp.csr_matrix, mask: np.ndarray, lay: Layout) -> list[ColumnBlock]:
+    """Psi-comp data of every subsystem (see column_block)."""
+    return [column_block(Z, mask, lay, j) for j in range(lay.n_sub)]
 
 
 # --------------------------------------------------------------------- problem

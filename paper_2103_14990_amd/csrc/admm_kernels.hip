@@ -1,0 +1,490 @@
+// HIP kernels of the DLMPC-ADMM hot loop (Algorithm 2) for CDNA4 (gfx950).
+//
+// One ADMM iteration is two launches:
+//   phi_kernel  — Phi-comp, one workgroup per row subsystem m: gathers the tiles
+//                 (Psi - Lambda)[rows of m, columns of P(m)], forms a_r = v_r . x_r for the
+//                 rs rows of m, takes the explicit row solution (clip of
+//                 rho a / (rho + 2 w ||x_r||^2) onto the row's box, Section II-A and
+//                 Algorithm 2), and writes Phi = v + alpha_r x_r and y_r = (Phi x0)_r.
+//   psi_kernel  — Psi-comp + Lambda-comp + Conv, one workgroup per column subsystem j:
+//                 projects the nx columns of (Phi + Lambda) on the support of j onto the
+//                 affine set of Z_AB psi = e_c with the null basis N_j (psi = N_j N_j' v + o_c),
+//                 updates Lambda <- Lambda + Phi - Psi, and reduces the per-column primal and
+//                 dual residual norms into a device-side max; the last workgroup to finish
+//                 takes the convergence decision (combined-kernel idea, Section III-C).
+// Between the two launches every tile written by one side is read by exactly one workgroup
+// of the other side, so the row->column exchange is the kernel boundary and no atomics
+// touch the iterate. Every reduction runs in a fixed order (bitwise reproducible).
+// A control block on the device carries the stop flag; once set, every later kernel of the
+// captured iteration graph returns immediately, so the host only polls it every K
+// iterations.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "dlmpc_device.h"
+
+namespace dlmpc {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T clip(T s, T lo, T hi) {
+  return s < lo ? lo : (s > hi ? hi : s);
+}
+
+__device__ __forceinline__ unsigned long long as_bits(double v) {
+  return static_cast<unsigned long long>(__double_as_longlong(v));
+}
+
+// ------------------------------------------------------------------ per-solve precompute
+
+// Per row subsystem m: ||x_r||^2 over its d-hop patch (the same for all rows of m), x0 in the
+// working precision, the cold-start Psi^0 = Lambda^0 = 0 on m's tiles, and (block 0) the
+// control block reset (Algorithm 1, per-step precomputation with x(t)).
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void precompute_kernel(KArgs<Tf> a, const double *x0,
+                                                            int cold, int max_iter, double eps) {
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid < NX) a.x0f[m * NX + tid] = static_cast<Tf>(x0[m * NX + tid]);
+  if (tid == 0) {
+    double s = 0.0;
+    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+      const int j = a.rt_col[q];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) s += x0[j * NX + c] * x0[j * NX + c];
+    }
+    a.nrm[m] = static_cast<Tf>(s);
+  }
+  if (cold) {
+    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+      const int64_t base = a.rt_tile[q] * a.ts;
+      for (int e = tid; e < a.ts; e += kBlock) {
+        a.psi[base + e] = Tf(0);
+        a.lam[base + e] = Tf(0);
+        a.phi[base + e] = Tf(0);
+      }
+    }
+  }
+  if (m == 0 && tid == 0) {
+    Ctl *c = a.ctl;
+    c->iters = 0;
+    c->stop = 0;
+    c->converged = 0;
+    c->numeric = 0;
+    c->max_iter = max_iter;
+    c->done_count = 0u;
+    c->rp_bits = 0ull;
+    c->rd_bits = 0ull;
+    c->last_rp = INFINITY;
+    c->last_rd = INFINITY;
+    c->eps = eps;
+    c->objective = 0.0;
+  }
+}
+
+// Warm start: Psi^0, Lambda^0 from canonical CSR values.
+template <typename Tf>
+__global__ __launch_bounds__(kBlock) void warm_kernel(Tf *psi, Tf *lam, const int64_t *map, int64_t n,
+                                                      const double *wpsi, const double *wlam) {
+  for (int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x; e < n; e += int64_t(gridDim.x) * kBlock) {
+    const int64_t c = map[e];
+    psi[e] = static_cast<Tf>(wpsi[c]);
+    lam[e] = static_cast<Tf>(wlam[c]);
+  }
+}
+
+// ------------------------------------------------------------------ Phi-comp
+
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void phi_kernel(KArgs<Tf> a) {
+  if (a.ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Tf *part = reinterpret_cast<Tf *>(smem_raw);  // [np][rs] partial dot products
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t t0 = a.rt_ptr[m];
+  const int np = int(a.rt_ptr[m + 1] - t0);
+  const int rs = a.rs;
+  Tf *alpha_s = part + np * rs;  // [rs]
+  Tf *xs = alpha_s + rs;         // [np][NX] x0 of the patch members
+  for (int i = tid; i < np * NX; i += kBlock) xs[i] = a.x0f[a.rt_col[t0 + i / NX] * NX + i % NX];
+  __syncthreads();
+  const int items = np * rs;
+  for (int it = tid; it < items; it += kBlock) {
+    const int k = it / rs, l = it - k * rs;
+    const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
+    Tf acc = Tf(0);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) acc += xs[k * NX + c] * (a.psi[base + c] - a.lam[base + c]);
+    part[it] = acc;
+  }
+  __syncthreads();
+  const Tf n = a.nrm[m];
+  for (int l = tid; l < rs; l += kBlock) {
+    Tf acc = Tf(0);
+    for (int k = 0; k < np; ++k) acc += part[k * rs + l];
+    const int64_t o = int64_t(m) * rs + l;
+    Tf s, al;
+    if (n > Tf(0)) {
+      s = clip(a.rho * acc / (a.rho + Tf(2) * a.w[o] * n), a.lb[o], a.ub[o]);
+      al = (s - acc) / n;
+    } else {
+      s = acc;
+      al = Tf(0);
+    }
+    alpha_s[l] = al;
+    a.y[o] = s;
+  }
+  __syncthreads();
+  for (int it = tid; it < items; it += kBlock) {
+    const int k = it / rs, l = it - k * rs;
+    const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
+    const Tf al = alpha_s[l];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) a.phi[base + c] = (a.psi[base + c] - a.lam[base + c]) + al * xs[k * NX + c];
+  }
+}
+
+// ------------------------------------------------------------------ Psi/Lambda/Conv
+
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void psi_kernel(KArgs<Tf> a) {
+  if (a.ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[kWaves][2 * NX];
+  __shared__ int am_last;
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t tb = a.tile_off[j];
+  const int D = int(a.tile_off[j + 1] - tb) * a.rs;
+  const int k = a.kdim[j];
+  const int64_t base = tb * a.ts;
+  const Tf *Nj = a.nb + a.nb_off[j];
+  const Tf *Oj = a.off + tb * int64_t(a.rs) * NX;
+  Tf *v = reinterpret_cast<Tf *>(smem_raw);  // [NX][D]
+  Tf *t = v + NX * D;                        // [NX][k]
+
+  for (int r = tid; r < D; r += kBlock) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) v[c * D + r] = a.phi[base + int64_t(r) * NX + c] + a.lam[base + int64_t(r) * NX + c];
+  }
+  __syncthreads();
+  // t = N_j' v : one wave per basis vector, lanes over the support rows.
+  for (int i = wave; i < k; i += kWaves) {
+    const Tf *ncol = Nj + int64_t(i) * D;
+    Tf acc[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) acc[c] = Tf(0);
+    for (int r = lane; r < D; r += 64) {
+      const Tf nv = ncol[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) acc[c] += nv * v[c * D + r];
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const Tf s = wave_sum(acc[c]);
+      if (lane == 0) t[c * k + i] = s;
+    }
+  }
+  __syncthreads();
+  // psi = N_j t + o_c, then Lambda and the residuals, row by row.
+  double rp[NX], rd[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) rp[c] = rd[c] = 0.0;
+  for (int r = tid; r < D; r += kBlock) {
+    Tf yv[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) yv[c] = Tf(0);
+    for (int i = 0; i < k; ++i) {
+      const Tf nv = Nj[int64_t(i) * D + r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) yv[c] += nv * t[c * k + i];
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const int64_t e = base + int64_t(r) * NX + c;
+      const Tf psn = yv[c] + Oj[int64_t(c) * D + r];
+      const Tf ph = a.phi[e], la = a.lam[e], pso = a.psi[e];
+      a.lam[e] = (la + ph) - psn;
+      a.psi[e] = psn;
+      const double dp = double(ph - psn), dd = double(psn - pso);
+      rp[c] += dp * dp;
+      rd[c] += dd * dd;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NX; ++c) {
+    rp[c] = wave_sum(rp[c]);
+    rd[c] = wave_sum(rd[c]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      red[wave][c] = rp[c];
+      red[wave][NX + c] = rd[c];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double mp = 0.0, md = 0.0;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      double sp = 0.0, sd = 0.0;
+      for (int w = 0; w < kWaves; ++w) {
+        sp += red[w][c];
+        sd += red[w][NX + c];
+      }
+      sp = sqrt(sp);
+      sd = sqrt(sd);
+      // NaN propagates: its bit pattern orders above every finite value
+      mp = (sp > mp || sp != sp) ? sp : mp;
+      md = (sd > md || sd != sd) ? sd : md;
+    }
+    atomicMax(&a.ctl->rp_bits, as_bits(mp));
+    atomicMax(&a.ctl->rd_bits, as_bits(md));
+    __threadfence();
+    const unsigned prev = atomicAdd(&a.ctl->done_count, 1u);
+    am_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (am_last && tid == 0) {
+    __threadfence();
+    Ctl *c = a.ctl;
+    const double rpm = __longlong_as_double(static_cast<long long>(atomicAdd(&c->rp_bits, 0ull)));
+    const double rdm = __longlong_as_double(static_cast<long long>(atomicAdd(&c->rd_bits, 0ull)));
+    const int it = c->iters + 1;
+    c->iters = it;
+    c->last_rp = rpm;
+    c->last_rd = rdm;
+    if (!(rpm == rpm) || !(rdm == rdm) || isinf(rpm) || isinf(rdm)) {
+      c->numeric = 1;
+      c->stop = 1;
+    } else if (rpm <= c->eps && rdm <= c->eps) {
+      c->converged = 1;
+      c->stop = 1;
+    } else if (it >= c->max_iter) {
+      c->stop = 1;
+    }
+    atomicExch(&c->rp_bits, 0ull);
+    atomicExch(&c->rd_bits, 0ull);
+    atomicExch(&c->done_count, 0u);
+  }
+}
+
+// ------------------------------------------------------------------ outputs
+
+// u(0) = the u_0 rows of Phi x0 (Algorithm 1: compute u(t) from Phi) and the FP64 objective
+// sum_r w_r y_r^2 at the stopping iterate. One workgroup.
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void output_kernel(KArgs<Tf> a, const double *w64, double *u0) {
+  __shared__ double red[kWaves];
+  const int tid = threadIdx.x;
+  const int64_t ny = int64_t(a.N) * a.rs;
+  double acc = 0.0;
+  for (int64_t i = tid; i < ny; i += kBlock) {
+    const double yv = double(a.y[i]);
+    acc += w64[i] * yv * yv;
+  }
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += red[w];
+    a.ctl->objective = s;
+  }
+  const int nu = a.nu;
+  for (int i = tid; i < a.N * nu; i += kBlock) {
+    const int m = i / nu, q = i - m * nu;
+    u0[i] = double(a.y[int64_t(m) * a.rs + NX * a.T + q]);
+  }
+}
+
+template <typename Tf>
+__global__ __launch_bounds__(kBlock) void export_kernel(const Tf *phi, const int64_t *map, int64_t n,
+                                                        double *out) {
+  for (int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x; e < n; e += int64_t(gridDim.x) * kBlock)
+    out[map[e]] = double(phi[e]);
+}
+
+// ------------------------------------------------------------------ engine
+
+#define ENG_CHECK(expr)                                                   \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
+      return DLMPC_EDEVICE;                                               \
+    }                                                                     \
+  } while (0)
+
+template <typename Tf, int NX>
+class EngineT final : public Engine {
+ public:
+  int init(const HostSetup &hs, double rho, hipStream_t s, std::string &err) override {
+    hs_ = &hs;
+    stream_ = s;
+    KArgs<Tf> &a = args_;
+    a.N = hs.N;
+    a.nx = hs.nx;
+    a.nu = hs.nu;
+    a.T = hs.T;
+    a.rs = hs.rs;
+    a.ts = hs.ts;
+    a.rho = static_cast<Tf>(rho);
+    int rc;
+    if ((rc = upload(hs.tile_off, &a.tile_off, err))) return rc;
+    if ((rc = upload(hs.rt_ptr, &a.rt_ptr, err))) return rc;
+    if ((rc = upload(hs.rt_tile, &a.rt_tile, err))) return rc;
+    if ((rc = upload(hs.rt_col, &a.rt_col, err))) return rc;
+    if ((rc = upload(hs.kdim, &a.kdim, err))) return rc;
+    if ((rc = upload(hs.nb_off, &a.nb_off, err))) return rc;
+    if ((rc = upload(hs.csr_map, &map_, err))) return rc;
+    if ((rc = upload_conv(hs.nb, &a.nb, err))) return rc;
+    if ((rc = upload_conv(hs.off, &a.off, err))) return rc;
+    if ((rc = upload_conv(hs.w, &a.w, err))) return rc;
+    if ((rc = upload_conv(hs.lb, &a.lb, err))) return rc;
+    if ((rc = upload_conv(hs.ub, &a.ub, err))) return rc;
+    if ((rc = upload(hs.w, &w64_, err))) return rc;
+    const size_t nst = size_t(hs.n_tiles) * hs.ts;
+    if ((rc = alloc(&a.phi, nst, err))) return rc;
+    if ((rc = alloc(&a.psi, nst, err))) return rc;
+    if ((rc = alloc(&a.lam, nst, err))) return rc;
+    if ((rc = alloc(&a.x0f, size_t(hs.N) * NX, err))) return rc;
+    if ((rc = alloc(&a.nrm, size_t(hs.N), err))) return rc;
+    if ((rc = alloc(&a.y, size_t(hs.N) * hs.rs, err))) return rc;
+    if ((rc = alloc(&a.ctl, 1, err))) return rc;
+    lds_phi_ = (size_t(hs.p_max) * hs.rs + hs.rs + size_t(hs.p_max) * NX) * sizeof(Tf);
+    lds_psi_ = (size_t(NX) * hs.d_col_max + size_t(NX) * hs.k_max) * sizeof(Tf);
+    if (lds_phi_ > kMaxLds || lds_psi_ > kMaxLds) {
+      err = "patch too large for the on-chip staging of this build (LDS " + std::to_string(lds_psi_) + " B)";
+      return DLMPC_EINVAL;
+    }
+    return DLMPC_OK;
+  }
+
+  int precompute(const double *x0_dev, const double *wpsi, const double *wlam, int max_iter,
+                 double eps, std::string &err) override {
+    const int cold = (wpsi == nullptr);
+    hipLaunchKernelGGL((precompute_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), 0, stream_, args_,
+                       x0_dev, cold, max_iter, eps);
+    ENG_CHECK(hipGetLastError());
+    if (!cold) {
+      const int64_t n = int64_t(hs_->n_tiles) * hs_->ts;
+      const int g = int(std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
+      hipLaunchKernelGGL((warm_kernel<Tf>), dim3(g), dim3(kBlock), 0, stream_, args_.psi, args_.lam,
+                         map_, n, wpsi, wlam);
+      ENG_CHECK(hipGetLastError());
+    }
+    return DLMPC_OK;
+  }
+
+  int iteration(std::string &err) override {
+    hipLaunchKernelGGL((phi_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_phi_, stream_, args_);
+    ENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((psi_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_psi_, stream_, args_);
+    ENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int output(double *u0_dev, std::string &err) override {
+    hipLaunchKernelGGL((output_kernel<Tf, NX>), dim3(1), dim3(kBlock), 0, stream_, args_, w64_, u0_dev);
+    ENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int export_phi(double *phi_dev, std::string &err) override {
+    const int64_t n = int64_t(hs_->n_tiles) * hs_->ts;
+    const int g = int(std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
+    hipLaunchKernelGGL((export_kernel<Tf>), dim3(g), dim3(kBlock), 0, stream_, args_.phi, map_, n, phi_dev);
+    ENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  Ctl *ctl() override { return args_.ctl; }
+
+  ~EngineT() override {
+    for (void *p : owned_) (void)hipFree(p);
+  }
+
+ private:
+  static constexpr size_t kMaxLds = 64 * 1024;
+
+  template <typename U>
+  int alloc(U **dst, size_t n, std::string &err) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(U);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+      return DLMPC_ENOMEM;
+    }
+    owned_.push_back(p);
+    *dst = static_cast<U *>(p);
+    return DLMPC_OK;
+  }
+  template <typename U, typename V>
+  int upload(const std::vector<U> &src, V **dst, std::string &err) {
+    static_assert(sizeof(U) == sizeof(V), "upload type");
+    U *p = nullptr;
+    int rc = alloc(&p, src.size(), err);
+    if (rc) return rc;
+    if (!src.empty()) ENG_CHECK(hipMemcpy(p, src.data(), src.size() * sizeof(U), hipMemcpyHostToDevice));
+    *dst = reinterpret_cast<V *>(p);
+    return DLMPC_OK;
+  }
+  template <typename V>
+  int upload_conv(const std::vector<double> &src, V **dst, std::string &err) {
+    std::vector<Tf> tmp(src.begin(), src.end());
+    Tf *p = nullptr;
+    int rc = alloc(&p, tmp.size(), err);
+    if (rc) return rc;
+    if (!tmp.empty()) ENG_CHECK(hipMemcpy(p, tmp.data(), tmp.size() * sizeof(Tf), hipMemcpyHostToDevice));
+    *dst = const_cast<V *>(reinterpret_cast<const V *>(p));
+    return DLMPC_OK;
+  }
+
+  const HostSetup *hs_ = nullptr;
+  hipStream_t stream_ = nullptr;
+  KArgs<Tf> args_{};
+  const int64_t *map_ = nullptr;
+  const double *w64_ = nullptr;
+  size_t lds_phi_ = 0, lds_psi_ = 0;
+  std::vector<void *> owned_;
+};
+
+template <typename Tf>
+std::unique_ptr<Engine> make_for_nx(int nx) {
+  switch (nx) {
+    case 1: return std::make_unique<EngineT<Tf, 1>>();
+    case 2: return std::make_unique<EngineT<Tf, 2>>();
+    case 3: return std::make_unique<EngineT<Tf, 3>>();
+    case 4: return std::make_unique<EngineT<Tf, 4>>();
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+std::unique_ptr<Engine> make_engine(int precision, int nx) {
+  if (precision == DLMPC_FP64) return make_for_nx<double>(nx);
+  if (precision == DLMPC_FP32) return make_for_nx<float>(nx);
+  return nullptr;
+}
+
+}  // namespace dlmpc

@@ -1,0 +1,336 @@
+// C ABI of libdlmpc (declared in include/dlmpc.h): argument checks, the offline setup,
+// device residency, the captured iteration graph and the per-step solve loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "dlmpc_device.h"
+
+using dlmpc::Ctl;
+using dlmpc::HostSetup;
+
+struct dlmpc_problem {
+  HostSetup hs;
+  dlmpc_options opt{};
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::unique_ptr<dlmpc::Engine> eng;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int K = 16;
+  Ctl *h_ctl = nullptr;  // pinned, 2 slots
+  hipEvent_t ev_ctl[2] = {nullptr, nullptr};
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+  double *d_x0 = nullptr, *d_u0 = nullptr, *d_phi = nullptr, *d_warm = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define API_HIP(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) return fail(DLMPC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void release_device(dlmpc_problem *p) {
+  if (!p || p->host_only) return;
+  (void)hipSetDevice(p->opt.device);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (hipEvent_t e : {p->ev_ctl[0], p->ev_ctl[1], p->ev_t0, p->ev_t1})
+    if (e) (void)hipEventDestroy(e);
+  if (p->h_ctl) (void)hipHostFree(p->h_ctl);
+  for (double *d : {p->d_x0, p->d_u0, p->d_phi, p->d_warm})
+    if (d) (void)hipFree(d);
+  p->eng.reset();
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->h_ctl = nullptr;
+  p->stream = nullptr;
+}
+
+int setup_device(dlmpc_problem *p) {
+  const HostSetup &hs = p->hs;
+  int ndev = 0;
+  API_HIP(hipGetDeviceCount(&ndev));
+  if (p->opt.device < 0 || p->opt.device >= ndev) return fail(DLMPC_EINVAL, "device ordinal out of range");
+  API_HIP(hipSetDevice(p->opt.device));
+  if (p->opt.stream) {
+    p->stream = static_cast<hipStream_t>(p->opt.stream);
+  } else {
+    API_HIP(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    p->own_stream = true;
+  }
+  p->eng = dlmpc::make_engine(p->opt.precision, hs.nx);
+  if (!p->eng) return fail(DLMPC_EINVAL, "unsupported (precision, nx) combination; nx must be 1..4");
+  std::string err;
+  int rc = p->eng->init(hs, p->opt.rho, p->stream, err);
+  if (rc) return fail(rc, err);
+  API_HIP(hipMalloc(&p->d_x0, sizeof(double) * size_t(hs.N) * hs.nx));
+  API_HIP(hipMalloc(&p->d_u0, sizeof(double) * size_t(hs.N) * hs.nu));
+  API_HIP(hipMalloc(&p->d_phi, sizeof(double) * size_t(std::max<int64_t>(hs.nnz, 1))));
+  API_HIP(hipMalloc(&p->d_warm, sizeof(double) * size_t(2 * std::max<int64_t>(hs.nnz, 1))));
+  API_HIP(hipHostMalloc(reinterpret_cast<void **>(&p->h_ctl), 2 * sizeof(Ctl), hipHostMallocDefault));
+  std::memset(p->h_ctl, 0, 2 * sizeof(Ctl));
+  for (auto *e : {&p->ev_ctl[0], &p->ev_ctl[1]}) API_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  API_HIP(hipEventCreate(&p->ev_t0));
+  API_HIP(hipEventCreate(&p->ev_t1));
+  // K ADMM iterations captured once; every launch after the device-side stop is a no-op.
+  p->K = p->opt.check_every > 0 ? p->opt.check_every : 16;
+  p->K = std::max(1, std::min(p->K, p->opt.max_iter));
+  API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < p->K; ++i) {
+    rc = p->eng->iteration(err);
+    if (rc) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(p->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      return fail(rc, err);
+    }
+  }
+  API_HIP(hipStreamEndCapture(p->stream, &p->graph));
+  API_HIP(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+  API_HIP(hipStreamSynchronize(p->stream));
+  return DLMPC_OK;
+}
+
+bool finite_all(const double *v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+// The solve loop shared by the host- and device-buffer entry points. x0_dev, u0_dev on device.
+int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const double *wlam,
+              double *u0_dev, double *phi_dev, dlmpc_stats *stats, double t_host0_ms) {
+  std::string err;
+  const int max_iter = p->opt.max_iter;
+  int rc = p->eng->precompute(x0_dev, wpsi, wlam, max_iter, p->opt.eps, err);
+  if (rc) return fail(rc, err);
+  API_HIP(hipEventRecord(p->ev_t0, p->stream));
+  int launched = 0, launches = 0, cur = 0, pending = -1;
+  bool stopped = false;
+  Ctl *d_ctl = p->eng->ctl();
+  for (;;) {
+    API_HIP(hipGraphLaunch(p->gexec, p->stream));
+    API_HIP(hipMemcpyAsync(&p->h_ctl[cur], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipEventRecord(p->ev_ctl[cur], p->stream));
+    launched += p->K;
+    ++launches;
+    if (pending >= 0) {
+      API_HIP(hipEventSynchronize(p->ev_ctl[pending]));
+      if (p->h_ctl[pending].stop) {
+        stopped = true;
+        break;
+      }
+    }
+    pending = cur;
+    cur ^= 1;
+    if (launched >= max_iter + p->K) {
+      API_HIP(hipEventSynchronize(p->ev_ctl[pending]));
+      stopped = p->h_ctl[pending].stop != 0;
+      break;
+    }
+  }
+  if (!stopped) return fail(DLMPC_EDEVICE, "iteration graph did not reach its stop condition");
+  API_HIP(hipEventRecord(p->ev_t1, p->stream));
+  rc = p->eng->output(u0_dev, err);
+  if (rc) return fail(rc, err);
+  if (phi_dev) {
+    rc = p->eng->export_phi(phi_dev, err);
+    if (rc) return fail(rc, err);
+  }
+  API_HIP(hipMemcpyAsync(&p->h_ctl[0], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+  API_HIP(hipStreamSynchronize(p->stream));
+  const Ctl &c = p->h_ctl[0];
+  if (stats) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
+    stats->iters = c.iters;
+    stats->converged = c.converged;
+    stats->r_primal = c.last_rp;
+    stats->r_dual = c.last_rd;
+    stats->objective = c.objective;
+    stats->t_iter_ms = ms;
+    stats->graph_launches = launches;
+    const double t_now = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now().time_since_epoch()).count();
+    stats->t_solve_ms = t_now - t_host0_ms;
+  }
+  if (c.numeric) return fail(DLMPC_ENUMERIC, "NaN/Inf in the ADMM iterate");
+  return c.converged ? DLMPC_OK : DLMPC_ENOCONV;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dlmpc_last_error(void) { return g_err.c_str(); }
+
+const char *dlmpc_status_string(int s) {
+  switch (s) {
+    case DLMPC_OK: return "ok";
+    case DLMPC_ENOCONV: return "not converged within max_iter";
+    case DLMPC_EINVAL: return "invalid argument";
+    case DLMPC_ENOMEM: return "out of memory";
+    case DLMPC_EDEVICE: return "device error";
+    case DLMPC_EINFEASIBLE_LOCALITY: return "locality constraint infeasible";
+    case DLMPC_ENUMERIC: return "numerical breakdown (NaN/Inf)";
+    default: return "unknown status";
+  }
+}
+
+int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *cost,
+                const dlmpc_options *opts, dlmpc_problem **out) {
+  if (!out) return fail(DLMPC_EINVAL, "out must be non-NULL");
+  *out = nullptr;
+  dlmpc_options o{};
+  if (opts) o = *opts;
+  if (o.rho == 0.0) o.rho = 5.0;
+  if (o.eps == 0.0) o.eps = 1e-4;
+  if (o.max_iter == 0) o.max_iter = 500;
+  if (!(o.rho > 0.0) || !std::isfinite(o.rho) || !(o.eps > 0.0) || o.max_iter < 0 || o.check_every < 0)
+    return fail(DLMPC_EINVAL, "options: need rho > 0, eps > 0, max_iter >= 0, check_every >= 0");
+  if (o.precision != DLMPC_FP64 && o.precision != DLMPC_FP32) return fail(DLMPC_EINVAL, "unknown precision");
+  auto p = std::make_unique<dlmpc_problem>();
+  p->opt = o;
+  p->host_only = (o.flags & DLMPC_FLAG_HOST_ONLY) != 0;
+  std::string err;
+  int rc = dlmpc::host_setup(sys, d, T, cost, p->hs, err);
+  if (rc) return fail(rc, err);
+  if (!p->host_only) {
+    rc = setup_device(p.get());
+    if (rc) {
+      const std::string keep = g_err;
+      release_device(p.get());
+      return fail(rc, keep);
+    }
+  }
+  *out = p.release();
+  return DLMPC_OK;
+}
+
+int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
+  if (!p || !info) return fail(DLMPC_EINVAL, "NULL argument");
+  const HostSetup &h = p->hs;
+  info->R = h.R;
+  info->n_cols = int64_t(h.N) * h.nx;
+  info->nnz = h.nnz;
+  info->n_tiles = h.n_tiles;
+  info->d_row_max = h.d_row_max;
+  info->d_col_max = h.d_col_max;
+  info->p_max = h.p_max;
+  info->k_max = h.k_max;
+  info->sum_dcol_k = h.sum_dcol_k;
+  info->sum_dcol2 = h.sum_dcol2;
+  info->setup_ms = h.setup_ms;
+  info->factor_ms = h.factor_ms;
+  return DLMPC_OK;
+}
+
+int dlmpc_phi_pattern(const dlmpc_problem *p, int64_t *row_ptr, int32_t *col_idx) {
+  if (!p || !row_ptr || !col_idx) return fail(DLMPC_EINVAL, "NULL argument");
+  const HostSetup &h = p->hs;
+  std::copy(h.csr_rowptr.begin(), h.csr_rowptr.end(), row_ptr);
+  const int64_t Nx = int64_t(h.N) * h.nx, Nu = int64_t(h.N) * h.nu;
+  for (int64_t r = 0; r < h.R; ++r) {
+    const int32_t m = (r < Nx * h.T) ? int32_t((r % Nx) / h.nx) : int32_t(((r - Nx * h.T) % Nu) / h.nu);
+    int64_t w = h.csr_rowptr[r];
+    for (int32_t j : h.patch[m])
+      for (int c = 0; c < h.nx; ++c) col_idx[w++] = j * h.nx + c;
+  }
+  return DLMPC_OK;
+}
+
+int dlmpc_column_block(const dlmpc_problem *p, int32_t j, int32_t *D_out, int64_t *rows, double *P,
+                       double *O) {
+  if (!p || j < 0 || j >= p->hs.N) return fail(DLMPC_EINVAL, "bad problem or subsystem index");
+  const HostSetup &h = p->hs;
+  const int32_t np = int32_t(h.patch[j].size());
+  const int32_t D = np * h.rs;
+  if (D_out) *D_out = D;
+  if (rows)
+    for (int a = 0; a < np; ++a)
+      for (int l = 0; l < h.rs; ++l) rows[a * h.rs + l] = dlmpc::canon_row(h, h.patch[j][a], l);
+  const int k = h.kdim[j];
+  const double *Nj = h.nb.data() + h.nb_off[j];
+  if (P)
+    for (int r = 0; r < D; ++r)
+      for (int c = 0; c < D; ++c) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += Nj[size_t(i) * D + r] * Nj[size_t(i) * D + c];
+        P[size_t(r) * D + c] = s;
+      }
+  if (O) {
+    const double *Oj = h.off.data() + size_t(h.tile_off[j]) * h.rs * h.nx;
+    for (int r = 0; r < D; ++r)
+      for (int c = 0; c < h.nx; ++c) O[size_t(r) * h.nx + c] = Oj[size_t(c) * D + r];
+  }
+  return DLMPC_OK;
+}
+
+int dlmpc_solve(dlmpc_problem *p, const double *x0, const dlmpc_warm *warm, double *u0, double *phi,
+                dlmpc_stats *stats) {
+  const double t0 = now_ms();
+  if (!p || !x0) return fail(DLMPC_EINVAL, "NULL argument");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  const HostSetup &h = p->hs;
+  const size_t nxs = size_t(h.N) * h.nx;
+  if (!finite_all(x0, nxs)) return fail(DLMPC_EINVAL, "x0 has a NaN/Inf entry");
+  const bool use_warm = warm && warm->psi0 && warm->lambda0;
+  if (warm && (!warm->psi0) != (!warm->lambda0)) return fail(DLMPC_EINVAL, "warm start needs both psi0 and lambda0");
+  if (use_warm && (!finite_all(warm->psi0, size_t(h.nnz)) || !finite_all(warm->lambda0, size_t(h.nnz))))
+    return fail(DLMPC_EINVAL, "warm start has a NaN/Inf entry");
+  API_HIP(hipSetDevice(p->opt.device));
+  API_HIP(hipMemcpyAsync(p->d_x0, x0, nxs * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  const double *wpsi = nullptr, *wlam = nullptr;
+  if (use_warm) {
+    API_HIP(hipMemcpyAsync(p->d_warm, warm->psi0, size_t(h.nnz) * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    API_HIP(hipMemcpyAsync(p->d_warm + h.nnz, warm->lambda0, size_t(h.nnz) * sizeof(double),
+                           hipMemcpyHostToDevice, p->stream));
+    wpsi = p->d_warm;
+    wlam = p->d_warm + h.nnz;
+  }
+  const int rc = run_solve(p, p->d_x0, wpsi, wlam, p->d_u0, phi ? p->d_phi : nullptr, stats, t0);
+  if (rc < 0) return rc;
+  if (u0) API_HIP(hipMemcpy(u0, p->d_u0, size_t(h.N) * h.nu * sizeof(double), hipMemcpyDeviceToHost));
+  if (phi) API_HIP(hipMemcpy(phi, p->d_phi, size_t(h.nnz) * sizeof(double), hipMemcpyDeviceToHost));
+  if (stats) stats->t_solve_ms = now_ms() - t0;
+  return rc;
+}
+
+int dlmpc_solve_device(dlmpc_problem *p, const double *x0_dev, double *u0_dev, double *phi_dev,
+                       dlmpc_stats *stats) {
+  const double t0 = now_ms();
+  if (!p || !x0_dev || !u0_dev) return fail(DLMPC_EINVAL, "NULL argument");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  API_HIP(hipSetDevice(p->opt.device));
+  return run_solve(p, x0_dev, nullptr, nullptr, u0_dev, phi_dev, stats, t0);
+}
+
+void dlmpc_destroy(dlmpc_problem *p) {
+  if (!p) return;
+  release_device(p);
+  delete p;
+}
+
+}  // extern "C"

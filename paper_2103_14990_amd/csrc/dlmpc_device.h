@@ -1,0 +1,68 @@
+// Device-side data of libdlmpc: the control block, kernel arguments and the engine interface
+// the C ABI drives. Host code sees only the Engine interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+
+#include "dlmpc_internal.h"
+
+namespace dlmpc {
+
+// Convergence/stop state of one solve, written by the last Psi-comp workgroup of every
+// iteration (see psi_kernel) and polled by the host every K iterations.
+struct Ctl {
+  int32_t iters;
+  int32_t stop;
+  int32_t converged;
+  int32_t numeric;
+  int32_t max_iter;
+  uint32_t done_count;
+  int32_t pad0, pad1;
+  unsigned long long rp_bits;  // max over columns of the primal residual, as ordered bits
+  unsigned long long rd_bits;  // same for the dual residual
+  double last_rp, last_rd;
+  double eps;
+  double objective;
+};
+
+template <typename Tf>
+struct KArgs {
+  int32_t N, nx, nu, T, rs, ts;
+  Tf rho;
+  const int64_t *tile_off;  // [N+1]
+  const int64_t *rt_ptr;    // [N+1]
+  const int64_t *rt_tile;   // [n_tiles]
+  const int32_t *rt_col;    // [n_tiles]
+  const int32_t *kdim;      // [N]
+  const int64_t *nb_off;    // [N+1]
+  const Tf *nb;             // null bases, column-major per subsystem
+  const Tf *off;            // offsets o_c, column-major per subsystem
+  const Tf *w, *lb, *ub;    // [N*rs] row data, local order
+  Tf *phi, *psi, *lam;      // [n_tiles * ts] packed iterates
+  Tf *x0f;                  // [N*nx]
+  Tf *nrm;                  // [N] ||x_r||^2 per row subsystem
+  Tf *y;                    // [N*rs] (Phi x0)_r of the latest Phi-comp
+  Ctl *ctl;
+};
+
+class Engine {
+ public:
+  virtual ~Engine() = default;
+  virtual int init(const HostSetup &hs, double rho, hipStream_t s, std::string &err) = 0;
+  // Enqueue the per-solve precompute (cold start when wpsi == nullptr) on the stream.
+  virtual int precompute(const double *x0_dev, const double *wpsi, const double *wlam,
+                         int max_iter, double eps, std::string &err) = 0;
+  // Enqueue one ADMM iteration (capturable).
+  virtual int iteration(std::string &err) = 0;
+  virtual int output(double *u0_dev, std::string &err) = 0;
+  virtual int export_phi(double *phi_dev, std::string &err) = 0;
+  virtual Ctl *ctl() = 0;
+};
+
+std::unique_ptr<Engine> make_engine(int precision, int nx);
+
+}  // namespace dlmpc

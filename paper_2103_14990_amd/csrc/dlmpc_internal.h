@@ -1,0 +1,65 @@
+// Internal data structures shared by the host setup and the HIP runtime of libdlmpc.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dlmpc.h"
+
+namespace dlmpc {
+
+// Host-side result of the offline precomputation (Algorithm 1, first step).
+//
+// Packing ("tiles"): for every column subsystem j and every row subsystem m in its d-hop
+// patch P(j) there is one tile holding the block Phi[rows of m, columns of j], rs x nx values
+// row-major, where rs = nx*T + nu*(T-1) and the rows of m are in local order
+// (x_0..x_{T-1} with nx states each, then u_0..u_{T-2} with nu inputs each). The tiles of j
+// are contiguous and ordered by m ascending, so the support of j's columns (D_col(j) rows)
+// is one contiguous [D_col(j) x nx] block: Psi-comp of j reads and writes exactly that
+// block, Phi-comp of m gathers its p_m tiles, one from each column subsystem in P(m).
+struct HostSetup {
+  int32_t N = 0, nx = 0, nu = 0, T = 0, d = 0;
+  int32_t rs = 0;  // rows per subsystem
+  int32_t ts = 0;  // values per tile (rs * nx)
+  int64_t R = 0, nnz = 0, n_tiles = 0;
+
+  std::vector<std::vector<int32_t>> patch;  // P(j), ascending
+
+  std::vector<int64_t> tile_off;    // [N+1] first tile of column subsystem j
+  std::vector<int32_t> tile_rsub;   // [n_tiles] row subsystem m of each tile
+  std::vector<int64_t> rt_ptr;      // [N+1] row-side CSR over row subsystems
+  std::vector<int64_t> rt_tile;     // [n_tiles] tile (j, m) for j in P(m), j ascending
+  std::vector<int32_t> rt_col;      // [n_tiles] the column subsystem j of that tile
+
+  // Null bases: N_j is D_col(j) x k_j, column-major, at nb[nb_off[j]].
+  std::vector<int32_t> kdim;        // [N]
+  std::vector<int64_t> nb_off;      // [N+1]
+  std::vector<double> nb;
+  // Offsets o_c: D_col(j) x nx column-major at off[tile_off[j] * rs * nx].
+  std::vector<double> off;
+
+  // Row data in local order: w (cost weight), lb/ub (bounds on (Phi x0)_r), [N * rs].
+  std::vector<double> w, lb, ub;
+
+  std::vector<int64_t> csr_rowptr;  // [R+1] canonical pattern
+  std::vector<int64_t> csr_map;     // [n_tiles*ts] tile element -> canonical CSR index
+
+  int32_t p_max = 0, k_max = 0, d_row_max = 0, d_col_max = 0;
+  int64_t sum_dcol_k = 0, sum_dcol2 = 0;
+  double setup_ms = 0, factor_ms = 0;
+};
+
+// Canonical Phi row of local row l of subsystem m.
+inline int64_t canon_row(const HostSetup &h, int32_t m, int32_t l) {
+  const int64_t Nx = int64_t(h.N) * h.nx, Nu = int64_t(h.N) * h.nu;
+  if (l < h.nx * h.T) return int64_t(l / h.nx) * Nx + int64_t(m) * h.nx + (l % h.nx);
+  const int32_t lu = l - h.nx * h.T;
+  return Nx * h.T + int64_t(lu / h.nu) * Nu + int64_t(m) * h.nu + (lu % h.nu);
+}
+
+// Builds everything above on the host in FP64. Returns a DLMPC_* status; err gets a message.
+int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *cost,
+               HostSetup &hs, std::string &err);
+
+}  // namespace dlmpc

@@ -1,0 +1,227 @@
+"""Python binding of libdlmpc (ctypes). Argument marshalling only: every step of the solve
+runs in the library's HIP kernels. Names follow include/dlmpc.h.
+
+The library must have been built (``python -m paper_2103_14990_amd.build``); loading fails
+loudly otherwise — there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libdlmpc.so")
+
+OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EINFEASIBLE_LOCALITY, ENUMERIC = 0, 1, -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+FLAG_HOST_ONLY = 0x1
+PRECISIONS = {"fp64": FP64, "fp32": FP32}
+
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+_i32p = C.POINTER(C.c_int32)
+
+
+class System(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("nx", C.c_int32), ("nu", C.c_int32),
+                ("a_rowptr", _i64p), ("a_colidx", _i32p), ("a_blocks", _dp), ("b_blocks", _dp)]
+
+
+class Cost(C.Structure):
+    _fields_ = [("q_diag", _dp), ("r_diag", _dp), ("x_lo", _dp), ("x_hi", _dp), ("u_lo", _dp),
+                ("u_hi", _dp)]
+
+
+class Options(C.Structure):
+    _fields_ = [("rho", C.c_double), ("eps", C.c_double), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
+                ("stream", C.c_void_p), ("flags", C.c_uint32)]
+
+
+class Warm(C.Structure):
+    _fields_ = [("psi0", _dp), ("lambda0", _dp)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_primal", C.c_double),
+                ("r_dual", C.c_double), ("objective", C.c_double), ("t_solve_ms", C.c_double),
+                ("t_iter_ms", C.c_double), ("graph_launches", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Info(C.Structure):
+    _fields_ = [("R", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64), ("n_tiles", C.c_int64),
+                ("d_row_max", C.c_int32), ("d_col_max", C.c_int32), ("p_max", C.c_int32),
+                ("k_max", C.c_int32), ("sum_dcol_k", C.c_int64), ("sum_dcol2", C.c_int64),
+                ("setup_ms", C.c_double), ("factor_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = {
+    "dlmpc_setup": (C.c_int, [C.POINTER(System), C.c_int32, C.c_int32, C.POINTER(Cost),
+                              C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "dlmpc_query": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "dlmpc_phi_pattern": (C.c_int, [C.c_void_p, _i64p, _i32p]),
+    "dlmpc_column_block": (C.c_int, [C.c_void_p, C.c_int32, _i32p, _i64p, _dp, _dp]),
+    "dlmpc_solve": (C.c_int, [C.c_void_p, _dp, C.POINTER(Warm), _dp, _dp, C.POINTER(Stats)]),
+    "dlmpc_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
+    "dlmpc_destroy": (None, [C.c_void_p]),
+    "dlmpc_status_string": (C.c_char_p, [C.c_int]),
+    "dlmpc_last_error": (C.c_char_p, []),
+}
+
+_lib: C.CDLL | None = None
+
+
+def load(path: str | None = None) -> C.CDLL:
+    """Loads the built library (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libdlmpc not built at {p}; run python -m paper_2103_14990_amd.build")
+    lib = C.CDLL(p)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class DlmpcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"dlmpc status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(a: np.ndarray | None, ctype=C.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _f64(a) -> np.ndarray | None:
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class SolveResult:
+    status: int
+    u0: np.ndarray
+    phi: np.ndarray | None
+    stats: dict
+
+    @property
+    def converged(self) -> bool:
+        return self.status == OK
+
+
+class Problem:
+    """One DLMPC problem resident on a device (dlmpc_setup ... dlmpc_destroy)."""
+
+    def __init__(self, n_sub: int, nx: int, nu: int, a_rowptr, a_colidx, a_blocks, b_blocks,
+                 d: int, T: int, q_diag, r_diag, x_lo=None, x_hi=None, u_lo=None, u_hi=None,
+                 rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500, precision: str = "fp64",
+                 device: int = 0, stream: int | None = None, check_every: int = 0,
+                 host_only: bool = False):
+        self._lib = load()
+        self._h = C.c_void_p()
+        keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
+                    colidx=np.ascontiguousarray(a_colidx, dtype=np.int32),
+                    ab=_f64(np.reshape(a_blocks, -1)), bb=_f64(np.reshape(b_blocks, -1)),
+                    q=_f64(q_diag), r=_f64(r_diag), xl=_f64(x_lo), xh=_f64(x_hi), ul=_f64(u_lo),
+                    uh=_f64(u_hi))
+        sysd = System(n_sub, nx, nu, _ptr(keep["rowptr"], C.c_int64), _ptr(keep["colidx"], C.c_int32),
+                      _ptr(keep["ab"]), _ptr(keep["bb"]))
+        cost = Cost(_ptr(keep["q"]), _ptr(keep["r"]), _ptr(keep["xl"]), _ptr(keep["xh"]),
+                    _ptr(keep["ul"]), _ptr(keep["uh"]))
+        opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
+                       C.c_void_p(stream) if stream else None, FLAG_HOST_ONLY if host_only else 0)
+        st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
+        if st != OK:
+            raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
+        self.n_sub, self.nx, self.nu, self.d, self.T = n_sub, nx, nu, d, T
+        self.precision = precision
+        inf = Info()
+        self._check(self._lib.dlmpc_query(self._h, C.byref(inf)))
+        self.info = inf.as_dict()
+
+    @classmethod
+    def from_network(cls, net, d: int, T: int, cost, **kw) -> "Problem":
+        return cls(net.n_sub, net.nx, net.nu, net.a_rowptr, net.a_colidx, net.a_blocks,
+                   net.b_blocks, d, T, cost.q_diag, cost.r_diag, cost.x_lo, cost.x_hi, cost.u_lo,
+                   cost.u_hi, **kw)
+
+    def _check(self, st: int) -> int:
+        if st < 0:
+            raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
+        return st
+
+    @property
+    def nnz(self) -> int:
+        return int(self.info["nnz"])
+
+    def phi_pattern(self):
+        rp = np.zeros(self.info["R"] + 1, dtype=np.int64)
+        ci = np.zeros(self.nnz, dtype=np.int32)
+        self._check(self._lib.dlmpc_phi_pattern(self._h, _ptr(rp, C.c_int64), _ptr(ci, C.c_int32)))
+        return rp, ci
+
+    def column_block(self, j: int, want_P: bool = True):
+        D = C.c_int32()
+        self._check(self._lib.dlmpc_column_block(self._h, j, C.byref(D), None, None, None))
+        D = D.value
+        rows = np.zeros(D, dtype=np.int64)
+        P = np.zeros((D, D)) if want_P else None
+        O = np.zeros((D, self.nx))
+        self._check(self._lib.dlmpc_column_block(self._h, j, None, _ptr(rows, C.c_int64), _ptr(P), _ptr(O)))
+        return rows, P, O
+
+    def solve(self, x0, psi0=None, lambda0=None, want_phi: bool = False) -> SolveResult:
+        x0 = _f64(x0)
+        u0 = np.zeros(self.n_sub * self.nu)
+        phi = np.zeros(self.nnz) if want_phi else None
+        st = Stats()
+        warm = None
+        if psi0 is not None or lambda0 is not None:
+            p0, l0 = _f64(psi0), _f64(lambda0)
+            warm = Warm(_ptr(p0), _ptr(l0))
+            self._keep_warm = (p0, l0)
+        s = self._check(self._lib.dlmpc_solve(self._h, _ptr(x0), C.byref(warm) if warm else None,
+                                              _ptr(u0), _ptr(phi), C.byref(st)))
+        return SolveResult(s, u0, phi, st.as_dict())
+
+    def solve_device(self, x0_dev: int, u0_dev: int, phi_dev: int = 0) -> tuple[int, dict]:
+        """Device pointers (e.g. ``tensor.data_ptr()`` of float64 tensors on the problem's device)."""
+        st = Stats()
+        s = self._check(self._lib.dlmpc_solve_device(self._h, C.c_void_p(x0_dev), C.c_void_p(u0_dev),
+                                                     C.c_void_p(phi_dev) if phi_dev else None,
+                                                     C.byref(st)))
+        return s, st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.dlmpc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

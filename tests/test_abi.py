@@ -1,0 +1,158 @@
+"""C ABI without a GPU: exports, argument checks, and the host-side setup products
+(graph, d-hop pattern, column-block factorisation) against the FP64 oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import dlmpc_oracle as O
+from paper_2103_14990_amd import dlmpc
+from paper_2103_14990_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "dlmpc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dlmpc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(dlmpc.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 9
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(dlmpc.EXPORTS)
+
+
+def _host(wl_or_net, d=None, T=None, cost=None, **kw):
+    if hasattr(wl_or_net, "net"):
+        wl = wl_or_net
+        return dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, host_only=True, **kw)
+    return dlmpc.Problem.from_network(wl_or_net, d, T, cost, host_only=True, **kw)
+
+
+def _compare_blocks(pr, pb, js, tol_p, tol_o):
+    for j in js:
+        rows, P, Ob = pr.column_block(j)
+        blk = pb.blocks[j]
+        idx = np.searchsorted(blk.rows, rows)
+        assert np.array_equal(blk.rows[idx], rows)
+        assert np.abs(P - blk.P[np.ix_(idx, idx)]).max() < tol_p
+        scale = max(1.0, np.abs(blk.O).max())
+        assert np.abs(Ob - blk.O[idx]).max() < tol_o * scale
+
+
+def _pattern_mask(pr):
+    rp, ci = pr.phi_pattern()
+    mask = np.zeros((len(rp) - 1, pr.n_sub * pr.nx), dtype=bool)
+    for r in range(len(rp) - 1):
+        assert np.all(np.diff(ci[rp[r]:rp[r + 1]]) > 0)
+        mask[r, ci[rp[r]:rp[r + 1]]] = True
+    return mask
+
+
+@pytest.mark.parametrize("name", ["chain10", "grid16_box"])
+def test_host_setup_matches_oracle(name):
+    wl = W.workload(name)
+    pr = _host(wl)
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
+    assert np.array_equal(_pattern_mask(pr), pb.mask)
+    assert pr.info["R"] == pb.lay.R and pr.info["nnz"] == int(pb.mask.sum())
+    assert pr.info["d_row_max"] == int(pb.mask.sum(1).max())
+    assert pr.info["d_col_max"] == int(pb.mask.sum(0).max())
+    _compare_blocks(pr, pb, range(wl.net.n_sub), 1e-10, 1e-9)
+    # null-space dimensions agree with the oracle's SVD rank
+    ks = [len(b.rows) - b.rank for b in pb.blocks]
+    assert pr.info["k_max"] == max(ks)
+
+
+@pytest.mark.parametrize("nx,nu,d,T,seed", [(1, 1, 1, 4, 0), (3, 2, 1, 3, 1), (2, 2, 2, 4, 2)])
+def test_host_setup_generic_shapes(nx, nu, d, T, seed):
+    """Dense random blocks on a small irregular graph, several (nx, nu)."""
+    edges = np.array([(0, 1), (1, 2), (2, 3), (3, 4), (1, 4), (4, 5), (5, 6)])
+    net = W.generic_network(7, edges, nx, nu, seed)
+    cost = W.unit_cost(net)
+    pb = O.setup_from_network(net, d, T, cost)
+    if not pb.feasible:
+        with pytest.raises(dlmpc.DlmpcError) as e:
+            _host(net, d, T, cost)
+        assert e.value.status == dlmpc.EINFEASIBLE_LOCALITY
+        return
+    pr = _host(net, d, T, cost)
+    assert np.array_equal(_pattern_mask(pr), pb.mask)
+    _compare_blocks(pr, pb, range(net.n_sub), 1e-9, 1e-8)
+
+
+def test_infeasible_locality_status():
+    net = W.chain(6)
+    net.b_blocks[2] = 0.0
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        _host(net, 1, 5, W.unit_cost(net))
+    assert e.value.status == dlmpc.EINFEASIBLE_LOCALITY
+
+
+def test_whole_graph_patch_has_no_ring():
+    """d >= diameter: one patch is the whole network (no ring equations)."""
+    net = W.chain(5)
+    pr = _host(net, 4, 4, W.unit_cost(net))
+    pb = O.setup_from_network(net, 4, 4, W.unit_cost(net))
+    _compare_blocks(pr, pb, range(5), 1e-10, 1e-9)
+
+
+@pytest.mark.parametrize("bad", ["T", "d", "nan_a", "q", "bounds", "colidx"])
+def test_invalid_arguments(bad):
+    net = W.chain(4)
+    cost = W.unit_cost(net)
+    d, T = 1, 5
+    kw = {}
+    if bad == "T":
+        T = 1
+    elif bad == "d":
+        d = -1
+    elif bad == "nan_a":
+        net.a_blocks[0, 0, 0] = np.nan
+    elif bad == "q":
+        cost.q_diag[0] = 0.0
+    elif bad == "bounds":
+        cost = W.box_cost(net)
+        cost.x_lo = cost.x_lo.copy()
+        cost.x_lo[0] = 0.5  # interval must contain 0
+    elif bad == "colidx":
+        net.a_colidx[1] = 99
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        _host(net, d, T, cost, **kw)
+    assert e.value.status == dlmpc.EINVAL
+
+
+def test_host_only_problem_refuses_solve():
+    wl = W.workload("chain10")
+    pr = _host(wl)
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        pr.solve(wl.x0(1))
+    assert e.value.status == dlmpc.EDEVICE
+
+
+@pytest.mark.slow
+def test_full_size_irregular_mesh_sampled_blocks():
+    """1024-node irregular mesh, d = 3, T = 15: sampled column blocks against the oracle's SVD
+    (the oracle factors only the sampled blocks)."""
+    wl = W.workload("irregular1024_box")
+    pr = _host(wl)
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost, blocks=False)
+    Z = O.build_zab(pb.A, pb.B, pb.lay.T)
+    rng = np.random.default_rng(0)
+    patch = [int(np.count_nonzero(pb.dist[j] <= wl.d)) for j in range(wl.net.n_sub)]
+    js = sorted({int(np.argmax(patch)), int(np.argmin(patch)), *rng.choice(wl.net.n_sub, 3, replace=False).tolist()})
+    lay = pb.lay
+    for j in js:
+        blk = O.column_block(Z, pb.mask, lay, j)
+        rows, P, Ob = pr.column_block(j)
+        idx = np.searchsorted(blk.rows, rows)
+        assert np.array_equal(blk.rows[idx], rows)
+        assert np.abs(P - blk.P[np.ix_(idx, idx)]).max() < 1e-8
+        assert np.abs(Ob - blk.O[idx]).max() < 1e-7 * max(1.0, np.abs(blk.O).max())
