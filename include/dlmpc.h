@@ -53,6 +53,13 @@ typedef enum {
 /* Setup flags (dlmpc_options.flags). */
 #define DLMPC_FLAG_HOST_ONLY 0x1u /* build host-side data only; no HIP call is made and every
                                      solve returns DLMPC_EDEVICE. For inspection and tests. */
+/* Iteration schedule. Neither flag = time both at setup and keep the faster one. */
+#define DLMPC_FLAG_SCHED_GRAPH 0x2u      /* two kernels per iteration, K iterations per captured
+                                            HIP graph launch, host polls the stop flag */
+#define DLMPC_FLAG_SCHED_PERSISTENT 0x4u /* one launch runs every iteration with grid barriers
+                                            between Phi-comp and Psi-comp; the grid is sized to be
+                                            co-resident, and a barrier wait that times out fails
+                                            the solve with DLMPC_EDEVICE */
 
 /* Networked plant. G_(A,B) is read off the block sparsity of A: subsystems i != j are
  * adjacent iff block A_ij or A_ji is present in the block-CSR with a nonzero entry. Every
@@ -105,8 +112,8 @@ typedef struct {
   double objective;     /* sum_r w_r (Phi x0)_r^2 at the stopping iterate, FP64 */
   double t_solve_ms;    /* host wall time of the solve call */
   double t_iter_ms;     /* device time of the iteration phase (HIP events) */
-  int32_t graph_launches;
-  int32_t reserved;
+  int32_t graph_launches; /* kernel-graph launches (graph schedule) or 1 (persistent) */
+  int32_t schedule;       /* 0 = graph, 1 = persistent */
 } dlmpc_stats;
 
 typedef struct {
@@ -122,6 +129,10 @@ typedef struct {
   int64_t sum_dcol2;    /* sum over subsystems of D_col(j)^2 */
   double setup_ms;      /* host wall time of dlmpc_setup */
   double factor_ms;     /* of which the FP64 factorisation of the column blocks */
+  int32_t schedule;     /* 0 = graph, 1 = persistent */
+  int32_t persistent_grid; /* co-resident blocks of the persistent schedule (0 = unavailable) */
+  double tune_graph_us;      /* per-iteration time measured at setup (0 if not measured) */
+  double tune_persistent_us;
 } dlmpc_info;
 
 /* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the
@@ -160,6 +171,14 @@ int dlmpc_solve(struct dlmpc_problem *p, const double *x0, const dlmpc_warm *war
  * after the outputs are written (the problem's stream is synchronised). */
 int dlmpc_solve_device(struct dlmpc_problem *p, const double *x0_dev, double *u0_dev,
                        double *phi_dev, dlmpc_stats *stats);
+
+/* Kernel timing for roofline measurement: runs `iters` ADMM iterations of the two-kernel
+ * schedule from x0_dev without early stop, each kernel launched on its own between HIP events
+ * on the problem's stream, and returns the mean device time per launch in microseconds of the
+ * Phi-comp kernel (*us_phi) and of the Psi-comp/Lambda/Conv kernel (*us_psi). The iterate is
+ * left in an unspecified state (the next solve starts afresh). */
+int dlmpc_time_kernels(struct dlmpc_problem *p, const double *x0_dev, int32_t iters, double *us_phi,
+                       double *us_psi);
 
 void dlmpc_destroy(struct dlmpc_problem *p);
 const char *dlmpc_status_string(int status);

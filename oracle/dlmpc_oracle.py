@@ -141,6 +141,7 @@ def build_zab(A: np.ndarray, B: np.ndarray, T: int) -> sp.csr_matrix:
 class ColumnBlock:
     """Psi-comp data of one subsystem j (shared by its nx columns)."""
 
+    j: int  # the subsystem whose columns this block serves
     rows: np.ndarray  # canonical row indices of the support (sorted)
     P: np.ndarray  # D x D projector onto null(H_j)
     O: np.ndarray  # D x nx offsets o_c = H_j^+ e_c
@@ -166,7 +167,7 @@ def column_block(Z: sp.csr_matrix, mask: np.ndarray, lay: Layout, j: int) -> Col
     Hpinv_E = Vr @ ((Ur.T @ E) / sr[:, None])
     P = np.eye(len(rows)) - Vr @ Vr.T
     feas = float(np.abs(H @ Hpinv_E - E).max())
-    return ColumnBlock(rows=rows, P=P, O=Hpinv_E, rank=r, feas_resid=feas)
+    return ColumnBlock(j=j, rows=rows, P=P, O=Hpinv_E, rank=r, feas_resid=feas)
 
 
 def column_blocks(Z: sp.csr_matrix, mask: np.ndarray, lay: Layout) -> list[ColumnBlock]:
@@ -258,8 +259,8 @@ def psi_comp(pb: Problem, Phi, Lam):
     """Column-wise projection (Algorithm 2, Psi-comp): Psi[S_j, c] = P_j (Phi + Lam)[S_j, c] + o_c."""
     Psi = np.zeros_like(Phi)
     nx = pb.lay.nx
-    for j, blk in enumerate(pb.blocks):
-        cols = slice(j * nx, (j + 1) * nx)
+    for blk in pb.blocks:
+        cols = slice(blk.j * nx, (blk.j + 1) * nx)
         Vv = Phi[blk.rows, cols] + Lam[blk.rows, cols]
         Psi[blk.rows, cols] = blk.P @ Vv + blk.O
     return Psi
@@ -329,8 +330,8 @@ def kkt_residuals(pb: Problem, res: Result, x0: np.ndarray, rho: float) -> dict:
     eq = float(np.abs(Z @ res.Psi - rhs).max())
     stat = 0.0
     nx = pb.lay.nx
-    for j, blk in enumerate(pb.blocks):
-        L = rho * res.Lam[blk.rows, j * nx:(j + 1) * nx]
+    for blk in pb.blocks:
+        L = rho * res.Lam[blk.rows, blk.j * nx:(blk.j + 1) * nx]
         stat = max(stat, float(np.abs(blk.P @ L).max()))
     y = res.Phi @ x0
     box = float(max(np.max(pb.lb - y), np.max(y - pb.ub), 0.0))

@@ -14,7 +14,9 @@ SOURCES = ["setup_host.cpp", "admm_kernels.hip", "dlmpc_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are disabled for all device code (see DESIGN notes on gfx950).
-DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Code object v5 so that the HIP runtime bundled with PyTorch (ROCm 7.0) loads it too.
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5",
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def build(verbose: bool = False) -> str:

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <vector>
 
 #include "dlmpc_device.h"
 
@@ -24,6 +25,8 @@ struct dlmpc_problem {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int K = 16;
+  int sched = 0;  // 0 = graph, 1 = persistent
+  double tune_graph_us = 0.0, tune_persistent_us = 0.0;
   Ctl *h_ctl = nullptr;  // pinned, 2 slots
   hipEvent_t ev_ctl[2] = {nullptr, nullptr};
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
@@ -63,6 +66,8 @@ void release_device(dlmpc_problem *p) {
   p->h_ctl = nullptr;
   p->stream = nullptr;
 }
+
+int choose_schedule(dlmpc_problem *p);
 
 int setup_device(dlmpc_problem *p) {
   const HostSetup &hs = p->hs;
@@ -106,6 +111,58 @@ int setup_device(dlmpc_problem *p) {
   API_HIP(hipStreamEndCapture(p->stream, &p->graph));
   API_HIP(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
   API_HIP(hipStreamSynchronize(p->stream));
+  return choose_schedule(p);
+}
+
+// Times n iterations of a schedule from x0 = (1, ..., 1) with the stop test disabled.
+int time_schedule(dlmpc_problem *p, int sched, int n, double *us_per_iter) {
+  std::string err;
+  const HostSetup &hs = p->hs;
+  std::vector<double> ones(size_t(hs.N) * hs.nx, 1.0);
+  API_HIP(hipMemcpy(p->d_x0, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+  float best = 1e30f;
+  for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms code and caches
+    int rc = p->eng->precompute(p->d_x0, nullptr, nullptr, n, -1.0, err);
+    if (rc) return fail(rc, err);
+    API_HIP(hipEventRecord(p->ev_t0, p->stream));
+    if (sched == 1) {
+      rc = p->eng->run_persistent(true, err);
+      if (rc) return fail(rc, err);
+    } else {
+      for (int done = 0; done < n; done += p->K) API_HIP(hipGraphLaunch(p->gexec, p->stream));
+    }
+    API_HIP(hipEventRecord(p->ev_t1, p->stream));
+    API_HIP(hipStreamSynchronize(p->stream));
+    float ms = 0.f;
+    API_HIP(hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1));
+    best = std::min(best, ms);
+    API_HIP(hipMemcpy(&p->h_ctl[0], p->eng->ctl(), sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (p->h_ctl[0].bar_fail) return fail(DLMPC_EDEVICE, "persistent grid barrier timed out");
+  }
+  *us_per_iter = 1e3 * double(best) / n;
+  return DLMPC_OK;
+}
+
+int choose_schedule(dlmpc_problem *p) {
+  const uint32_t f = p->opt.flags;
+  const bool can_persist = p->eng->persistent_grid() > 0;
+  if (f & DLMPC_FLAG_SCHED_GRAPH) {
+    p->sched = 0;
+    return DLMPC_OK;
+  }
+  if (f & DLMPC_FLAG_SCHED_PERSISTENT) {
+    if (!can_persist) return fail(DLMPC_EDEVICE, "persistent schedule unavailable on this device");
+    p->sched = 1;
+    return DLMPC_OK;
+  }
+  const int n = 2 * p->K;
+  int rc = time_schedule(p, 0, n, &p->tune_graph_us);
+  if (rc) return rc;
+  if (can_persist) {
+    rc = time_schedule(p, 1, n, &p->tune_persistent_us);
+    if (rc) return rc;
+  }
+  p->sched = (can_persist && p->tune_persistent_us < p->tune_graph_us) ? 1 : 0;
   return DLMPC_OK;
 }
 
@@ -126,7 +183,13 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
   int launched = 0, launches = 0, cur = 0, pending = -1;
   bool stopped = false;
   Ctl *d_ctl = p->eng->ctl();
-  for (;;) {
+  if (p->sched == 1) {
+    rc = p->eng->run_persistent(false, err);
+    if (rc) return fail(rc, err);
+    launches = 1;
+    stopped = true;
+  }
+  for (; !stopped;) {
     API_HIP(hipGraphLaunch(p->gexec, p->stream));
     API_HIP(hipMemcpyAsync(&p->h_ctl[cur], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
     API_HIP(hipEventRecord(p->ev_ctl[cur], p->stream));
@@ -168,10 +231,12 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     stats->objective = c.objective;
     stats->t_iter_ms = ms;
     stats->graph_launches = launches;
+    stats->schedule = p->sched;
     const double t_now = std::chrono::duration<double, std::milli>(
                              std::chrono::steady_clock::now().time_since_epoch()).count();
     stats->t_solve_ms = t_now - t_host0_ms;
   }
+  if (c.bar_fail) return fail(DLMPC_EDEVICE, "persistent grid barrier timed out");
   if (c.numeric) return fail(DLMPC_ENUMERIC, "NaN/Inf in the ADMM iterate");
   return c.converged ? DLMPC_OK : DLMPC_ENOCONV;
 }
@@ -244,6 +309,10 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   info->sum_dcol2 = h.sum_dcol2;
   info->setup_ms = h.setup_ms;
   info->factor_ms = h.factor_ms;
+  info->schedule = p->sched;
+  info->persistent_grid = (p->eng ? p->eng->persistent_grid() : 0);
+  info->tune_graph_us = p->tune_graph_us;
+  info->tune_persistent_us = p->tune_persistent_us;
   return DLMPC_OK;
 }
 
@@ -272,18 +341,19 @@ int dlmpc_column_block(const dlmpc_problem *p, int32_t j, int32_t *D_out, int64_
     for (int a = 0; a < np; ++a)
       for (int l = 0; l < h.rs; ++l) rows[a * h.rs + l] = dlmpc::canon_row(h, h.patch[j][a], l);
   const int k = h.kdim[j];
+  const int ld = dlmpc::padded_ld(D);
   const double *Nj = h.nb.data() + h.nb_off[j];
   if (P)
     for (int r = 0; r < D; ++r)
       for (int c = 0; c < D; ++c) {
         double s = 0.0;
-        for (int i = 0; i < k; ++i) s += Nj[size_t(i) * D + r] * Nj[size_t(i) * D + c];
+        for (int i = 0; i < k; ++i) s += Nj[size_t(i) * ld + r] * Nj[size_t(i) * ld + c];
         P[size_t(r) * D + c] = s;
       }
   if (O) {
-    const double *Oj = h.off.data() + size_t(h.tile_off[j]) * h.rs * h.nx;
+    const double *Oj = h.off.data() + h.off_ptr[j];
     for (int r = 0; r < D; ++r)
-      for (int c = 0; c < h.nx; ++c) O[size_t(r) * h.nx + c] = Oj[size_t(c) * D + r];
+      for (int c = 0; c < h.nx; ++c) O[size_t(r) * h.nx + c] = Oj[size_t(c) * ld + r];
   }
   return DLMPC_OK;
 }
@@ -325,6 +395,39 @@ int dlmpc_solve_device(dlmpc_problem *p, const double *x0_dev, double *u0_dev, d
   if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
   API_HIP(hipSetDevice(p->opt.device));
   return run_solve(p, x0_dev, nullptr, nullptr, u0_dev, phi_dev, stats, t0);
+}
+
+int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, double *us_phi,
+                       double *us_psi) {
+  if (!p || !x0_dev || iters < 1 || !us_phi || !us_psi) return fail(DLMPC_EINVAL, "bad argument");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  API_HIP(hipSetDevice(p->opt.device));
+  std::string err;
+  int rc = p->eng->precompute(x0_dev, nullptr, nullptr, iters, -1.0, err);
+  if (rc) return fail(rc, err);
+  std::vector<hipEvent_t> ev(2 * size_t(iters) + 1);
+  for (auto &e : ev) API_HIP(hipEventCreate(&e));
+  API_HIP(hipEventRecord(ev[0], p->stream));
+  for (int i = 0; i < iters && rc == DLMPC_OK; ++i) {
+    rc = p->eng->phi_only(err);
+    if (!rc) API_HIP(hipEventRecord(ev[2 * i + 1], p->stream));
+    if (!rc) rc = p->eng->psi_only(err);
+    if (!rc) API_HIP(hipEventRecord(ev[2 * i + 2], p->stream));
+  }
+  API_HIP(hipStreamSynchronize(p->stream));
+  double sphi = 0.0, spsi = 0.0;
+  for (int i = 0; i < iters && rc == DLMPC_OK; ++i) {
+    float a = 0.f, b = 0.f;
+    API_HIP(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
+    API_HIP(hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]));
+    sphi += a;
+    spsi += b;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (rc) return fail(rc, err);
+  *us_phi = 1e3 * sphi / iters;
+  *us_psi = 1e3 * spsi / iters;
+  return DLMPC_OK;
 }
 
 void dlmpc_destroy(dlmpc_problem *p) {

@@ -27,6 +27,15 @@ struct Ctl {
   double last_rp, last_rd;
   double eps;
   double objective;
+  // persistent schedule: grid barrier and per-iteration residual slots (ping-pong)
+  unsigned bar_count, bar_gen, bar_fail, pad2;
+  unsigned long long slot_rp[2], slot_rd[2];
+};
+
+// Static work lists of the persistent schedule: block b runs Phi-comp for
+// phi_list[phi_ptr[b] .. phi_ptr[b+1]) and Psi-comp for psi_list[psi_ptr[b] .. psi_ptr[b+1]).
+struct Sched {
+  const int32_t *phi_ptr, *phi_list, *psi_ptr, *psi_list;
 };
 
 template <typename Tf>
@@ -39,8 +48,11 @@ struct KArgs {
   const int32_t *rt_col;    // [n_tiles]
   const int32_t *kdim;      // [N]
   const int64_t *nb_off;    // [N+1]
-  const Tf *nb;             // null bases, column-major per subsystem
-  const Tf *off;            // offsets o_c, column-major per subsystem
+  const int64_t *off_ptr;   // [N+1]
+  const int32_t *phi_order; // [N] launch order of the Phi-comp blocks
+  const int32_t *psi_order; // [N] launch order of the Psi-comp blocks
+  const Tf *nb;             // null bases, column-major per subsystem, padded leading dim
+  const Tf *off;            // offsets o_c, column-major per subsystem, padded leading dim
   const Tf *w, *lb, *ub;    // [N*rs] row data, local order
   Tf *phi, *psi, *lam;      // [n_tiles * ts] packed iterates
   Tf *x0f;                  // [N*nx]
@@ -56,8 +68,13 @@ class Engine {
   // Enqueue the per-solve precompute (cold start when wpsi == nullptr) on the stream.
   virtual int precompute(const double *x0_dev, const double *wpsi, const double *wlam,
                          int max_iter, double eps, std::string &err) = 0;
-  // Enqueue one ADMM iteration (capturable).
+  // Enqueue one ADMM iteration (capturable), or one of its two kernels.
   virtual int iteration(std::string &err) = 0;
+  virtual int phi_only(std::string &err) = 0;
+  virtual int psi_only(std::string &err) = 0;
+  // Enqueue all iterations of one solve as one launch (persistent schedule).
+  virtual int run_persistent(bool tune, std::string &err) = 0;
+  virtual int persistent_grid() const = 0;  // 0 when the device cannot co-schedule the grid
   virtual int output(double *u0_dev, std::string &err) = 0;
   virtual int export_phi(double *phi_dev, std::string &err) = 0;
   virtual Ctl *ctl() = 0;

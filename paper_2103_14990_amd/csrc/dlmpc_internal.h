@@ -32,11 +32,13 @@ struct HostSetup {
   std::vector<int64_t> rt_tile;     // [n_tiles] tile (j, m) for j in P(m), j ascending
   std::vector<int32_t> rt_col;      // [n_tiles] the column subsystem j of that tile
 
-  // Null bases: N_j is D_col(j) x k_j, column-major, at nb[nb_off[j]].
+  // Null bases: N_j is D_col(j) x k_j, column-major with leading dimension ld(j) =
+  // D_col(j) rounded up to a multiple of 4 (zero rows below D_col(j)), at nb[nb_off[j]].
   std::vector<int32_t> kdim;        // [N]
   std::vector<int64_t> nb_off;      // [N+1]
   std::vector<double> nb;
-  // Offsets o_c: D_col(j) x nx column-major at off[tile_off[j] * rs * nx].
+  // Offsets o_c: ld(j) x nx column-major (zero padded) at off[off_ptr[j]].
+  std::vector<int64_t> off_ptr;     // [N+1]
   std::vector<double> off;
 
   // Row data in local order: w (cost weight), lb/ub (bounds on (Phi x0)_r), [N * rs].
@@ -49,6 +51,8 @@ struct HostSetup {
   int64_t sum_dcol_k = 0, sum_dcol2 = 0;
   double setup_ms = 0, factor_ms = 0;
 };
+
+inline int32_t padded_ld(int32_t D) { return (D + 3) & ~3; }
 
 // Canonical Phi row of local row l of subsystem m.
 inline int64_t canon_row(const HostSetup &h, int32_t m, int32_t l) {

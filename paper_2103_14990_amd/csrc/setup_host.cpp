@@ -548,14 +548,24 @@ int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *
     }
   hs.kdim = ks;
   hs.nb_off.assign(N + 1, 0);
-  for (int j = 0; j < N; ++j) hs.nb_off[j + 1] = hs.nb_off[j] + int64_t(nbs[j].size());
-  hs.nb.resize(size_t(hs.nb_off[N]));
-  hs.off.resize(size_t(hs.n_tiles) * hs.rs * nx);
+  hs.off_ptr.assign(N + 1, 0);
   for (int j = 0; j < N; ++j) {
-    std::copy(nbs[j].begin(), nbs[j].end(), hs.nb.begin() + hs.nb_off[j]);
-    std::copy(offs[j].begin(), offs[j].end(), hs.off.begin() + size_t(hs.tile_off[j]) * hs.rs * nx);
+    const int64_t ld = padded_ld(int32_t(hs.patch[j].size()) * hs.rs);
+    hs.nb_off[j + 1] = hs.nb_off[j] + ld * ks[j];
+    hs.off_ptr[j + 1] = hs.off_ptr[j] + ld * nx;
+  }
+  hs.nb.assign(size_t(hs.nb_off[N]), 0.0);
+  hs.off.assign(size_t(hs.off_ptr[N]), 0.0);
+  for (int j = 0; j < N; ++j) {
+    const int32_t D = int32_t(hs.patch[j].size()) * hs.rs, ld = padded_ld(D);
+    for (int i = 0; i < ks[j]; ++i)
+      std::copy(nbs[j].begin() + size_t(i) * D, nbs[j].begin() + size_t(i + 1) * D,
+                hs.nb.begin() + hs.nb_off[j] + size_t(i) * ld);
+    for (int c = 0; c < nx; ++c)
+      std::copy(offs[j].begin() + size_t(c) * D, offs[j].begin() + size_t(c + 1) * D,
+                hs.off.begin() + hs.off_ptr[j] + size_t(c) * ld);
     hs.k_max = std::max(hs.k_max, ks[j]);
-    hs.sum_dcol_k += int64_t(hs.patch[j].size()) * hs.rs * ks[j];
+    hs.sum_dcol_k += int64_t(D) * ks[j];
   }
   const auto t_end = std::chrono::steady_clock::now();
   hs.factor_ms = std::chrono::duration<double, std::milli>(t_end - t_fac).count();

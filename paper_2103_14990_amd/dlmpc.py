@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_PKG, "_lib", "libdlmpc.so")
 OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EINFEASIBLE_LOCALITY, ENUMERIC = 0, 1, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 FLAG_HOST_ONLY = 0x1
+FLAG_SCHED_GRAPH = 0x2
+FLAG_SCHED_PERSISTENT = 0x4
+SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
 _dp = C.POINTER(C.c_double)
@@ -48,17 +51,19 @@ class Warm(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_primal", C.c_double),
                 ("r_dual", C.c_double), ("objective", C.c_double), ("t_solve_ms", C.c_double),
-                ("t_iter_ms", C.c_double), ("graph_launches", C.c_int32), ("reserved", C.c_int32)]
+                ("t_iter_ms", C.c_double), ("graph_launches", C.c_int32), ("schedule", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Info(C.Structure):
     _fields_ = [("R", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64), ("n_tiles", C.c_int64),
                 ("d_row_max", C.c_int32), ("d_col_max", C.c_int32), ("p_max", C.c_int32),
                 ("k_max", C.c_int32), ("sum_dcol_k", C.c_int64), ("sum_dcol2", C.c_int64),
-                ("setup_ms", C.c_double), ("factor_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("factor_ms", C.c_double), ("schedule", C.c_int32),
+                ("persistent_grid", C.c_int32), ("tune_graph_us", C.c_double),
+                ("tune_persistent_us", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -72,6 +77,7 @@ EXPORTS = {
     "dlmpc_column_block": (C.c_int, [C.c_void_p, C.c_int32, _i32p, _i64p, _dp, _dp]),
     "dlmpc_solve": (C.c_int, [C.c_void_p, _dp, C.POINTER(Warm), _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
+    "dlmpc_time_kernels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, _dp, _dp]),
     "dlmpc_destroy": (None, [C.c_void_p]),
     "dlmpc_status_string": (C.c_char_p, [C.c_int]),
     "dlmpc_last_error": (C.c_char_p, []),
@@ -88,6 +94,12 @@ def load(path: str | None = None) -> C.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"libdlmpc not built at {p}; run python -m paper_2103_14990_amd.build")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7, and the library must
+    # bind to that one (same soname) rather than load the system copy first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(p)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)
@@ -133,7 +145,7 @@ class Problem:
                  d: int, T: int, q_diag, r_diag, x_lo=None, x_hi=None, u_lo=None, u_hi=None,
                  rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500, precision: str = "fp64",
                  device: int = 0, stream: int | None = None, check_every: int = 0,
-                 host_only: bool = False):
+                 host_only: bool = False, schedule: str = "auto"):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -146,7 +158,8 @@ class Problem:
         cost = Cost(_ptr(keep["q"]), _ptr(keep["r"]), _ptr(keep["xl"]), _ptr(keep["xh"]),
                     _ptr(keep["ul"]), _ptr(keep["uh"]))
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
-                       C.c_void_p(stream) if stream else None, FLAG_HOST_ONLY if host_only else 0)
+                       C.c_void_p(stream) if stream else None,
+                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule])
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
             raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
@@ -208,6 +221,12 @@ class Problem:
                                                      C.c_void_p(phi_dev) if phi_dev else None,
                                                      C.byref(st)))
         return s, st.as_dict()
+
+    def time_kernels(self, x0_dev: int, iters: int) -> tuple[float, float]:
+        """Mean microseconds per launch of the Phi-comp and Psi-comp kernels (no early stop)."""
+        a, b = C.c_double(), C.c_double()
+        self._check(self._lib.dlmpc_time_kernels(self._h, C.c_void_p(x0_dev), iters, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

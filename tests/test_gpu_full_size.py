@@ -1,0 +1,72 @@
+"""Full-size parity on the 1024-subsystem irregular mesh (d = 3, T = 15, boxes), against oracle
+values stored by tests/golden/make_full_size.py (FP64 CPU oracle only; the oracle needs about
+half an hour per x0 here, so it does not run inside the test)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2103_14990_amd import dlmpc
+from paper_2103_14990_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "irregular1024_box.json")
+
+
+@pytest.fixture(scope="module")
+def golden():
+    return json.load(open(GOLDEN))
+
+
+@pytest.fixture(scope="module")
+def wl():
+    return W.workload("irregular1024_box")
+
+
+def _problem(wl, precision, schedule="auto"):
+    return dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps,
+                                      max_iter=wl.max_iter, precision=precision, schedule=schedule)
+
+
+@pytest.mark.parametrize("schedule", ["graph", "persistent"])
+def test_fp64_matches_oracle(golden, wl, schedule):
+    pr = _problem(wl, "fp64", schedule)
+    for rec in golden["records"]:
+        assert rec["sigma"] == wl.sigma and rec["eps"] == wl.eps
+        res = pr.solve(wl.x0(rec["seed"]))
+        u0 = np.array(rec["u0"])
+        err = np.abs(res.u0 - u0).max() / np.abs(u0).max()
+        print(f"  seed {rec['seed']}: iters gpu={res.stats['iters']} oracle={rec['iters']} "
+              f"u0 rel {err:.2e}", flush=True)
+        assert res.stats["iters"] == rec["iters"]
+        assert (res.status == dlmpc.OK) == rec["converged"]
+        assert err < 1e-9
+        assert abs(res.stats["objective"] - rec["J"]) < 1e-9 * rec["J"]
+
+
+def test_fp32_matches_oracle(golden, wl):
+    pr = _problem(wl, "fp32")
+    for rec in golden["records"]:
+        res = pr.solve(wl.x0(rec["seed"]))
+        u0 = np.array(rec["u0"])
+        err = np.abs(res.u0 - u0).max() / np.abs(u0).max()
+        jerr = abs(res.stats["objective"] - rec["J"]) / rec["J"]
+        print(f"  seed {rec['seed']}: fp32 iters {res.stats['iters']} (oracle {rec['iters']}) "
+              f"u0 rel {err:.2e} J rel {jerr:.2e}", flush=True)
+        assert res.status == dlmpc.OK
+        assert err < 1e-4
+        assert jerr < 1e-5
+
+
+def test_full_size_properties(wl):
+    """Any size: u(0) inside its box, Phi x0 rows within bounds, deterministic reruns."""
+    pr = _problem(wl, "fp32")
+    x0 = wl.x0(1234)
+    a = pr.solve(x0, want_phi=True)
+    b = pr.solve(x0, want_phi=True)
+    assert a.status == dlmpc.OK
+    assert np.all(np.abs(a.u0) <= 2.0 + 1e-6)
+    assert np.array_equal(a.u0, b.u0) and np.array_equal(a.phi, b.phi)
+    assert a.stats["r_primal"] <= wl.eps and a.stats["r_dual"] <= wl.eps

@@ -35,6 +35,9 @@ def csr_to_dense(pr, vals, shape):
     return out
 
 
+SCHEDULES = ["graph", "persistent"]
+
+
 class Case:
     def __init__(self, wl, precision="fp64", **kw):
         self.wl = wl
@@ -44,14 +47,14 @@ class Case:
                                              precision=precision, **kw)
 
 
-@pytest.fixture(scope="module")
-def chain10():
-    return Case(W.workload("chain10"))
+@pytest.fixture(scope="module", params=SCHEDULES)
+def chain10(request):
+    return Case(W.workload("chain10"), schedule=request.param)
 
 
-@pytest.fixture(scope="module")
-def grid16_box():
-    return Case(W.workload("grid16_box"))
+@pytest.fixture(scope="module", params=SCHEDULES)
+def grid16_box(request):
+    return Case(W.workload("grid16_box"), schedule=request.param)
 
 
 def check_fp64(case, x0, res, ores):
@@ -79,12 +82,13 @@ def test_grid16_box_fp64(grid16_box):
     check_fp64(grid16_box, x0, res, ores)
 
 
-def test_grid16_box_active_bounds_fp64():
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_grid16_box_active_bounds_fp64(schedule):
     """Tighter input bound so that the clip of the row solve is active on the GPU path."""
     net = W.grid(16)
     cost = W.box_cost(net, theta_max=0.8, u_max=0.05)
     wl = W.Workload("grid16_tight", net, 2, 10, cost, sigma=0.2)
-    case = Case(wl)
+    case = Case(wl, schedule=schedule)
     x0 = wl.x0(1001)
     ores = O.solve(case.pb, x0, RHO, EPS, MAXIT)
     n_active = int(np.sum(np.isclose(np.abs(ores.y[case.pb.lay.Nx * 10:]), 0.05, atol=1e-12)))
@@ -93,8 +97,9 @@ def test_grid16_box_active_bounds_fp64():
     check_fp64(case, x0, case.pr.solve(x0, want_phi=True), ores)
 
 
-def test_not_converged_returns_last_iterate(chain10):
-    c = Case(chain10.wl, max_iter=7)
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_not_converged_returns_last_iterate(chain10, schedule):
+    c = Case(chain10.wl, max_iter=7, schedule=schedule)
     x0 = chain10.wl.x0(1)
     ores = O.solve(c.pb, x0, RHO, EPS, 7)
     res = c.pr.solve(x0, want_phi=True)
@@ -135,24 +140,26 @@ def test_deterministic(grid16_box):
     assert a.stats["iters"] == b.stats["iters"]
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("nx,nu,T,seed", [(1, 1, 4, 0), (3, 2, 3, 1), (4, 1, 3, 3)])
-def test_generic_shapes_fp64(nx, nu, T, seed):
+def test_generic_shapes_fp64(nx, nu, T, seed, schedule):
     edges = np.array([(0, 1), (1, 2), (2, 3), (3, 4), (1, 4), (4, 5), (5, 6)])
     net = W.generic_network(7, edges, nx, nu, seed)
     wl = W.Workload("generic", net, 1, T, W.unit_cost(net), sigma=1.0)
     pb = O.setup_from_network(net, 1, T, wl.cost)
     if not pb.feasible:
         pytest.skip("random plant not localisable at d = 1")
-    case = Case(wl)
+    case = Case(wl, schedule=schedule)
     x0 = wl.x0(7)
     ores = O.solve(case.pb, x0, RHO, EPS, MAXIT)
     check_fp64(case, x0, case.pr.solve(x0, want_phi=True), ores)
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("name,seed", [("chain10", 1), ("grid16_box", 1000)])
-def test_fp32_tier(name, seed):
+def test_fp32_tier(name, seed, schedule):
     wl = W.workload(name)
-    case = Case(wl, precision="fp32")
+    case = Case(wl, precision="fp32", schedule=schedule)
     x0 = wl.x0(seed)
     ores = O.solve(case.pb, x0, RHO, EPS, MAXIT)
     res = case.pr.solve(x0)
@@ -161,6 +168,35 @@ def test_fp32_tier(name, seed):
     assert res.status == dlmpc.OK
     assert rel(res.u0, ores.u0) < 1e-4
     assert abs(res.stats["objective"] - ores.J) < 1e-5 * ores.J
+
+
+def test_schedules_agree_bitwise():
+    """Both schedules run the same kernels bodies in the same order: identical FP64 results."""
+    wl = W.workload("grid16_box")
+    a = Case(wl, schedule="graph").pr.solve(wl.x0(1003), want_phi=True)
+    b = Case(wl, schedule="persistent").pr.solve(wl.x0(1003), want_phi=True)
+    assert a.stats["iters"] == b.stats["iters"]
+    assert np.array_equal(a.u0, b.u0) and np.array_equal(a.phi, b.phi)
+
+
+def test_auto_schedule_reports_tuning():
+    wl = W.workload("chain10")
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost)
+    print(f"  chain10 tuning: {pr.info}", flush=True)
+    assert pr.info["tune_graph_us"] > 0
+    assert pr.info["schedule"] in (0, 1)
+
+
+def test_kernel_timing_entry(chain10):
+    import torch
+    xd = torch.tensor(chain10.wl.x0(1), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    us_phi, us_psi = chain10.pr.time_kernels(xd.data_ptr(), 10)
+    assert us_phi > 0 and us_psi > 0
+    # the problem still solves correctly afterwards
+    x0 = chain10.wl.x0(1)
+    ores = O.solve(chain10.pb, x0, RHO, EPS, MAXIT)
+    check_fp64(chain10, x0, chain10.pr.solve(x0, want_phi=True), ores)
 
 
 def test_solve_device_matches_host_entry(chain10):

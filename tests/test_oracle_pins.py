@@ -287,7 +287,7 @@ def test_planted_mistake_dropped_boundary_rows_fails_pin(chain10, monkeypatch):
             E = np.zeros((Z.shape[0], 2))
             E[2 * j, 0] = 1
             E[2 * j + 1, 1] = 1
-            out.append(O.ColumnBlock(b.rows, P, Hp @ E[keep & own], b.rank, 0.0))
+            out.append(O.ColumnBlock(b.j, b.rows, P, Hp @ E[keep & own], b.rank, 0.0))
         return out
 
     monkeypatch.setattr(O, "column_blocks", no_boundary)
