@@ -37,16 +37,20 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(info: dict, rs: int, n_sub: int, elem: int) -> dict:
-    """Bytes the method must move per ADMM iteration (see the design notes).
+    """Bytes each kernel must move per launch (see the design notes), s = element size.
 
-    Psi-comp: null bases once (sum_j D_col(j) k_j), offsets once (nnz), Phi/Lambda/Psi read
-    and Psi/Lambda written (5 nnz). Phi-comp: Psi/Lambda read, Phi written (3 nnz), row data
-    (3 R) and y written (R).
+    Null bases are counted once per kernel that applies them (sum_j D_col(j) k_j entries).
+    phi_kernel: Psi, Lambda read, Phi written (3 nnz), w/lb/ub read and y written (4 R).
+    psi_pass1_kernel: N_j once, Phi and Lambda read (2 nnz).
+    psi_pass2_kernel: N_j once, o_c, Phi, Lambda, Psi read, Psi and Lambda written (6 nnz).
+    iteration: the minimum for one ADMM iteration, N_j read once (sum_dcol_k + 9 nnz + 4 R).
     """
-    nnz, R = info["nnz"], n_sub * rs
-    psi = elem * (info["sum_dcol_k"] + 6 * nnz)
-    phi = elem * (3 * nnz + 4 * R)
-    return {"psi_kernel": psi, "phi_kernel": phi, "iteration": psi + phi}
+    nnz, R, dk = info["nnz"], n_sub * rs, info["sum_dcol_k"]
+    return {"phi_kernel": elem * (3 * nnz + 4 * R),
+            "psi_pass1_kernel": elem * (dk + 2 * nnz),
+            "psi_pass2_kernel": elem * (dk + 6 * nnz),
+            "conv_kernel": 0,
+            "iteration": elem * (dk + 9 * nnz + 4 * R)}
 
 
 def cpu_baseline(wl, iters_gpu_mean: float, sample_blocks: int = 16) -> dict:
@@ -179,30 +183,37 @@ def main() -> int:
     solve_ms = sorted(s["t_solve_ms"] for s in st)
     conv = sum(1 for s in st if s["status"] == dlmpc.OK)
     u0_main = u0[args.warmup:].cpu().numpy().copy()
-    log(f"timed {args.steps} solves in {elapsed:.3f} s; iters {iters}; converged {conv}/{args.steps}")
+    log(f"timed {args.steps} solves in {elapsed:.3f} s; iters {iters}; converged {conv}/{args.steps}; "
+        f"host checks {[s['graph_launches'] for s in st]}")
 
-    # Dominant kernel: the persistent kernel (one launch per solve) or the Psi-comp kernel.
+    # Dominant kernel: the persistent kernel (one launch per solve), or the longest kernel of
+    # the graph schedule's iteration, timed launch by launch with HIP events on the problem's
+    # stream (every launch does work there; no early stop).
     elem = 4 if args.precision == "fp32" else 8
     ab = algorithmic_bytes(pr.info, rs, net.n_sub, elem)
+    ku = pr.time_kernels(x0[args.warmup].data_ptr(), 50)
     if pr.info["schedule"] == 1:
         kname = "persistent_kernel"
         dur_s = sum(s["t_iter_ms"] for s in st) / 1e3
         bytes_total = sum(ab["iteration"] * s["iters"] for s in st)
         launch_bytes = bytes_total / len(st)
         avg_launch_us = 1e6 * dur_s / len(st)
-    us_phi, us_psi = pr.time_kernels(x0[args.warmup].data_ptr(), 50)
-    if pr.info["schedule"] != 1:
-        kname = "psi_kernel"
-        launch_bytes = ab["psi_kernel"]
-        avg_launch_us = us_psi
-        dur_s = us_psi * 1e-6
+    else:
+        kname = max(ku, key=ku.get)
+        launch_bytes = ab[kname]
+        avg_launch_us = ku[kname]
+        dur_s = avg_launch_us * 1e-6
         bytes_total = launch_bytes
     achieved = bytes_total / dur_s / 1e9
+    per_kernel = {k: {"us": round(v, 2), "GB/s": round(ab[k] / (v * 1e-6) / 1e9, 1) if ab[k] else None}
+                  for k, v in ku.items()}
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "avg_launch_us": round(avg_launch_us, 2),
                 "algorithmic_bytes_per_launch": int(launch_bytes),
-                "kernel_us": {"phi_kernel": round(us_phi, 2), "psi_kernel": round(us_psi, 2)},
+                "iteration_us": round(sum(ku.values()), 2),
+                "iteration_algorithmic_bytes": int(ab["iteration"]),
+                "per_kernel": per_kernel,
                 "traffic": traffic_record(args.workload, kname, launch_bytes)}
 
     # Plain FP64 cold-start GPU solve on the same x0 (the reference the FP32 path is quoted against).

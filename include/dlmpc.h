@@ -172,13 +172,16 @@ int dlmpc_solve(struct dlmpc_problem *p, const double *x0, const dlmpc_warm *war
 int dlmpc_solve_device(struct dlmpc_problem *p, const double *x0_dev, double *u0_dev,
                        double *phi_dev, dlmpc_stats *stats);
 
-/* Kernel timing for roofline measurement: runs `iters` ADMM iterations of the two-kernel
- * schedule from x0_dev without early stop, each kernel launched on its own between HIP events
- * on the problem's stream, and returns the mean device time per launch in microseconds of the
- * Phi-comp kernel (*us_phi) and of the Psi-comp/Lambda/Conv kernel (*us_psi). The iterate is
- * left in an unspecified state (the next solve starts afresh). */
-int dlmpc_time_kernels(struct dlmpc_problem *p, const double *x0_dev, int32_t iters, double *us_phi,
-                       double *us_psi);
+/* Kernel timing for roofline measurement: runs `iters` ADMM iterations of the graph schedule
+ * from x0_dev without early stop, each kernel launched on its own between HIP events on the
+ * problem's stream, and writes the mean device time per launch in microseconds of each of
+ * the DLMPC_TIMED_KERNELS kernels of one iteration, in this order: Phi-comp (phi_kernel),
+ * Psi-comp pass 1 (psi_pass1_kernel: t = N_j' v), Psi-comp pass 2 with Lambda-comp and the
+ * residual partial sums (psi_pass2_kernel), Conv (conv_kernel). us_per_launch has
+ * DLMPC_TIMED_KERNELS entries. The iterate is left in an unspecified state. */
+#define DLMPC_TIMED_KERNELS 4
+int dlmpc_time_kernels(struct dlmpc_problem *p, const double *x0_dev, int32_t iters,
+                       double *us_per_launch);
 
 void dlmpc_destroy(struct dlmpc_problem *p);
 const char *dlmpc_status_string(int status);

@@ -22,7 +22,7 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5",
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-shared", *DEVICE_FLAGS,
+    cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Werror", *DEVICE_FLAGS,
            "-I", os.path.join(ROOT, "include"),
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp, "-lpthread"]
     if verbose:

@@ -1,20 +1,21 @@
 // HIP kernels of the DLMPC-ADMM hot loop (Algorithm 2) for CDNA4 (gfx950).
 //
-// One ADMM iteration is two launches:
+// One ADMM iteration is a Phi-comp launch and a Psi-comp/Lambda/Conv phase:
 //   phi_kernel  — Phi-comp, one workgroup per row subsystem m: gathers the tiles
 //                 (Psi - Lambda)[rows of m, columns of P(m)], forms a_r = v_r . x_r for the
 //                 rs rows of m, takes the explicit row solution (clip of
 //                 rho a / (rho + 2 w ||x_r||^2) onto the row's box, Section II-A and
 //                 Algorithm 2), and writes Phi = v + alpha_r x_r and y_r = (Phi x0)_r.
-//   psi_kernel  — Psi-comp + Lambda-comp + Conv, one workgroup per column subsystem j:
-//                 projects the nx columns of (Phi + Lambda) on the support of j onto the
-//                 affine set of Z_AB psi = e_c with the null basis N_j (psi = N_j N_j' v + o_c),
-//                 updates Lambda <- Lambda + Phi - Psi, and reduces the per-column primal and
-//                 dual residual norms into a device-side max; the last workgroup to finish
-//                 takes the convergence decision (combined-kernel idea, Section III-C).
-// Between the two launches every tile written by one side is read by exactly one workgroup
-// of the other side, so the row->column exchange is the kernel boundary and no atomics
-// touch the iterate. Every reduction runs in a fixed order (bitwise reproducible).
+//   Psi-comp    — projects the nx columns of (Phi + Lambda) on the support of each column
+//                 subsystem j onto the affine set of Z_AB psi = e_c with the null basis N_j
+//                 (psi = N_j N_j' v + o_c), updates Lambda <- Lambda + Phi - Psi and reduces the
+//                 per-column primal and dual residual norms to the stop decision (combined
+//                 kernels, Section III-C). In the graph schedule this is three launches of
+//                 uniform work units (psi_pass1_kernel, psi_pass2_kernel, conv_kernel); the
+//                 persistent schedule runs one workgroup per column subsystem (psi_body).
+// Every tile written by one step is read by exactly one workgroup of the other step, so the
+// row->column exchange is a kernel boundary (or grid barrier) and no atomics touch the
+// iterate. Every reduction runs in a fixed order (bitwise reproducible).
 // A control block on the device carries the stop flag; once set, every later kernel of the
 // captured iteration graph returns immediately, so the host only polls it every K
 // iterations.
@@ -36,6 +37,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kNumIterKernels = 4;
 constexpr unsigned long long kSpinLimit = 20000000ull;  // ~1 s of polling per barrier
 
 template <typename T>
@@ -189,11 +191,8 @@ struct VecT<double> {
   static constexpr int N = 2;
 };
 
-template <typename V>
-__device__ __forceinline__ auto hsum(const V &x) -> decltype(x[0]) {
-  if constexpr (sizeof(V) / sizeof(x[0]) == 4) return (x[0] + x[1]) + (x[2] + x[3]);
-  else return x[0] + x[1];
-}
+__device__ __forceinline__ float hsum(const VecT<float>::type &x) { return (x[0] + x[1]) + (x[2] + x[3]); }
+__device__ __forceinline__ double hsum(const VecT<double>::type &x) { return x[0] + x[1]; }
 
 // Psi-comp, Lambda-comp and the Conv residuals of column subsystem j. On return thread 0
 // holds the largest primal and dual residual norm over j's columns in *rp_out / *rd_out
@@ -226,10 +225,9 @@ __device__ __forceinline__ void psi_body(const KArgs<Tf> &a, int j, unsigned cha
   Tf *v = reinterpret_cast<Tf *>(smem_raw);  // [NX][ld], zero padded
   Tf *t = v + NX * ld;                       // [NX][k]
 
-  for (int r = tid; r < ld; r += kBlock) {
-#pragma unroll
-    for (int c = 0; c < NX; ++c)
-      v[c * ld + r] = (r < D) ? a.phi[base + int64_t(r) * NX + c] + a.lam[base + int64_t(r) * NX + c] : Tf(0);
+  for (int e = tid; e < ld * NX; e += kBlock) {
+    const int r = e / NX, c = e - r * NX;
+    v[c * ld + r] = (r < D) ? a.phi[base + e] + a.lam[base + e] : Tf(0);
   }
   __syncthreads();
   for (int i0 = wave * kUC; i0 < k; i0 += kWaves * kUC) {
@@ -260,9 +258,7 @@ __device__ __forceinline__ void psi_body(const KArgs<Tf> &a, int j, unsigned cha
       }
   }
   __syncthreads();
-  double rp[NX], rd[NX];
-#pragma unroll
-  for (int c = 0; c < NX; ++c) rp[c] = rd[c] = 0.0;
+  // v is free after pass 1: stage psi (row-major, the global layout) for a coalesced epilogue
   for (int q = tid; q < nvec; q += kBlock) {
     V y[NX];
 #pragma unroll
@@ -278,17 +274,27 @@ __device__ __forceinline__ void psi_body(const KArgs<Tf> &a, int j, unsigned cha
       const int r = q * VN + e;
       if (r >= D) break;
 #pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        const int64_t idx = base + int64_t(r) * NX + c;
-        const Tf psn = y[c][e] + Oj[c * ld + r];
-        const Tf ph = a.phi[idx], la = a.lam[idx], pso = a.psi[idx];
-        a.lam[idx] = (la + ph) - psn;
-        a.psi[idx] = psn;
-        const double dp = double(ph - psn), dd = double(psn - pso);
-        rp[c] += dp * dp;
-        rd[c] += dd * dd;
-      }
+      for (int c = 0; c < NX; ++c) v[r * NX + c] = y[c][e] + Oj[c * ld + r];
     }
+  }
+  __syncthreads();
+  double rp[NX], rd[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) rp[c] = rd[c] = 0.0;
+  for (int e = tid; e < D * NX; e += kBlock) {
+    const int c = e % NX;
+    const Tf psn = v[e];
+    const int64_t idx = base + e;
+    const Tf ph = a.phi[idx], la = a.lam[idx], pso = a.psi[idx];
+    a.lam[idx] = (la + ph) - psn;
+    a.psi[idx] = psn;
+    const double dp = double(ph - psn), dd = double(psn - pso);
+#pragma unroll
+    for (int cc = 0; cc < NX; ++cc)
+      if (cc == c) {
+        rp[cc] += dp * dp;
+        rd[cc] += dd * dd;
+      }
   }
 #pragma unroll
   for (int c = 0; c < NX; ++c) {
@@ -339,30 +345,191 @@ __device__ __forceinline__ void decide(Ctl *c, int it, double rpm, double rdm) {
   }
 }
 
+// ------------------------------------------------------------------ split Psi-comp (graph schedule)
+//
+// Psi-comp of all column subsystems as two launches of uniform work units, so that the long
+// patches do not bound the kernel time:
+//   psi_pass1_kernel  unit (j, i0): t_j[i] = N_j[:, i]' v_j for kP1Cols basis vectors from i0;
+//   psi_pass2_kernel  unit (j, r0): psi = N_j t_j + o_c on rows [r0, r0 + RB) with the basis
+//                     split over the block's waves (partial sums combined in LDS in a fixed
+//                     order), then Lambda and the residual partial sums of those rows;
+//   conv_kernel       one block: per column subsystem, the residual partial sums of its units in
+//                     unit order, the column norms, their maximum and the stop decision.
+// Kernel boundaries order the three launches; nothing is exchanged through atomics.
+
+constexpr int kP1Cols = kWaves * 8;  // basis vectors per pass-1 unit (8 per wave)
+
 template <typename Tf, int NX>
-__global__ __launch_bounds__(kBlock) void psi_kernel(KArgs<Tf> a) {
+__global__ __launch_bounds__(kBlock) void psi_pass1_kernel(KArgs<Tf> a, PsiUnits<Tf> pu) {
   if (a.ctl->stop) return;
+  using V = typename VecT<Tf>::type;
+  constexpr int VN = VecT<Tf>::N;
+  constexpr int kUC = 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int am_last;
-  double mp = 0.0, md = 0.0;
-  psi_body<Tf, NX>(a, a.psi_order[blockIdx.x], smem_raw, &mp, &md);
-  if (threadIdx.x == 0) {
-    atomicMax(&a.ctl->rp_bits, as_bits(mp));
-    atomicMax(&a.ctl->rd_bits, as_bits(md));
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.ctl->done_count, 1u);
-    am_last = (prev == gridDim.x - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = pu.p1[2 * blockIdx.x], ibase = pu.p1[2 * blockIdx.x + 1];
+  const int64_t tb = a.tile_off[j];
+  const int D = int(a.tile_off[j + 1] - tb) * a.rs;
+  const int ld = (D + 3) & ~3;
+  const int nvec = ld / VN;
+  const int k = a.kdim[j];
+  const int64_t base = tb * a.ts;
+  const Tf *__restrict__ Nj = a.nb + a.nb_off[j];
+  Tf *v = reinterpret_cast<Tf *>(smem_raw);  // [NX][ld], zero padded
+  for (int e = tid; e < ld * NX; e += kBlock) {
+    const int r = e / NX, c = e - r * NX;
+    v[c * ld + r] = (r < D) ? a.phi[base + e] + a.lam[base + e] : Tf(0);
   }
   __syncthreads();
-  if (am_last && threadIdx.x == 0) {
-    __threadfence();
-    Ctl *c = a.ctl;
-    const double rpm = __longlong_as_double(static_cast<long long>(atomicAdd(&c->rp_bits, 0ull)));
-    const double rdm = __longlong_as_double(static_cast<long long>(atomicAdd(&c->rd_bits, 0ull)));
-    decide(c, c->iters + 1, rpm, rdm);
-    atomicExch(&c->rp_bits, 0ull);
-    atomicExch(&c->rd_bits, 0ull);
-    atomicExch(&c->done_count, 0u);
+  const int i0 = ibase + wave * kUC;
+  if (i0 >= k) return;
+  Tf acc[kUC][NX];
+#pragma unroll
+  for (int u = 0; u < kUC; ++u)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) acc[u][c] = Tf(0);
+  for (int q = lane; q < nvec; q += 64) {
+    V nv[kUC];
+#pragma unroll
+    for (int u = 0; u < kUC; ++u)
+      nv[u] = (i0 + u < k) ? *reinterpret_cast<const V *>(Nj + int64_t(i0 + u) * ld + q * VN) : V(0);
+    V vv[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) vv[c] = *reinterpret_cast<const V *>(v + c * ld + q * VN);
+#pragma unroll
+    for (int u = 0; u < kUC; ++u)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) acc[u][c] += hsum(nv[u] * vv[c]);
+  }
+  Tf *tj = pu.t + pu.t_off[j];
+#pragma unroll
+  for (int u = 0; u < kUC; ++u)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const Tf s = wave_sum(acc[u][c]);
+      if (lane == 0 && i0 + u < k) tj[c * k + i0 + u] = s;
+    }
+}
+
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void psi_pass2_kernel(KArgs<Tf> a, PsiUnits<Tf> pu) {
+  if (a.ctl->stop) return;
+  using V = typename VecT<Tf>::type;
+  constexpr int VN = VecT<Tf>::N;
+  constexpr int RB = 64 * VN;  // rows per unit
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[kWaves][2 * NX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = pu.p2[2 * blockIdx.x], r0 = pu.p2[2 * blockIdx.x + 1];
+  const int64_t tb = a.tile_off[j];
+  const int D = int(a.tile_off[j + 1] - tb) * a.rs;
+  const int ld = (D + 3) & ~3;
+  const int k = a.kdim[j];
+  const int64_t base = tb * a.ts;
+  const Tf *__restrict__ Nj = a.nb + a.nb_off[j];
+  const Tf *__restrict__ Oj = a.off + a.off_ptr[j];
+  Tf *ypart = reinterpret_cast<Tf *>(smem_raw);  // [kWaves][NX][RB]
+  Tf *tl = ypart + kWaves * NX * RB;             // [NX][k]
+  const Tf *tj = pu.t + pu.t_off[j];
+  for (int e = tid; e < NX * k; e += kBlock) tl[e] = tj[e];
+  __syncthreads();
+  const int kq = (k + kWaves - 1) / kWaves;
+  const int ib = wave * kq, ie = min(k, ib + kq);
+  const int q = r0 / VN + lane;
+  V y[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) y[c] = V(0);
+  if (q * VN < ld) {
+#pragma unroll 8
+    for (int i = ib; i < ie; ++i) {
+      const V nv = *reinterpret_cast<const V *>(Nj + int64_t(i) * ld + q * VN);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) y[c] += nv * tl[c * k + i];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NX; ++c) *reinterpret_cast<V *>(ypart + (wave * NX + c) * RB + lane * VN) = y[c];
+  __syncthreads();
+  const int rows = min(RB, D - r0);
+  double rp[NX], rd[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) rp[c] = rd[c] = 0.0;
+  for (int e = tid; e < rows * NX; e += kBlock) {
+    const int rl = e / NX, c = e - rl * NX;
+    Tf ys = ypart[c * RB + rl];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) ys += ypart[(w * NX + c) * RB + rl];
+    const Tf psn = ys + Oj[c * ld + r0 + rl];
+    const int64_t idx = base + int64_t(r0) * NX + e;
+    const Tf ph = a.phi[idx], la = a.lam[idx], pso = a.psi[idx];
+    a.lam[idx] = (la + ph) - psn;
+    a.psi[idx] = psn;
+    const double dp = double(ph - psn), dd = double(psn - pso);
+#pragma unroll
+    for (int cc = 0; cc < NX; ++cc)
+      if (cc == c) {
+        rp[cc] += dp * dp;
+        rd[cc] += dd * dd;
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < NX; ++c) {
+    rp[c] = wave_sum(rp[c]);
+    rd[c] = wave_sum(rd[c]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      red[wave][c] = rp[c];
+      red[wave][NX + c] = rd[c];
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * NX) {
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += red[w][tid];
+    pu.part[int64_t(blockIdx.x) * 2 * NX + tid] = s;
+  }
+}
+
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void conv_kernel(KArgs<Tf> a, PsiUnits<Tf> pu) {
+  if (a.ctl->stop) return;
+  __shared__ double redp[kWaves], redd[kWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double mp = 0.0, md = 0.0;
+  for (int j = tid; j < a.N; j += kBlock) {
+    const int f = pu.p2_first[j], n = pu.p2_count[j];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      double sp = 0.0, sd = 0.0;
+      for (int u = f; u < f + n; ++u) {
+        sp += pu.part[int64_t(u) * 2 * NX + c];
+        sd += pu.part[int64_t(u) * 2 * NX + NX + c];
+      }
+      sp = sqrt(sp);
+      sd = sqrt(sd);
+      mp = (sp > mp || sp != sp) ? sp : mp;
+      md = (sd > md || sd != sd) ? sd : md;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double op = __shfl_xor(mp, o, 64), od = __shfl_xor(md, o, 64);
+    mp = (op > mp || op != op) ? op : mp;
+    md = (od > md || od != od) ? od : md;
+  }
+  if (lane == 0) {
+    redp[wave] = mp;
+    redd[wave] = md;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < kWaves; ++w) {
+      mp = (redp[w] > mp || redp[w] != redp[w]) ? redp[w] : mp;
+      md = (redd[w] > md || redd[w] != redd[w]) ? redd[w] : md;
+    }
+    decide(a.ctl, a.ctl->iters + 1, mp, md);
   }
 }
 
@@ -561,7 +728,52 @@ class EngineT final : public Engine {
       err = "patch too large for the on-chip staging of this build (LDS " + std::to_string(lds_psi_) + " B)";
       return DLMPC_EINVAL;
     }
+    int rc2 = build_units(hs, err);
+    if (rc2) return rc2;
     return build_schedule(hs, err);
+  }
+
+  // Work units of the split Psi-comp, larger work first.
+  int build_units(const HostSetup &hs, std::string &err) {
+    constexpr int RB = 64 * VecT<Tf>::N;
+    std::vector<int32_t> order(hs.N);
+    for (int i = 0; i < hs.N; ++i) order[i] = i;
+    auto D_of = [&](int j) { return int(hs.patch[j].size()) * hs.rs; };
+    std::vector<int32_t> p1, p2, first(hs.N), count(hs.N);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return D_of(x) > D_of(y); });
+    for (int j : order)
+      for (int i0 = 0; i0 < hs.kdim[j]; i0 += kP1Cols) {
+        p1.push_back(j);
+        p1.push_back(i0);
+      }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return hs.kdim[x] > hs.kdim[y]; });
+    for (int j : order) {
+      first[j] = int32_t(p2.size() / 2);
+      for (int r0 = 0; r0 < D_of(j); r0 += RB) {
+        p2.push_back(j);
+        p2.push_back(r0);
+      }
+      count[j] = int32_t(p2.size() / 2) - first[j];
+    }
+    n1_ = int(p1.size() / 2);
+    n2_ = int(p2.size() / 2);
+    std::vector<int64_t> toff(hs.N + 1, 0);
+    for (int j = 0; j < hs.N; ++j) toff[j + 1] = toff[j] + int64_t(hs.kdim[j]) * NX;
+    int rc;
+    if ((rc = upload(p1, &pu_.p1, err))) return rc;
+    if ((rc = upload(p2, &pu_.p2, err))) return rc;
+    if ((rc = upload(first, &pu_.p2_first, err))) return rc;
+    if ((rc = upload(count, &pu_.p2_count, err))) return rc;
+    if ((rc = upload(toff, &pu_.t_off, err))) return rc;
+    if ((rc = alloc(&pu_.t, size_t(toff[hs.N]), err))) return rc;
+    if ((rc = alloc(&pu_.part, size_t(std::max(n2_, 1)) * 2 * NX, err))) return rc;
+    lds_p1_ = size_t(NX) * padded_ld(hs.d_col_max) * sizeof(Tf);
+    lds_p2_ = (size_t(kWaves) * NX * RB + size_t(NX) * hs.k_max) * sizeof(Tf);
+    if (lds_p1_ > kMaxLds || lds_p2_ > kMaxLds) {
+      err = "patch too large for the on-chip staging of this build";
+      return DLMPC_EINVAL;
+    }
+    return DLMPC_OK;
   }
 
   // Persistent schedule: as many blocks as can be co-resident (at most one per subsystem),
@@ -646,16 +858,28 @@ class EngineT final : public Engine {
   }
 
   int iteration(std::string &err) override {
-    const int rc = phi_only(err);
-    return rc ? rc : psi_only(err);
-  }
-  int phi_only(std::string &err) override {
-    hipLaunchKernelGGL((phi_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_phi_, stream_, args_);
-    ENG_CHECK(hipGetLastError());
+    for (int kk = 0; kk < kNumIterKernels; ++kk) {
+      const int rc = launch_one(kk, err);
+      if (rc) return rc;
+    }
     return DLMPC_OK;
   }
-  int psi_only(std::string &err) override {
-    hipLaunchKernelGGL((psi_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_psi_, stream_, args_);
+  // Kernels of one iteration in order: 0 Phi-comp, 1 Psi pass 1, 2 Psi pass 2, 3 Conv.
+  int launch_one(int which, std::string &err) override {
+    switch (which) {
+      case 0:
+        hipLaunchKernelGGL((phi_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_phi_, stream_, args_);
+        break;
+      case 1:
+        hipLaunchKernelGGL((psi_pass1_kernel<Tf, NX>), dim3(n1_), dim3(kBlock), lds_p1_, stream_, args_, pu_);
+        break;
+      case 2:
+        hipLaunchKernelGGL((psi_pass2_kernel<Tf, NX>), dim3(n2_), dim3(kBlock), lds_p2_, stream_, args_, pu_);
+        break;
+      default:
+        hipLaunchKernelGGL((conv_kernel<Tf, NX>), dim3(1), dim3(kBlock), 0, stream_, args_, pu_);
+        break;
+    }
     ENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -721,7 +945,9 @@ class EngineT final : public Engine {
   KArgs<Tf> args_{};
   const int64_t *map_ = nullptr;
   const double *w64_ = nullptr;
-  size_t lds_phi_ = 0, lds_psi_ = 0, lds_persist_ = 0;
+  size_t lds_phi_ = 0, lds_psi_ = 0, lds_persist_ = 0, lds_p1_ = 0, lds_p2_ = 0;
+  int n1_ = 0, n2_ = 0;
+  PsiUnits<Tf> pu_{};
   int grid_ = 0;
   Sched sched_{};
   std::vector<void *> owned_;

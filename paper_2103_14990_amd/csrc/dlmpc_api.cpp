@@ -22,9 +22,11 @@ struct dlmpc_problem {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::unique_ptr<dlmpc::Engine> eng;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  int K = 16;
+  // Captured graphs of 1, 2, 4, ..., 2^(kGraphs-1) iterations of the graph schedule.
+  static constexpr int kGraphs = 6;
+  hipGraph_t graph[kGraphs] = {};
+  hipGraphExec_t gexec[kGraphs] = {};
+  int K = 32;  // fixed chunk when check_every > 0; otherwise the first chunk
   int sched = 0;  // 0 = graph, 1 = persistent
   double tune_graph_us = 0.0, tune_persistent_us = 0.0;
   Ctl *h_ctl = nullptr;  // pinned, 2 slots
@@ -52,8 +54,12 @@ void release_device(dlmpc_problem *p) {
   if (!p || p->host_only) return;
   (void)hipSetDevice(p->opt.device);
   if (p->stream) (void)hipStreamSynchronize(p->stream);
-  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
+    if (p->gexec[g]) (void)hipGraphExecDestroy(p->gexec[g]);
+    if (p->graph[g]) (void)hipGraphDestroy(p->graph[g]);
+    p->gexec[g] = nullptr;
+    p->graph[g] = nullptr;
+  }
   for (hipEvent_t e : {p->ev_ctl[0], p->ev_ctl[1], p->ev_t0, p->ev_t1})
     if (e) (void)hipEventDestroy(e);
   if (p->h_ctl) (void)hipHostFree(p->h_ctl);
@@ -61,8 +67,6 @@ void release_device(dlmpc_problem *p) {
     if (d) (void)hipFree(d);
   p->eng.reset();
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
-  p->gexec = nullptr;
-  p->graph = nullptr;
   p->h_ctl = nullptr;
   p->stream = nullptr;
 }
@@ -95,23 +99,36 @@ int setup_device(dlmpc_problem *p) {
   for (auto *e : {&p->ev_ctl[0], &p->ev_ctl[1]}) API_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   API_HIP(hipEventCreate(&p->ev_t0));
   API_HIP(hipEventCreate(&p->ev_t1));
-  // K ADMM iterations captured once; every launch after the device-side stop is a no-op.
-  p->K = p->opt.check_every > 0 ? p->opt.check_every : 16;
-  p->K = std::max(1, std::min(p->K, p->opt.max_iter));
-  API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  for (int i = 0; i < p->K; ++i) {
-    rc = p->eng->iteration(err);
-    if (rc) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(p->stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      return fail(rc, err);
+  // Iteration graphs of 2^g iterations; every launch after the device-side stop is a no-op.
+  p->K = p->opt.check_every > 0 ? std::min(p->opt.check_every, p->opt.max_iter) : 32;
+  for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
+    API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < (1 << g); ++i) {
+      rc = p->eng->iteration(err);
+      if (rc) {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(p->stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(rc, err);
+      }
     }
+    API_HIP(hipStreamEndCapture(p->stream, &p->graph[g]));
+    API_HIP(hipGraphInstantiate(&p->gexec[g], p->graph[g], nullptr, nullptr, 0));
   }
-  API_HIP(hipStreamEndCapture(p->stream, &p->graph));
-  API_HIP(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
   API_HIP(hipStreamSynchronize(p->stream));
   return choose_schedule(p);
+}
+
+// Enqueues n iterations of the graph schedule as a sum of captured power-of-two graphs.
+int launch_iterations(dlmpc_problem *p, int n) {
+  constexpr int top = dlmpc_problem::kGraphs - 1;
+  while (n >= (1 << top)) {
+    API_HIP(hipGraphLaunch(p->gexec[top], p->stream));
+    n -= 1 << top;
+  }
+  for (int g = top - 1; g >= 0; --g)
+    if (n & (1 << g)) API_HIP(hipGraphLaunch(p->gexec[g], p->stream));
+  return DLMPC_OK;
 }
 
 // Times n iterations of a schedule from x0 = (1, ..., 1) with the stop test disabled.
@@ -129,7 +146,8 @@ int time_schedule(dlmpc_problem *p, int sched, int n, double *us_per_iter) {
       rc = p->eng->run_persistent(true, err);
       if (rc) return fail(rc, err);
     } else {
-      for (int done = 0; done < n; done += p->K) API_HIP(hipGraphLaunch(p->gexec, p->stream));
+      rc = launch_iterations(p, n);
+      if (rc) return rc;
     }
     API_HIP(hipEventRecord(p->ev_t1, p->stream));
     API_HIP(hipStreamSynchronize(p->stream));
@@ -155,7 +173,7 @@ int choose_schedule(dlmpc_problem *p) {
     p->sched = 1;
     return DLMPC_OK;
   }
-  const int n = 2 * p->K;
+  const int n = 32;
   int rc = time_schedule(p, 0, n, &p->tune_graph_us);
   if (rc) return rc;
   if (can_persist) {
@@ -180,7 +198,7 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
   int rc = p->eng->precompute(x0_dev, wpsi, wlam, max_iter, p->opt.eps, err);
   if (rc) return fail(rc, err);
   API_HIP(hipEventRecord(p->ev_t0, p->stream));
-  int launched = 0, launches = 0, cur = 0, pending = -1;
+  int launched = 0, launches = 0;
   bool stopped = false;
   Ctl *d_ctl = p->eng->ctl();
   if (p->sched == 1) {
@@ -189,25 +207,58 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     launches = 1;
     stopped = true;
   }
-  for (; !stopped;) {
-    API_HIP(hipGraphLaunch(p->gexec, p->stream));
-    API_HIP(hipMemcpyAsync(&p->h_ctl[cur], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
-    API_HIP(hipEventRecord(p->ev_ctl[cur], p->stream));
-    launched += p->K;
+  // Graph schedule: launch a chunk of iterations, read the control block, and size the next
+  // chunk from the decay of the residual (least-squares slope of log max(r_p, r_d) over the
+  // last checks), so that few launches land after the device-side stop and few host checks
+  // are needed. With check_every > 0 the chunk is fixed.
+  double hk[4] = {0, 0, 0, 0}, hr[4] = {0, 0, 0, 0};
+  int nh = 0;
+  int n = p->K;
+  while (!stopped) {
+    n = std::max(1, std::min(n, max_iter - launched));
+    rc = launch_iterations(p, n);
+    if (rc) return rc;
+    launched += n;
     ++launches;
-    if (pending >= 0) {
-      API_HIP(hipEventSynchronize(p->ev_ctl[pending]));
-      if (p->h_ctl[pending].stop) {
-        stopped = true;
-        break;
-      }
-    }
-    pending = cur;
-    cur ^= 1;
-    if (launched >= max_iter + p->K) {
-      API_HIP(hipEventSynchronize(p->ev_ctl[pending]));
-      stopped = p->h_ctl[pending].stop != 0;
+    API_HIP(hipMemcpyAsync(&p->h_ctl[1], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipEventRecord(p->ev_ctl[1], p->stream));
+    API_HIP(hipEventSynchronize(p->ev_ctl[1]));
+    const Ctl &c = p->h_ctl[1];
+    if (c.stop) {
+      stopped = true;
       break;
+    }
+    if (launched >= max_iter) break;
+    if (p->opt.check_every > 0) continue;
+    const double r = std::max(c.last_rp, c.last_rd);
+    if (!(r > 0.0) || !std::isfinite(r)) {
+      n = 8;
+      continue;
+    }
+    for (int i = 3; i > 0; --i) {
+      hk[i] = hk[i - 1];
+      hr[i] = hr[i - 1];
+    }
+    hk[0] = c.iters;
+    hr[0] = std::log(r);
+    nh = std::min(nh + 1, 4);
+    n = 8;
+    if (nh >= 2) {
+      double mk = 0, mr = 0;
+      for (int i = 0; i < nh; ++i) {
+        mk += hk[i] / nh;
+        mr += hr[i] / nh;
+      }
+      double sxy = 0, sxx = 0;
+      for (int i = 0; i < nh; ++i) {
+        sxy += (hk[i] - mk) * (hr[i] - mr);
+        sxx += (hk[i] - mk) * (hk[i] - mk);
+      }
+      const double slope = sxx > 0 ? sxy / sxx : 0.0;
+      if (slope < -1e-9) {
+        const double need = (std::log(p->opt.eps) - hr[0]) / slope;
+        n = int(std::min(64.0, std::max(1.0, std::round(need))));
+      }
     }
   }
   if (!stopped) return fail(DLMPC_EDEVICE, "iteration graph did not reach its stop condition");
@@ -230,7 +281,7 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     stats->r_dual = c.last_rd;
     stats->objective = c.objective;
     stats->t_iter_ms = ms;
-    stats->graph_launches = launches;
+    stats->graph_launches = launches;  // host checks (graph schedule) or 1 (persistent)
     stats->schedule = p->sched;
     const double t_now = std::chrono::duration<double, std::milli>(
                              std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -397,36 +448,33 @@ int dlmpc_solve_device(dlmpc_problem *p, const double *x0_dev, double *u0_dev, d
   return run_solve(p, x0_dev, nullptr, nullptr, u0_dev, phi_dev, stats, t0);
 }
 
-int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, double *us_phi,
-                       double *us_psi) {
-  if (!p || !x0_dev || iters < 1 || !us_phi || !us_psi) return fail(DLMPC_EINVAL, "bad argument");
+int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, double *us_per_launch) {
+  if (!p || !x0_dev || iters < 1 || !us_per_launch) return fail(DLMPC_EINVAL, "bad argument");
   if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
   API_HIP(hipSetDevice(p->opt.device));
   std::string err;
   int rc = p->eng->precompute(x0_dev, nullptr, nullptr, iters, -1.0, err);
   if (rc) return fail(rc, err);
-  std::vector<hipEvent_t> ev(2 * size_t(iters) + 1);
+  constexpr int nk = DLMPC_TIMED_KERNELS;
+  std::vector<hipEvent_t> ev(size_t(nk) * iters + 1);
   for (auto &e : ev) API_HIP(hipEventCreate(&e));
   API_HIP(hipEventRecord(ev[0], p->stream));
-  for (int i = 0; i < iters && rc == DLMPC_OK; ++i) {
-    rc = p->eng->phi_only(err);
-    if (!rc) API_HIP(hipEventRecord(ev[2 * i + 1], p->stream));
-    if (!rc) rc = p->eng->psi_only(err);
-    if (!rc) API_HIP(hipEventRecord(ev[2 * i + 2], p->stream));
-  }
+  for (int i = 0; i < iters && rc == DLMPC_OK; ++i)
+    for (int k = 0; k < nk && rc == DLMPC_OK; ++k) {
+      rc = p->eng->launch_one(k, err);
+      if (!rc) API_HIP(hipEventRecord(ev[size_t(i) * nk + k + 1], p->stream));
+    }
   API_HIP(hipStreamSynchronize(p->stream));
-  double sphi = 0.0, spsi = 0.0;
-  for (int i = 0; i < iters && rc == DLMPC_OK; ++i) {
-    float a = 0.f, b = 0.f;
-    API_HIP(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
-    API_HIP(hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]));
-    sphi += a;
-    spsi += b;
-  }
+  double sum[nk] = {};
+  for (int i = 0; i < iters && rc == DLMPC_OK; ++i)
+    for (int k = 0; k < nk; ++k) {
+      float ms = 0.f;
+      API_HIP(hipEventElapsedTime(&ms, ev[size_t(i) * nk + k], ev[size_t(i) * nk + k + 1]));
+      sum[k] += ms;
+    }
   for (auto &e : ev) (void)hipEventDestroy(e);
   if (rc) return fail(rc, err);
-  *us_phi = 1e3 * sphi / iters;
-  *us_psi = 1e3 * spsi / iters;
+  for (int k = 0; k < nk; ++k) us_per_launch[k] = 1e3 * sum[k] / iters;
   return DLMPC_OK;
 }
 

@@ -38,6 +38,18 @@ struct Sched {
   const int32_t *phi_ptr, *phi_list, *psi_ptr, *psi_list;
 };
 
+// Work units of the split Psi-comp (graph schedule); p1/p2 hold (j, start) pairs.
+template <typename Tf>
+struct PsiUnits {
+  const int32_t *p1;        // [2*n1] (column subsystem, first basis vector)
+  const int32_t *p2;        // [2*n2] (column subsystem, first row)
+  const int32_t *p2_first;  // [N] first pass-2 unit of each column subsystem
+  const int32_t *p2_count;  // [N] number of its pass-2 units (consecutive)
+  const int64_t *t_off;     // [N+1] offset of t_j (NX*k_j values)
+  Tf *t;                    // N_j' v for every j
+  double *part;             // [n2][2*NX] per-unit residual partial sums
+};
+
 template <typename Tf>
 struct KArgs {
   int32_t N, nx, nu, T, rs, ts;
@@ -68,10 +80,10 @@ class Engine {
   // Enqueue the per-solve precompute (cold start when wpsi == nullptr) on the stream.
   virtual int precompute(const double *x0_dev, const double *wpsi, const double *wlam,
                          int max_iter, double eps, std::string &err) = 0;
-  // Enqueue one ADMM iteration (capturable), or one of its two kernels.
+  // Enqueue one ADMM iteration of the graph schedule (capturable), or one of its kernels
+  // (0 Phi-comp, 1 Psi pass 1, 2 Psi pass 2, 3 Conv).
   virtual int iteration(std::string &err) = 0;
-  virtual int phi_only(std::string &err) = 0;
-  virtual int psi_only(std::string &err) = 0;
+  virtual int launch_one(int which, std::string &err) = 0;
   // Enqueue all iterations of one solve as one launch (persistent schedule).
   virtual int run_persistent(bool tune, std::string &err) = 0;
   virtual int persistent_grid() const = 0;  // 0 when the device cannot co-schedule the grid

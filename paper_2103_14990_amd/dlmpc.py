@@ -22,6 +22,8 @@ FLAG_SCHED_GRAPH = 0x2
 FLAG_SCHED_PERSISTENT = 0x4
 SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
+TIMED_KERNELS = 4
+KERNEL_NAMES = ("phi_kernel", "psi_pass1_kernel", "psi_pass2_kernel", "conv_kernel")
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -77,7 +79,7 @@ EXPORTS = {
     "dlmpc_column_block": (C.c_int, [C.c_void_p, C.c_int32, _i32p, _i64p, _dp, _dp]),
     "dlmpc_solve": (C.c_int, [C.c_void_p, _dp, C.POINTER(Warm), _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
-    "dlmpc_time_kernels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, _dp, _dp]),
+    "dlmpc_time_kernels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, _dp]),
     "dlmpc_destroy": (None, [C.c_void_p]),
     "dlmpc_status_string": (C.c_char_p, [C.c_int]),
     "dlmpc_last_error": (C.c_char_p, []),
@@ -222,11 +224,11 @@ class Problem:
                                                      C.byref(st)))
         return s, st.as_dict()
 
-    def time_kernels(self, x0_dev: int, iters: int) -> tuple[float, float]:
-        """Mean microseconds per launch of the Phi-comp and Psi-comp kernels (no early stop)."""
-        a, b = C.c_double(), C.c_double()
-        self._check(self._lib.dlmpc_time_kernels(self._h, C.c_void_p(x0_dev), iters, C.byref(a), C.byref(b)))
-        return a.value, b.value
+    def time_kernels(self, x0_dev: int, iters: int) -> dict:
+        """Mean microseconds per launch of each kernel of one iteration (no early stop)."""
+        us = np.zeros(TIMED_KERNELS)
+        self._check(self._lib.dlmpc_time_kernels(self._h, C.c_void_p(x0_dev), iters, _ptr(us)))
+        return dict(zip(KERNEL_NAMES, us.tolist()))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -170,6 +170,14 @@ def test_fp32_tier(name, seed, schedule):
     assert abs(res.stats["objective"] - ores.J) < 1e-5 * ores.J
 
 
+def test_fixed_check_interval(chain10):
+    """check_every > 0: fixed chunks of iterations between host checks, same result."""
+    c = Case(chain10.wl, check_every=7, schedule="graph")
+    x0 = chain10.wl.x0(2)
+    ores = O.solve(c.pb, x0, RHO, EPS, MAXIT)
+    check_fp64(c, x0, c.pr.solve(x0, want_phi=True), ores)
+
+
 def test_schedules_agree_bitwise():
     """Both schedules run the same kernels bodies in the same order: identical FP64 results."""
     wl = W.workload("grid16_box")
@@ -191,8 +199,8 @@ def test_kernel_timing_entry(chain10):
     import torch
     xd = torch.tensor(chain10.wl.x0(1), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    us_phi, us_psi = chain10.pr.time_kernels(xd.data_ptr(), 10)
-    assert us_phi > 0 and us_psi > 0
+    us = chain10.pr.time_kernels(xd.data_ptr(), 10)
+    assert set(us) == set(dlmpc.KERNEL_NAMES) and all(v > 0 for v in us.values())
     # the problem still solves correctly afterwards
     x0 = chain10.wl.x0(1)
     ores = O.solve(chain10.pb, x0, RHO, EPS, MAXIT)
