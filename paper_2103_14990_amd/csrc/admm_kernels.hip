@@ -121,50 +121,84 @@ __global__ __launch_bounds__(kBlock) void warm_kernel(Tf *psi, Tf *lam, const in
 
 // ------------------------------------------------------------------ Phi-comp
 
+// Phi-comp of row subsystem m. Lane l of every wave owns local row l0 + l of a 64-row chunk;
+// the waves split the patch tiles (tile k goes to wave k mod kWaves), accumulate
+// a_r = v_r . x_r over their tiles, combine the kWaves partial sums in LDS in a fixed order,
+// and apply the explicit row solution to the tile values they still hold in registers.
+constexpr int kPhiRegTiles = 16;  // tiles per wave kept in registers between the two sweeps
+
 template <typename Tf, int NX>
 __device__ __forceinline__ void phi_body(const KArgs<Tf> &a, int m, unsigned char *smem_raw) {
-  Tf *part = reinterpret_cast<Tf *>(smem_raw);  // [np][rs] partial dot products
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t t0 = a.rt_ptr[m];
   const int np = int(a.rt_ptr[m + 1] - t0);
   const int rs = a.rs;
-  Tf *alpha_s = part + np * rs;  // [rs]
-  Tf *xs = alpha_s + rs;         // [np][NX] x0 of the patch members
+  Tf *xs = reinterpret_cast<Tf *>(smem_raw);  // [np][NX] x0 of the patch members
+  Tf *part = xs + ((np * NX + 3) & ~3);       // [kWaves][64]
+  Tf *alpha_s = part + kWaves * 64;           // [64]
   for (int i = tid; i < np * NX; i += kBlock) xs[i] = a.x0f[a.rt_col[t0 + i / NX] * NX + i % NX];
   __syncthreads();
-  const int items = np * rs;
-  for (int it = tid; it < items; it += kBlock) {
-    const int k = it / rs, l = it - k * rs;
-    const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
-    Tf acc = Tf(0);
-#pragma unroll
-    for (int c = 0; c < NX; ++c) acc += xs[k * NX + c] * (a.psi[base + c] - a.lam[base + c]);
-    part[it] = acc;
-  }
-  __syncthreads();
   const Tf n = a.nrm[m];
-  for (int l = tid; l < rs; l += kBlock) {
+  for (int l0 = 0; l0 < rs; l0 += 64) {
+    const int l = l0 + lane;
+    const bool act = l < rs;
+    Tf vreg[kPhiRegTiles][NX];
     Tf acc = Tf(0);
-    for (int k = 0; k < np; ++k) acc += part[k * rs + l];
-    const int64_t o = int64_t(m) * rs + l;
-    Tf s, al;
-    if (n > Tf(0)) {
-      s = clip(a.rho * acc / (a.rho + Tf(2) * a.w[o] * n), a.lb[o], a.ub[o]);
-      al = (s - acc) / n;
-    } else {
-      s = acc;
-      al = Tf(0);
-    }
-    alpha_s[l] = al;
-    a.y[o] = s;
-  }
-  __syncthreads();
-  for (int it = tid; it < items; it += kBlock) {
-    const int k = it / rs, l = it - k * rs;
-    const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
-    const Tf al = alpha_s[l];
 #pragma unroll
-    for (int c = 0; c < NX; ++c) a.phi[base + c] = (a.psi[base + c] - a.lam[base + c]) + al * xs[k * NX + c];
+    for (int kk = 0; kk < kPhiRegTiles; ++kk) {
+      const int k = wave + kk * kWaves;
+      if (act && k < np) {
+        const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          vreg[kk][c] = a.psi[base + c] - a.lam[base + c];
+          acc += xs[k * NX + c] * vreg[kk][c];
+        }
+      }
+    }
+    for (int k = wave + kPhiRegTiles * kWaves; k < np; k += kWaves) {
+      if (!act) break;
+      const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) acc += xs[k * NX + c] * (a.psi[base + c] - a.lam[base + c]);
+    }
+    part[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave == 0 && act) {
+      Tf s = part[lane];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) s += part[w * 64 + lane];
+      const int64_t o = int64_t(m) * rs + l;
+      Tf sv, al;
+      if (n > Tf(0)) {
+        sv = clip(a.rho * s / (a.rho + Tf(2) * a.w[o] * n), a.lb[o], a.ub[o]);
+        al = (sv - s) / n;
+      } else {
+        sv = s;
+        al = Tf(0);
+      }
+      alpha_s[lane] = al;
+      a.y[o] = sv;
+    }
+    __syncthreads();
+    if (act) {
+      const Tf al = alpha_s[lane];
+#pragma unroll
+      for (int kk = 0; kk < kPhiRegTiles; ++kk) {
+        const int k = wave + kk * kWaves;
+        if (k < np) {
+          const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
+#pragma unroll
+          for (int c = 0; c < NX; ++c) a.phi[base + c] = vreg[kk][c] + al * xs[k * NX + c];
+        }
+      }
+      for (int k = wave + kPhiRegTiles * kWaves; k < np; k += kWaves) {
+        const int64_t base = a.rt_tile[t0 + k] * a.ts + int64_t(l) * NX;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) a.phi[base + c] = (a.psi[base + c] - a.lam[base + c]) + al * xs[k * NX + c];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -488,24 +522,28 @@ __global__ __launch_bounds__(kBlock) void psi_pass2_kernel(KArgs<Tf> a, PsiUnits
   if (tid < 2 * NX) {
     double s = 0.0;
     for (int w = 0; w < kWaves; ++w) s += red[w][tid];
-    pu.part[int64_t(blockIdx.x) * 2 * NX + tid] = s;
+    pu.part[(int64_t(j) * pu.max_units + r0 / RB) * 2 * NX + tid] = s;
   }
 }
 
+constexpr int kConvBlock = 1024;
+
 template <typename Tf, int NX>
-__global__ __launch_bounds__(kBlock) void conv_kernel(KArgs<Tf> a, PsiUnits<Tf> pu) {
+__global__ __launch_bounds__(kConvBlock) void conv_kernel(KArgs<Tf> a, PsiUnits<Tf> pu) {
   if (a.ctl->stop) return;
-  __shared__ double redp[kWaves], redd[kWaves];
+  constexpr int kCW = kConvBlock / 64;
+  __shared__ double redp[kCW], redd[kCW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double mp = 0.0, md = 0.0;
-  for (int j = tid; j < a.N; j += kBlock) {
-    const int f = pu.p2_first[j], n = pu.p2_count[j];
+  for (int j = tid; j < a.N; j += kConvBlock) {
+    // j's pass-2 units own slots [j * max_units, (j + 1) * max_units); unused slots hold zeros
+    const double *pj = pu.part + int64_t(j) * pu.max_units * 2 * NX;
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       double sp = 0.0, sd = 0.0;
-      for (int u = f; u < f + n; ++u) {
-        sp += pu.part[int64_t(u) * 2 * NX + c];
-        sd += pu.part[int64_t(u) * 2 * NX + NX + c];
+      for (int u = 0; u < pu.max_units; ++u) {
+        sp += pj[u * 2 * NX + c];
+        sd += pj[u * 2 * NX + NX + c];
       }
       sp = sqrt(sp);
       sd = sqrt(sd);
@@ -525,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void conv_kernel(KArgs<Tf> a, PsiUnits<Tf> 
   }
   __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < kWaves; ++w) {
+    for (int w = 1; w < kCW; ++w) {
       mp = (redp[w] > mp || redp[w] != redp[w]) ? redp[w] : mp;
       md = (redd[w] > md || redd[w] != redd[w]) ? redd[w] : md;
     }
@@ -722,7 +760,7 @@ class EngineT final : public Engine {
     if ((rc = alloc(&a.nrm, size_t(hs.N), err))) return rc;
     if ((rc = alloc(&a.y, size_t(hs.N) * hs.rs, err))) return rc;
     if ((rc = alloc(&a.ctl, 1, err))) return rc;
-    lds_phi_ = (size_t(hs.p_max) * hs.rs + hs.rs + size_t(hs.p_max) * NX) * sizeof(Tf);
+    lds_phi_ = (size_t((hs.p_max * NX + 3) & ~3) + size_t(kWaves) * 64 + 64) * sizeof(Tf);
     lds_psi_ = (size_t(NX) * padded_ld(hs.d_col_max) + size_t(NX) * hs.k_max) * sizeof(Tf);
     if (lds_phi_ > kMaxLds || lds_psi_ > kMaxLds) {
       err = "patch too large for the on-chip staging of this build (LDS " + std::to_string(lds_psi_) + " B)";
@@ -746,7 +784,9 @@ class EngineT final : public Engine {
         p1.push_back(j);
         p1.push_back(i0);
       }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return hs.kdim[x] > hs.kdim[y]; });
+    // Pass 2 visits the subsystems in the reverse order of pass 1, so that it starts on the
+    // null bases pass 1 streamed last (the ones most likely still in the memory-side cache).
+    std::reverse(order.begin(), order.end());
     for (int j : order) {
       first[j] = int32_t(p2.size() / 2);
       for (int r0 = 0; r0 < D_of(j); r0 += RB) {
@@ -766,7 +806,11 @@ class EngineT final : public Engine {
     if ((rc = upload(count, &pu_.p2_count, err))) return rc;
     if ((rc = upload(toff, &pu_.t_off, err))) return rc;
     if ((rc = alloc(&pu_.t, size_t(toff[hs.N]), err))) return rc;
-    if ((rc = alloc(&pu_.part, size_t(std::max(n2_, 1)) * 2 * NX, err))) return rc;
+    int max_units = 1;
+    for (int j = 0; j < hs.N; ++j) max_units = std::max(max_units, count[j]);
+    pu_.max_units = max_units;
+    if ((rc = alloc(&pu_.part, size_t(hs.N) * max_units * 2 * NX, err))) return rc;
+    ENG_CHECK(hipMemset(pu_.part, 0, sizeof(double) * size_t(hs.N) * max_units * 2 * NX));
     lds_p1_ = size_t(NX) * padded_ld(hs.d_col_max) * sizeof(Tf);
     lds_p2_ = (size_t(kWaves) * NX * RB + size_t(NX) * hs.k_max) * sizeof(Tf);
     if (lds_p1_ > kMaxLds || lds_p2_ > kMaxLds) {
@@ -877,7 +921,7 @@ class EngineT final : public Engine {
         hipLaunchKernelGGL((psi_pass2_kernel<Tf, NX>), dim3(n2_), dim3(kBlock), lds_p2_, stream_, args_, pu_);
         break;
       default:
-        hipLaunchKernelGGL((conv_kernel<Tf, NX>), dim3(1), dim3(kBlock), 0, stream_, args_, pu_);
+        hipLaunchKernelGGL((conv_kernel<Tf, NX>), dim3(1), dim3(kConvBlock), 0, stream_, args_, pu_);
         break;
     }
     ENG_CHECK(hipGetLastError());

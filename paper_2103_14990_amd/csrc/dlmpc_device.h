@@ -47,7 +47,8 @@ struct PsiUnits {
   const int32_t *p2_count;  // [N] number of its pass-2 units (consecutive)
   const int64_t *t_off;     // [N+1] offset of t_j (NX*k_j values)
   Tf *t;                    // N_j' v for every j
-  double *part;             // [n2][2*NX] per-unit residual partial sums
+  double *part;             // [N][max_units][2*NX] residual partial sums, slot = first row / RB
+  int32_t max_units;        // most pass-2 units of any column subsystem
 };
 
 template <typename Tf>

@@ -178,13 +178,14 @@ def test_fixed_check_interval(chain10):
     check_fp64(c, x0, c.pr.solve(x0, want_phi=True), ores)
 
 
-def test_schedules_agree_bitwise():
-    """Both schedules run the same kernels bodies in the same order: identical FP64 results."""
+def test_schedules_agree():
+    """The two schedules sum the projection in different orders (split over waves vs one
+    thread per row) but follow the same trajectory: same iterations, FP64 results to 1e-12."""
     wl = W.workload("grid16_box")
     a = Case(wl, schedule="graph").pr.solve(wl.x0(1003), want_phi=True)
     b = Case(wl, schedule="persistent").pr.solve(wl.x0(1003), want_phi=True)
     assert a.stats["iters"] == b.stats["iters"]
-    assert np.array_equal(a.u0, b.u0) and np.array_equal(a.phi, b.phi)
+    assert rel(a.u0, b.u0) < 1e-12 and rel(a.phi, b.phi) < 1e-12
 
 
 def test_auto_schedule_reports_tuning():
