@@ -94,6 +94,8 @@ typedef struct {
   int32_t device;      /* HIP device ordinal */
   void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
   uint32_t flags;      /* DLMPC_FLAG_* */
+  int32_t max_batch;   /* 0, or 1..64: also set up the batched engine for up to this many x0
+                          per dlmpc_solve_batch call (FP32 precision only) */
 } dlmpc_options;
 
 /* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
@@ -182,6 +184,20 @@ int dlmpc_solve_device(struct dlmpc_problem *p, const double *x0_dev, double *u0
 #define DLMPC_TIMED_KERNELS 4
 int dlmpc_time_kernels(struct dlmpc_problem *p, const double *x0_dev, int32_t iters,
                        double *us_per_launch);
+
+/* Batched per-step solve: B in 1..max_batch independent MPC instances on this network (distinct
+ * x0, same plant, cost and bounds), iterated together. Each instance follows the iteration of
+ * Algorithm 2 from the cold start and stops at its own convergence (or max_iter); stopped
+ * instances are frozen while the others continue. The iteration is run in an exact compact
+ * form (per instance: the Phi-comp row scalars and the null-space coordinates of the Psi and
+ * Lambda columns), and both products of an iteration run on the matrix cores (bf16 hi/lo split
+ * operands, three products, FP32 accumulation). x0 [B][N*nx], u0 [B][N*nu] row-major (host for
+ * dlmpc_solve_batch, device for dlmpc_solve_batch_device); stats [B] or NULL. Returns
+ * DLMPC_OK when every instance converged, DLMPC_ENOCONV otherwise (per-instance stats). */
+int dlmpc_solve_batch(struct dlmpc_problem *p, int32_t B, const double *x0, double *u0,
+                      dlmpc_stats *stats);
+int dlmpc_solve_batch_device(struct dlmpc_problem *p, int32_t B, const double *x0_dev, double *u0_dev,
+                             dlmpc_stats *stats);
 
 void dlmpc_destroy(struct dlmpc_problem *p);
 const char *dlmpc_status_string(int status);

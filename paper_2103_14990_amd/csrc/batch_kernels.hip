@@ -1,0 +1,675 @@
+// Batched DLMPC-ADMM (many x0 on one network) in the compact form of Algorithm 2, with the two
+// products of an iteration on the gfx950 matrix cores.
+//
+// Compact form. With the cold start of Algorithm 2 (Psi^0 = Lambda^0 = 0) every iterate from
+// the second one on has, per column c of subsystem j and on its support,
+//   Psi[:,c]    = o_c + x0_c N_j tau_j,          tau_j = N_j' beta,  beta = sum of past alpha,
+//   Lambda[:,c] = x0_c (I - N_j N_j') alpha,      eta_j = N_j' alpha,
+// where alpha_r is the row scalar of the Phi-comp solution (Phi row = v + alpha_r x_r). Hence
+//   Phi-comp : a_r = c_it b_r + sum_{j in P(m)} ||x0_j||^2 [N_j (tau_j + eta_j)]_r - n_r alpha_r,
+//              b_r = sum_{j in P(m)} sum_c x0_c o_c[r], c_it = 0, 2, 1 for iterations 1, 2, >= 3,
+//              then the explicit clipped row solution gives the new alpha and s_r = (Phi x0)_r;
+//   Psi-comp : eta_j <- N_j' alpha|_{supp j}, tau_j <- tau_j + eta_j;
+//   Conv     : ||Psi^{k+1} - Psi^k||_c = |x0_c| ||eta_j||,
+//              ||Phi - Psi||_c^2 = x0_c^2 (||d_j||^2 - ||eta_j - eta_j^old||^2), d = alpha - alpha^old
+//              (iteration 2 adds the o_c terms of Lambda^1 = -o).
+// This is an exact rewriting of the iteration (same trajectory up to rounding). Per instance the
+// state is alpha and the k-space vectors, and both products share N_j across the instances:
+//   bphi_kernel : (rs x B) += N_j[rows of m, :] (rs x k_j) * W_j (k_j x B) for j in P(m),
+//   bpsi_kernel : eta_j (k_j x B) = N_j' (k_j x D_j) * A_j (D_j x B),
+// run as v_mfma_f32_16x16x32_bf16 with every FP32 operand split into bf16 hi + lo and the three
+// significant partial products (hi*hi, hi*lo, lo*hi) accumulated in FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dlmpc_device.h"
+
+namespace dlmpc {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBMax = 64;         // instances per batch (four 16-wide MFMA tiles)
+constexpr int kNT = kBMax / 16;
+constexpr int kPsiThreads = 512;  // 8 waves
+constexpr int kPsiWaves = kPsiThreads / 64;
+constexpr int kMTW = 4;           // M tiles (16 basis vectors) per wave: k_j <= 512
+constexpr int kKC = 64;           // support rows staged per chunk in bpsi_kernel
+
+__device__ __forceinline__ unsigned long long ord_bits(double v) {
+  return static_cast<unsigned long long>(__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void split8(const float *x, bf16x8 &hi, bf16x8 &lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = static_cast<__bf16>(x[e]);
+    hi[e] = h;
+    lo[e] = static_cast<__bf16>(x[e] - static_cast<float>(h));
+  }
+}
+
+// A*B with A = ah + al, B = bh + bl, dropping al*bl (below FP32 rounding of the sum).
+__device__ __forceinline__ f32x4 mfma3(const bf16x8 &ah, const bf16x8 &al, const bf16x8 &bh,
+                                       const bf16x8 &bl, f32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  return c;
+}
+
+__device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ per-solve precompute
+
+template <int NX>
+__global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double *x0, int B, int warm,
+                                                          int max_iter, double eps) {
+  const int m = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int rs = a.rs;
+  const int64_t nxs = int64_t(a.N) * NX;
+  const double *xb = x0 + int64_t(b) * nxs;
+  if (tid < NX) a.x0[int64_t(b) * nxs + m * NX + tid] = static_cast<float>(xb[m * NX + tid]);
+  if (tid == 0) {
+    double sm = 0.0, sn = 0.0;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) sm += xb[m * NX + c] * xb[m * NX + c];
+    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+      const int j = a.rt_col[q];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) sn += xb[j * NX + c] * xb[j * NX + c];
+    }
+    a.xn[int64_t(b) * a.N + m] = static_cast<float>(sm);
+    a.nrm[int64_t(b) * a.N + m] = static_cast<float>(sn);
+  }
+  const int64_t rb = int64_t(b) * a.N * rs + int64_t(m) * rs;
+  const int64_t plane = int64_t(a.Bmax) * a.N * rs;
+  for (int l = tid; l < rs; l += 256) {
+    double bv = 0.0;
+    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+      const int j = a.rt_col[q];
+      const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
+      const int ld = (D + 3) & ~3;
+      const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) bv += xb[j * NX + c] * double(a.off[a.off_ptr[j] + int64_t(c) * ld + ro + l]);
+    }
+    a.bvec[rb + l] = static_cast<float>(bv);
+    a.alpha[rb + l] = 0.f;
+    a.alpha[plane + rb + l] = 0.f;
+    a.s[rb + l] = 0.f;
+  }
+  for (int64_t i = a.koff[m] + tid; i < a.koff[m + 1]; i += 256) {
+    a.tau[int64_t(b) * a.ktot + i] = 0.f;
+    a.eta[int64_t(b) * a.ktot + i] = 0.f;
+  }
+  if (m == 0 && tid == 0) {
+    BCtl &ic = a.ictl[b];
+    ic.iters = 0;
+    ic.stop = 0;
+    ic.converged = 0;
+    ic.numeric = 0;
+    ic.last_rp = ic.last_rd = INFINITY;
+    ic.objective = 0.0;
+    a.slot[2 * b] = a.slot[2 * b + 1] = 0ull;
+    if (b == 0) {
+      Ctl *c = a.ctl;
+      c->iters = 0;
+      c->stop = 0;
+      c->converged = 0;
+      c->numeric = 0;
+      c->max_iter = max_iter;
+      c->eps = eps;
+      c->last_rp = c->last_rd = INFINITY;
+      c->batch = B;
+      c->warm = warm;
+    }
+  }
+}
+
+// Compact warm start: alpha^0 into the previous-iterate plane (plane 0, read by iteration 1).
+__global__ __launch_bounds__(256) void bwarm_alpha_kernel(BArgs a, const double *alpha0, int B) {
+  const int64_t ny = int64_t(a.N) * a.rs;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < int64_t(B) * ny; i += int64_t(gridDim.x) * 256)
+    a.alpha[i] = static_cast<float>(alpha0[i]);
+}
+
+__global__ __launch_bounds__(256) void bexport_alpha_kernel(BArgs a, double *out, int B) {
+  const int64_t ny = int64_t(a.N) * a.rs;
+  const int64_t plane = int64_t(a.Bmax) * ny;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < int64_t(B) * ny; i += int64_t(gridDim.x) * 256) {
+    const int b = int(i / ny);
+    const int p = a.ictl[b].iters & 1;  // the plane the stopping iteration wrote
+    out[i] = double(a.alpha[p * plane + i]);
+  }
+}
+
+// ------------------------------------------------------------------ Phi-comp (batched)
+
+// One block per row subsystem m; wave mt owns rows [16 mt, 16 mt + 16) of m and all instances.
+template <int NX>
+__global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
+  if (a.ctl->stop) return;
+  __shared__ float Ct[64][kBMax + 1];
+  const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, mt = tid >> 6;
+  const int rs = a.rs, B = a.ctl->batch;
+  const bool warm = a.ctl->warm != 0;
+  const int it = a.ctl->iters + 1;
+  const float coef = warm ? 1.f : (it == 1 ? 0.f : (it == 2 ? 2.f : 1.f));
+  f32x4 acc[kNT];
+#pragma unroll
+  for (int nt = 0; nt < kNT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (warm || it >= 3) {  // from a cold start tau = eta = 0 before the third iteration
+    const int row = mt * 16 + (lane & 15);
+    const bool rowok = row < rs;
+    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+      const int j = a.rt_col[q];
+      const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
+      const int k32 = int(a.koff[j + 1] - a.koff[j]);
+      const int64_t arow = a.nrm_off[j] + int64_t(ro + (rowok ? row : 0)) * k32;
+      for (int i0 = 8 * (lane >> 4); i0 < k32; i0 += 32) {
+        bf16x8 ah = {}, al = {};
+        if (rowok) {
+          ah = load8(a.nrm_hi + arow + i0);
+          al = load8(a.nrm_lo + arow + i0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+          const int b = nt * 16 + (lane & 15);
+          if (nt * 16 >= B) break;
+          float w[8];
+          if (b < B) {
+            const float xj = a.xn[int64_t(b) * a.N + j];
+            const int64_t kb = int64_t(b) * a.ktot + a.koff[j] + i0;
+            const float4 t0 = *reinterpret_cast<const float4 *>(a.tau + kb);
+            const float4 t1 = *reinterpret_cast<const float4 *>(a.tau + kb + 4);
+            const float4 e0 = *reinterpret_cast<const float4 *>(a.eta + kb);
+            const float4 e1 = *reinterpret_cast<const float4 *>(a.eta + kb + 4);
+            w[0] = xj * (t0.x + e0.x); w[1] = xj * (t0.y + e0.y); w[2] = xj * (t0.z + e0.z); w[3] = xj * (t0.w + e0.w);
+            w[4] = xj * (t1.x + e1.x); w[5] = xj * (t1.y + e1.y); w[6] = xj * (t1.z + e1.z); w[7] = xj * (t1.w + e1.w);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w[e] = 0.f;
+          }
+          bf16x8 bh, bl;
+          split8(w, bh, bl);
+          acc[nt] = mfma3(ah, al, bh, bl, acc[nt]);
+        }
+      }
+    }
+  }
+  // C tile: lane holds rows 16 mt + 4 (lane / 16) + e of instance column nt * 16 + lane % 16
+#pragma unroll
+  for (int nt = 0; nt < kNT; ++nt)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Ct[mt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[nt][e];
+  __syncthreads();
+  const int64_t plane = int64_t(a.Bmax) * a.N * rs;
+  const int cur = it & 1, prev = cur ^ 1;
+  for (int idx = tid; idx < rs * B; idx += blockDim.x) {
+    const int l = idx / B, b = idx - l * B;
+    if (a.ictl[b].stop) continue;
+    const int64_t o = int64_t(m) * rs + l;
+    const int64_t rb = int64_t(b) * a.N * rs + o;
+    const float n = a.nrm[int64_t(b) * a.N + m];
+    const float ap = a.alpha[prev * plane + rb];
+    const float av = coef * a.bvec[rb] + Ct[l][b] - n * ap;
+    float sv, al;
+    if (n > 0.f) {
+      sv = a.rho * av / (a.rho + 2.f * a.w[o] * n);
+      sv = sv < a.lb[o] ? a.lb[o] : (sv > a.ub[o] ? a.ub[o] : sv);
+      al = (sv - av) / n;
+    } else {
+      sv = av;
+      al = 0.f;
+    }
+    a.alpha[cur * plane + rb] = al;
+    a.s[rb] = sv;
+  }
+}
+
+// ------------------------------------------------------------------ Psi-comp + Conv (batched)
+
+// One block per column subsystem j: eta_j = N_j' A_j over K-chunks of its support rows staged
+// (as bf16 hi/lo) in LDS; wave w owns the M tiles w, w + 8, ... of the basis vectors.
+template <int NX>
+__global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
+  if (a.ctl->stop) return;
+  __shared__ __align__(16) __bf16 sh_hi[kBMax][kKC + 8];
+  __shared__ __align__(16) __bf16 sh_lo[kBMax][kKC + 8];
+  __shared__ double red_e[kPsiWaves][kBMax], red_d[kPsiWaves][kBMax];
+  __shared__ double red_dl[kBMax][8], red_od[kBMax][8][NX];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rs = a.rs, B = a.ctl->batch;
+  const bool warm = a.ctl->warm != 0;
+  const int it = a.ctl->iters + 1;
+  const int64_t tb = a.tile_off[j];
+  const int D = int(a.tile_off[j + 1] - tb) * rs;
+  const int k = a.kdim[j];
+  const int kc16 = (k + 15) & ~15;
+  const int ld64 = (D + 63) & ~63;
+  const int ld4 = (D + 3) & ~3;
+  const int64_t plane = int64_t(a.Bmax) * a.N * rs;
+  const bool initp = a.init_pass != 0;
+  const bool cold2 = !warm && it == 2;
+  // the warm-start pass reads alpha^0, stored where iteration 1 reads the previous iterate
+  const int cur = initp ? 0 : (it & 1), prev = cur ^ 1;
+  const int sb = tid >> 3, sub = tid & 7;  // staging: instance sb, rows 8 sub .. 8 sub + 7
+
+  if (!warm && it == 1 && !initp) {  // alpha^1 = 0: Psi^1 = o, residuals ||o_c||, eta stays 0
+    if (tid < B && !a.ictl[tid].stop) {
+      double mx = 0.0;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) mx = fmax(mx, sqrt(a.onorm2[j * NX + c]));
+      atomicMax(&a.slot[2 * tid], ord_bits(mx));
+      atomicMax(&a.slot[2 * tid + 1], ord_bits(mx));
+    }
+    return;
+  }
+
+  f32x4 acc[kMTW][kNT];
+#pragma unroll
+  for (int t = 0; t < kMTW; ++t)
+#pragma unroll
+    for (int nt = 0; nt < kNT; ++nt) acc[t][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double dl2 = 0.0, od[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) od[c] = 0.0;
+  const bool sact = sb < B;
+  for (int r0 = 0; r0 < ld64; r0 += kKC) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int rr = r0 + 8 * sub + e;
+      float an = 0.f;
+      if (sact && rr < D) {
+        const int ta = rr / rs, l = rr - ta * rs;
+        const int mm = a.tile_rsub[tb + ta];
+        const int64_t idx = int64_t(sb) * a.N * rs + int64_t(mm) * rs + l;
+        an = a.alpha[cur * plane + idx];
+        const float ap = a.alpha[prev * plane + idx];
+        dl2 += double(an - ap) * double(an - ap);
+        if (cold2) {
+#pragma unroll
+          for (int c = 0; c < NX; ++c) od[c] += double(an) * double(a.off[a.off_ptr[j] + int64_t(c) * ld4 + rr]);
+        }
+      }
+      v[e] = an;
+    }
+    bf16x8 vh, vl;
+    split8(v, vh, vl);
+    *reinterpret_cast<bf16x8 *>(&sh_hi[sb][8 * sub]) = vh;
+    *reinterpret_cast<bf16x8 *>(&sh_lo[sb][8 * sub]) = vl;
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKC / 32; ++ks) {
+      const int kr = ks * 32 + 8 * (lane >> 4);
+      bf16x8 bh[kNT], bl[kNT];
+#pragma unroll
+      for (int nt = 0; nt < kNT; ++nt) {
+        bh[nt] = *reinterpret_cast<const bf16x8 *>(&sh_hi[nt * 16 + (lane & 15)][kr]);
+        bl[nt] = *reinterpret_cast<const bf16x8 *>(&sh_lo[nt * 16 + (lane & 15)][kr]);
+      }
+#pragma unroll
+      for (int t = 0; t < kMTW; ++t) {
+        const int mtile = wave + kPsiWaves * t;
+        if (mtile * 16 >= kc16) break;
+        const int64_t ai = a.ncm_off[j] + int64_t(mtile * 16 + (lane & 15)) * ld64 + r0 + kr;
+        const bf16x8 ah = load8(a.ncm_hi + ai), al = load8(a.ncm_lo + ai);
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+          if (nt * 16 >= B) break;
+          acc[t][nt] = mfma3(ah, al, bh[nt], bl[nt], acc[t][nt]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // eta_new, tau and the k-space residual terms; lane holds basis rows 4 (lane/16) + e of tile.
+  double e2[kNT], d2[kNT];
+#pragma unroll
+  for (int nt = 0; nt < kNT; ++nt) e2[nt] = d2[nt] = 0.0;
+#pragma unroll
+  for (int t = 0; t < kMTW; ++t) {
+    const int mtile = wave + kPsiWaves * t;
+    if (mtile * 16 >= kc16) break;
+#pragma unroll
+    for (int nt = 0; nt < kNT; ++nt) {
+      const int b = nt * 16 + (lane & 15);
+      if (b >= B || a.ictl[b].stop) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = mtile * 16 + 4 * (lane >> 4) + e;
+        if (i >= k) continue;
+        const int64_t ki = int64_t(b) * a.ktot + a.koff[j] + i;
+        const float en = acc[t][nt][e];
+        const float eo = a.eta[ki];
+        a.eta[ki] = en;
+        if (!initp) a.tau[ki] += en;
+        e2[nt] += double(en) * double(en);
+        d2[nt] += double(en - eo) * double(en - eo);
+      }
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < kNT; ++nt) {  // lanes l, l^16, l^32, l^48 share an instance
+    e2[nt] += __shfl_xor(e2[nt], 16, 64);
+    e2[nt] += __shfl_xor(e2[nt], 32, 64);
+    d2[nt] += __shfl_xor(d2[nt], 16, 64);
+    d2[nt] += __shfl_xor(d2[nt], 32, 64);
+    if (lane < 16) {
+      red_e[wave][nt * 16 + lane] = e2[nt];
+      red_d[wave][nt * 16 + lane] = d2[nt];
+    }
+  }
+  if (initp) return;  // warm-start pass: eta only, no residuals
+  red_dl[sb][sub] = dl2;
+#pragma unroll
+  for (int c = 0; c < NX; ++c) red_od[sb][sub][c] = od[c];
+  __syncthreads();
+  if (tid < B && !a.ictl[tid].stop) {
+    const int b = tid;
+    double se = 0.0, sd = 0.0, sdl = 0.0;
+    for (int w = 0; w < kPsiWaves; ++w) {
+      se += red_e[w][b];
+      sd += red_d[w][b];
+    }
+    for (int q = 0; q < 8; ++q) sdl += red_dl[b][q];
+    double mp = 0.0, md = 0.0;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const double xc = double(a.x0[int64_t(b) * a.N * NX + j * NX + c]);
+      const double rd = fabs(xc) * sqrt(se);
+      double rp2;
+      if (cold2) {
+        double odc = 0.0;
+        for (int q = 0; q < 8; ++q) odc += red_od[b][q][c];
+        rp2 = a.onorm2[j * NX + c] + 2.0 * xc * odc + xc * xc * (sdl - se);
+      } else {
+        rp2 = xc * xc * (sdl - sd);
+      }
+      const double rp = sqrt(fmax(rp2, 0.0));
+      mp = (rp > mp || rp != rp) ? rp : mp;
+      md = (rd > md || rd != rd) ? rd : md;
+    }
+    atomicMax(&a.slot[2 * b], ord_bits(mp));
+    atomicMax(&a.slot[2 * b + 1], ord_bits(md));
+  }
+}
+
+// ------------------------------------------------------------------ decision, outputs
+
+__global__ __launch_bounds__(64) void bdecide_kernel(BArgs a) {
+  if (a.ctl->stop) return;
+  __shared__ int n_stop;
+  __shared__ unsigned long long worst_p, worst_d;
+  const int b = threadIdx.x;
+  if (b == 0) {
+    n_stop = 0;
+    worst_p = worst_d = 0ull;
+  }
+  __syncthreads();
+  Ctl *c = a.ctl;
+  const int it = c->iters + 1;
+  const int B = c->batch;
+  if (b < B) {
+    BCtl &ic = a.ictl[b];
+    if (!ic.stop) {
+      const double rp = __longlong_as_double(static_cast<long long>(a.slot[2 * b]));
+      const double rd = __longlong_as_double(static_cast<long long>(a.slot[2 * b + 1]));
+      ic.iters = it;
+      ic.last_rp = rp;
+      ic.last_rd = rd;
+      if (!(rp == rp) || !(rd == rd) || isinf(rp) || isinf(rd)) {
+        ic.numeric = 1;
+        ic.stop = 1;
+      } else if (rp <= c->eps && rd <= c->eps) {
+        ic.converged = 1;
+        ic.stop = 1;
+      } else if (it >= c->max_iter) {
+        ic.stop = 1;
+      }
+      if (!ic.stop) {
+        atomicMax(&worst_p, ord_bits(rp));
+        atomicMax(&worst_d, ord_bits(rd));
+      }
+    }
+    a.slot[2 * b] = a.slot[2 * b + 1] = 0ull;
+    if (ic.stop) atomicAdd(&n_stop, 1);
+  }
+  __syncthreads();
+  if (b == 0) {
+    c->iters = it;
+    c->last_rp = __longlong_as_double(static_cast<long long>(worst_p));
+    c->last_rd = __longlong_as_double(static_cast<long long>(worst_d));
+    if (n_stop == B) c->stop = 1;
+  }
+}
+
+template <int NX>
+__global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t ny = int64_t(a.N) * a.rs;
+  const float *sb = a.s + int64_t(b) * ny;
+  double acc = 0.0;
+  for (int64_t i = tid; i < ny; i += 256) acc += a.w64[i] * double(sb[i]) * double(sb[i]);
+  acc = wsum(acc);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) a.ictl[b].objective = (red[0] + red[1]) + (red[2] + red[3]);
+  for (int i = tid; i < a.N * a.nu; i += 256) {
+    const int m = i / a.nu, q = i - m * a.nu;
+    u0[int64_t(b) * a.N * a.nu + i] = double(sb[int64_t(m) * a.rs + NX * a.T + q]);
+  }
+}
+
+// ------------------------------------------------------------------ engine
+
+#define BENG_CHECK(expr)                                                  \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
+      return DLMPC_EDEVICE;                                               \
+    }                                                                     \
+  } while (0)
+
+template <int NX>
+class BatchEngineT final : public BatchEngine {
+ public:
+  int init(const HostSetup &hs, double rho, int bmax, hipStream_t s, std::string &err) override {
+    if (bmax < 1 || bmax > kBMax) {
+      err = "max_batch must be in 1..64";
+      return DLMPC_EINVAL;
+    }
+    if (hs.k_max > kPsiWaves * kMTW * 16 || hs.rs > 64) {
+      err = "batched engine needs k_j <= 512 and nx*T + nu*(T-1) <= 64";
+      return DLMPC_EINVAL;
+    }
+    hs_ = &hs;
+    stream_ = s;
+    BArgs &a = args_;
+    a.N = hs.N;
+    a.nx = hs.nx;
+    a.nu = hs.nu;
+    a.T = hs.T;
+    a.rs = hs.rs;
+    a.Bmax = bmax;
+    a.rho = float(rho);
+    const int N = hs.N;
+    std::vector<int64_t> koff(N + 1, 0), cmo(N + 1, 0), rmo(N + 1, 0);
+    for (int j = 0; j < N; ++j) {
+      const int64_t D = int64_t(hs.patch[j].size()) * hs.rs, k = hs.kdim[j];
+      koff[j + 1] = koff[j] + ((k + 31) & ~31);
+      cmo[j + 1] = cmo[j] + ((k + 15) & ~15) * ((D + 63) & ~63);
+      rmo[j + 1] = rmo[j] + D * ((k + 31) & ~31);
+    }
+    a.ktot = koff[N];
+    std::vector<__bf16> chi(cmo[N]), clo(cmo[N]), rhi(rmo[N]), rlo(rmo[N]);
+    const __bf16 z = static_cast<__bf16>(0.f);
+    std::fill(chi.begin(), chi.end(), z);
+    std::fill(clo.begin(), clo.end(), z);
+    std::fill(rhi.begin(), rhi.end(), z);
+    std::fill(rlo.begin(), rlo.end(), z);
+    for (int j = 0; j < N; ++j) {
+      const int D = int(hs.patch[j].size()) * hs.rs, k = hs.kdim[j], ld = padded_ld(D);
+      const int ld64 = (D + 63) & ~63, k32 = (k + 31) & ~31;
+      const double *Nj = hs.nb.data() + hs.nb_off[j];
+      for (int i = 0; i < k; ++i)
+        for (int r = 0; r < D; ++r) {
+          const float x = float(Nj[size_t(i) * ld + r]);
+          const __bf16 h = static_cast<__bf16>(x);
+          const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
+          chi[cmo[j] + size_t(i) * ld64 + r] = h;
+          clo[cmo[j] + size_t(i) * ld64 + r] = l;
+          rhi[rmo[j] + size_t(r) * k32 + i] = h;
+          rlo[rmo[j] + size_t(r) * k32 + i] = l;
+        }
+    }
+    std::vector<double> on2(size_t(N) * NX, 0.0);
+    for (int j = 0; j < N; ++j) {
+      const int D = int(hs.patch[j].size()) * hs.rs, ld = padded_ld(D);
+      for (int c = 0; c < NX; ++c)
+        for (int r = 0; r < D; ++r) {
+          const double o = hs.off[hs.off_ptr[j] + size_t(c) * ld + r];
+          on2[size_t(j) * NX + c] += o * o;
+        }
+    }
+    int rc;
+    if ((rc = up(hs.tile_off, &a.tile_off, err)) || (rc = up(hs.rt_ptr, &a.rt_ptr, err)) ||
+        (rc = up(hs.rt_tile, &a.rt_tile, err)) || (rc = up(hs.rt_col, &a.rt_col, err)) ||
+        (rc = up(hs.kdim, &a.kdim, err)) || (rc = up(hs.tile_rsub, &a.tile_rsub, err)) ||
+        (rc = up(koff, &a.koff, err)) || (rc = up(cmo, &a.ncm_off, err)) || (rc = up(rmo, &a.nrm_off, err)) ||
+        (rc = up(chi, &a.ncm_hi, err)) || (rc = up(clo, &a.ncm_lo, err)) || (rc = up(rhi, &a.nrm_hi, err)) ||
+        (rc = up(rlo, &a.nrm_lo, err)) || (rc = up(hs.off_ptr, &a.off_ptr, err)) || (rc = up(on2, &a.onorm2, err)) ||
+        (rc = up(hs.w, &a.w64, err)))
+      return rc;
+    std::vector<float> offf(hs.off.begin(), hs.off.end()), wf(hs.w.begin(), hs.w.end()),
+        lbf(hs.lb.begin(), hs.lb.end()), ubf(hs.ub.begin(), hs.ub.end());
+    if ((rc = up(offf, &a.off, err)) || (rc = up(wf, &a.w, err)) || (rc = up(lbf, &a.lb, err)) ||
+        (rc = up(ubf, &a.ub, err)))
+      return rc;
+    const size_t ny = size_t(N) * hs.rs;
+    if ((rc = al(&a.alpha, 2 * size_t(bmax) * ny, err)) || (rc = al(&a.tau, size_t(bmax) * a.ktot, err)) ||
+        (rc = al(&a.eta, size_t(bmax) * a.ktot, err)) || (rc = al(&a.xn, size_t(bmax) * N, err)) ||
+        (rc = al(&a.nrm, size_t(bmax) * N, err)) || (rc = al(&a.bvec, size_t(bmax) * ny, err)) ||
+        (rc = al(&a.s, size_t(bmax) * ny, err)) || (rc = al(&a.x0, size_t(bmax) * N * NX, err)) ||
+        (rc = al(&a.ictl, size_t(bmax), err)) || (rc = al(&a.slot, 2 * size_t(bmax), err)) ||
+        (rc = al(&a.ctl, 1, err)))
+      return rc;
+    BENG_CHECK(hipMemset(a.slot, 0, sizeof(unsigned long long) * 2 * bmax));
+    return DLMPC_OK;
+  }
+
+  int precompute(const double *x0_dev, const double *alpha0_dev, int B, int max_iter, double eps,
+                 std::string &err) override {
+    if (B < 1 || B > args_.Bmax) {
+      err = "batch size out of range";
+      return DLMPC_EINVAL;
+    }
+    B_ = B;
+    args_.init_pass = 0;
+    hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, B), dim3(256), 0, stream_, args_, x0_dev, B,
+                       alpha0_dev ? 1 : 0, max_iter, eps);
+    BENG_CHECK(hipGetLastError());
+    if (alpha0_dev) {
+      hipLaunchKernelGGL(bwarm_alpha_kernel, dim3(1024), dim3(256), 0, stream_, args_, alpha0_dev, B);
+      BENG_CHECK(hipGetLastError());
+      BArgs ia = args_;
+      ia.init_pass = 1;
+      hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, ia);
+      BENG_CHECK(hipGetLastError());
+    }
+    return DLMPC_OK;
+  }
+
+  int export_alpha(double *alpha_dev, std::string &err) override {
+    hipLaunchKernelGGL(bexport_alpha_kernel, dim3(1024), dim3(256), 0, stream_, args_, alpha_dev, B_);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int iteration(std::string &err) override {
+    const int waves = (hs_->rs + 15) / 16;
+    hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(64 * waves), 0, stream_, args_);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, args_);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bdecide_kernel, dim3(1), dim3(64), 0, stream_, args_);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int output(double *u0_dev, std::string &err) override {
+    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, u0_dev);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  Ctl *ctl() override { return args_.ctl; }
+  BCtl *ictl() override { return args_.ictl; }
+  int bmax() const override { return args_.Bmax; }
+
+  ~BatchEngineT() override {
+    for (void *p : owned_) (void)hipFree(p);
+  }
+
+ private:
+  template <typename U>
+  int al(U **dst, size_t n, std::string &err) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(U);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+      return DLMPC_ENOMEM;
+    }
+    owned_.push_back(p);
+    *dst = static_cast<U *>(p);
+    return DLMPC_OK;
+  }
+  template <typename U, typename V>
+  int up(const std::vector<U> &src, V **dst, std::string &err) {
+    static_assert(sizeof(U) == sizeof(V), "upload type");
+    U *p = nullptr;
+    int rc = al(&p, src.size(), err);
+    if (rc) return rc;
+    if (!src.empty()) BENG_CHECK(hipMemcpy(p, src.data(), src.size() * sizeof(U), hipMemcpyHostToDevice));
+    *dst = reinterpret_cast<V *>(p);
+    return DLMPC_OK;
+  }
+
+  const HostSetup *hs_ = nullptr;
+  hipStream_t stream_ = nullptr;
+  BArgs args_{};
+  int B_ = 0;
+  std::vector<void *> owned_;
+};
+
+}  // namespace
+
+std::unique_ptr<BatchEngine> make_batch_engine(int nx) {
+  switch (nx) {
+    case 1: return std::make_unique<BatchEngineT<1>>();
+    case 2: return std::make_unique<BatchEngineT<2>>();
+    case 3: return std::make_unique<BatchEngineT<3>>();
+    case 4: return std::make_unique<BatchEngineT<4>>();
+    default: return nullptr;
+  }
+}
+
+}  // namespace dlmpc

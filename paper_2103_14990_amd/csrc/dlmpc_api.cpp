@@ -33,6 +33,12 @@ struct dlmpc_problem {
   hipEvent_t ev_ctl[2] = {nullptr, nullptr};
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
   double *d_x0 = nullptr, *d_u0 = nullptr, *d_phi = nullptr, *d_warm = nullptr;
+  // batched engine
+  std::unique_ptr<dlmpc::BatchEngine> beng;
+  hipGraph_t bgraph[kGraphs] = {};
+  hipGraphExec_t bgexec[kGraphs] = {};
+  double *d_bx0 = nullptr, *d_bu0 = nullptr;
+  dlmpc::BCtl *h_bctl = nullptr;
 };
 
 namespace {
@@ -57,9 +63,19 @@ void release_device(dlmpc_problem *p) {
   for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
     if (p->gexec[g]) (void)hipGraphExecDestroy(p->gexec[g]);
     if (p->graph[g]) (void)hipGraphDestroy(p->graph[g]);
+    if (p->bgexec[g]) (void)hipGraphExecDestroy(p->bgexec[g]);
+    if (p->bgraph[g]) (void)hipGraphDestroy(p->bgraph[g]);
     p->gexec[g] = nullptr;
     p->graph[g] = nullptr;
+    p->bgexec[g] = nullptr;
+    p->bgraph[g] = nullptr;
   }
+  if (p->h_bctl) (void)hipHostFree(p->h_bctl);
+  for (double *d : {p->d_bx0, p->d_bu0})
+    if (d) (void)hipFree(d);
+  p->beng.reset();
+  p->h_bctl = nullptr;
+  p->d_bx0 = p->d_bu0 = nullptr;
   for (hipEvent_t e : {p->ev_ctl[0], p->ev_ctl[1], p->ev_t0, p->ev_t1})
     if (e) (void)hipEventDestroy(e);
   if (p->h_ctl) (void)hipHostFree(p->h_ctl);
@@ -72,6 +88,7 @@ void release_device(dlmpc_problem *p) {
 }
 
 int choose_schedule(dlmpc_problem *p);
+int setup_batch(dlmpc_problem *p);
 
 int setup_device(dlmpc_problem *p) {
   const HostSetup &hs = p->hs;
@@ -116,20 +133,89 @@ int setup_device(dlmpc_problem *p) {
     API_HIP(hipGraphInstantiate(&p->gexec[g], p->graph[g], nullptr, nullptr, 0));
   }
   API_HIP(hipStreamSynchronize(p->stream));
+  if (p->opt.max_batch > 0) {
+    rc = setup_batch(p);
+    if (rc) return rc;
+  }
   return choose_schedule(p);
 }
 
-// Enqueues n iterations of the graph schedule as a sum of captured power-of-two graphs.
-int launch_iterations(dlmpc_problem *p, int n) {
+int setup_batch(dlmpc_problem *p) {
+  const HostSetup &hs = p->hs;
+  std::string err;
+  if (p->opt.precision != DLMPC_FP32) return fail(DLMPC_EINVAL, "the batched engine runs in FP32 precision");
+  p->beng = dlmpc::make_batch_engine(hs.nx);
+  if (!p->beng) return fail(DLMPC_EINVAL, "batched engine: nx must be 1..4");
+  int rc = p->beng->init(hs, p->opt.rho, p->opt.max_batch, p->stream, err);
+  if (rc) return fail(rc, err);
+  const int B = p->opt.max_batch;
+  API_HIP(hipMalloc(&p->d_bx0, sizeof(double) * size_t(B) * hs.N * hs.nx));
+  API_HIP(hipMalloc(&p->d_bu0, sizeof(double) * size_t(B) * hs.N * hs.nu));
+  API_HIP(hipHostMalloc(reinterpret_cast<void **>(&p->h_bctl), sizeof(dlmpc::BCtl) * B, hipHostMallocDefault));
+  for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
+    API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < (1 << g); ++i) {
+      rc = p->beng->iteration(err);
+      if (rc) {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(p->stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(rc, err);
+      }
+    }
+    API_HIP(hipStreamEndCapture(p->stream, &p->bgraph[g]));
+    API_HIP(hipGraphInstantiate(&p->bgexec[g], p->bgraph[g], nullptr, nullptr, 0));
+  }
+  API_HIP(hipStreamSynchronize(p->stream));
+  return DLMPC_OK;
+}
+
+// Enqueues n iterations as a sum of captured power-of-two iteration graphs.
+int launch_graphs(hipGraphExec_t *ex, hipStream_t s, int n) {
   constexpr int top = dlmpc_problem::kGraphs - 1;
   while (n >= (1 << top)) {
-    API_HIP(hipGraphLaunch(p->gexec[top], p->stream));
+    API_HIP(hipGraphLaunch(ex[top], s));
     n -= 1 << top;
   }
   for (int g = top - 1; g >= 0; --g)
-    if (n & (1 << g)) API_HIP(hipGraphLaunch(p->gexec[g], p->stream));
+    if (n & (1 << g)) API_HIP(hipGraphLaunch(ex[g], s));
   return DLMPC_OK;
 }
+
+int launch_iterations(dlmpc_problem *p, int n) { return launch_graphs(p->gexec, p->stream, n); }
+
+// Sizes the next chunk of iterations from the decay of the residual: least-squares slope of
+// log max(r_p, r_d) over the last (up to 4) host checks, extrapolated to eps.
+struct ChunkPredictor {
+  double hk[4] = {0, 0, 0, 0}, hr[4] = {0, 0, 0, 0};
+  int nh = 0;
+  int next(int iters, double rp, double rd, double eps) {
+    const double r = std::max(rp, rd);
+    if (!(r > 0.0) || !std::isfinite(r)) return 8;
+    for (int i = 3; i > 0; --i) {
+      hk[i] = hk[i - 1];
+      hr[i] = hr[i - 1];
+    }
+    hk[0] = iters;
+    hr[0] = std::log(r);
+    nh = std::min(nh + 1, 4);
+    if (nh < 2) return 8;
+    double mk = 0, mr = 0;
+    for (int i = 0; i < nh; ++i) {
+      mk += hk[i] / nh;
+      mr += hr[i] / nh;
+    }
+    double sxy = 0, sxx = 0;
+    for (int i = 0; i < nh; ++i) {
+      sxy += (hk[i] - mk) * (hr[i] - mr);
+      sxx += (hk[i] - mk) * (hk[i] - mk);
+    }
+    const double slope = sxx > 0 ? sxy / sxx : 0.0;
+    if (!(slope < -1e-9)) return 8;
+    const double need = (std::log(eps) - hr[0]) / slope;
+    return int(std::min(64.0, std::max(1.0, std::round(need))));
+  }
+};
 
 // Times n iterations of a schedule from x0 = (1, ..., 1) with the stop test disabled.
 int time_schedule(dlmpc_problem *p, int sched, int n, double *us_per_iter) {
@@ -208,11 +294,9 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     stopped = true;
   }
   // Graph schedule: launch a chunk of iterations, read the control block, and size the next
-  // chunk from the decay of the residual (least-squares slope of log max(r_p, r_d) over the
-  // last checks), so that few launches land after the device-side stop and few host checks
-  // are needed. With check_every > 0 the chunk is fixed.
-  double hk[4] = {0, 0, 0, 0}, hr[4] = {0, 0, 0, 0};
-  int nh = 0;
+  // chunk from the residual decay (ChunkPredictor), so that few launches land after the
+  // device-side stop and few host checks are needed. With check_every > 0 the chunk is fixed.
+  ChunkPredictor pred;
   int n = p->K;
   while (!stopped) {
     n = std::max(1, std::min(n, max_iter - launched));
@@ -230,36 +314,7 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     }
     if (launched >= max_iter) break;
     if (p->opt.check_every > 0) continue;
-    const double r = std::max(c.last_rp, c.last_rd);
-    if (!(r > 0.0) || !std::isfinite(r)) {
-      n = 8;
-      continue;
-    }
-    for (int i = 3; i > 0; --i) {
-      hk[i] = hk[i - 1];
-      hr[i] = hr[i - 1];
-    }
-    hk[0] = c.iters;
-    hr[0] = std::log(r);
-    nh = std::min(nh + 1, 4);
-    n = 8;
-    if (nh >= 2) {
-      double mk = 0, mr = 0;
-      for (int i = 0; i < nh; ++i) {
-        mk += hk[i] / nh;
-        mr += hr[i] / nh;
-      }
-      double sxy = 0, sxx = 0;
-      for (int i = 0; i < nh; ++i) {
-        sxy += (hk[i] - mk) * (hr[i] - mr);
-        sxx += (hk[i] - mk) * (hk[i] - mk);
-      }
-      const double slope = sxx > 0 ? sxy / sxx : 0.0;
-      if (slope < -1e-9) {
-        const double need = (std::log(p->opt.eps) - hr[0]) / slope;
-        n = int(std::min(64.0, std::max(1.0, std::round(need))));
-      }
-    }
+    n = pred.next(c.iters, c.last_rp, c.last_rd, p->opt.eps);
   }
   if (!stopped) return fail(DLMPC_EDEVICE, "iteration graph did not reach its stop condition");
   API_HIP(hipEventRecord(p->ev_t1, p->stream));
@@ -327,6 +382,7 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
   if (!(o.rho > 0.0) || !std::isfinite(o.rho) || !(o.eps > 0.0) || o.max_iter < 0 || o.check_every < 0)
     return fail(DLMPC_EINVAL, "options: need rho > 0, eps > 0, max_iter >= 0, check_every >= 0");
   if (o.precision != DLMPC_FP64 && o.precision != DLMPC_FP32) return fail(DLMPC_EINVAL, "unknown precision");
+  if (o.max_batch < 0 || o.max_batch > 64) return fail(DLMPC_EINVAL, "max_batch must be in 0..64");
   auto p = std::make_unique<dlmpc_problem>();
   p->opt = o;
   p->host_only = (o.flags & DLMPC_FLAG_HOST_ONLY) != 0;
@@ -476,6 +532,101 @@ int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, do
   if (rc) return fail(rc, err);
   for (int k = 0; k < nk; ++k) us_per_launch[k] = 1e3 * sum[k] / iters;
   return DLMPC_OK;
+}
+
+namespace {
+
+int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, dlmpc_stats *stats, double t0) {
+  std::string err;
+  const int max_iter = p->opt.max_iter;
+  int rc = p->beng->precompute(x0_dev, nullptr, B, max_iter, p->opt.eps, err);
+  if (rc) return fail(rc, err);
+  API_HIP(hipEventRecord(p->ev_t0, p->stream));
+  Ctl *d_ctl = p->beng->ctl();
+  ChunkPredictor pred;
+  int launched = 0, checks = 0, n = p->K;
+  bool stopped = false;
+  while (!stopped) {
+    n = std::max(1, std::min(n, max_iter - launched));
+    rc = launch_graphs(p->bgexec, p->stream, n);
+    if (rc) return rc;
+    launched += n;
+    ++checks;
+    API_HIP(hipMemcpyAsync(&p->h_ctl[1], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipEventRecord(p->ev_ctl[1], p->stream));
+    API_HIP(hipEventSynchronize(p->ev_ctl[1]));
+    const Ctl &c = p->h_ctl[1];
+    if (c.stop) {
+      stopped = true;
+      break;
+    }
+    if (launched >= max_iter) break;
+    n = p->opt.check_every > 0 ? p->K : pred.next(c.iters, c.last_rp, c.last_rd, p->opt.eps);
+  }
+  if (!stopped) return fail(DLMPC_EDEVICE, "batched iteration did not reach its stop condition");
+  API_HIP(hipEventRecord(p->ev_t1, p->stream));
+  rc = p->beng->output(u0_dev, err);
+  if (rc) return fail(rc, err);
+  API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * B, hipMemcpyDeviceToHost, p->stream));
+  API_HIP(hipStreamSynchronize(p->stream));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
+  bool all = true, numeric = false;
+  for (int b = 0; b < B; ++b) {
+    const dlmpc::BCtl &ic = p->h_bctl[b];
+    all = all && ic.converged;
+    numeric = numeric || ic.numeric;
+    if (stats) {
+      dlmpc_stats &st = stats[b];
+      st.iters = ic.iters;
+      st.converged = ic.converged;
+      st.r_primal = ic.last_rp;
+      st.r_dual = ic.last_rd;
+      st.objective = ic.objective;
+      st.t_iter_ms = ms;
+      st.graph_launches = checks;
+      st.schedule = 2;
+      st.t_solve_ms = now_ms() - t0;
+    }
+  }
+  if (numeric) return fail(DLMPC_ENUMERIC, "NaN/Inf in a batched ADMM iterate");
+  return all ? DLMPC_OK : DLMPC_ENOCONV;
+}
+
+int check_batch(dlmpc_problem *p, int32_t B) {
+  if (!p) return fail(DLMPC_EINVAL, "NULL problem");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  if (!p->beng) return fail(DLMPC_EINVAL, "problem was set up without max_batch");
+  if (B < 1 || B > p->beng->bmax()) return fail(DLMPC_EINVAL, "batch size out of range");
+  return DLMPC_OK;
+}
+
+}  // namespace
+
+int dlmpc_solve_batch(dlmpc_problem *p, int32_t B, const double *x0, double *u0, dlmpc_stats *stats) {
+  const double t0 = now_ms();
+  int rc = check_batch(p, B);
+  if (rc) return rc;
+  if (!x0) return fail(DLMPC_EINVAL, "NULL x0");
+  const HostSetup &h = p->hs;
+  const size_t nxs = size_t(B) * h.N * h.nx;
+  if (!finite_all(x0, nxs)) return fail(DLMPC_EINVAL, "x0 has a NaN/Inf entry");
+  API_HIP(hipSetDevice(p->opt.device));
+  API_HIP(hipMemcpyAsync(p->d_bx0, x0, nxs * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  rc = run_batch(p, B, p->d_bx0, p->d_bu0, stats, t0);
+  if (rc < 0) return rc;
+  if (u0) API_HIP(hipMemcpy(u0, p->d_bu0, size_t(B) * h.N * h.nu * sizeof(double), hipMemcpyDeviceToHost));
+  return rc;
+}
+
+int dlmpc_solve_batch_device(dlmpc_problem *p, int32_t B, const double *x0_dev, double *u0_dev,
+                             dlmpc_stats *stats) {
+  const double t0 = now_ms();
+  int rc = check_batch(p, B);
+  if (rc) return rc;
+  if (!x0_dev || !u0_dev) return fail(DLMPC_EINVAL, "NULL argument");
+  API_HIP(hipSetDevice(p->opt.device));
+  return run_batch(p, B, x0_dev, u0_dev, stats, t0);
 }
 
 void dlmpc_destroy(dlmpc_problem *p) {

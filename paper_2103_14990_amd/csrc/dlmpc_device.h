@@ -30,6 +30,9 @@ struct Ctl {
   // persistent schedule: grid barrier and per-iteration residual slots (ping-pong)
   unsigned bar_count, bar_gen, bar_fail, pad2;
   unsigned long long slot_rp[2], slot_rd[2];
+  // batched engine: instances of the current solve and its start (kernels captured in graphs
+  // read these here, not from their launch arguments)
+  int32_t batch, warm;
 };
 
 // Static work lists of the persistent schedule: block b runs Phi-comp for
@@ -94,5 +97,62 @@ class Engine {
 };
 
 std::unique_ptr<Engine> make_engine(int precision, int nx);
+
+// ----------------------------------------------------------------------------- batched engine
+// B instances of one network (distinct x0) iterated together in the compact form of Algorithm 2:
+// per instance only the Phi-comp row scalars alpha (current and previous iterate) and, per column
+// subsystem j, tau_j = N_j' beta and eta_j = N_j' alpha (beta = running sum of alpha), from which
+//   Psi[:,c] = o_c + x0_c N_j tau_j,  Lambda[:,c] = x0_c (I - N_j N_j') alpha   (on supp j),
+// so that both products of an iteration are GEMMs over the instances with the shared N_j.
+
+struct BCtl {  // per-instance control block
+  int32_t iters, stop, converged, numeric;
+  double last_rp, last_rd, objective;
+};
+
+struct BArgs {
+  int32_t N, nx, nu, T, rs, Bmax;
+  float rho;
+  const int64_t *tile_off, *rt_ptr, *rt_tile;
+  const int32_t *rt_col, *kdim, *tile_rsub;
+  const int64_t *koff;      // [N+1] offsets of the k-space vectors (multiples of 16)
+  const int64_t *ncm_off;   // [N+1] column-major copy: k16(j) columns of ld64(j) rows
+  const int64_t *nrm_off;   // [N+1] row-major copy: D(j) rows of k32(j) entries
+  const __bf16 *ncm_hi, *ncm_lo, *nrm_hi, *nrm_lo;
+  const float *off;         // o_c, column-major per subsystem (leading dim ld4)
+  const int64_t *off_ptr;
+  const float *w, *lb, *ub; // [N*rs]
+  const double *w64;
+  const double *onorm2;     // [N*nx] ||o_c||^2
+  float *alpha;             // [2][Bmax][N*rs] (iteration parity)
+  float *tau, *eta;         // [Bmax][Ktot]
+  float *xn, *nrm;          // [Bmax][N] ||x0_j||^2 and ||x_r||^2 of row subsystem m
+  float *bvec, *s;          // [Bmax][N*rs]
+  float *x0;                // [Bmax][N*nx]
+  BCtl *ictl;               // [Bmax]
+  unsigned long long *slot; // [Bmax][2] residual maxima of the current iteration (ordered bits)
+  Ctl *ctl;                 // shared: iteration count, all-stopped flag
+  int64_t ktot;
+  int32_t init_pass;        // 1 while bpsi_kernel computes eta = N' alpha of the warm start
+};
+
+class BatchEngine {
+ public:
+  virtual ~BatchEngine() = default;
+  virtual int init(const HostSetup &hs, double rho, int bmax, hipStream_t s, std::string &err) = 0;
+  // alpha0_dev: NULL (cold start) or [B][N*rs] row multipliers of a compact warm start
+  // (Psi^0[:,c] = o_c, Lambda^0[:,c] = x0_c (I - N_j N_j') alpha0 on supp j).
+  virtual int precompute(const double *x0_dev, const double *alpha0_dev, int B, int max_iter,
+                         double eps, std::string &err) = 0;
+  // Current row multipliers alpha of every instance, [B][N*rs] doubles.
+  virtual int export_alpha(double *alpha_dev, std::string &err) = 0;
+  virtual int iteration(std::string &err) = 0;  // capturable
+  virtual int output(double *u0_dev, std::string &err) = 0;
+  virtual Ctl *ctl() = 0;
+  virtual BCtl *ictl() = 0;
+  virtual int bmax() const = 0;
+};
+
+std::unique_ptr<BatchEngine> make_batch_engine(int nx);
 
 }  // namespace dlmpc

@@ -43,7 +43,7 @@ class Cost(C.Structure):
 class Options(C.Structure):
     _fields_ = [("rho", C.c_double), ("eps", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("flags", C.c_uint32)]
+                ("stream", C.c_void_p), ("flags", C.c_uint32), ("max_batch", C.c_int32)]
 
 
 class Warm(C.Structure):
@@ -80,6 +80,8 @@ EXPORTS = {
     "dlmpc_solve": (C.c_int, [C.c_void_p, _dp, C.POINTER(Warm), _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_time_kernels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, _dp]),
+    "dlmpc_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, C.POINTER(Stats)]),
+    "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_destroy": (None, [C.c_void_p]),
     "dlmpc_status_string": (C.c_char_p, [C.c_int]),
     "dlmpc_last_error": (C.c_char_p, []),
@@ -147,7 +149,7 @@ class Problem:
                  d: int, T: int, q_diag, r_diag, x_lo=None, x_hi=None, u_lo=None, u_hi=None,
                  rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500, precision: str = "fp64",
                  device: int = 0, stream: int | None = None, check_every: int = 0,
-                 host_only: bool = False, schedule: str = "auto"):
+                 host_only: bool = False, schedule: str = "auto", max_batch: int = 0):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -161,7 +163,7 @@ class Problem:
                     _ptr(keep["ul"]), _ptr(keep["uh"]))
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
-                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule])
+                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule], max_batch)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
             raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
@@ -223,6 +225,21 @@ class Problem:
                                                      C.c_void_p(phi_dev) if phi_dev else None,
                                                      C.byref(st)))
         return s, st.as_dict()
+
+    def solve_batch(self, x0s) -> tuple[int, np.ndarray, list[dict]]:
+        """x0s [B, N*nx] -> (status, u0 [B, N*nu], per-instance stats)."""
+        x0s = np.ascontiguousarray(x0s, dtype=np.float64)
+        B = x0s.shape[0]
+        u0 = np.zeros((B, self.n_sub * self.nu))
+        st = (Stats * B)()
+        s = self._check(self._lib.dlmpc_solve_batch(self._h, B, _ptr(x0s), _ptr(u0), st))
+        return s, u0, [x.as_dict() for x in st]
+
+    def solve_batch_device(self, B: int, x0_dev: int, u0_dev: int) -> tuple[int, list[dict]]:
+        st = (Stats * B)()
+        s = self._check(self._lib.dlmpc_solve_batch_device(self._h, B, C.c_void_p(x0_dev),
+                                                           C.c_void_p(u0_dev), st))
+        return s, [x.as_dict() for x in st]
 
     def time_kernels(self, x0_dev: int, iters: int) -> dict:
         """Mean microseconds per launch of each kernel of one iteration (no early stop)."""

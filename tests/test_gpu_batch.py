@@ -1,0 +1,126 @@
+"""Batched solves (many x0 on one network; compact iteration with split-bf16 matrix-core
+products) against the FP64 oracle, instance by instance, through the C ABI (needs a GPU).
+
+Bar (reduced precision): u(0) within 1e-4 and the objective within 1e-5 relative of the FP64
+oracle run with the same eps and stopping rule; the iteration count may differ by a few.
+"""
+import numpy as np
+import pytest
+
+from oracle import dlmpc_oracle as O
+from paper_2103_14990_amd import dlmpc
+from paper_2103_14990_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RHO, EPS, MAXIT = 5.0, 1e-4, 500
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def batch_problem(wl, max_batch=64, max_iter=MAXIT):
+    return dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=max_iter,
+                                      precision="fp32", max_batch=max_batch)
+
+
+def check_instances(pb, x0s, u0, stats, n_check=None, iter_slack=3):
+    idx = range(len(x0s)) if n_check is None else np.linspace(0, len(x0s) - 1, n_check).astype(int)
+    for i in idx:
+        ref = O.solve(pb, x0s[i], RHO, EPS, MAXIT)
+        e = rel(u0[i], ref.u0) if np.abs(ref.u0).max() > 0 else float(np.abs(u0[i]).max())
+        je = abs(stats[i]["objective"] - ref.J) / max(ref.J, 1e-300)
+        print(f"  instance {i}: iters {stats[i]['iters']} (oracle {ref.iters}) u0 rel {e:.2e} J rel {je:.2e}",
+              flush=True)
+        assert stats[i]["converged"] == int(ref.converged)
+        assert abs(stats[i]["iters"] - ref.iters) <= iter_slack
+        assert e < 1e-4
+        assert je < 1e-5 or ref.J == 0.0
+
+
+@pytest.mark.parametrize("B", [1, 13, 64])
+def test_grid8_batch_matches_oracle(B):
+    wl = W.workload("grid8")
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
+    pr = batch_problem(wl)
+    x0s = np.stack([wl.x0(2000 + i) for i in range(B)])
+    st, u0, stats = pr.solve_batch(x0s)
+    assert st == dlmpc.OK
+    check_instances(pb, x0s, u0, stats, n_check=min(B, 6))
+
+
+def test_chain10_batch_mixed_instances():
+    """Instances converging at different iterations (one is x0 = 0) freeze independently."""
+    wl = W.workload("chain10")
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
+    pr = batch_problem(wl, max_batch=16)
+    scales = [0.3, 0.6, 1.0, 1.5, 2.0, 1.0, 0.8]
+    x0s = np.stack([wl.x0(1 + i) * sc for i, sc in enumerate(scales)] + [np.zeros(20)])
+    st, u0, stats = pr.solve_batch(x0s)
+    check_instances(pb, x0s, u0, stats)
+    assert st == (dlmpc.OK if all(s["converged"] for s in stats) else dlmpc.ENOCONV)
+    assert len({s["iters"] for s in stats}) > 2
+    assert stats[-1]["iters"] == 3 and np.all(u0[-1] == 0.0)
+
+
+def test_batch_active_bounds():
+    """Box-constrained chain with active input bounds, batched."""
+    net = W.chain(10)
+    cost = W.box_cost(net, theta_max=0.8, u_max=0.3)
+    wl = W.Workload("chain10_tight", net, 1, 5, cost, sigma=0.4)
+    pb = O.setup_from_network(net, 1, 5, cost)
+    pr = batch_problem(wl, max_batch=8)
+    x0s = np.stack([wl.x0(s) for s in (9, 10, 3)])
+    st, u0, stats = pr.solve_batch(x0s)
+    check_instances(pb, x0s, u0, stats, iter_slack=25)
+    assert np.any(np.isclose(np.abs(u0), 0.3, atol=1e-6))
+
+
+def test_batch_not_converged_status():
+    wl = W.workload("chain10")
+    pr = batch_problem(wl, max_batch=4, max_iter=9)
+    st, u0, stats = pr.solve_batch(np.stack([wl.x0(1), wl.x0(2)]))
+    assert st == dlmpc.ENOCONV
+    assert all(s["iters"] == 9 and not s["converged"] for s in stats)
+
+
+def test_batch_device_entry_matches_host_entry():
+    import torch
+    wl = W.workload("grid8")
+    pr = batch_problem(wl, max_batch=8)
+    x0s = np.stack([wl.x0(3000 + i) for i in range(5)])
+    _, u0h, sh = pr.solve_batch(x0s)
+    xd = torch.tensor(x0s, dtype=torch.float64, device="cuda")
+    ud = torch.zeros((5, 64), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    st, sd = pr.solve_batch_device(5, xd.data_ptr(), ud.data_ptr())
+    assert st == dlmpc.OK
+    assert np.array_equal(ud.cpu().numpy(), u0h)
+    assert [s["iters"] for s in sd] == [s["iters"] for s in sh]
+
+
+def test_batch_matches_single_instance_fp32():
+    """Instance i of a batch and the same x0 solved alone agree (both FP32-tier paths)."""
+    wl = W.workload("grid16")
+    pr = batch_problem(wl, max_batch=16)
+    x0s = np.stack([wl.x0(4000 + i) for i in range(16)])
+    _, u0, stats = pr.solve_batch(x0s)
+    single = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                        precision="fp32")
+    for i in (0, 7, 15):
+        r = single.solve(x0s[i])
+        assert rel(u0[i], r.u0) < 2e-4
+        assert abs(stats[i]["iters"] - r.stats["iters"]) <= max(5, 0.05 * r.stats["iters"])
+
+
+def test_batch_argument_errors():
+    wl = W.workload("chain10")
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, precision="fp32")
+    with pytest.raises(dlmpc.DlmpcError):
+        pr.solve_batch(np.zeros((2, 20)))  # no batched engine
+    with pytest.raises(dlmpc.DlmpcError):
+        dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, precision="fp64", max_batch=4)
+    pb = batch_problem(wl, max_batch=4)
+    with pytest.raises(dlmpc.DlmpcError):
+        pb.solve_batch(np.zeros((5, 20)))

@@ -70,3 +70,23 @@ def test_full_size_properties(wl):
     assert np.all(np.abs(a.u0) <= 2.0 + 1e-6)
     assert np.array_equal(a.u0, b.u0) and np.array_equal(a.phi, b.phi)
     assert a.stats["r_primal"] <= wl.eps and a.stats["r_dual"] <= wl.eps
+
+
+def test_grid32_batch_matches_oracle():
+    """32x32 grid (d = 2, T = 10), 64 instances in one batched solve; the two instances with
+    stored oracle values are checked at the reduced-precision bar, the batch converges."""
+    gold = json.load(open(os.path.join(os.path.dirname(GOLDEN), "grid32.json")))
+    wl = W.workload("grid32")
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps,
+                                    max_iter=wl.max_iter, precision="fp32", max_batch=64)
+    seeds = [r["seed"] for r in gold["records"]] + [5000 + i for i in range(62)]
+    st, u0, stats = pr.solve_batch(np.stack([wl.x0(s) for s in seeds]))
+    assert st == dlmpc.OK
+    for i, rec in enumerate(gold["records"]):
+        ref = np.array(rec["u0"])
+        err = np.abs(u0[i] - ref).max() / np.abs(ref).max()
+        jerr = abs(stats[i]["objective"] - rec["J"]) / rec["J"]
+        print(f"  seed {rec['seed']}: iters {stats[i]['iters']} (oracle {rec['iters']}) u0 rel {err:.2e} "
+              f"J rel {jerr:.2e}", flush=True)
+        assert abs(stats[i]["iters"] - rec["iters"]) <= 5
+        assert err < 1e-4 and jerr < 1e-5
