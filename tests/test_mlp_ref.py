@@ -26,13 +26,29 @@ def test_backprop_matches_finite_differences():
     L, grads = M.loss_and_grads(params, X, Yt)
     flat, gflat = M.flatten(params), M.flatten(grads)
     h = 1e-6
-    for idx in rng.choice(flat.size, 40, replace=False):
+    offs = np.cumsum([0] + [int(np.prod(s)) for s in M.shapes(G, IN, H, OUT)])
+    picks = np.concatenate([rng.choice(np.arange(a, b), 8, replace=False) for a, b in zip(offs[:-1], offs[1:])])
+    for idx in picks:  # eight entries of every parameter block
         p = flat.copy()
         p[idx] += h
         lp, _ = M.loss_and_grads(M.unflatten(p, G, IN, H, OUT), X, Yt)
         p[idx] -= 2 * h
         lm, _ = M.loss_and_grads(M.unflatten(p, G, IN, H, OUT), X, Yt)
         assert abs((lp - lm) / (2 * h) - gflat[idx]) < 1e-7 * max(1.0, abs(gflat[idx]))
+
+
+def test_skip_path_is_linear_map():
+    """With zero hidden weights and biases the hidden activations are gelu(0) = 0, so the network
+    is the affine map x -> x W3[H:] + b3 of its input."""
+    rng = np.random.default_rng(1)
+    G, S, IN, H, OUT = 2, 7, 5, 4, 3
+    W1, b1, W2, b2 = (np.zeros(s) for s in M.shapes(G, IN, H, OUT)[:4])
+    W3 = rng.standard_normal((G, H + IN, OUT))
+    b3 = rng.standard_normal((G, OUT))
+    X = rng.standard_normal((G, S, IN))
+    Y, _ = M.forward([W1, b1, W2, b2, W3, b3], X)
+    for g in range(G):
+        assert np.allclose(Y[g], X[g] @ W3[g, H:] + b3[g], rtol=1e-14, atol=1e-14)
 
 
 def test_adam_step_by_hand():
