@@ -96,6 +96,7 @@ typedef struct {
   uint32_t flags;      /* DLMPC_FLAG_* */
   int32_t max_batch;   /* 0, or 1..64: also set up the batched engine for up to this many x0
                           per dlmpc_solve_batch call (FP32 precision only) */
+  int32_t warm_cg_iters; /* CG steps of the trajectory warm start (0: 16) */
 } dlmpc_options;
 
 /* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
@@ -115,7 +116,11 @@ typedef struct {
   double t_solve_ms;    /* host wall time of the solve call */
   double t_iter_ms;     /* device time of the iteration phase (HIP events) */
   int32_t graph_launches; /* kernel-graph launches (graph schedule) or 1 (persistent) */
-  int32_t schedule;       /* 0 = graph, 1 = persistent */
+  int32_t schedule;       /* 0 = graph, 1 = persistent, 2 = batched */
+  int32_t start;          /* initial iterate: one of DLMPC_START_* */
+  int32_t fell_back;      /* 1 if the warm-started run did not converge and the instance was
+                             solved again from the cold start (iters then counts both runs) */
+  double t_warm_ms;       /* device time of the warm-start network inference (learned start) */
 } dlmpc_stats;
 
 typedef struct {
@@ -198,6 +203,75 @@ int dlmpc_solve_batch(struct dlmpc_problem *p, int32_t B, const double *x0, doub
                       dlmpc_stats *stats);
 int dlmpc_solve_batch_device(struct dlmpc_problem *p, int32_t B, const double *x0_dev, double *u0_dev,
                              dlmpc_stats *stats);
+
+/* Initial iterate of a batched solve (dlmpc_solve_batch_ex). */
+#define DLMPC_START_COLD 0       /* Psi^0 = Lambda^0 = 0 (Algorithm 2 as printed) */
+#define DLMPC_START_ALPHA 1      /* compact start from given row multipliers */
+#define DLMPC_START_TRAJECTORY 2 /* start from a given input trajectory */
+#define DLMPC_START_LEARNED 3    /* input trajectory predicted by the warm-start network */
+#define DLMPC_START_STATE 4      /* (dlmpc_solve) Psi^0, Lambda^0 given in canonical CSR order */
+
+/* Batched solve with a choice of initial iterate (the better initial point that Section V lists
+ * as future work). Device buffers on the problem's device: x0_dev [B][N*nx], u0_dev [B][N*nu].
+ * Vectors over the R = N*rs rows of Phi (rs = nx*T + nu*(T-1)) are [B][R] in the library's
+ * subsystem-major order: row l of subsystem g is entry g*rs + l, rows x_0..x_{T-1} (nx each)
+ * then u_0..u_{T-2} (nu each).
+ *  - DLMPC_START_ALPHA: start_dev = alpha0 [B][R]; Psi^0[:,c] = o_c and
+ *    Lambda^0[:,c] = x0_c (I - N_j N_j') alpha0 on the support of column c (j = its subsystem).
+ *  - DLMPC_START_TRAJECTORY: start_dev = y0 [B][R], of which only the input rows are read.
+ *    The state rows are simulated from x0 (y = x0, A y + B u, ...), then warm_cg_iters
+ *    conjugate-gradient steps from zero on M beta = y - b with M = sum_j ||x0_j||^2 N_j N_j'
+ *    (lifted from j's support) and b = sum_c x0_c o_c give Psi^0[:,c] = o_c + x0_c N_j N_j' beta
+ *    (feasible and local, trajectory close to y), and alpha = -2 w y / rho gives
+ *    Lambda^0[:,c] = x0_c (I - N_j N_j') alpha.
+ *  - DLMPC_START_LEARNED: as TRAJECTORY with the input rows predicted by the problem's
+ *    warm-start network (dlmpc_ws_init / dlmpc_warmstart_load); start_dev is ignored.
+ * Every start is a valid initial point of Algorithm 2 and each instance stops on the same eps
+ * rule. Any warm-started instance that does not converge within max_iter (or meets a NaN/Inf)
+ * is solved again from the cold start (stats fell_back = 1, iters counts both runs).
+ * y_out_dev [B][R] (or NULL) receives each instance's trajectory Phi x0 at its stopping iterate
+ * (training targets of the warm-start network), alpha_out_dev [B][R] (or NULL) its Phi-comp row
+ * multipliers. Returns as dlmpc_solve_batch; stats t_warm_ms is the device time of the start
+ * construction (network inference, simulation, CG). */
+int dlmpc_solve_batch_ex(struct dlmpc_problem *p, int32_t B, const double *x0_dev, double *u0_dev,
+                         int32_t start, const double *start_dev, double *y_out_dev,
+                         double *alpha_out_dev, dlmpc_stats *stats);
+
+/* ---- Learned warm start: one network per subsystem g (separate FP32 weights), input the x0
+ * entries of the subsystems within d hops of g (ascending subsystem order, each nx entries,
+ * zero-padded to IN = p_max*nx) divided by x_scale; two GELU hidden layers of width `hidden`;
+ * the output layer sees [h2, x]; output = g's input rows u_0..u_{T-2} (OUT = nu*(T-1) values)
+ * divided by y_scale. Parameter layout (flat FP32, this order, row-major): W1 [N][IN][H],
+ * b1 [N][H], W2 [N][H][H], b2 [N][H], W3 [N][H+IN][OUT], b3 [N][OUT]. Training minimises the
+ * mean squared error over subsystems, samples and outputs (in units of y_scale) with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8); all products run on the matrix cores (bf16 hi/lo split
+ * operands, FP32 accumulation). Trajectories are [S][R] as for dlmpc_solve_batch_ex. Needs a
+ * device problem. */
+
+/* Create (or re-create) the network with seeded initial weights. max_samples bounds S below. */
+int dlmpc_ws_init(struct dlmpc_problem *p, int32_t hidden, int32_t max_samples, uint64_t seed,
+                  double x_scale, double y_scale);
+/* Sizes: IN, hidden, OUT and the parameter count (any pointer may be NULL). */
+int dlmpc_ws_shape(const struct dlmpc_problem *p, int32_t *in, int32_t *hidden, int32_t *out,
+                   int64_t *n_params);
+/* Copy the parameters to host get [n_params] (if non-NULL), then from host set (if non-NULL). */
+int dlmpc_ws_params(struct dlmpc_problem *p, float *get, const float *set);
+/* Loss (mean squared error in scaled units) and its gradient for S samples: x0_dev [S][N*nx],
+ * y_dev [S][R] target trajectories (input rows read; device). grad [n_params] host or NULL.
+ * Weights unchanged. */
+int dlmpc_ws_loss_grad(struct dlmpc_problem *p, int32_t S, const double *x0_dev,
+                       const double *y_dev, double *loss, float *grad);
+/* One Adam step on S samples (loss before the step returned in *loss if non-NULL). */
+int dlmpc_ws_train_step(struct dlmpc_problem *p, int32_t S, const double *x0_dev,
+                        const double *y_dev, double lr, double *loss);
+/* Predicted input rows written into y_dev [S][R] (device; other rows untouched) for
+ * S <= max_samples inputs. */
+int dlmpc_ws_predict(struct dlmpc_problem *p, int32_t S, const double *x0_dev, double *y_dev);
+/* Weights file: int32 {tag, N, IN, hidden, OUT, version}, double {x_scale, y_scale}, FP32
+ * parameters. Load creates the network if needed (max_samples = max_batch, at least 1) and
+ * fails with DLMPC_EINVAL if the shape does not match this problem. */
+int dlmpc_ws_save(struct dlmpc_problem *p, const char *path);
+int dlmpc_warmstart_load(struct dlmpc_problem *p, const char *path);
 
 void dlmpc_destroy(struct dlmpc_problem *p);
 const char *dlmpc_status_string(int status);

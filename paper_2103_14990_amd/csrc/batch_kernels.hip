@@ -168,12 +168,13 @@ __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
   const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, mt = tid >> 6;
   const int rs = a.rs, B = a.ctl->batch;
   const bool warm = a.ctl->warm != 0;
+  const bool cgm = a.phi_mode != 0;  // set-up pass: q = sum_j ||x0_j||^2 N_j eta_j
   const int it = a.ctl->iters + 1;
   const float coef = warm ? 1.f : (it == 1 ? 0.f : (it == 2 ? 2.f : 1.f));
   f32x4 acc[kNT];
 #pragma unroll
   for (int nt = 0; nt < kNT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (warm || it >= 3) {  // from a cold start tau = eta = 0 before the third iteration
+  if (cgm || warm || it >= 3) {  // from a cold start tau = eta = 0 before the third iteration
     const int row = mt * 16 + (lane & 15);
     const bool rowok = row < rs;
     for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
@@ -199,8 +200,13 @@ __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
             const float4 t1 = *reinterpret_cast<const float4 *>(a.tau + kb + 4);
             const float4 e0 = *reinterpret_cast<const float4 *>(a.eta + kb);
             const float4 e1 = *reinterpret_cast<const float4 *>(a.eta + kb + 4);
-            w[0] = xj * (t0.x + e0.x); w[1] = xj * (t0.y + e0.y); w[2] = xj * (t0.z + e0.z); w[3] = xj * (t0.w + e0.w);
-            w[4] = xj * (t1.x + e1.x); w[5] = xj * (t1.y + e1.y); w[6] = xj * (t1.z + e1.z); w[7] = xj * (t1.w + e1.w);
+            if (cgm) {
+              w[0] = xj * e0.x; w[1] = xj * e0.y; w[2] = xj * e0.z; w[3] = xj * e0.w;
+              w[4] = xj * e1.x; w[5] = xj * e1.y; w[6] = xj * e1.z; w[7] = xj * e1.w;
+            } else {
+              w[0] = xj * (t0.x + e0.x); w[1] = xj * (t0.y + e0.y); w[2] = xj * (t0.z + e0.z); w[3] = xj * (t0.w + e0.w);
+              w[4] = xj * (t1.x + e1.x); w[5] = xj * (t1.y + e1.y); w[6] = xj * (t1.z + e1.z); w[7] = xj * (t1.w + e1.w);
+            }
           } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e) w[e] = 0.f;
@@ -218,6 +224,13 @@ __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) Ct[mt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[nt][e];
   __syncthreads();
+  if (cgm) {
+    for (int idx = tid; idx < rs * B; idx += blockDim.x) {
+      const int l = idx / B, b = idx - l * B;
+      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = Ct[l][b];
+    }
+    return;
+  }
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
   const int cur = it & 1, prev = cur ^ 1;
   for (int idx = tid; idx < rs * B; idx += blockDim.x) {
@@ -266,8 +279,9 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
   const bool initp = a.init_pass != 0;
   const bool cold2 = !warm && it == 2;
-  // the warm-start pass reads alpha^0, stored where iteration 1 reads the previous iterate
-  const int cur = initp ? 0 : (it & 1), prev = cur ^ 1;
+  const int cur = it & 1, prev = cur ^ 1;
+  // a set-up pass stages the row vectors src; the iteration stages the current alpha
+  const float *stage_src = initp ? a.src : a.alpha + cur * plane;
   const int sb = tid >> 3, sub = tid & 7;  // staging: instance sb, rows 8 sub .. 8 sub + 7
 
   if (!warm && it == 1 && !initp) {  // alpha^1 = 0: Psi^1 = o, residuals ||o_c||, eta stays 0
@@ -300,9 +314,11 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
         const int ta = rr / rs, l = rr - ta * rs;
         const int mm = a.tile_rsub[tb + ta];
         const int64_t idx = int64_t(sb) * a.N * rs + int64_t(mm) * rs + l;
-        an = a.alpha[cur * plane + idx];
-        const float ap = a.alpha[prev * plane + idx];
-        dl2 += double(an - ap) * double(an - ap);
+        an = stage_src[idx];
+        if (!initp) {
+          const float ap = a.alpha[prev * plane + idx];
+          dl2 += double(an - ap) * double(an - ap);
+        }
         if (cold2) {
 #pragma unroll
           for (int c = 0; c < NX; ++c) od[c] += double(an) * double(a.off[a.off_ptr[j] + int64_t(c) * ld4 + rr]);
@@ -357,14 +373,19 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
         if (i >= k) continue;
         const int64_t ki = int64_t(b) * a.ktot + a.koff[j] + i;
         const float en = acc[t][nt][e];
+        if (initp) {
+          a.dst_k[ki] = en;
+          continue;
+        }
         const float eo = a.eta[ki];
         a.eta[ki] = en;
-        if (!initp) a.tau[ki] += en;
+        a.tau[ki] += en;
         e2[nt] += double(en) * double(en);
         d2[nt] += double(en - eo) * double(en - eo);
       }
     }
   }
+  if (initp) return;  // set-up pass: the k-space vectors only
 #pragma unroll
   for (int nt = 0; nt < kNT; ++nt) {  // lanes l, l^16, l^32, l^48 share an instance
     e2[nt] += __shfl_xor(e2[nt], 16, 64);
@@ -376,7 +397,6 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       red_d[wave][nt * 16 + lane] = d2[nt];
     }
   }
-  if (initp) return;  // warm-start pass: eta only, no residuals
   red_dl[sb][sub] = dl2;
 #pragma unroll
   for (int c = 0; c < NX; ++c) red_od[sb][sub][c] = od[c];
@@ -478,6 +498,115 @@ __global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0) {
   }
 }
 
+// ------------------------------------------------------------------ trajectory warm start
+
+// Input rows of y0 (FP64, [B][N*rs]) into yhat.
+__global__ __launch_bounds__(256) void btraj_load_kernel(BArgs a, const double *y0, int B) {
+  const int ux = a.nx * a.T, nur = a.rs - ux;
+  const int64_t n = int64_t(B) * a.N * nur;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int64_t row = i / nur;  // b * N + g
+    const int64_t o = row * a.rs + ux + (i - row * nur);
+    a.yhat[o] = float(y0[o]);
+  }
+}
+
+// State rows of yhat: x_0 = x0, x_{t+1} = sum_j A_ij x_j(t) + B_i u_i(t), one block per
+// instance, one time step per barrier interval.
+template <int NX>
+__global__ __launch_bounds__(256) void bsim_kernel(BArgs a) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int rs = a.rs, nu = a.nu, N = a.N;
+  float *y = a.yhat + int64_t(b) * N * rs;
+  const float *x0 = a.x0 + int64_t(b) * N * NX;
+  for (int i = tid; i < N; i += 256)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) y[int64_t(i) * rs + c] = x0[i * NX + c];
+  __syncthreads();
+  for (int t = 0; t + 1 < a.T; ++t) {
+    for (int i = tid; i < N; i += 256) {
+      float v[NX];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v[c] = 0.f;
+      for (int64_t q = a.a_rowptr[i]; q < a.a_rowptr[i + 1]; ++q) {
+        const float *blk = a.a_blk + q * NX * NX;
+        const float *xj = y + int64_t(a.a_colidx[q]) * rs + t * NX;
+#pragma unroll
+        for (int c = 0; c < NX; ++c)
+#pragma unroll
+          for (int c2 = 0; c2 < NX; ++c2) v[c] += blk[c * NX + c2] * xj[c2];
+      }
+      const float *u = y + int64_t(i) * rs + NX * a.T + t * nu;
+      const float *bb = a.b_blk + int64_t(i) * NX * nu;
+      for (int k = 0; k < nu; ++k)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) v[c] += bb[c * nu + k] * u[k];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) y[int64_t(i) * rs + (t + 1) * NX + c] = v[c];
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double block_sum1024(double v, double *red) {
+  v = wsum(v);
+  __syncthreads();  // red may still be read by the previous call
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) s += red[w];
+  return s;
+}
+
+// r = yhat - b, p = r, x = 0, rr = r'r; alpha^0 = -2 w yhat / rho into the previous plane.
+__global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a) {
+  __shared__ double red[16];
+  const int b = blockIdx.x;
+  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < ny; i += 1024) {
+    const float y = a.yhat[o + i];
+    const float r = y - a.bvec[o + i];
+    a.cg_r[o + i] = r;
+    a.cg_p[o + i] = r;
+    a.cg_x[o + i] = 0.f;
+    a.alpha[o + i] = -2.f * a.w[i] * y / a.rho;
+    acc += double(r) * double(r);
+  }
+  acc = block_sum1024(acc, red);
+  if (threadIdx.x == 0) a.cg_rr[b] = acc;
+}
+
+// One CG step per instance after cg_q = M cg_p.
+__global__ __launch_bounds__(1024) void bcg_step_kernel(BArgs a) {
+  __shared__ double red[16];
+  const int b = blockIdx.x;
+  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
+  const double rr = a.cg_rr[b];
+  double pq = 0.0;
+  for (int64_t i = threadIdx.x; i < ny; i += 1024) pq += double(a.cg_p[o + i]) * double(a.cg_q[o + i]);
+  pq = block_sum1024(pq, red);
+  if (!(rr > 0.0) || !(pq > 0.0)) return;  // converged (or breakdown): keep x
+  const float step = float(rr / pq);
+  double rn = 0.0;
+  for (int64_t i = threadIdx.x; i < ny; i += 1024) {
+    a.cg_x[o + i] += step * a.cg_p[o + i];
+    const float r = a.cg_r[o + i] - step * a.cg_q[o + i];
+    a.cg_r[o + i] = r;
+    rn += double(r) * double(r);
+  }
+  rn = block_sum1024(rn, red);
+  const float g = float(rn / rr);
+  for (int64_t i = threadIdx.x; i < ny; i += 1024) a.cg_p[o + i] = a.cg_r[o + i] + g * a.cg_p[o + i];
+  if (threadIdx.x == 0) a.cg_rr[b] = rn;
+}
+
+__global__ __launch_bounds__(256) void bexport_y_kernel(BArgs a, double *out, int B) {
+  const int64_t n = int64_t(B) * a.N * a.rs;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) out[i] = double(a.s[i]);
+}
+
 // ------------------------------------------------------------------ engine
 
 #define BENG_CHECK(expr)                                                  \
@@ -572,29 +701,81 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&a.ictl, size_t(bmax), err)) || (rc = al(&a.slot, 2 * size_t(bmax), err)) ||
         (rc = al(&a.ctl, 1, err)))
       return rc;
+    // trajectory warm start: vectors and the plant in FP32
+    if ((rc = al(&a.yhat, size_t(bmax) * ny, err)) || (rc = al(&a.cg_x, size_t(bmax) * ny, err)) ||
+        (rc = al(&a.cg_r, size_t(bmax) * ny, err)) || (rc = al(&a.cg_p, size_t(bmax) * ny, err)) ||
+        (rc = al(&a.cg_q, size_t(bmax) * ny, err)) || (rc = al(&a.cg_rr, size_t(bmax), err)))
+      return rc;
+    std::vector<float> ablk(hs.a_blocks.begin(), hs.a_blocks.end()), bblk(hs.b_blocks.begin(), hs.b_blocks.end());
+    if ((rc = up(hs.a_rowptr, &a.a_rowptr, err)) || (rc = up(hs.a_colidx, &a.a_colidx, err)) ||
+        (rc = up(ablk, &a.a_blk, err)) || (rc = up(bblk, &a.b_blk, err)))
+      return rc;
+    a.init_pass = 0;
+    a.phi_mode = 0;
+    a.src = nullptr;
+    a.dst_k = nullptr;
     BENG_CHECK(hipMemset(a.slot, 0, sizeof(unsigned long long) * 2 * bmax));
     return DLMPC_OK;
   }
 
-  int precompute(const double *x0_dev, const double *alpha0_dev, int B, int max_iter, double eps,
-                 std::string &err) override {
+  int precompute(const double *x0_dev, int B, int max_iter, double eps, int warm, std::string &err) override {
     if (B < 1 || B > args_.Bmax) {
       err = "batch size out of range";
       return DLMPC_EINVAL;
     }
     B_ = B;
-    args_.init_pass = 0;
     hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, B), dim3(256), 0, stream_, args_, x0_dev, B,
-                       alpha0_dev ? 1 : 0, max_iter, eps);
+                       warm ? 1 : 0, max_iter, eps);
     BENG_CHECK(hipGetLastError());
-    if (alpha0_dev) {
-      hipLaunchKernelGGL(bwarm_alpha_kernel, dim3(1024), dim3(256), 0, stream_, args_, alpha0_dev, B);
-      BENG_CHECK(hipGetLastError());
-      BArgs ia = args_;
-      ia.init_pass = 1;
-      hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, ia);
+    return DLMPC_OK;
+  }
+
+  // dst_k = N_j' src for every column subsystem j and instance
+  int project_t(const float *src, float *dst_k, std::string &err) {
+    BArgs ia = args_;
+    ia.init_pass = 1;
+    ia.src = src;
+    ia.dst_k = dst_k;
+    hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, ia);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int start_alpha(const double *alpha0_dev, std::string &err) override {
+    hipLaunchKernelGGL(bwarm_alpha_kernel, dim3(1024), dim3(256), 0, stream_, args_, alpha0_dev, B_);
+    BENG_CHECK(hipGetLastError());
+    return project_t(args_.alpha, args_.eta, err);  // plane 0: the previous iterate of iteration 1
+  }
+
+  int start_trajectory(const double *y0_dev, int cg_iters, std::string &err) override {
+    if (y0_dev) {
+      hipLaunchKernelGGL(btraj_load_kernel, dim3(1024), dim3(256), 0, stream_, args_, y0_dev, B_);
       BENG_CHECK(hipGetLastError());
     }
+    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bcg_init_kernel, dim3(B_), dim3(1024), 0, stream_, args_);
+    BENG_CHECK(hipGetLastError());
+    BArgs qa = args_;
+    qa.phi_mode = 1;
+    const int waves = (hs_->rs + 15) / 16;
+    int rc;
+    for (int k = 0; k < cg_iters; ++k) {
+      if ((rc = project_t(args_.cg_p, args_.eta, err))) return rc;  // eta = N' p
+      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(64 * waves), 0, stream_, qa);  // q = M p
+      BENG_CHECK(hipGetLastError());
+      hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_);
+      BENG_CHECK(hipGetLastError());
+    }
+    if ((rc = project_t(args_.cg_x, args_.tau, err))) return rc;  // tau = N' beta
+    return project_t(args_.alpha, args_.eta, err);                 // eta = N' alpha^0
+  }
+
+  float *yhat() override { return args_.yhat; }
+
+  int export_y(double *y_dev, std::string &err) override {
+    hipLaunchKernelGGL(bexport_y_kernel, dim3(1024), dim3(256), 0, stream_, args_, y_dev, B_);
+    BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
 

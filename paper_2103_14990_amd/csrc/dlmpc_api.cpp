@@ -39,6 +39,11 @@ struct dlmpc_problem {
   hipGraphExec_t bgexec[kGraphs] = {};
   double *d_bx0 = nullptr, *d_bu0 = nullptr;
   dlmpc::BCtl *h_bctl = nullptr;
+  // learned warm start: network, predicted multipliers [Bmax][R], cold re-solve staging
+  std::unique_ptr<dlmpc::WarmStart> ws;
+  double *d_fx0 = nullptr, *d_fu0 = nullptr, *d_falpha = nullptr, *d_fy = nullptr;
+  int cg_iters = 16;
+  hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
 };
 
 namespace {
@@ -71,8 +76,13 @@ void release_device(dlmpc_problem *p) {
     p->bgraph[g] = nullptr;
   }
   if (p->h_bctl) (void)hipHostFree(p->h_bctl);
-  for (double *d : {p->d_bx0, p->d_bu0})
+  for (double *d : {p->d_bx0, p->d_bu0, p->d_fx0, p->d_fu0, p->d_falpha, p->d_fy})
     if (d) (void)hipFree(d);
+  p->d_fx0 = p->d_fu0 = p->d_falpha = p->d_fy = nullptr;
+  for (hipEvent_t e : {p->ev_w0, p->ev_w1})
+    if (e) (void)hipEventDestroy(e);
+  p->ev_w0 = p->ev_w1 = nullptr;
+  p->ws.reset();
   p->beng.reset();
   p->h_bctl = nullptr;
   p->d_bx0 = p->d_bu0 = nullptr;
@@ -152,6 +162,14 @@ int setup_batch(dlmpc_problem *p) {
   API_HIP(hipMalloc(&p->d_bx0, sizeof(double) * size_t(B) * hs.N * hs.nx));
   API_HIP(hipMalloc(&p->d_bu0, sizeof(double) * size_t(B) * hs.N * hs.nu));
   API_HIP(hipHostMalloc(reinterpret_cast<void **>(&p->h_bctl), sizeof(dlmpc::BCtl) * B, hipHostMallocDefault));
+  const size_t R = size_t(hs.N) * hs.rs;
+  API_HIP(hipMalloc(&p->d_fy, sizeof(double) * size_t(B) * R));
+  API_HIP(hipMalloc(&p->d_falpha, sizeof(double) * size_t(B) * R));
+  p->cg_iters = p->opt.warm_cg_iters > 0 ? p->opt.warm_cg_iters : 16;
+  API_HIP(hipMalloc(&p->d_fx0, sizeof(double) * size_t(B) * hs.N * hs.nx));
+  API_HIP(hipMalloc(&p->d_fu0, sizeof(double) * size_t(B) * hs.N * hs.nu));
+  API_HIP(hipEventCreate(&p->ev_w0));
+  API_HIP(hipEventCreate(&p->ev_w1));
   for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
     API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < (1 << g); ++i) {
@@ -276,6 +294,12 @@ bool finite_all(const double *v, size_t n) {
   return true;
 }
 
+bool finite_all(const float *v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
 // The solve loop shared by the host- and device-buffer entry points. x0_dev, u0_dev on device.
 int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const double *wlam,
               double *u0_dev, double *phi_dev, dlmpc_stats *stats, double t_host0_ms) {
@@ -338,6 +362,9 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     stats->t_iter_ms = ms;
     stats->graph_launches = launches;  // host checks (graph schedule) or 1 (persistent)
     stats->schedule = p->sched;
+    stats->start = wpsi ? DLMPC_START_STATE : DLMPC_START_COLD;
+    stats->fell_back = 0;
+    stats->t_warm_ms = 0.0;
     const double t_now = std::chrono::duration<double, std::milli>(
                              std::chrono::steady_clock::now().time_since_epoch()).count();
     stats->t_solve_ms = t_now - t_host0_ms;
@@ -536,11 +563,33 @@ int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, do
 
 namespace {
 
-int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, dlmpc_stats *stats, double t0) {
+// One batched run from the given start. Per-instance control blocks land in p->h_bctl;
+// y_out_dev / alpha_out_dev (or NULL) get the stopping trajectories and multipliers.
+// *t_warm_ms is the device time of the start construction. Returns DLMPC_OK or a negative
+// status (per-instance outcomes are left to the caller).
+int run_batch_once(dlmpc_problem *p, int B, const double *x0_dev, int start, const double *start_dev,
+                   double *u0_dev, double *y_out_dev, double *alpha_out_dev, float *t_iter_ms, float *t_warm_ms,
+                   int *checks_out) {
   std::string err;
   const int max_iter = p->opt.max_iter;
-  int rc = p->beng->precompute(x0_dev, nullptr, B, max_iter, p->opt.eps, err);
+  const HostSetup &h = p->hs;
+  int rc = p->beng->precompute(x0_dev, B, max_iter, p->opt.eps, start != DLMPC_START_COLD ? 1 : 0, err);
   if (rc) return fail(rc, err);
+  API_HIP(hipEventRecord(p->ev_w0, p->stream));
+  if (start == DLMPC_START_ALPHA) {
+    rc = p->beng->start_alpha(start_dev, err);
+  } else if (start == DLMPC_START_TRAJECTORY) {
+    rc = p->beng->start_trajectory(start_dev, p->cg_iters, err);
+  } else if (start == DLMPC_START_LEARNED) {
+    const size_t nxs = size_t(h.N) * h.nx, R = size_t(h.N) * h.rs;
+    for (int s0 = 0; s0 < B && !rc; s0 += p->ws->Smax) {
+      const int S = std::min(p->ws->Smax, B - s0);
+      rc = p->ws->predict(S, x0_dev + s0 * nxs, p->beng->yhat() + s0 * R, err);
+    }
+    if (!rc) rc = p->beng->start_trajectory(nullptr, p->cg_iters, err);
+  }
+  if (rc) return fail(rc, err);
+  API_HIP(hipEventRecord(p->ev_w1, p->stream));
   API_HIP(hipEventRecord(p->ev_t0, p->stream));
   Ctl *d_ctl = p->beng->ctl();
   ChunkPredictor pred;
@@ -566,27 +615,89 @@ int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, dlm
   if (!stopped) return fail(DLMPC_EDEVICE, "batched iteration did not reach its stop condition");
   API_HIP(hipEventRecord(p->ev_t1, p->stream));
   rc = p->beng->output(u0_dev, err);
+  if (!rc && alpha_out_dev) rc = p->beng->export_alpha(alpha_out_dev, err);
+  if (!rc && y_out_dev) rc = p->beng->export_y(y_out_dev, err);
   if (rc) return fail(rc, err);
   API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * B, hipMemcpyDeviceToHost, p->stream));
   API_HIP(hipStreamSynchronize(p->stream));
-  float ms = 0.f;
+  float ms = 0.f, mw = 0.f;
   (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
+  (void)hipEventElapsedTime(&mw, p->ev_w0, p->ev_w1);
+  *t_iter_ms = ms;
+  *t_warm_ms = start == DLMPC_START_COLD ? 0.f : mw;
+  *checks_out = checks;
+  return DLMPC_OK;
+}
+
+void fill_stats(dlmpc_stats &st, const dlmpc::BCtl &ic, float ms, int checks, int start, double t0) {
+  st.iters = ic.iters;
+  st.converged = ic.converged;
+  st.r_primal = ic.last_rp;
+  st.r_dual = ic.last_rd;
+  st.objective = ic.objective;
+  st.t_iter_ms = ms;
+  st.graph_launches = checks;
+  st.schedule = 2;
+  st.start = start;
+  st.fell_back = 0;
+  st.t_warm_ms = 0.0;
+  st.t_solve_ms = now_ms() - t0;
+}
+
+// Batched solve with the given start; warm-started instances that end unconverged (or with a
+// NaN/Inf) are solved again from the cold start in one more batched run.
+int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, int start, const double *start_dev,
+              double *y_out_dev, double *alpha_out_dev, dlmpc_stats *stats, double t0) {
+  const HostSetup &h = p->hs;
+  const size_t nxs = size_t(h.N) * h.nx, nus = size_t(h.N) * h.nu, R = size_t(h.N) * h.rs;
+  float ms = 0.f, mw = 0.f;
+  int checks = 0;
+  int rc = run_batch_once(p, B, x0_dev, start, start_dev, u0_dev, y_out_dev, alpha_out_dev, &ms, &mw, &checks);
+  if (rc) return rc;
+  std::vector<dlmpc::BCtl> first(p->h_bctl, p->h_bctl + B);
+  std::vector<int> redo;
+  for (int b = 0; b < B; ++b)
+    if (stats) fill_stats(stats[b], first[b], ms, checks, start, t0);
+  if (start != DLMPC_START_COLD)
+    for (int b = 0; b < B; ++b)
+      if (!first[b].converged || first[b].numeric) redo.push_back(b);
+  if (!redo.empty()) {
+    const int F = int(redo.size());
+    for (int f = 0; f < F; ++f)
+      API_HIP(hipMemcpyAsync(p->d_fx0 + f * nxs, x0_dev + redo[f] * nxs, nxs * sizeof(double),
+                             hipMemcpyDeviceToDevice, p->stream));
+    float ms2 = 0.f, mw2 = 0.f;
+    int checks2 = 0;
+    rc = run_batch_once(p, F, p->d_fx0, DLMPC_START_COLD, nullptr, p->d_fu0, y_out_dev ? p->d_fy : nullptr,
+                        alpha_out_dev ? p->d_falpha : nullptr, &ms2, &mw2, &checks2);
+    if (rc) return rc;
+    for (int f = 0; f < F; ++f) {
+      const int b = redo[f];
+      API_HIP(hipMemcpyAsync(u0_dev + b * nus, p->d_fu0 + f * nus, nus * sizeof(double), hipMemcpyDeviceToDevice,
+                             p->stream));
+      if (y_out_dev)
+        API_HIP(hipMemcpyAsync(y_out_dev + b * R, p->d_fy + f * R, R * sizeof(double), hipMemcpyDeviceToDevice,
+                               p->stream));
+      if (alpha_out_dev)
+        API_HIP(hipMemcpyAsync(alpha_out_dev + b * R, p->d_falpha + f * R, R * sizeof(double),
+                               hipMemcpyDeviceToDevice, p->stream));
+      dlmpc::BCtl ic = p->h_bctl[f];
+      ic.iters += first[b].iters;
+      first[b] = ic;
+      if (stats) {
+        fill_stats(stats[b], ic, ms + ms2, checks + checks2, start, t0);
+        stats[b].fell_back = 1;
+      }
+    }
+    API_HIP(hipStreamSynchronize(p->stream));
+  }
   bool all = true, numeric = false;
   for (int b = 0; b < B; ++b) {
-    const dlmpc::BCtl &ic = p->h_bctl[b];
-    all = all && ic.converged;
-    numeric = numeric || ic.numeric;
+    all = all && first[b].converged;
+    numeric = numeric || first[b].numeric;
     if (stats) {
-      dlmpc_stats &st = stats[b];
-      st.iters = ic.iters;
-      st.converged = ic.converged;
-      st.r_primal = ic.last_rp;
-      st.r_dual = ic.last_rd;
-      st.objective = ic.objective;
-      st.t_iter_ms = ms;
-      st.graph_launches = checks;
-      st.schedule = 2;
-      st.t_solve_ms = now_ms() - t0;
+      stats[b].t_warm_ms = mw;
+      stats[b].t_solve_ms = now_ms() - t0;
     }
   }
   if (numeric) return fail(DLMPC_ENUMERIC, "NaN/Inf in a batched ADMM iterate");
@@ -613,7 +724,7 @@ int dlmpc_solve_batch(dlmpc_problem *p, int32_t B, const double *x0, double *u0,
   if (!finite_all(x0, nxs)) return fail(DLMPC_EINVAL, "x0 has a NaN/Inf entry");
   API_HIP(hipSetDevice(p->opt.device));
   API_HIP(hipMemcpyAsync(p->d_bx0, x0, nxs * sizeof(double), hipMemcpyHostToDevice, p->stream));
-  rc = run_batch(p, B, p->d_bx0, p->d_bu0, stats, t0);
+  rc = run_batch(p, B, p->d_bx0, p->d_bu0, DLMPC_START_COLD, nullptr, nullptr, nullptr, stats, t0);
   if (rc < 0) return rc;
   if (u0) API_HIP(hipMemcpy(u0, p->d_bu0, size_t(B) * h.N * h.nu * sizeof(double), hipMemcpyDeviceToHost));
   return rc;
@@ -626,7 +737,143 @@ int dlmpc_solve_batch_device(dlmpc_problem *p, int32_t B, const double *x0_dev, 
   if (rc) return rc;
   if (!x0_dev || !u0_dev) return fail(DLMPC_EINVAL, "NULL argument");
   API_HIP(hipSetDevice(p->opt.device));
-  return run_batch(p, B, x0_dev, u0_dev, stats, t0);
+  return run_batch(p, B, x0_dev, u0_dev, DLMPC_START_COLD, nullptr, nullptr, nullptr, stats, t0);
+}
+
+int dlmpc_solve_batch_ex(dlmpc_problem *p, int32_t B, const double *x0_dev, double *u0_dev, int32_t start,
+                         const double *start_dev, double *y_out_dev, double *alpha_out_dev, dlmpc_stats *stats) {
+  const double t0 = now_ms();
+  int rc = check_batch(p, B);
+  if (rc) return rc;
+  if (!x0_dev || !u0_dev) return fail(DLMPC_EINVAL, "NULL argument");
+  if (start != DLMPC_START_COLD && start != DLMPC_START_ALPHA && start != DLMPC_START_TRAJECTORY &&
+      start != DLMPC_START_LEARNED)
+    return fail(DLMPC_EINVAL, "unknown start mode");
+  if ((start == DLMPC_START_ALPHA || start == DLMPC_START_TRAJECTORY) && !start_dev)
+    return fail(DLMPC_EINVAL, "this start mode needs start_dev");
+  if (start == DLMPC_START_LEARNED && !p->ws)
+    return fail(DLMPC_EINVAL, "no warm-start network (dlmpc_ws_init or dlmpc_warmstart_load)");
+  API_HIP(hipSetDevice(p->opt.device));
+  return run_batch(p, B, x0_dev, u0_dev, start, start_dev, y_out_dev, alpha_out_dev, stats, t0);
+}
+
+namespace {
+
+int check_ws(dlmpc_problem *p) {
+  if (!p) return fail(DLMPC_EINVAL, "NULL problem");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  if (!p->ws) return fail(DLMPC_EINVAL, "no warm-start network (dlmpc_ws_init or dlmpc_warmstart_load)");
+  return DLMPC_OK;
+}
+
+}  // namespace
+
+int dlmpc_ws_init(dlmpc_problem *p, int32_t hidden, int32_t max_samples, uint64_t seed, double x_scale,
+                  double y_scale) {
+  if (!p) return fail(DLMPC_EINVAL, "NULL problem");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  API_HIP(hipSetDevice(p->opt.device));
+  API_HIP(hipStreamSynchronize(p->stream));
+  p->ws.reset();
+  auto ws = std::make_unique<dlmpc::WarmStart>();
+  std::string err;
+  const int rc = ws->init(p->hs, hidden, max_samples, seed, x_scale, y_scale, p->stream, err);
+  if (rc) return fail(rc, err);
+  p->ws = std::move(ws);
+  return DLMPC_OK;
+}
+
+int dlmpc_ws_shape(const dlmpc_problem *p, int32_t *in, int32_t *hidden, int32_t *out, int64_t *n_params) {
+  int rc = check_ws(const_cast<dlmpc_problem *>(p));
+  if (rc) return rc;
+  if (in) *in = p->ws->IN;
+  if (hidden) *hidden = p->ws->H;
+  if (out) *out = p->ws->OUT;
+  if (n_params) *n_params = p->ws->n_params;
+  return DLMPC_OK;
+}
+
+int dlmpc_ws_params(dlmpc_problem *p, float *get, const float *set) {
+  int rc = check_ws(p);
+  if (rc) return rc;
+  API_HIP(hipSetDevice(p->opt.device));
+  API_HIP(hipStreamSynchronize(p->stream));
+  const size_t bytes = sizeof(float) * size_t(p->ws->n_params);
+  if (get) API_HIP(hipMemcpy(get, p->ws->theta, bytes, hipMemcpyDeviceToHost));
+  if (set) {
+    if (!finite_all(set, size_t(p->ws->n_params))) return fail(DLMPC_EINVAL, "parameters have a NaN/Inf entry");
+    API_HIP(hipMemcpy(p->ws->theta, set, bytes, hipMemcpyHostToDevice));
+  }
+  return DLMPC_OK;
+}
+
+int dlmpc_ws_loss_grad(dlmpc_problem *p, int32_t S, const double *x0_dev, const double *y_dev, double *loss,
+                       float *grad) {
+  int rc = check_ws(p);
+  if (rc) return rc;
+  API_HIP(hipSetDevice(p->opt.device));
+  std::string err;
+  double l = 0.0;
+  if ((rc = p->ws->forward(S, x0_dev, err)) || (rc = p->ws->backward(S, y_dev, &l, err))) return fail(rc, err);
+  if (loss) *loss = l;
+  if (grad)
+    API_HIP(hipMemcpy(grad, p->ws->grad, sizeof(float) * size_t(p->ws->n_params), hipMemcpyDeviceToHost));
+  return DLMPC_OK;
+}
+
+int dlmpc_ws_train_step(dlmpc_problem *p, int32_t S, const double *x0_dev, const double *y_dev, double lr,
+                        double *loss) {
+  int rc = check_ws(p);
+  if (rc) return rc;
+  API_HIP(hipSetDevice(p->opt.device));
+  std::string err;
+  if ((rc = p->ws->forward(S, x0_dev, err)) || (rc = p->ws->backward(S, y_dev, loss, err)) ||
+      (rc = p->ws->adam(lr, err)))
+    return fail(rc, err);
+  return DLMPC_OK;
+}
+
+int dlmpc_ws_predict(dlmpc_problem *p, int32_t S, const double *x0_dev, double *y_dev) {
+  int rc = check_ws(p);
+  if (rc) return rc;
+  if (!y_dev) return fail(DLMPC_EINVAL, "NULL output");
+  API_HIP(hipSetDevice(p->opt.device));
+  std::string err;
+  if ((rc = p->ws->predict(S, x0_dev, y_dev, err))) return fail(rc, err);
+  API_HIP(hipStreamSynchronize(p->stream));
+  return DLMPC_OK;
+}
+
+int dlmpc_ws_save(dlmpc_problem *p, const char *path) {
+  int rc = check_ws(p);
+  if (rc) return rc;
+  if (!path) return fail(DLMPC_EINVAL, "NULL path");
+  API_HIP(hipSetDevice(p->opt.device));
+  API_HIP(hipStreamSynchronize(p->stream));
+  std::string err;
+  if ((rc = p->ws->save(path, err))) return fail(rc, err);
+  return DLMPC_OK;
+}
+
+int dlmpc_warmstart_load(dlmpc_problem *p, const char *path) {
+  if (!p || !path) return fail(DLMPC_EINVAL, "NULL argument");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  std::string err;
+  int32_t hidden = 0;
+  int rc = dlmpc::WarmStart::peek(path, &hidden, err);
+  if (rc) return fail(rc, err);
+  const bool created = !p->ws || p->ws->H != hidden;
+  if (created) {
+    rc = dlmpc_ws_init(p, hidden, std::max(1, p->opt.max_batch), 0, 1.0, 1.0);
+    if (rc) return rc;
+  }
+  API_HIP(hipSetDevice(p->opt.device));
+  API_HIP(hipStreamSynchronize(p->stream));
+  if ((rc = p->ws->load(path, err))) {
+    if (created) p->ws.reset();  // no half-made network is left behind
+    return fail(rc, err);
+  }
+  return DLMPC_OK;
 }
 
 void dlmpc_destroy(dlmpc_problem *p) {

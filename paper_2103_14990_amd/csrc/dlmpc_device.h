@@ -133,19 +133,40 @@ struct BArgs {
   unsigned long long *slot; // [Bmax][2] residual maxima of the current iteration (ordered bits)
   Ctl *ctl;                 // shared: iteration count, all-stopped flag
   int64_t ktot;
-  int32_t init_pass;        // 1 while bpsi_kernel computes eta = N' alpha of the warm start
+  // Set-up passes outside the iteration (a copy of the arguments is launched with them):
+  // init_pass 1: bpsi_kernel writes dst_k = N_j' src (row vectors [Bmax][N*rs]) per instance;
+  // phi_mode 1: bphi_kernel writes cg_q = sum_{j in P(m)} ||x0_j||^2 N_j eta_j (rows of m).
+  int32_t init_pass, phi_mode;
+  const float *src;
+  float *dst_k;
+  // Trajectory warm start: predicted trajectory (state rows simulated), CG vectors, r'r.
+  float *yhat, *cg_x, *cg_r, *cg_p, *cg_q;
+  double *cg_rr;
+  const int64_t *a_rowptr;
+  const int32_t *a_colidx;
+  const float *a_blk, *b_blk;  // plant blocks (row-major nx x nx, nx x nu)
 };
 
 class BatchEngine {
  public:
   virtual ~BatchEngine() = default;
   virtual int init(const HostSetup &hs, double rho, int bmax, hipStream_t s, std::string &err) = 0;
-  // alpha0_dev: NULL (cold start) or [B][N*rs] row multipliers of a compact warm start
-  // (Psi^0[:,c] = o_c, Lambda^0[:,c] = x0_c (I - N_j N_j') alpha0 on supp j).
-  virtual int precompute(const double *x0_dev, const double *alpha0_dev, int B, int max_iter,
-                         double eps, std::string &err) = 0;
-  // Current row multipliers alpha of every instance, [B][N*rs] doubles.
+  // Per-solve set-up of B instances; warm != 0 selects the iteration of a warm start (one of
+  // the start_* calls below must follow before the first iteration).
+  virtual int precompute(const double *x0_dev, int B, int max_iter, double eps, int warm,
+                         std::string &err) = 0;
+  // Compact start from row multipliers alpha0 [B][N*rs]: Psi^0[:,c] = o_c,
+  // Lambda^0[:,c] = x0_c (I - N_j N_j') alpha0 on supp j.
+  virtual int start_alpha(const double *alpha0_dev, std::string &err) = 0;
+  // Start from a trajectory: input rows from y0_dev [B][N*rs] (or, if NULL, already in
+  // yhat()), state rows simulated from x0, cg_iters CG steps on M beta = y - b, then
+  // Psi^0[:,c] = o_c + x0_c N_j N_j' beta and Lambda^0[:,c] = x0_c (I - N_j N_j') alpha with
+  // alpha = -2 w y / rho.
+  virtual int start_trajectory(const double *y0_dev, int cg_iters, std::string &err) = 0;
+  virtual float *yhat() = 0;  // [Bmax][N*rs] FP32
+  // Current row multipliers alpha and trajectory rows (Phi x0) of every instance, [B][N*rs].
   virtual int export_alpha(double *alpha_dev, std::string &err) = 0;
+  virtual int export_y(double *y_dev, std::string &err) = 0;
   virtual int iteration(std::string &err) = 0;  // capturable
   virtual int output(double *u0_dev, std::string &err) = 0;
   virtual Ctl *ctl() = 0;
@@ -154,5 +175,49 @@ class BatchEngine {
 };
 
 std::unique_ptr<BatchEngine> make_batch_engine(int nx);
+
+// ----------------------------------------------------------------------------- learned warm start
+// One network per subsystem g (separate weights): x = x0 of the members of P(g) in ascending
+// order / xs (zero-padded to IN = p_max nx), h1 = gelu(x W1 + b1), h2 = gelu(h1 W2 + b2),
+// y = [h2, x] W3 + b3, the input rows u_0..u_{T-2} of g's trajectory = ys y (OUT = nu (T-1)).
+// Parameters are FP32, flat, in the order W1 [G][IN][H], b1 [G][H], W2 [G][H][H], b2 [G][H],
+// W3 [G][H+IN][OUT], b3 [G][OUT]. Trajectories are [S][N*rs] in library row order.
+class WarmStart {
+ public:
+  ~WarmStart();
+  int init(const HostSetup &hs, int hidden, int max_samples, uint64_t seed, double x_scale, double y_scale,
+           hipStream_t s, std::string &err);
+  // Forward pass for S samples x0_dev [S][N*nx] (activations kept for backward).
+  int forward(int S, const double *x0_dev, std::string &err);
+  // After forward: loss against the input rows of trajectories y_dev [S][N*rs], gradient in grad.
+  int backward(int S, const double *y_dev, double *loss, std::string &err);
+  int adam(double lr, std::string &err);
+  // Writes the predicted input rows into y [S][N*rs] (other rows untouched), FP64 or FP32.
+  int predict(int S, const double *x0_dev, double *y_dev, std::string &err);
+  int predict(int S, const double *x0_dev, float *y_dev, std::string &err);
+  int save(const char *path, std::string &err);
+  int load(const char *path, std::string &err);  // shape must match; scales are read
+  static int peek(const char *path, int32_t *hidden, std::string &err);
+
+  int G = 0, nx = 0, rs = 0, roff = 0, IN = 0, H = 0, OUT = 0, Smax = 0;
+  double xs = 1.0, ys = 1.0;
+  int64_t n_params = 0, step = 0;
+  float *theta = nullptr, *grad = nullptr;
+
+ private:
+  static constexpr int kLossBlocks = 256;
+  static constexpr int32_t kMagic = 0x57534d31;  // file tag
+  int alloc_bytes(void **dst, size_t bytes, std::string &err);
+  void views(float *base, float **W1, float **b1, float **W2, float **b2, float **W3, float **b3) const;
+  std::vector<void *> owned_;
+  hipStream_t stream_ = nullptr;
+  int64_t *rt_ptr_ = nullptr;
+  int32_t *rt_col_ = nullptr;
+  float *mom1_ = nullptr, *mom2_ = nullptr;
+  float *XA_ = nullptr;  // [G][S][H+IN]: h2 in the first H columns, x in the last IN
+  float *Z1_ = nullptr, *A1_ = nullptr, *Z2_ = nullptr, *Y_ = nullptr, *T_ = nullptr, *dY_ = nullptr;
+  float *dZ2_ = nullptr, *dZ1_ = nullptr;
+  double *loss_part_ = nullptr;
+};
 
 }  // namespace dlmpc

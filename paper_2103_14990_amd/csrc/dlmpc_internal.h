@@ -26,6 +26,11 @@ struct HostSetup {
 
   std::vector<std::vector<int32_t>> patch;  // P(j), ascending
 
+  // The plant as given (block-CSR A with row-major nx x nx blocks, diagonal nx x nu B blocks).
+  std::vector<int64_t> a_rowptr;
+  std::vector<int32_t> a_colidx;
+  std::vector<double> a_blocks, b_blocks;
+
   std::vector<int64_t> tile_off;    // [N+1] first tile of column subsystem j
   std::vector<int32_t> tile_rsub;   // [n_tiles] row subsystem m of each tile
   std::vector<int64_t> rt_ptr;      // [N+1] row-side CSR over row subsystems

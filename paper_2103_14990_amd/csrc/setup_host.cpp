@@ -388,6 +388,10 @@ int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *
   hs.rs = nx * T + nu * (T - 1);
   hs.ts = hs.rs * nx;
   hs.R = Nx * T + Nu * (T - 1);
+  hs.a_rowptr.assign(sys->a_rowptr, sys->a_rowptr + N + 1);
+  hs.a_colidx.assign(sys->a_colidx, sys->a_colidx + nnzb);
+  hs.a_blocks.assign(sys->a_blocks, sys->a_blocks + size_t(nnzb) * nx * nx);
+  hs.b_blocks.assign(sys->b_blocks, sys->b_blocks + size_t(N) * nx * nu);
 
   // Block rows of A and the interconnection graph G_(A,B).
   std::vector<std::vector<BlockRef>> arow(N);

@@ -24,10 +24,12 @@ SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERS
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 TIMED_KERNELS = 4
 KERNEL_NAMES = ("phi_kernel", "psi_pass1_kernel", "psi_pass2_kernel", "conv_kernel")
+STARTS = {"cold": 0, "alpha": 1, "trajectory": 2, "learned": 3, "state": 4}
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
 _i32p = C.POINTER(C.c_int32)
+_fp = C.POINTER(C.c_float)
 
 
 class System(C.Structure):
@@ -43,7 +45,8 @@ class Cost(C.Structure):
 class Options(C.Structure):
     _fields_ = [("rho", C.c_double), ("eps", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("flags", C.c_uint32), ("max_batch", C.c_int32)]
+                ("stream", C.c_void_p), ("flags", C.c_uint32), ("max_batch", C.c_int32),
+                ("warm_cg_iters", C.c_int32)]
 
 
 class Warm(C.Structure):
@@ -53,7 +56,8 @@ class Warm(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_primal", C.c_double),
                 ("r_dual", C.c_double), ("objective", C.c_double), ("t_solve_ms", C.c_double),
-                ("t_iter_ms", C.c_double), ("graph_launches", C.c_int32), ("schedule", C.c_int32)]
+                ("t_iter_ms", C.c_double), ("graph_launches", C.c_int32), ("schedule", C.c_int32),
+                ("start", C.c_int32), ("fell_back", C.c_int32), ("t_warm_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -82,6 +86,16 @@ EXPORTS = {
     "dlmpc_time_kernels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, _dp]),
     "dlmpc_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
+    "dlmpc_solve_batch_ex": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
+    "dlmpc_ws_init": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_double, C.c_double]),
+    "dlmpc_ws_shape": (C.c_int, [C.c_void_p, _i32p, _i32p, _i32p, _i64p]),
+    "dlmpc_ws_params": (C.c_int, [C.c_void_p, _fp, _fp]),
+    "dlmpc_ws_loss_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, _dp, _fp]),
+    "dlmpc_ws_train_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, _dp]),
+    "dlmpc_ws_predict": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dlmpc_ws_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "dlmpc_warmstart_load": (C.c_int, [C.c_void_p, C.c_char_p]),
     "dlmpc_destroy": (None, [C.c_void_p]),
     "dlmpc_status_string": (C.c_char_p, [C.c_int]),
     "dlmpc_last_error": (C.c_char_p, []),
@@ -149,7 +163,8 @@ class Problem:
                  d: int, T: int, q_diag, r_diag, x_lo=None, x_hi=None, u_lo=None, u_hi=None,
                  rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500, precision: str = "fp64",
                  device: int = 0, stream: int | None = None, check_every: int = 0,
-                 host_only: bool = False, schedule: str = "auto", max_batch: int = 0):
+                 host_only: bool = False, schedule: str = "auto", max_batch: int = 0,
+                 warm_cg_iters: int = 0):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -163,7 +178,8 @@ class Problem:
                     _ptr(keep["ul"]), _ptr(keep["uh"]))
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
-                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule], max_batch)
+                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule], max_batch,
+                       warm_cg_iters)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
             raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
@@ -240,6 +256,57 @@ class Problem:
         s = self._check(self._lib.dlmpc_solve_batch_device(self._h, B, C.c_void_p(x0_dev),
                                                            C.c_void_p(u0_dev), st))
         return s, [x.as_dict() for x in st]
+
+    def solve_batch_ex(self, B: int, x0_dev: int, u0_dev: int, start: str = "cold", start_dev: int = 0,
+                       y_out_dev: int = 0, alpha_out_dev: int = 0) -> tuple[int, list[dict]]:
+        """Batched solve from the cold start, given row multipliers (``start="alpha"``), a given
+        input trajectory (``"trajectory"``) or the warm-start network (``"learned"``); device
+        pointers of float64 buffers ([B][R] for start_dev, y_out_dev, alpha_out_dev)."""
+        st = (Stats * B)()
+        opt = lambda v: C.c_void_p(v) if v else None  # noqa: E731
+        s = self._check(self._lib.dlmpc_solve_batch_ex(
+            self._h, B, C.c_void_p(x0_dev), C.c_void_p(u0_dev), STARTS[start], opt(start_dev),
+            opt(y_out_dev), opt(alpha_out_dev), st))
+        return s, [x.as_dict() for x in st]
+
+    # ---- learned warm start
+    def ws_init(self, hidden: int, max_samples: int, seed: int = 0, x_scale: float = 1.0,
+                y_scale: float = 1.0):
+        self._check(self._lib.dlmpc_ws_init(self._h, hidden, max_samples, seed, x_scale, y_scale))
+
+    def ws_shape(self) -> dict:
+        i, h, o, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        self._check(self._lib.dlmpc_ws_shape(self._h, C.byref(i), C.byref(h), C.byref(o), C.byref(n)))
+        return dict(IN=i.value, H=h.value, OUT=o.value, n_params=n.value)
+
+    def ws_params(self, set_to=None) -> np.ndarray:
+        """Returns the current flat FP32 parameters; sets them afterwards if ``set_to`` is given."""
+        out = np.zeros(self.ws_shape()["n_params"], dtype=np.float32)
+        src = None if set_to is None else np.ascontiguousarray(set_to, dtype=np.float32)
+        self._check(self._lib.dlmpc_ws_params(self._h, _ptr(out, C.c_float), _ptr(src, C.c_float)))
+        return out
+
+    def ws_loss_grad(self, S: int, x0_dev: int, y_dev: int, want_grad: bool = True):
+        loss = C.c_double()
+        g = np.zeros(self.ws_shape()["n_params"], dtype=np.float32) if want_grad else None
+        self._check(self._lib.dlmpc_ws_loss_grad(self._h, S, C.c_void_p(x0_dev), C.c_void_p(y_dev),
+                                                 C.byref(loss), _ptr(g, C.c_float)))
+        return loss.value, g
+
+    def ws_train_step(self, S: int, x0_dev: int, y_dev: int, lr: float) -> float:
+        loss = C.c_double()
+        self._check(self._lib.dlmpc_ws_train_step(self._h, S, C.c_void_p(x0_dev), C.c_void_p(y_dev),
+                                                  lr, C.byref(loss)))
+        return loss.value
+
+    def ws_predict(self, S: int, x0_dev: int, y_dev: int):
+        self._check(self._lib.dlmpc_ws_predict(self._h, S, C.c_void_p(x0_dev), C.c_void_p(y_dev)))
+
+    def ws_save(self, path: str):
+        self._check(self._lib.dlmpc_ws_save(self._h, os.fsencode(path)))
+
+    def warmstart_load(self, path: str):
+        self._check(self._lib.dlmpc_warmstart_load(self._h, os.fsencode(path)))
 
     def time_kernels(self, x0_dev: int, iters: int) -> dict:
         """Mean microseconds per launch of each kernel of one iteration (no early stop)."""
