@@ -140,6 +140,7 @@ typedef struct {
   int32_t persistent_grid; /* co-resident blocks of the persistent schedule (0 = unavailable) */
   double tune_graph_us;      /* per-iteration time measured at setup (0 if not measured) */
   double tune_persistent_us;
+  int64_t sum_k;        /* sum over subsystems of k_j (null-space coordinates per instance) */
 } dlmpc_info;
 
 /* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the
@@ -189,6 +190,17 @@ int dlmpc_solve_device(struct dlmpc_problem *p, const double *x0_dev, double *u0
 #define DLMPC_TIMED_KERNELS 4
 int dlmpc_time_kernels(struct dlmpc_problem *p, const double *x0_dev, int32_t iters,
                        double *us_per_launch);
+
+/* Kernel timing of the batched engine for roofline measurement: B instances from x0_dev
+ * [B][N*nx] (device), cold start without early stop; after two untimed iterations, `iters`
+ * iterations with each kernel launched on its own between HIP events on the problem's stream.
+ * us_per_launch gets the mean device time per launch of, in this order, the batched Phi-comp
+ * (bphi_kernel: row solves of all instances, products with the null bases on the matrix
+ * cores), the batched Psi-comp with Lambda and Conv terms (bpsi_kernel) and the per-instance
+ * stopping decision (bdecide_kernel). The batched state is left unspecified. */
+#define DLMPC_BATCH_TIMED_KERNELS 3
+int dlmpc_time_batch_kernels(struct dlmpc_problem *p, int32_t B, const double *x0_dev,
+                             int32_t iters, double *us_per_launch);
 
 /* Batched per-step solve: B in 1..max_batch independent MPC instances on this network (distinct
  * x0, same plant, cost and bounds), iterated together. Each instance follows the iteration of

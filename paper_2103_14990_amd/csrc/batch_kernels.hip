@@ -42,6 +42,7 @@ constexpr int kPsiThreads = 512;  // 8 waves
 constexpr int kPsiWaves = kPsiThreads / 64;
 constexpr int kMTW = 4;           // M tiles (16 basis vectors) per wave: k_j <= 512
 constexpr int kKC = 64;           // support rows staged per chunk in bpsi_kernel
+constexpr int kRT = 4;            // row tiles of 16 per subsystem in bphi_kernel (rs <= 64)
 
 __device__ __forceinline__ unsigned long long ord_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(v));
@@ -160,69 +161,58 @@ __global__ __launch_bounds__(256) void bexport_alpha_kernel(BArgs a, double *out
 
 // ------------------------------------------------------------------ Phi-comp (batched)
 
-// One block per row subsystem m; wave mt owns rows [16 mt, 16 mt + 16) of m and all instances.
+// One block per row subsystem m; wave nt owns instances [16 nt, 16 nt + 16) and all rows of m.
+// The right operand W_j = ||x0_j||^2 (tau_j + eta_j) is read pre-split (bf16 hi/lo, written by
+// bpsi_kernel) once per block; the rows of N_j that belong to m are the left operand.
 template <int NX>
 __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
   if (a.ctl->stop) return;
   __shared__ float Ct[64][kBMax + 1];
-  const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, mt = tid >> 6;
+  __shared__ double red[4][kBMax];
+  const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, nt = tid >> 6;
   const int rs = a.rs, B = a.ctl->batch;
   const bool warm = a.ctl->warm != 0;
   const bool cgm = a.phi_mode != 0;  // set-up pass: q = sum_j ||x0_j||^2 N_j eta_j
   const int it = a.ctl->iters + 1;
   const float coef = warm ? 1.f : (it == 1 ? 0.f : (it == 2 ? 2.f : 1.f));
-  f32x4 acc[kNT];
+  const int nrt = (rs + 15) >> 4;
+  f32x4 acc[kRT];
 #pragma unroll
-  for (int nt = 0; nt < kNT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (cgm || warm || it >= 3) {  // from a cold start tau = eta = 0 before the third iteration
-    const int row = mt * 16 + (lane & 15);
-    const bool rowok = row < rs;
+  for (int rt = 0; rt < kRT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // from a cold start tau = eta = 0 before the third iteration
+  if ((cgm || warm || it >= 3) && nt * 16 < B) {
+    const int b = nt * 16 + (lane & 15);
     for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
       const int j = a.rt_col[q];
       const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
       const int k32 = int(a.koff[j + 1] - a.koff[j]);
-      const int64_t arow = a.nrm_off[j] + int64_t(ro + (rowok ? row : 0)) * k32;
-      for (int i0 = 8 * (lane >> 4); i0 < k32; i0 += 32) {
-        bf16x8 ah = {}, al = {};
-        if (rowok) {
-          ah = load8(a.nrm_hi + arow + i0);
-          al = load8(a.nrm_lo + arow + i0);
-        }
+      const int64_t koff8 = a.koff[j] >> 3;
+      const int64_t arow = a.nrm_off[j] + int64_t(ro) * k32 + 8 * (lane >> 4);
+      for (int i0 = 0; i0 < k32; i0 += 32) {
+        const int64_t wi = ((koff8 + (i0 >> 3) + (lane >> 4)) * a.Bw + b) * 8;
+        const bf16x8 bh = load8(a.w_hi + wi), bl = load8(a.w_lo + wi);
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) {
-          const int b = nt * 16 + (lane & 15);
-          if (nt * 16 >= B) break;
-          float w[8];
-          if (b < B) {
-            const float xj = a.xn[int64_t(b) * a.N + j];
-            const int64_t kb = int64_t(b) * a.ktot + a.koff[j] + i0;
-            const float4 t0 = *reinterpret_cast<const float4 *>(a.tau + kb);
-            const float4 t1 = *reinterpret_cast<const float4 *>(a.tau + kb + 4);
-            const float4 e0 = *reinterpret_cast<const float4 *>(a.eta + kb);
-            const float4 e1 = *reinterpret_cast<const float4 *>(a.eta + kb + 4);
-            if (cgm) {
-              w[0] = xj * e0.x; w[1] = xj * e0.y; w[2] = xj * e0.z; w[3] = xj * e0.w;
-              w[4] = xj * e1.x; w[5] = xj * e1.y; w[6] = xj * e1.z; w[7] = xj * e1.w;
-            } else {
-              w[0] = xj * (t0.x + e0.x); w[1] = xj * (t0.y + e0.y); w[2] = xj * (t0.z + e0.z); w[3] = xj * (t0.w + e0.w);
-              w[4] = xj * (t1.x + e1.x); w[5] = xj * (t1.y + e1.y); w[6] = xj * (t1.z + e1.z); w[7] = xj * (t1.w + e1.w);
-            }
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) w[e] = 0.f;
+        for (int rt = 0; rt < kRT; ++rt) {
+          if (rt >= nrt) break;
+          const int row = rt * 16 + (lane & 15);
+          bf16x8 ah = {}, al = {};
+          if (row < rs) {
+            const int64_t ai = arow + int64_t(row) * k32 + i0;
+            ah = load8(a.nrm_hi + ai);
+            al = load8(a.nrm_lo + ai);
           }
-          bf16x8 bh, bl;
-          split8(w, bh, bl);
-          acc[nt] = mfma3(ah, al, bh, bl, acc[nt]);
+          acc[rt] = mfma3(ah, al, bh, bl, acc[rt]);
         }
       }
     }
   }
-  // C tile: lane holds rows 16 mt + 4 (lane / 16) + e of instance column nt * 16 + lane % 16
+  // C tile: lane holds rows 16 rt + 4 (lane / 16) + e of instance column 16 nt + lane % 16
 #pragma unroll
-  for (int nt = 0; nt < kNT; ++nt)
+  for (int rt = 0; rt < kRT; ++rt) {
+    if (rt >= nrt) break;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) Ct[mt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[nt][e];
+    for (int e = 0; e < 4; ++e) Ct[rt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[rt][e];
+  }
   __syncthreads();
   if (cgm) {
     for (int idx = tid; idx < rs * B; idx += blockDim.x) {
@@ -231,28 +221,36 @@ __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
     }
     return;
   }
+  // Row update: thread (instance b, row group lg) handles rows lg, lg + 4, ... of m, and the
+  // sum of (alpha - alpha_prev)^2 over m's rows (the residual term Psi-comp needs) per instance.
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
   const int cur = it & 1, prev = cur ^ 1;
-  for (int idx = tid; idx < rs * B; idx += blockDim.x) {
-    const int l = idx / B, b = idx - l * B;
-    if (a.ictl[b].stop) continue;
-    const int64_t o = int64_t(m) * rs + l;
-    const int64_t rb = int64_t(b) * a.N * rs + o;
+  const int b = tid & 63, lg = tid >> 6;
+  double dl = 0.0;
+  if (b < B && !a.ictl[b].stop) {
     const float n = a.nrm[int64_t(b) * a.N + m];
-    const float ap = a.alpha[prev * plane + rb];
-    const float av = coef * a.bvec[rb] + Ct[l][b] - n * ap;
-    float sv, al;
-    if (n > 0.f) {
-      sv = a.rho * av / (a.rho + 2.f * a.w[o] * n);
-      sv = sv < a.lb[o] ? a.lb[o] : (sv > a.ub[o] ? a.ub[o] : sv);
-      al = (sv - av) / n;
-    } else {
-      sv = av;
-      al = 0.f;
+    for (int l = lg; l < rs; l += 4) {
+      const int64_t o = int64_t(m) * rs + l;
+      const int64_t rb = int64_t(b) * a.N * rs + o;
+      const float ap = a.alpha[prev * plane + rb];
+      const float av = coef * a.bvec[rb] + Ct[l][b] - n * ap;
+      float sv, al;
+      if (n > 0.f) {
+        sv = a.rho * av / (a.rho + 2.f * a.w[o] * n);
+        sv = sv < a.lb[o] ? a.lb[o] : (sv > a.ub[o] ? a.ub[o] : sv);
+        al = (sv - av) / n;
+      } else {
+        sv = av;
+        al = 0.f;
+      }
+      a.alpha[cur * plane + rb] = al;
+      a.s[rb] = sv;
+      dl += double(al - ap) * double(al - ap);
     }
-    a.alpha[cur * plane + rb] = al;
-    a.s[rb] = sv;
   }
+  red[lg][b] = dl;
+  __syncthreads();
+  if (tid < B && !a.ictl[tid].stop) a.dlm[int64_t(tid) * a.N + m] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // ------------------------------------------------------------------ Psi-comp + Conv (batched)
@@ -265,7 +263,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   __shared__ __align__(16) __bf16 sh_hi[kBMax][kKC + 8];
   __shared__ __align__(16) __bf16 sh_lo[kBMax][kKC + 8];
   __shared__ double red_e[kPsiWaves][kBMax], red_d[kPsiWaves][kBMax];
-  __shared__ double red_dl[kBMax][8], red_od[kBMax][8][NX];
+  __shared__ double red_od[kBMax][8][NX];
   const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rs = a.rs, B = a.ctl->batch;
   const bool warm = a.ctl->warm != 0;
@@ -279,7 +277,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
   const bool initp = a.init_pass != 0;
   const bool cold2 = !warm && it == 2;
-  const int cur = it & 1, prev = cur ^ 1;
+  const int cur = it & 1;
   // a set-up pass stages the row vectors src; the iteration stages the current alpha
   const float *stage_src = initp ? a.src : a.alpha + cur * plane;
   const int sb = tid >> 3, sub = tid & 7;  // staging: instance sb, rows 8 sub .. 8 sub + 7
@@ -300,12 +298,12 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   for (int t = 0; t < kMTW; ++t)
 #pragma unroll
     for (int nt = 0; nt < kNT; ++nt) acc[t][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  double dl2 = 0.0, od[NX];
+  double od[NX];
 #pragma unroll
   for (int c = 0; c < NX; ++c) od[c] = 0.0;
   const bool sact = sb < B;
-  for (int r0 = 0; r0 < ld64; r0 += kKC) {
-    float v[8];
+  // staging values of instance sb for support rows r0 + 8 sub .. + 7 (zero past D)
+  auto fetch = [&](int r0, float *v) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int rr = r0 + 8 * sub + e;
@@ -313,12 +311,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       if (sact && rr < D) {
         const int ta = rr / rs, l = rr - ta * rs;
         const int mm = a.tile_rsub[tb + ta];
-        const int64_t idx = int64_t(sb) * a.N * rs + int64_t(mm) * rs + l;
-        an = stage_src[idx];
-        if (!initp) {
-          const float ap = a.alpha[prev * plane + idx];
-          dl2 += double(an - ap) * double(an - ap);
-        }
+        an = stage_src[int64_t(sb) * a.N * rs + int64_t(mm) * rs + l];
         if (cold2) {
 #pragma unroll
           for (int c = 0; c < NX; ++c) od[c] += double(an) * double(a.off[a.off_ptr[j] + int64_t(c) * ld4 + rr]);
@@ -326,11 +319,16 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       }
       v[e] = an;
     }
+  };
+  float v[8];
+  fetch(0, v);
+  for (int r0 = 0; r0 < ld64; r0 += kKC) {
     bf16x8 vh, vl;
     split8(v, vh, vl);
     *reinterpret_cast<bf16x8 *>(&sh_hi[sb][8 * sub]) = vh;
     *reinterpret_cast<bf16x8 *>(&sh_lo[sb][8 * sub]) = vl;
     __syncthreads();
+    if (r0 + kKC < ld64) fetch(r0 + kKC, v);  // next chunk in flight during the products
 #pragma unroll
     for (int ks = 0; ks < kKC / 32; ++ks) {
       const int kr = ks * 32 + 8 * (lane >> 4);
@@ -372,16 +370,26 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
         const int i = mtile * 16 + 4 * (lane >> 4) + e;
         if (i >= k) continue;
         const int64_t ki = int64_t(b) * a.ktot + a.koff[j] + i;
+        const int64_t wi = (((a.koff[j] + i) >> 3) * a.Bw + b) * 8 + (i & 7);
+        const float xj = a.xn[int64_t(b) * a.N + j];
         const float en = acc[t][nt][e];
+        float wv;
         if (initp) {
           a.dst_k[ki] = en;
-          continue;
+          if (a.wmode == 0) continue;
+          wv = xj * (a.wmode == 2 ? a.tau[ki] + en : en);
+        } else {
+          const float eo = a.eta[ki];
+          const float tn = a.tau[ki] + en;
+          a.eta[ki] = en;
+          a.tau[ki] = tn;
+          e2[nt] += double(en) * double(en);
+          d2[nt] += double(en - eo) * double(en - eo);
+          wv = xj * (tn + en);
         }
-        const float eo = a.eta[ki];
-        a.eta[ki] = en;
-        a.tau[ki] += en;
-        e2[nt] += double(en) * double(en);
-        d2[nt] += double(en - eo) * double(en - eo);
+        const __bf16 wh = static_cast<__bf16>(wv);
+        a.w_hi[wi] = wh;
+        a.w_lo[wi] = static_cast<__bf16>(wv - static_cast<float>(wh));
       }
     }
   }
@@ -397,7 +405,6 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       red_d[wave][nt * 16 + lane] = d2[nt];
     }
   }
-  red_dl[sb][sub] = dl2;
 #pragma unroll
   for (int c = 0; c < NX; ++c) red_od[sb][sub][c] = od[c];
   __syncthreads();
@@ -408,7 +415,8 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       se += red_e[w][b];
       sd += red_d[w][b];
     }
-    for (int q = 0; q < 8; ++q) sdl += red_dl[b][q];
+    // ||alpha - alpha_prev||^2 on the support of j: per-row-subsystem sums from bphi_kernel
+    for (int64_t ta = tb; ta < a.tile_off[j + 1]; ++ta) sdl += a.dlm[int64_t(b) * a.N + a.tile_rsub[ta]];
     double mp = 0.0, md = 0.0;
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
@@ -702,6 +710,14 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&a.ctl, 1, err)))
       return rc;
     // trajectory warm start: vectors and the plant in FP32
+    a.Bw = (bmax + 15) & ~15;
+    if ((rc = al(&a.w_hi, size_t(a.Bw) * a.ktot, err)) || (rc = al(&a.w_lo, size_t(a.Bw) * a.ktot, err)) ||
+        (rc = al(&a.dlm, size_t(bmax) * N, err)))
+      return rc;
+    // padded k entries and instances of W stay zero: the products read whole 32-wide k blocks
+    // of 16 instances
+    BENG_CHECK(hipMemset(a.w_hi, 0, sizeof(__bf16) * size_t(a.Bw) * a.ktot));
+    BENG_CHECK(hipMemset(a.w_lo, 0, sizeof(__bf16) * size_t(a.Bw) * a.ktot));
     if ((rc = al(&a.yhat, size_t(bmax) * ny, err)) || (rc = al(&a.cg_x, size_t(bmax) * ny, err)) ||
         (rc = al(&a.cg_r, size_t(bmax) * ny, err)) || (rc = al(&a.cg_p, size_t(bmax) * ny, err)) ||
         (rc = al(&a.cg_q, size_t(bmax) * ny, err)) || (rc = al(&a.cg_rr, size_t(bmax), err)))
@@ -711,6 +727,7 @@ class BatchEngineT final : public BatchEngine {
         (rc = up(ablk, &a.a_blk, err)) || (rc = up(bblk, &a.b_blk, err)))
       return rc;
     a.init_pass = 0;
+    a.wmode = 0;
     a.phi_mode = 0;
     a.src = nullptr;
     a.dst_k = nullptr;
@@ -730,10 +747,12 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
-  // dst_k = N_j' src for every column subsystem j and instance
-  int project_t(const float *src, float *dst_k, std::string &err) {
+  // dst_k = N_j' src for every column subsystem j and instance; wmode 1 also writes the
+  // product operand W = ||x0_j||^2 dst_k, wmode 2 W = ||x0_j||^2 (tau + dst_k).
+  int project_t(const float *src, float *dst_k, int wmode, std::string &err) {
     BArgs ia = args_;
     ia.init_pass = 1;
+    ia.wmode = wmode;
     ia.src = src;
     ia.dst_k = dst_k;
     hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, ia);
@@ -744,7 +763,7 @@ class BatchEngineT final : public BatchEngine {
   int start_alpha(const double *alpha0_dev, std::string &err) override {
     hipLaunchKernelGGL(bwarm_alpha_kernel, dim3(1024), dim3(256), 0, stream_, args_, alpha0_dev, B_);
     BENG_CHECK(hipGetLastError());
-    return project_t(args_.alpha, args_.eta, err);  // plane 0: the previous iterate of iteration 1
+    return project_t(args_.alpha, args_.eta, 2, err);  // plane 0: the previous iterate of iteration 1
   }
 
   int start_trajectory(const double *y0_dev, int cg_iters, std::string &err) override {
@@ -758,17 +777,16 @@ class BatchEngineT final : public BatchEngine {
     BENG_CHECK(hipGetLastError());
     BArgs qa = args_;
     qa.phi_mode = 1;
-    const int waves = (hs_->rs + 15) / 16;
     int rc;
     for (int k = 0; k < cg_iters; ++k) {
-      if ((rc = project_t(args_.cg_p, args_.eta, err))) return rc;  // eta = N' p
-      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(64 * waves), 0, stream_, qa);  // q = M p
+      if ((rc = project_t(args_.cg_p, args_.eta, 1, err))) return rc;  // eta = N' p, W = ||x0_j||^2 eta
+      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, qa);  // q = M p
       BENG_CHECK(hipGetLastError());
       hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_);
       BENG_CHECK(hipGetLastError());
     }
-    if ((rc = project_t(args_.cg_x, args_.tau, err))) return rc;  // tau = N' beta
-    return project_t(args_.alpha, args_.eta, err);                 // eta = N' alpha^0
+    if ((rc = project_t(args_.cg_x, args_.tau, 0, err))) return rc;  // tau = N' beta
+    return project_t(args_.alpha, args_.eta, 2, err);                 // eta = N' alpha^0, W
   }
 
   float *yhat() override { return args_.yhat; }
@@ -785,9 +803,19 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
+  int launch_one(int k, std::string &err) override {
+    if (k == 0)
+      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_);
+    else if (k == 1)
+      hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, args_);
+    else
+      hipLaunchKernelGGL(bdecide_kernel, dim3(1), dim3(64), 0, stream_, args_);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
   int iteration(std::string &err) override {
-    const int waves = (hs_->rs + 15) / 16;
-    hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(64 * waves), 0, stream_, args_);
+    hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, args_);
     BENG_CHECK(hipGetLastError());

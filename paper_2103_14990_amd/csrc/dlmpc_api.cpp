@@ -440,6 +440,7 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   info->p_max = h.p_max;
   info->k_max = h.k_max;
   info->sum_dcol_k = h.sum_dcol_k;
+  info->sum_k = h.sum_k;
   info->sum_dcol2 = h.sum_dcol2;
   info->setup_ms = h.setup_ms;
   info->factor_ms = h.factor_ms;
@@ -545,6 +546,42 @@ int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, do
   for (int i = 0; i < iters && rc == DLMPC_OK; ++i)
     for (int k = 0; k < nk && rc == DLMPC_OK; ++k) {
       rc = p->eng->launch_one(k, err);
+      if (!rc) API_HIP(hipEventRecord(ev[size_t(i) * nk + k + 1], p->stream));
+    }
+  API_HIP(hipStreamSynchronize(p->stream));
+  double sum[nk] = {};
+  for (int i = 0; i < iters && rc == DLMPC_OK; ++i)
+    for (int k = 0; k < nk; ++k) {
+      float ms = 0.f;
+      API_HIP(hipEventElapsedTime(&ms, ev[size_t(i) * nk + k], ev[size_t(i) * nk + k + 1]));
+      sum[k] += ms;
+    }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (rc) return fail(rc, err);
+  for (int k = 0; k < nk; ++k) us_per_launch[k] = 1e3 * sum[k] / iters;
+  return DLMPC_OK;
+}
+
+int dlmpc_time_batch_kernels(dlmpc_problem *p, int32_t B, const double *x0_dev, int32_t iters,
+                             double *us_per_launch) {
+  if (!p || !x0_dev || iters < 1 || !us_per_launch) return fail(DLMPC_EINVAL, "bad argument");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  if (!p->beng) return fail(DLMPC_EINVAL, "problem was set up without max_batch");
+  if (B < 1 || B > p->beng->bmax()) return fail(DLMPC_EINVAL, "batch size out of range");
+  API_HIP(hipSetDevice(p->opt.device));
+  std::string err;
+  // cold start, no stop (eps < 0); two untimed iterations first (the cold start skips the
+  // products in its first two)
+  int rc = p->beng->precompute(x0_dev, B, iters + 2, -1.0, 0, err);
+  for (int i = 0; i < 2 && !rc; ++i) rc = p->beng->iteration(err);
+  if (rc) return fail(rc, err);
+  constexpr int nk = DLMPC_BATCH_TIMED_KERNELS;
+  std::vector<hipEvent_t> ev(size_t(nk) * iters + 1);
+  for (auto &e : ev) API_HIP(hipEventCreate(&e));
+  API_HIP(hipEventRecord(ev[0], p->stream));
+  for (int i = 0; i < iters && rc == DLMPC_OK; ++i)
+    for (int k = 0; k < nk && rc == DLMPC_OK; ++k) {
+      rc = p->beng->launch_one(k, err);
       if (!rc) API_HIP(hipEventRecord(ev[size_t(i) * nk + k + 1], p->stream));
     }
   API_HIP(hipStreamSynchronize(p->stream));

@@ -136,9 +136,16 @@ struct BArgs {
   // Set-up passes outside the iteration (a copy of the arguments is launched with them):
   // init_pass 1: bpsi_kernel writes dst_k = N_j' src (row vectors [Bmax][N*rs]) per instance;
   // phi_mode 1: bphi_kernel writes cg_q = sum_{j in P(m)} ||x0_j||^2 N_j eta_j (rows of m).
-  int32_t init_pass, phi_mode;
+  int32_t init_pass, phi_mode, wmode;
   const float *src;
   float *dst_k;
+  // Right operand of the Phi-comp products, W_j = ||x0_j||^2 (tau_j + eta_j) as bf16 hi + lo,
+  // element (b, k) of subsystem j at ((koff_j + k) / 8 * Bw + b) * 8 + k % 8 with Bw = Bmax
+  // rounded up to 16 (a product tile always covers 16 instances); and the
+  // per-row-subsystem sums of (alpha - alpha_prev)^2 [Bmax][N].
+  int32_t Bw;
+  __bf16 *w_hi, *w_lo;
+  double *dlm;
   // Trajectory warm start: predicted trajectory (state rows simulated), CG vectors, r'r.
   float *yhat, *cg_x, *cg_r, *cg_p, *cg_q;
   double *cg_rr;
@@ -168,6 +175,8 @@ class BatchEngine {
   virtual int export_alpha(double *alpha_dev, std::string &err) = 0;
   virtual int export_y(double *y_dev, std::string &err) = 0;
   virtual int iteration(std::string &err) = 0;  // capturable
+  // One kernel of an iteration: 0 bphi_kernel, 1 bpsi_kernel, 2 bdecide_kernel.
+  virtual int launch_one(int k, std::string &err) = 0;
   virtual int output(double *u0_dev, std::string &err) = 0;
   virtual Ctl *ctl() = 0;
   virtual BCtl *ictl() = 0;

@@ -53,7 +53,7 @@ struct HostSetup {
   std::vector<int64_t> csr_map;     // [n_tiles*ts] tile element -> canonical CSR index
 
   int32_t p_max = 0, k_max = 0, d_row_max = 0, d_col_max = 0;
-  int64_t sum_dcol_k = 0, sum_dcol2 = 0;
+  int64_t sum_dcol_k = 0, sum_dcol2 = 0, sum_k = 0;
   double setup_ms = 0, factor_ms = 0;
 };
 

@@ -570,6 +570,7 @@ int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *
                 hs.off.begin() + hs.off_ptr[j] + size_t(c) * ld);
     hs.k_max = std::max(hs.k_max, ks[j]);
     hs.sum_dcol_k += int64_t(D) * ks[j];
+    hs.sum_k += ks[j];
   }
   const auto t_end = std::chrono::steady_clock::now();
   hs.factor_ms = std::chrono::duration<double, std::milli>(t_end - t_fac).count();

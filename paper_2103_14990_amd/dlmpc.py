@@ -24,6 +24,7 @@ SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERS
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 TIMED_KERNELS = 4
 KERNEL_NAMES = ("phi_kernel", "psi_pass1_kernel", "psi_pass2_kernel", "conv_kernel")
+BATCH_KERNEL_NAMES = ("bphi_kernel", "bpsi_kernel", "bdecide_kernel")
 STARTS = {"cold": 0, "alpha": 1, "trajectory": 2, "learned": 3, "state": 4}
 
 _dp = C.POINTER(C.c_double)
@@ -69,7 +70,7 @@ class Info(C.Structure):
                 ("k_max", C.c_int32), ("sum_dcol_k", C.c_int64), ("sum_dcol2", C.c_int64),
                 ("setup_ms", C.c_double), ("factor_ms", C.c_double), ("schedule", C.c_int32),
                 ("persistent_grid", C.c_int32), ("tune_graph_us", C.c_double),
-                ("tune_persistent_us", C.c_double)]
+                ("tune_persistent_us", C.c_double), ("sum_k", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -84,6 +85,7 @@ EXPORTS = {
     "dlmpc_solve": (C.c_int, [C.c_void_p, _dp, C.POINTER(Warm), _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_time_kernels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, _dp]),
+    "dlmpc_time_batch_kernels": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, _dp]),
     "dlmpc_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_solve_batch_ex": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
@@ -313,6 +315,12 @@ class Problem:
         us = np.zeros(TIMED_KERNELS)
         self._check(self._lib.dlmpc_time_kernels(self._h, C.c_void_p(x0_dev), iters, _ptr(us)))
         return dict(zip(KERNEL_NAMES, us.tolist()))
+
+    def time_batch_kernels(self, B: int, x0_dev: int, iters: int) -> dict:
+        """Mean microseconds per launch of each batched-engine kernel (no early stop)."""
+        us = np.zeros(len(BATCH_KERNEL_NAMES))
+        self._check(self._lib.dlmpc_time_batch_kernels(self._h, B, C.c_void_p(x0_dev), iters, _ptr(us)))
+        return dict(zip(BATCH_KERNEL_NAMES, us.tolist()))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
