@@ -127,8 +127,8 @@ def main() -> int:
     ap.add_argument("--workload", default="irregular1024_box")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--start", default="learned", choices=["learned", "cold"])
-    ap.add_argument("--train-solves", type=int, default=2048)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-solves", type=int, default=8192)
+    ap.add_argument("--train-steps", type=int, default=10000)
     ap.add_argument("--hidden", type=int, default=64)
     ap.add_argument("--single-steps", type=int, default=8, help="single-instance FP32 solves")
     ap.add_argument("--ref-steps", type=int, default=4, help="plain FP64 single-instance solves")

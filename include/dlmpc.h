@@ -96,7 +96,7 @@ typedef struct {
   uint32_t flags;      /* DLMPC_FLAG_* */
   int32_t max_batch;   /* 0, or 1..64: also set up the batched engine for up to this many x0
                           per dlmpc_solve_batch call (FP32 precision only) */
-  int32_t warm_cg_iters; /* CG steps of the trajectory warm start (0: 16) */
+  int32_t warm_cg_iters; /* CG steps of the trajectory warm start (0: 12) */
 } dlmpc_options;
 
 /* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
@@ -192,8 +192,9 @@ int dlmpc_time_kernels(struct dlmpc_problem *p, const double *x0_dev, int32_t it
                        double *us_per_launch);
 
 /* Kernel timing of the batched engine for roofline measurement: B instances from x0_dev
- * [B][N*nx] (device), cold start without early stop; after two untimed iterations, `iters`
- * iterations with each kernel launched on its own between HIP events on the problem's stream.
+ * [B][N*nx] (device), started from row multipliers alpha0 = 0 (DLMPC_START_ALPHA, so that
+ * every iteration runs the full products) without early stop; `iters` iterations with each
+ * kernel launched on its own between HIP events on the problem's stream.
  * us_per_launch gets the mean device time per launch of, in this order, the batched Phi-comp
  * (bphi_kernel: row solves of all instances, products with the null bases on the matrix
  * cores), the batched Psi-comp with Lambda and Conv terms (bpsi_kernel) and the per-instance

@@ -43,6 +43,7 @@ constexpr int kPsiWaves = kPsiThreads / 64;
 constexpr int kMTW = 4;           // M tiles (16 basis vectors) per wave: k_j <= 512
 constexpr int kKC = 64;           // support rows staged per chunk in bpsi_kernel
 constexpr int kRT = 4;            // row tiles of 16 per subsystem in bphi_kernel (rs <= 64)
+constexpr int kPhiThreads = 512;  // bphi_kernel: 4 instance tiles x 2 halves of the tile list
 
 __device__ __forceinline__ unsigned long long ord_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(v));
@@ -97,9 +98,9 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
     a.xn[int64_t(b) * a.N + m] = static_cast<float>(sm);
     a.nrm[int64_t(b) * a.N + m] = static_cast<float>(sn);
   }
-  const int64_t rb = int64_t(b) * a.N * rs + int64_t(m) * rs;
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
   for (int l = tid; l < rs; l += 256) {
+    const int64_t ri = (int64_t(m) * rs + l) * a.Bmax + b;  // row vectors: [R][Bmax]
     double bv = 0.0;
     for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
       const int j = a.rt_col[q];
@@ -109,14 +110,14 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
 #pragma unroll
       for (int c = 0; c < NX; ++c) bv += xb[j * NX + c] * double(a.off[a.off_ptr[j] + int64_t(c) * ld + ro + l]);
     }
-    a.bvec[rb + l] = static_cast<float>(bv);
-    a.alpha[rb + l] = 0.f;
-    a.alpha[plane + rb + l] = 0.f;
-    a.s[rb + l] = 0.f;
+    a.bvec[ri] = static_cast<float>(bv);
+    a.alpha[ri] = 0.f;
+    a.alpha[plane + ri] = 0.f;
+    a.s[ri] = 0.f;
   }
   for (int64_t i = a.koff[m] + tid; i < a.koff[m + 1]; i += 256) {
-    a.tau[int64_t(b) * a.ktot + i] = 0.f;
-    a.eta[int64_t(b) * a.ktot + i] = 0.f;
+    a.tau[i * a.Bmax + b] = 0.f;
+    a.eta[i * a.Bmax + b] = 0.f;
   }
   if (m == 0 && tid == 0) {
     BCtl &ic = a.ictl[b];
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
 __global__ __launch_bounds__(256) void bwarm_alpha_kernel(BArgs a, const double *alpha0, int B) {
   const int64_t ny = int64_t(a.N) * a.rs;
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < int64_t(B) * ny; i += int64_t(gridDim.x) * 256)
-    a.alpha[i] = static_cast<float>(alpha0[i]);
+    a.alpha[(i % ny) * a.Bmax + i / ny] = static_cast<float>(alpha0[i]);
 }
 
 __global__ __launch_bounds__(256) void bexport_alpha_kernel(BArgs a, double *out, int B) {
@@ -155,21 +156,23 @@ __global__ __launch_bounds__(256) void bexport_alpha_kernel(BArgs a, double *out
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < int64_t(B) * ny; i += int64_t(gridDim.x) * 256) {
     const int b = int(i / ny);
     const int p = a.ictl[b].iters & 1;  // the plane the stopping iteration wrote
-    out[i] = double(a.alpha[p * plane + i]);
+    out[i] = double(a.alpha[p * plane + (i - int64_t(b) * ny) * a.Bmax + b]);
   }
 }
 
 // ------------------------------------------------------------------ Phi-comp (batched)
 
-// One block per row subsystem m; wave nt owns instances [16 nt, 16 nt + 16) and all rows of m.
-// The right operand W_j = ||x0_j||^2 (tau_j + eta_j) is read pre-split (bf16 hi/lo, written by
-// bpsi_kernel) once per block; the rows of N_j that belong to m are the left operand.
+// One block per row subsystem m (8 waves); wave w owns instances [16 nt, 16 nt + 16), nt = w % 4,
+// for every other tile of m's row (half w / 4), all rows of m; the two halves are summed in a
+// fixed order. The right operand W_j = ||x0_j||^2 (tau_j + eta_j) is read pre-split (bf16 hi/lo,
+// written by bpsi_kernel) once per block; the rows of N_j that belong to m are the left operand.
 template <int NX>
-__global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
+__global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   if (a.ctl->stop) return;
-  __shared__ float Ct[64][kBMax + 1];
-  __shared__ double red[4][kBMax];
-  const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, nt = tid >> 6;
+  __shared__ float Ct[2][64][kBMax + 1];
+  __shared__ double red[kPhiThreads / 64][kBMax];
+  const int m = a.phi_order[blockIdx.x], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = wave & 3, half = wave >> 2;
   const int rs = a.rs, B = a.ctl->batch;
   const bool warm = a.ctl->warm != 0;
   const bool cgm = a.phi_mode != 0;  // set-up pass: q = sum_j ||x0_j||^2 N_j eta_j
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
   // from a cold start tau = eta = 0 before the third iteration
   if ((cgm || warm || it >= 3) && nt * 16 < B) {
     const int b = nt * 16 + (lane & 15);
-    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+    for (int64_t q = a.rt_ptr[m] + half; q < a.rt_ptr[m + 1]; q += 2) {
       const int j = a.rt_col[q];
       const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
       const int k32 = int(a.koff[j + 1] - a.koff[j]);
@@ -211,29 +214,30 @@ __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
   for (int rt = 0; rt < kRT; ++rt) {
     if (rt >= nrt) break;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) Ct[rt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[rt][e];
+    for (int e = 0; e < 4; ++e) Ct[half][rt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[rt][e];
   }
   __syncthreads();
   if (cgm) {
     for (int idx = tid; idx < rs * B; idx += blockDim.x) {
       const int l = idx / B, b = idx - l * B;
-      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = Ct[l][b];
+      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = Ct[0][l][b] + Ct[1][l][b];
     }
     return;
   }
-  // Row update: thread (instance b, row group lg) handles rows lg, lg + 4, ... of m, and the
+  // Row update: thread (instance b, row group lg) handles rows lg, lg + 8, ... of m, and the
   // sum of (alpha - alpha_prev)^2 over m's rows (the residual term Psi-comp needs) per instance.
+  constexpr int kLG = kPhiThreads / 64;
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
   const int cur = it & 1, prev = cur ^ 1;
   const int b = tid & 63, lg = tid >> 6;
   double dl = 0.0;
   if (b < B && !a.ictl[b].stop) {
     const float n = a.nrm[int64_t(b) * a.N + m];
-    for (int l = lg; l < rs; l += 4) {
+    for (int l = lg; l < rs; l += kLG) {
       const int64_t o = int64_t(m) * rs + l;
-      const int64_t rb = int64_t(b) * a.N * rs + o;
+      const int64_t rb = o * a.Bmax + b;  // consecutive instances: consecutive addresses
       const float ap = a.alpha[prev * plane + rb];
-      const float av = coef * a.bvec[rb] + Ct[l][b] - n * ap;
+      const float av = coef * a.bvec[rb] + (Ct[0][l][b] + Ct[1][l][b]) - n * ap;
       float sv, al;
       if (n > 0.f) {
         sv = a.rho * av / (a.rho + 2.f * a.w[o] * n);
@@ -250,7 +254,12 @@ __global__ __launch_bounds__(256) void bphi_kernel(BArgs a) {
   }
   red[lg][b] = dl;
   __syncthreads();
-  if (tid < B && !a.ictl[tid].stop) a.dlm[int64_t(tid) * a.N + m] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  if (tid < B && !a.ictl[tid].stop) {
+    double sum = 0.0;
+#pragma unroll
+    for (int g = 0; g < kLG; ++g) sum += red[g][tid];
+    a.dlm[int64_t(tid) * a.N + m] = sum;
+  }
 }
 
 // ------------------------------------------------------------------ Psi-comp + Conv (batched)
@@ -264,7 +273,8 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   __shared__ __align__(16) __bf16 sh_lo[kBMax][kKC + 8];
   __shared__ double red_e[kPsiWaves][kBMax], red_d[kPsiWaves][kBMax];
   __shared__ double red_od[kBMax][8][NX];
-  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // blocks in decreasing order of work (D_col(j) k_j), so that the heavy ones start first
+  const int j = a.psi_order[blockIdx.x], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rs = a.rs, B = a.ctl->batch;
   const bool warm = a.ctl->warm != 0;
   const int it = a.ctl->iters + 1;
@@ -280,7 +290,10 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   const int cur = it & 1;
   // a set-up pass stages the row vectors src; the iteration stages the current alpha
   const float *stage_src = initp ? a.src : a.alpha + cur * plane;
-  const int sb = tid >> 3, sub = tid & 7;  // staging: instance sb, rows 8 sub .. 8 sub + 7
+  // element (b, row) of the staged vectors: alpha planes are [R][Bmax], set-up sources carry
+  // their own strides
+  // staging: instance sb (fastest across the wave), rows 8 sub .. 8 sub + 7 of the chunk
+  const int sb = tid & 63, sub = tid >> 6;
 
   if (!warm && it == 1 && !initp) {  // alpha^1 = 0: Psi^1 = o, residuals ||o_c||, eta stays 0
     if (tid < B && !a.ictl[tid].stop) {
@@ -311,7 +324,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       if (sact && rr < D) {
         const int ta = rr / rs, l = rr - ta * rs;
         const int mm = a.tile_rsub[tb + ta];
-        an = stage_src[int64_t(sb) * a.N * rs + int64_t(mm) * rs + l];
+        an = stage_src[int64_t(sb) * a.src_bs + (int64_t(mm) * rs + l) * a.src_rs];
         if (cold2) {
 #pragma unroll
           for (int c = 0; c < NX; ++c) od[c] += double(an) * double(a.off[a.off_ptr[j] + int64_t(c) * ld4 + rr]);
@@ -369,7 +382,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       for (int e = 0; e < 4; ++e) {
         const int i = mtile * 16 + 4 * (lane >> 4) + e;
         if (i >= k) continue;
-        const int64_t ki = int64_t(b) * a.ktot + a.koff[j] + i;
+        const int64_t ki = (a.koff[j] + i) * a.Bmax + b;  // instance-minor: lanes b coalesce
         const int64_t wi = (((a.koff[j] + i) >> 3) * a.Bw + b) * 8 + (i & 7);
         const float xj = a.xn[int64_t(b) * a.N + j];
         const float en = acc[t][nt][e];
@@ -493,16 +506,16 @@ __global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0) {
   __shared__ double red[4];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int64_t ny = int64_t(a.N) * a.rs;
-  const float *sb = a.s + int64_t(b) * ny;
+  const float *sb = a.s + b;  // row i of instance b at sb[i * Bmax]
   double acc = 0.0;
-  for (int64_t i = tid; i < ny; i += 256) acc += a.w64[i] * double(sb[i]) * double(sb[i]);
+  for (int64_t i = tid; i < ny; i += 256) acc += a.w64[i] * double(sb[i * a.Bmax]) * double(sb[i * a.Bmax]);
   acc = wsum(acc);
   if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
   if (tid == 0) a.ictl[b].objective = (red[0] + red[1]) + (red[2] + red[3]);
   for (int i = tid; i < a.N * a.nu; i += 256) {
     const int m = i / a.nu, q = i - m * a.nu;
-    u0[int64_t(b) * a.N * a.nu + i] = double(sb[int64_t(m) * a.rs + NX * a.T + q]);
+    u0[int64_t(b) * a.N * a.nu + i] = double(sb[(int64_t(m) * a.rs + NX * a.T + q) * a.Bmax]);
   }
 }
 
@@ -575,11 +588,11 @@ __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a) {
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < ny; i += 1024) {
     const float y = a.yhat[o + i];
-    const float r = y - a.bvec[o + i];
+    const float r = y - a.bvec[i * a.Bmax + b];
     a.cg_r[o + i] = r;
     a.cg_p[o + i] = r;
     a.cg_x[o + i] = 0.f;
-    a.alpha[o + i] = -2.f * a.w[i] * y / a.rho;
+    a.alpha[i * a.Bmax + b] = -2.f * a.w[i] * y / a.rho;
     acc += double(r) * double(r);
   }
   acc = block_sum1024(acc, red);
@@ -612,7 +625,11 @@ __global__ __launch_bounds__(1024) void bcg_step_kernel(BArgs a) {
 
 __global__ __launch_bounds__(256) void bexport_y_kernel(BArgs a, double *out, int B) {
   const int64_t n = int64_t(B) * a.N * a.rs;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) out[i] = double(a.s[i]);
+  const int64_t ny = int64_t(a.N) * a.rs;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int64_t b = i / ny;
+    out[i] = double(a.s[(i - b * ny) * a.Bmax + b]);
+  }
 }
 
 // ------------------------------------------------------------------ engine
@@ -657,6 +674,12 @@ class BatchEngineT final : public BatchEngine {
       rmo[j + 1] = rmo[j] + D * ((k + 31) & ~31);
     }
     a.ktot = koff[N];
+    // dispatch orders: heaviest blocks first (Psi-comp: D_col(j) k_j, Phi-comp: tiles of m)
+    std::vector<int32_t> po(N), fo(N);
+    for (int j = 0; j < N; ++j) po[j] = fo[j] = j;
+    auto psi_cost = [&](int j) { return int64_t(hs.patch[j].size()) * hs.rs * hs.kdim[j]; };
+    std::stable_sort(po.begin(), po.end(), [&](int x, int y) { return psi_cost(x) > psi_cost(y); });
+    std::stable_sort(fo.begin(), fo.end(), [&](int x, int y) { return hs.patch[x].size() > hs.patch[y].size(); });
     std::vector<__bf16> chi(cmo[N]), clo(cmo[N]), rhi(rmo[N]), rlo(rmo[N]);
     const __bf16 z = static_cast<__bf16>(0.f);
     std::fill(chi.begin(), chi.end(), z);
@@ -694,7 +717,7 @@ class BatchEngineT final : public BatchEngine {
         (rc = up(koff, &a.koff, err)) || (rc = up(cmo, &a.ncm_off, err)) || (rc = up(rmo, &a.nrm_off, err)) ||
         (rc = up(chi, &a.ncm_hi, err)) || (rc = up(clo, &a.ncm_lo, err)) || (rc = up(rhi, &a.nrm_hi, err)) ||
         (rc = up(rlo, &a.nrm_lo, err)) || (rc = up(hs.off_ptr, &a.off_ptr, err)) || (rc = up(on2, &a.onorm2, err)) ||
-        (rc = up(hs.w, &a.w64, err)))
+        (rc = up(hs.w, &a.w64, err)) || (rc = up(po, &a.psi_order, err)) || (rc = up(fo, &a.phi_order, err)))
       return rc;
     std::vector<float> offf(hs.off.begin(), hs.off.end()), wf(hs.w.begin(), hs.w.end()),
         lbf(hs.lb.begin(), hs.lb.end()), ubf(hs.ub.begin(), hs.ub.end());
@@ -728,6 +751,9 @@ class BatchEngineT final : public BatchEngine {
       return rc;
     a.init_pass = 0;
     a.wmode = 0;
+    a.src_bs = 1;
+    a.src_rs = bmax;
+    ny_ = int64_t(N) * hs.rs;
     a.phi_mode = 0;
     a.src = nullptr;
     a.dst_k = nullptr;
@@ -749,11 +775,13 @@ class BatchEngineT final : public BatchEngine {
 
   // dst_k = N_j' src for every column subsystem j and instance; wmode 1 also writes the
   // product operand W = ||x0_j||^2 dst_k, wmode 2 W = ||x0_j||^2 (tau + dst_k).
-  int project_t(const float *src, float *dst_k, int wmode, std::string &err) {
+  int project_t(const float *src, int64_t src_bs, int64_t src_rs, float *dst_k, int wmode, std::string &err) {
     BArgs ia = args_;
     ia.init_pass = 1;
     ia.wmode = wmode;
     ia.src = src;
+    ia.src_bs = src_bs;
+    ia.src_rs = src_rs;
     ia.dst_k = dst_k;
     hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, ia);
     BENG_CHECK(hipGetLastError());
@@ -763,7 +791,7 @@ class BatchEngineT final : public BatchEngine {
   int start_alpha(const double *alpha0_dev, std::string &err) override {
     hipLaunchKernelGGL(bwarm_alpha_kernel, dim3(1024), dim3(256), 0, stream_, args_, alpha0_dev, B_);
     BENG_CHECK(hipGetLastError());
-    return project_t(args_.alpha, args_.eta, 2, err);  // plane 0: the previous iterate of iteration 1
+    return project_t(args_.alpha, 1, args_.Bmax, args_.eta, 2, err);  // plane 0: previous iterate of iteration 1
   }
 
   int start_trajectory(const double *y0_dev, int cg_iters, std::string &err) override {
@@ -779,14 +807,14 @@ class BatchEngineT final : public BatchEngine {
     qa.phi_mode = 1;
     int rc;
     for (int k = 0; k < cg_iters; ++k) {
-      if ((rc = project_t(args_.cg_p, args_.eta, 1, err))) return rc;  // eta = N' p, W = ||x0_j||^2 eta
-      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, qa);  // q = M p
+      if ((rc = project_t(args_.cg_p, ny_, 1, args_.eta, 1, err))) return rc;  // eta = N' p, W = ||x0_j||^2 eta
+      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, qa);  // q = M p
       BENG_CHECK(hipGetLastError());
       hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_);
       BENG_CHECK(hipGetLastError());
     }
-    if ((rc = project_t(args_.cg_x, args_.tau, 0, err))) return rc;  // tau = N' beta
-    return project_t(args_.alpha, args_.eta, 2, err);                 // eta = N' alpha^0, W
+    if ((rc = project_t(args_.cg_x, ny_, 1, args_.tau, 0, err))) return rc;  // tau = N' beta
+    return project_t(args_.alpha, 1, args_.Bmax, args_.eta, 2, err);         // eta = N' alpha^0, W
   }
 
   float *yhat() override { return args_.yhat; }
@@ -805,7 +833,7 @@ class BatchEngineT final : public BatchEngine {
 
   int launch_one(int k, std::string &err) override {
     if (k == 0)
-      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_);
+      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, args_);
     else if (k == 1)
       hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, args_);
     else
@@ -815,7 +843,7 @@ class BatchEngineT final : public BatchEngine {
   }
 
   int iteration(std::string &err) override {
-    hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_);
+    hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, args_);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, args_);
     BENG_CHECK(hipGetLastError());
@@ -866,6 +894,7 @@ class BatchEngineT final : public BatchEngine {
   hipStream_t stream_ = nullptr;
   BArgs args_{};
   int B_ = 0;
+  int64_t ny_ = 0;  // N * rs
   std::vector<void *> owned_;
 };
 

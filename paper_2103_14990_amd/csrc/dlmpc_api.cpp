@@ -42,7 +42,7 @@ struct dlmpc_problem {
   // learned warm start: network, predicted multipliers [Bmax][R], cold re-solve staging
   std::unique_ptr<dlmpc::WarmStart> ws;
   double *d_fx0 = nullptr, *d_fu0 = nullptr, *d_falpha = nullptr, *d_fy = nullptr;
-  int cg_iters = 16;
+  int cg_iters = 12;
   hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
 };
 
@@ -165,7 +165,7 @@ int setup_batch(dlmpc_problem *p) {
   const size_t R = size_t(hs.N) * hs.rs;
   API_HIP(hipMalloc(&p->d_fy, sizeof(double) * size_t(B) * R));
   API_HIP(hipMalloc(&p->d_falpha, sizeof(double) * size_t(B) * R));
-  p->cg_iters = p->opt.warm_cg_iters > 0 ? p->opt.warm_cg_iters : 16;
+  p->cg_iters = p->opt.warm_cg_iters > 0 ? p->opt.warm_cg_iters : 12;
   API_HIP(hipMalloc(&p->d_fx0, sizeof(double) * size_t(B) * hs.N * hs.nx));
   API_HIP(hipMalloc(&p->d_fu0, sizeof(double) * size_t(B) * hs.N * hs.nu));
   API_HIP(hipEventCreate(&p->ev_w0));
@@ -570,11 +570,18 @@ int dlmpc_time_batch_kernels(dlmpc_problem *p, int32_t B, const double *x0_dev, 
   if (B < 1 || B > p->beng->bmax()) return fail(DLMPC_EINVAL, "batch size out of range");
   API_HIP(hipSetDevice(p->opt.device));
   std::string err;
-  // cold start, no stop (eps < 0); two untimed iterations first (the cold start skips the
-  // products in its first two)
-  int rc = p->beng->precompute(x0_dev, B, iters + 2, -1.0, 0, err);
-  for (int i = 0; i < 2 && !rc; ++i) rc = p->beng->iteration(err);
-  if (rc) return fail(rc, err);
+  // Warm start from alpha0 = 0 (every iteration then runs the full products, unlike the
+  // first two of the cold start) and no stop (eps < 0).
+  const size_t nrow = size_t(B) * p->hs.N * p->hs.rs;
+  double *zero = nullptr;
+  API_HIP(hipMalloc(&zero, sizeof(double) * nrow));
+  int rc = hipMemsetAsync(zero, 0, sizeof(double) * nrow, p->stream) == hipSuccess ? DLMPC_OK : DLMPC_EDEVICE;
+  if (!rc) rc = p->beng->precompute(x0_dev, B, iters, -1.0, 1, err);
+  if (!rc) rc = p->beng->start_alpha(zero, err);
+  const bool dev_ok = hipStreamSynchronize(p->stream) == hipSuccess;
+  (void)hipFree(zero);
+  if (!dev_ok) return fail(DLMPC_EDEVICE, "device error while preparing the timing run");
+  if (rc) return fail(rc, err.empty() ? std::string("hipMemsetAsync failed") : err);
   constexpr int nk = DLMPC_BATCH_TIMED_KERNELS;
   std::vector<hipEvent_t> ev(size_t(nk) * iters + 1);
   for (auto &e : ev) API_HIP(hipEventCreate(&e));

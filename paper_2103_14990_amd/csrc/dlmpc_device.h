@@ -115,7 +115,8 @@ struct BArgs {
   float rho;
   const int64_t *tile_off, *rt_ptr, *rt_tile;
   const int32_t *rt_col, *kdim, *tile_rsub;
-  const int64_t *koff;      // [N+1] offsets of the k-space vectors (multiples of 16)
+  const int64_t *koff;      // [N+1] offsets of the k-space vectors (multiples of 32)
+  const int32_t *psi_order, *phi_order;  // [N] block -> subsystem dispatch orders
   const int64_t *ncm_off;   // [N+1] column-major copy: k16(j) columns of ld64(j) rows
   const int64_t *nrm_off;   // [N+1] row-major copy: D(j) rows of k32(j) entries
   const __bf16 *ncm_hi, *ncm_lo, *nrm_hi, *nrm_lo;
@@ -124,10 +125,10 @@ struct BArgs {
   const float *w, *lb, *ub; // [N*rs]
   const double *w64;
   const double *onorm2;     // [N*nx] ||o_c||^2
-  float *alpha;             // [2][Bmax][N*rs] (iteration parity)
-  float *tau, *eta;         // [Bmax][Ktot]
+  float *alpha;             // [2][N*rs][Bmax] (iteration parity; instance index fastest)
+  float *tau, *eta;         // [Ktot][Bmax] (instance index fastest)
   float *xn, *nrm;          // [Bmax][N] ||x0_j||^2 and ||x_r||^2 of row subsystem m
-  float *bvec, *s;          // [Bmax][N*rs]
+  float *bvec, *s;          // [N*rs][Bmax]
   float *x0;                // [Bmax][N*nx]
   BCtl *ictl;               // [Bmax]
   unsigned long long *slot; // [Bmax][2] residual maxima of the current iteration (ordered bits)
@@ -138,6 +139,7 @@ struct BArgs {
   // phi_mode 1: bphi_kernel writes cg_q = sum_{j in P(m)} ||x0_j||^2 N_j eta_j (rows of m).
   int32_t init_pass, phi_mode, wmode;
   const float *src;
+  int64_t src_bs, src_rs;   // element (b, row) of src at b * src_bs + row * src_rs
   float *dst_k;
   // Right operand of the Phi-comp products, W_j = ||x0_j||^2 (tau_j + eta_j) as bf16 hi + lo,
   // element (b, k) of subsystem j at ((koff_j + k) / 8 * Bw + b) * 8 + k % 8 with Bw = Bmax
