@@ -42,8 +42,9 @@ constexpr int kPsiThreads = 512;  // 8 waves
 constexpr int kPsiWaves = kPsiThreads / 64;
 constexpr int kMTW = 4;           // M tiles (16 basis vectors) per wave: k_j <= 512
 constexpr int kKC = 64;           // support rows staged per chunk in bpsi_kernel
-constexpr int kRT = 4;            // row tiles of 16 per subsystem in bphi_kernel (rs <= 64)
+constexpr int kRPT = kKC / 8;     // staged rows per thread (8 row groups of 64 threads)
 constexpr int kPhiThreads = 512;  // bphi_kernel: 4 instance tiles x 2 halves of the tile list
+constexpr int kMaxPatch = 64;     // subsystems per d-hop patch (batched engine)
 
 __device__ __forceinline__ unsigned long long ord_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(v));
@@ -163,14 +164,18 @@ __global__ __launch_bounds__(256) void bexport_alpha_kernel(BArgs a, double *out
 // ------------------------------------------------------------------ Phi-comp (batched)
 
 // One block per row subsystem m (8 waves); wave w owns instances [16 nt, 16 nt + 16), nt = w % 4,
-// for every other tile of m's row (half w / 4), all rows of m; the two halves are summed in a
-// fixed order. The right operand W_j = ||x0_j||^2 (tau_j + eta_j) is read pre-split (bf16 hi/lo,
-// written by bpsi_kernel) once per block; the rows of N_j that belong to m are the left operand.
-template <int NX>
+// for every other tile of m's row (half w / 4), all NRT row tiles of m; the two halves are summed
+// in a fixed order. The right operand W_j = ||x0_j||^2 (tau_j + eta_j) is read pre-split (bf16
+// hi/lo, written by bpsi_kernel) once per block; the rows of N_j that belong to m (fragment
+// order) are the left operand. The (tile, k-step) sequence of a wave is one flat loop whose
+// next step's operands are in flight while the current step's products run.
+template <int NX, int NRT>
 __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   if (a.ctl->stop) return;
   __shared__ float Ct[2][64][kBMax + 1];
   __shared__ double red[kPhiThreads / 64][kBMax];
+  __shared__ int64_t s_fb[kMaxPatch], s_w8[kMaxPatch];
+  __shared__ int s_nkt[kMaxPatch];
   const int m = a.phi_order[blockIdx.x], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nt = wave & 3, half = wave >> 2;
   const int rs = a.rs, B = a.ctl->batch;
@@ -178,44 +183,74 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   const bool cgm = a.phi_mode != 0;  // set-up pass: q = sum_j ||x0_j||^2 N_j eta_j
   const int it = a.ctl->iters + 1;
   const float coef = warm ? 1.f : (it == 1 ? 0.f : (it == 2 ? 2.f : 1.f));
-  const int nrt = (rs + 15) >> 4;
-  f32x4 acc[kRT];
+  const int64_t q0 = a.rt_ptr[m];
+  const int pm = int(a.rt_ptr[m + 1] - q0);
+  for (int t = tid; t < pm; t += kPhiThreads) {  // per-tile descriptors of m's row
+    const int j = a.rt_col[q0 + t];
+    s_fb[t] = a.nf_off[a.rt_tile[q0 + t]];
+    s_w8[t] = a.koff[j] >> 3;
+    s_nkt[t] = int(a.koff[j + 1] - a.koff[j]) >> 5;
+  }
+  __syncthreads();
+  constexpr int nrt = NRT;
+  f32x4 acc[NRT];
 #pragma unroll
-  for (int rt = 0; rt < kRT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int rt = 0; rt < NRT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
   // from a cold start tau = eta = 0 before the third iteration
-  if ((cgm || warm || it >= 3) && nt * 16 < B) {
+  if ((cgm || warm || it >= 3) && nt * 16 < B && half < pm) {
     const int b = nt * 16 + (lane & 15);
-    for (int64_t q = a.rt_ptr[m] + half; q < a.rt_ptr[m + 1]; q += 2) {
-      const int j = a.rt_col[q];
-      const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
-      const int k32 = int(a.koff[j + 1] - a.koff[j]);
-      const int64_t koff8 = a.koff[j] >> 3;
-      const int64_t arow = a.nrm_off[j] + int64_t(ro) * k32 + 8 * (lane >> 4);
-      for (int i0 = 0; i0 < k32; i0 += 32) {
-        const int64_t wi = ((koff8 + (i0 >> 3) + (lane >> 4)) * a.Bw + b) * 8;
-        const bf16x8 bh = load8(a.w_hi + wi), bl = load8(a.w_lo + wi);
+    bf16x8 wh, wl, ah[NRT], al[NRT];
+    auto load_step = [&](int t, int kt, bf16x8 &ph, bf16x8 &pl, bf16x8 *qh, bf16x8 *ql) {
+      const int64_t wi = ((s_w8[t] + 4 * kt + (lane >> 4)) * a.Bw + b) * 8;
+      ph = load8(a.w_hi + wi);
+      pl = load8(a.w_lo + wi);
+      const int64_t fb = s_fb[t] + lane * 8 + int64_t(kt) * 1024, stride = int64_t(s_nkt[t]) * 1024;
 #pragma unroll
-        for (int rt = 0; rt < kRT; ++rt) {
-          if (rt >= nrt) break;
-          const int row = rt * 16 + (lane & 15);
-          bf16x8 ah = {}, al = {};
-          if (row < rs) {
-            const int64_t ai = arow + int64_t(row) * k32 + i0;
-            ah = load8(a.nrm_hi + ai);
-            al = load8(a.nrm_lo + ai);
-          }
-          acc[rt] = mfma3(ah, al, bh, bl, acc[rt]);
-        }
+      for (int rt = 0; rt < NRT; ++rt) {  // rows past rs are zero in the fragments
+        qh[rt] = load8(a.nf + fb + rt * stride);
+        ql[rt] = load8(a.nf + fb + rt * stride + 512);
       }
+    };
+    // two operand sets used alternately: the loads of one are in flight while the products of
+    // the other run (no register copies between steps)
+    // (the loads of the step after the last one repeat the last step: always issued, so that
+    // the number of loads in flight is the same on every path)
+    bf16x8 wh2, wl2, ah2[NRT], al2[NRT];
+    int t = half, kt = 0;
+    auto advance = [&]() {
+      int tn = t, kn = kt + 1;
+      if (kn >= s_nkt[t]) {
+        tn = t + 2;
+        kn = 0;
+      }
+      const bool more = tn < pm;
+      if (more) {
+        t = tn;
+        kt = kn;
+      }
+      return more;
+    };
+    load_step(t, kt, wh, wl, ah, al);
+    while (true) {
+      bool more = advance();
+      load_step(t, kt, wh2, wl2, ah2, al2);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt) acc[rt] = mfma3(ah[rt], al[rt], wh, wl, acc[rt]);
+      if (!more) break;
+      more = advance();
+      load_step(t, kt, wh, wl, ah, al);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt) acc[rt] = mfma3(ah2[rt], al2[rt], wh2, wl2, acc[rt]);
+      if (!more) break;
     }
   }
   // C tile: lane holds rows 16 rt + 4 (lane / 16) + e of instance column 16 nt + lane % 16
 #pragma unroll
-  for (int rt = 0; rt < kRT; ++rt) {
-    if (rt >= nrt) break;
+  for (int rt = 0; rt < nrt; ++rt)
 #pragma unroll
     for (int e = 0; e < 4; ++e) Ct[half][rt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[rt][e];
-  }
   __syncthreads();
   if (cgm) {
     for (int idx = tid; idx < rs * B; idx += blockDim.x) {
@@ -266,15 +301,20 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
 
 // One block per column subsystem j: eta_j = N_j' A_j over K-chunks of its support rows staged
 // (as bf16 hi/lo) in LDS; wave w owns the M tiles w, w + 8, ... of the basis vectors.
-template <int NX>
+template <int NX, int MTW>
 __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   if (a.ctl->stop) return;
   __shared__ __align__(16) __bf16 sh_hi[kBMax][kKC + 8];
   __shared__ __align__(16) __bf16 sh_lo[kBMax][kKC + 8];
+  __shared__ int s_rsub[kMaxPatch];
   __shared__ double red_e[kPsiWaves][kBMax], red_d[kPsiWaves][kBMax];
   __shared__ double red_od[kBMax][8][NX];
-  // blocks in decreasing order of work (D_col(j) k_j), so that the heavy ones start first
-  const int j = a.psi_order[blockIdx.x], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // One work unit per block: rows [r_begin, r_end) of column subsystem j (part `part` of
+  // np), units in decreasing order of work so that the heavy ones start first.
+  __shared__ int s_last;
+  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = a.pu_j[u], r_begin = a.pu_r0[u], r_end = a.pu_r1[u], part = a.pu_p[u];
+  const int np = a.pj_n[j];
   const int rs = a.rs, B = a.ctl->batch;
   const bool warm = a.ctl->warm != 0;
   const int it = a.ctl->iters + 1;
@@ -282,7 +322,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   const int D = int(a.tile_off[j + 1] - tb) * rs;
   const int k = a.kdim[j];
   const int kc16 = (k + 15) & ~15;
-  const int ld64 = (D + 63) & ~63;
+  const int ldK = (D + kKC - 1) / kKC * kKC;  // support rows padded to whole chunks
   const int ld4 = (D + 3) & ~3;
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
   const bool initp = a.init_pass != 0;
@@ -296,7 +336,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   const int sb = tid & 63, sub = tid >> 6;
 
   if (!warm && it == 1 && !initp) {  // alpha^1 = 0: Psi^1 = o, residuals ||o_c||, eta stays 0
-    if (tid < B && !a.ictl[tid].stop) {
+    if (part == 0 && tid < B && !a.ictl[tid].stop) {
       double mx = 0.0;
 #pragma unroll
       for (int c = 0; c < NX; ++c) mx = fmax(mx, sqrt(a.onorm2[j * NX + c]));
@@ -306,42 +346,58 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
     return;
   }
 
-  f32x4 acc[kMTW][kNT];
+  for (int t = tid; t < D / rs; t += kPsiThreads) s_rsub[t] = a.tile_rsub[tb + t];
+  __syncthreads();
+  const int nmt = kc16 >> 4, nkt = ldK >> 5;
+  f32x4 acc[MTW][kNT];
 #pragma unroll
-  for (int t = 0; t < kMTW; ++t)
+  for (int t = 0; t < MTW; ++t)
 #pragma unroll
     for (int nt = 0; nt < kNT; ++nt) acc[t][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
   double od[NX];
 #pragma unroll
   for (int c = 0; c < NX; ++c) od[c] = 0.0;
   const bool sact = sb < B;
-  // staging values of instance sb for support rows r0 + 8 sub .. + 7 (zero past D)
+  // Staging values of instance sb for support rows r0 + 8 sub .. + 7 (zero past D): eight
+  // independent loads (clamped address, then a select), the row's subsystem from LDS.
   auto fetch = [&](int r0, float *v) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int rr = r0 + 8 * sub + e;
-      float an = 0.f;
-      if (sact && rr < D) {
-        const int ta = rr / rs, l = rr - ta * rs;
-        const int mm = a.tile_rsub[tb + ta];
-        an = stage_src[int64_t(sb) * a.src_bs + (int64_t(mm) * rs + l) * a.src_rs];
-        if (cold2) {
-#pragma unroll
-          for (int c = 0; c < NX; ++c) od[c] += double(an) * double(a.off[a.off_ptr[j] + int64_t(c) * ld4 + rr]);
-        }
-      }
-      v[e] = an;
+    for (int e = 0; e < kRPT; ++e) {
+      const int rr = r0 + kRPT * sub + e;
+      const bool ok = sact && rr < D;
+      const int rc = ok ? rr : 0;
+      const int ta = rc / rs, l = rc - ta * rs;
+      const float x = stage_src[int64_t(ok ? sb : 0) * a.src_bs + (int64_t(s_rsub[ta]) * rs + l) * a.src_rs];
+      v[e] = ok ? x : 0.f;
     }
   };
-  float v[8];
-  fetch(0, v);
-  for (int r0 = 0; r0 < ld64; r0 += kKC) {
-    bf16x8 vh, vl;
-    split8(v, vh, vl);
-    *reinterpret_cast<bf16x8 *>(&sh_hi[sb][8 * sub]) = vh;
-    *reinterpret_cast<bf16x8 *>(&sh_lo[sb][8 * sub]) = vl;
+  float v[kRPT];
+  fetch(r_begin, v);
+  for (int r0 = r_begin; r0 < r_end; r0 += kKC) {
+    // this chunk's basis fragments (both k-steps) are issued before the staging barrier
+    bf16x8 ah[kKC / 32][MTW], al[kKC / 32][MTW];
+#pragma unroll
+    for (int ks = 0; ks < kKC / 32; ++ks)
+#pragma unroll
+      for (int t = 0; t < MTW; ++t) {
+        const int mt = min(wave + kPsiWaves * t, nmt - 1);  // tiles past nmt: loaded, unused
+        const int64_t ai = a.ntf_off[j] + (int64_t(mt) * nkt + (r0 >> 5) + ks) * 1024 + lane * 8;
+        ah[ks][t] = load8(a.ntf + ai);
+        al[ks][t] = load8(a.ntf + ai + 512);
+      }
+    __builtin_amdgcn_sched_barrier(0);  // fragments in flight before the staging barrier
+#pragma unroll
+    for (int h = 0; h < kRPT / 8; ++h) {
+      bf16x8 vh, vl;
+      split8(v + 8 * h, vh, vl);
+      *reinterpret_cast<bf16x8 *>(&sh_hi[sb][kRPT * sub + 8 * h]) = vh;
+      *reinterpret_cast<bf16x8 *>(&sh_lo[sb][kRPT * sub + 8 * h]) = vl;
+    }
     __syncthreads();
-    if (r0 + kKC < ld64) fetch(r0 + kKC, v);  // next chunk in flight during the products
+    // next chunk in flight during the products (the last chunk fetches itself again, so the
+    // loads in flight are the same on every path)
+    fetch(r0 + kKC < r_end ? r0 + kKC : r0, v);
+    __builtin_amdgcn_sched_barrier(0);  // next chunk's staging loads ahead of the products
 #pragma unroll
     for (int ks = 0; ks < kKC / 32; ++ks) {
       const int kr = ks * 32 + 8 * (lane >> 4);
@@ -352,26 +408,83 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
         bl[nt] = *reinterpret_cast<const bf16x8 *>(&sh_lo[nt * 16 + (lane & 15)][kr]);
       }
 #pragma unroll
-      for (int t = 0; t < kMTW; ++t) {
-        const int mtile = wave + kPsiWaves * t;
-        if (mtile * 16 >= kc16) break;
-        const int64_t ai = a.ncm_off[j] + int64_t(mtile * 16 + (lane & 15)) * ld64 + r0 + kr;
-        const bf16x8 ah = load8(a.ncm_hi + ai), al = load8(a.ncm_lo + ai);
+      for (int t = 0; t < MTW; ++t) {
+        if (wave + kPsiWaves * t >= nmt) break;
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt) {
           if (nt * 16 >= B) break;
-          acc[t][nt] = mfma3(ah, al, bh[nt], bl[nt], acc[t][nt]);
+          acc[t][nt] = mfma3(ah[ks][t], al[ks][t], bh[nt], bl[nt], acc[t][nt]);
         }
       }
     }
     __syncthreads();
+  }
+  if (cold2) {  // offset terms of the second cold iteration: sum_rows alpha o_c over the unit
+    for (int r0 = r_begin; r0 < r_end; r0 += kKC) {
+      fetch(r0, v);
+#pragma unroll
+      for (int e = 0; e < kRPT; ++e) {
+        const int rr = r0 + kRPT * sub + e;
+        if (sact && rr < D) {
+#pragma unroll
+          for (int c = 0; c < NX; ++c) od[c] += double(v[e]) * double(a.off[a.off_ptr[j] + int64_t(c) * ld4 + rr]);
+        }
+      }
+    }
+  }
+  if (np > 1) {
+    // Partial sums of a split column block: store, publish, and let the last part to finish
+    // add all parts in part order (the result does not depend on which part is last).
+    float *P = a.ppart + a.pj_off[j];
+    double *Q = a.ppod + int64_t(a.pj_first[j]) * kBMax * 8 * NX;
+#pragma unroll
+    for (int t = 0; t < MTW; ++t) {
+      const int mtile = wave + kPsiWaves * t;
+      if (mtile * 16 >= kc16) break;
+#pragma unroll
+      for (int nt = 0; nt < kNT; ++nt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = mtile * 16 + 4 * (lane >> 4) + e;
+          P[(int64_t(part) * kc16 + i) * kBMax + nt * 16 + (lane & 15)] = acc[t][nt][e];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) Q[((int64_t(part) * kBMax + sb) * 8 + sub) * NX + c] = od[c];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&a.pcnt[j], 1) == np - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+#pragma unroll
+    for (int t = 0; t < MTW; ++t) {
+      const int mtile = wave + kPsiWaves * t;
+      if (mtile * 16 >= kc16) break;
+#pragma unroll
+      for (int nt = 0; nt < kNT; ++nt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = mtile * 16 + 4 * (lane >> 4) + e;
+          float sum = 0.f;
+          for (int q = 0; q < np; ++q) sum += P[(int64_t(q) * kc16 + i) * kBMax + nt * 16 + (lane & 15)];
+          acc[t][nt][e] = sum;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      double sum = 0.0;
+      for (int q = 0; q < np; ++q) sum += Q[((int64_t(q) * kBMax + sb) * 8 + sub) * NX + c];
+      od[c] = sum;
+    }
+    if (tid == 0) a.pcnt[j] = 0;  // ready for the next launch
   }
   // eta_new, tau and the k-space residual terms; lane holds basis rows 4 (lane/16) + e of tile.
   double e2[kNT], d2[kNT];
 #pragma unroll
   for (int nt = 0; nt < kNT; ++nt) e2[nt] = d2[nt] = 0.0;
 #pragma unroll
-  for (int t = 0; t < kMTW; ++t) {
+  for (int t = 0; t < MTW; ++t) {
     const int mtile = wave + kPsiWaves * t;
     if (mtile * 16 >= kc16) break;
 #pragma unroll
@@ -651,10 +764,12 @@ class BatchEngineT final : public BatchEngine {
       err = "max_batch must be in 1..64";
       return DLMPC_EINVAL;
     }
-    if (hs.k_max > kPsiWaves * kMTW * 16 || hs.rs > 64) {
-      err = "batched engine needs k_j <= 512 and nx*T + nu*(T-1) <= 64";
+    if (hs.k_max > kPsiWaves * kMTW * 16 || hs.rs > 64 || hs.p_max > kMaxPatch) {
+      err = "batched engine needs k_j <= 512, nx*T + nu*(T-1) <= 64 and d-hop patches of <= 64 subsystems";
       return DLMPC_EINVAL;
     }
+    nrt_ = (hs.rs + 15) / 16;
+    mtw_ = std::max(1, ((hs.k_max + 15) / 16 + kPsiWaves - 1) / kPsiWaves);
     hs_ = &hs;
     stream_ = s;
     BArgs &a = args_;
@@ -666,39 +781,100 @@ class BatchEngineT final : public BatchEngine {
     a.Bmax = bmax;
     a.rho = float(rho);
     const int N = hs.N;
-    std::vector<int64_t> koff(N + 1, 0), cmo(N + 1, 0), rmo(N + 1, 0);
+    // Null bases in matrix-core fragment order (bf16 hi and lo of one fragment adjacent, 1024
+    // values): a wave's load of one fragment is one contiguous 1 KB block per half.
+    //  ntf (left operand of N_j' alpha): fragment (M-tile mt of 16 basis vectors, K-step kt of
+    //      32 support rows) of j at ntf_off[j] + (mt * nkt + kt) * 1024, lane l, element e:
+    //      N_j[32 kt + 8 (l / 16) + e][16 mt + l % 16];
+    //  nf (left operand of N_j W_j for the rows of one tile (j, m)): fragment (row tile rt of 16
+    //      rows of m, K-step kt of 32 basis vectors) at nf_off[tile] + (rt * nkt + kt) * 1024:
+    //      N_j[ro + 16 rt + l % 16][32 kt + 8 (l / 16) + e]; zero outside N_j.
+    const int nrt = (hs.rs + 15) / 16;
+    std::vector<int64_t> koff(N + 1, 0), ntf_off(N + 1, 0), nf_off(hs.n_tiles + 1, 0);
     for (int j = 0; j < N; ++j) {
       const int64_t D = int64_t(hs.patch[j].size()) * hs.rs, k = hs.kdim[j];
-      koff[j + 1] = koff[j] + ((k + 31) & ~31);
-      cmo[j + 1] = cmo[j] + ((k + 15) & ~15) * ((D + 63) & ~63);
-      rmo[j + 1] = rmo[j] + D * ((k + 31) & ~31);
+      const int64_t k32 = (k + 31) & ~31;
+      koff[j + 1] = koff[j] + k32;
+      ntf_off[j + 1] = ntf_off[j] + ((k + 15) & ~15) / 16 * ((D + kKC - 1) / kKC * kKC / 32) * 1024;
+      for (size_t t = 0; t < hs.patch[j].size(); ++t) {
+        const int64_t tile = hs.tile_off[j] + int64_t(t);
+        nf_off[tile + 1] = nf_off[tile] + int64_t(nrt) * (k32 / 32) * 1024;
+      }
     }
     a.ktot = koff[N];
-    // dispatch orders: heaviest blocks first (Psi-comp: D_col(j) k_j, Phi-comp: tiles of m)
-    std::vector<int32_t> po(N), fo(N);
-    for (int j = 0; j < N; ++j) po[j] = fo[j] = j;
-    auto psi_cost = [&](int j) { return int64_t(hs.patch[j].size()) * hs.rs * hs.kdim[j]; };
-    std::stable_sort(po.begin(), po.end(), [&](int x, int y) { return psi_cost(x) > psi_cost(y); });
+    // Psi-comp work units: column blocks whose basis is more than eight times the mean are
+    // split into np row ranges of whole kKC-row chunks (measured: splitting blocks of two to
+    // four times the mean costs more in partial sums than it gains in balance); units are
+    // dispatched heaviest first.
+    std::vector<int64_t> cost(N);
+    int64_t csum = 0;
+    for (int j = 0; j < N; ++j) {
+      const int64_t D = int64_t(hs.patch[j].size()) * hs.rs;
+      cost[j] = ((D + kKC - 1) / kKC * kKC) * ((hs.kdim[j] + 15) & ~15);
+      csum += cost[j];
+    }
+    const int64_t cap = std::max<int64_t>(1, 8 * csum / N);
+    struct Unit { int32_t j, r0, r1, p; int64_t c; };
+    std::vector<Unit> units;
+    std::vector<int32_t> pj_n(N, 1), pj_first(N, 0);
+    std::vector<int64_t> pj_off(N, 0);
+    int64_t poff = 0;
+    int32_t pfirst = 0;
+    for (int j = 0; j < N; ++j) {
+      const int D = int(hs.patch[j].size()) * hs.rs, chunks = (D + kKC - 1) / kKC;
+      const int np = int(std::min<int64_t>(chunks, (cost[j] + cap - 1) / cap));
+      const int per = (chunks + np - 1) / np;
+      int p = 0;
+      for (int c0 = 0; c0 < chunks; c0 += per, ++p)
+        units.push_back({j, kKC * c0, kKC * std::min(chunks, c0 + per), p,
+                         cost[j] * (std::min(chunks, c0 + per) - c0) / chunks});
+      pj_n[j] = p;
+      if (p > 1) {
+        pj_off[j] = poff;
+        pj_first[j] = pfirst;
+        poff += int64_t(p) * ((hs.kdim[j] + 15) & ~15) * kBMax;
+        pfirst += p;
+      }
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit &x, const Unit &y) { return x.c > y.c; });
+    n_units_ = int(units.size());
+    std::vector<int32_t> pu_j(n_units_), pu_r0(n_units_), pu_r1(n_units_), pu_p(n_units_);
+    for (int q = 0; q < n_units_; ++q) {
+      pu_j[q] = units[q].j;
+      pu_r0[q] = units[q].r0;
+      pu_r1[q] = units[q].r1;
+      pu_p[q] = units[q].p;
+    }
+    // Phi-comp dispatch order: row subsystems with the most tiles first
+    std::vector<int32_t> fo(N);
+    for (int j = 0; j < N; ++j) fo[j] = j;
     std::stable_sort(fo.begin(), fo.end(), [&](int x, int y) { return hs.patch[x].size() > hs.patch[y].size(); });
-    std::vector<__bf16> chi(cmo[N]), clo(cmo[N]), rhi(rmo[N]), rlo(rmo[N]);
     const __bf16 z = static_cast<__bf16>(0.f);
-    std::fill(chi.begin(), chi.end(), z);
-    std::fill(clo.begin(), clo.end(), z);
-    std::fill(rhi.begin(), rhi.end(), z);
-    std::fill(rlo.begin(), rlo.end(), z);
+    std::vector<__bf16> ntf(ntf_off[N], z), nf(nf_off[hs.n_tiles], z);
     for (int j = 0; j < N; ++j) {
       const int D = int(hs.patch[j].size()) * hs.rs, k = hs.kdim[j], ld = padded_ld(D);
-      const int ld64 = (D + 63) & ~63, k32 = (k + 31) & ~31;
+      const int nkt_c = (D + kKC - 1) / kKC * kKC / 32, nkt_r = ((k + 31) & ~31) / 32;
       const double *Nj = hs.nb.data() + hs.nb_off[j];
+      auto put = [&](std::vector<__bf16> &dst, int64_t at, double v) {
+        const float x = float(v);
+        const __bf16 h = static_cast<__bf16>(x);
+        dst[at] = h;
+        dst[at + 512] = static_cast<__bf16>(x - static_cast<float>(h));
+      };
       for (int i = 0; i < k; ++i)
         for (int r = 0; r < D; ++r) {
-          const float x = float(Nj[size_t(i) * ld + r]);
-          const __bf16 h = static_cast<__bf16>(x);
-          const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
-          chi[cmo[j] + size_t(i) * ld64 + r] = h;
-          clo[cmo[j] + size_t(i) * ld64 + r] = l;
-          rhi[rmo[j] + size_t(r) * k32 + i] = h;
-          rlo[rmo[j] + size_t(r) * k32 + i] = l;
+          const double v = Nj[size_t(i) * ld + r];
+          {  // ntf: M = basis i, K = row r
+            const int mt = i / 16, kt = r / 32, kk = r % 32;
+            const int l = (i % 16) + 16 * (kk / 8), e = kk % 8;
+            put(ntf, ntf_off[j] + (int64_t(mt) * nkt_c + kt) * 1024 + l * 8 + e, v);
+          }
+          {  // nf: M = row of the tile, K = basis i
+            const int t = r / hs.rs, rr = r % hs.rs;
+            const int rt = rr / 16, kt = i / 32, kk = i % 32;
+            const int l = (rr % 16) + 16 * (kk / 8), e = kk % 8;
+            put(nf, nf_off[hs.tile_off[j] + t] + (int64_t(rt) * nkt_r + kt) * 1024 + l * 8 + e, v);
+          }
         }
     }
     std::vector<double> on2(size_t(N) * NX, 0.0);
@@ -714,11 +890,18 @@ class BatchEngineT final : public BatchEngine {
     if ((rc = up(hs.tile_off, &a.tile_off, err)) || (rc = up(hs.rt_ptr, &a.rt_ptr, err)) ||
         (rc = up(hs.rt_tile, &a.rt_tile, err)) || (rc = up(hs.rt_col, &a.rt_col, err)) ||
         (rc = up(hs.kdim, &a.kdim, err)) || (rc = up(hs.tile_rsub, &a.tile_rsub, err)) ||
-        (rc = up(koff, &a.koff, err)) || (rc = up(cmo, &a.ncm_off, err)) || (rc = up(rmo, &a.nrm_off, err)) ||
-        (rc = up(chi, &a.ncm_hi, err)) || (rc = up(clo, &a.ncm_lo, err)) || (rc = up(rhi, &a.nrm_hi, err)) ||
-        (rc = up(rlo, &a.nrm_lo, err)) || (rc = up(hs.off_ptr, &a.off_ptr, err)) || (rc = up(on2, &a.onorm2, err)) ||
-        (rc = up(hs.w, &a.w64, err)) || (rc = up(po, &a.psi_order, err)) || (rc = up(fo, &a.phi_order, err)))
+        (rc = up(koff, &a.koff, err)) || (rc = up(ntf_off, &a.ntf_off, err)) || (rc = up(nf_off, &a.nf_off, err)) ||
+        (rc = up(ntf, &a.ntf, err)) || (rc = up(nf, &a.nf, err)) ||
+        (rc = up(hs.off_ptr, &a.off_ptr, err)) || (rc = up(on2, &a.onorm2, err)) ||
+        (rc = up(hs.w, &a.w64, err)) || (rc = up(fo, &a.phi_order, err)) || (rc = up(pu_j, &a.pu_j, err)) ||
+        (rc = up(pu_r0, &a.pu_r0, err)) || (rc = up(pu_r1, &a.pu_r1, err)) || (rc = up(pu_p, &a.pu_p, err)) ||
+        (rc = up(pj_n, &a.pj_n, err)) || (rc = up(pj_first, &a.pj_first, err)) || (rc = up(pj_off, &a.pj_off, err)))
       return rc;
+    if ((rc = al(&a.ppart, size_t(std::max<int64_t>(poff, 1)), err)) ||
+        (rc = al(&a.ppod, size_t(std::max<int32_t>(pfirst, 1)) * kBMax * 8 * NX, err)) ||
+        (rc = al(&a.pcnt, size_t(N), err)))
+      return rc;
+    BENG_CHECK(hipMemset(a.pcnt, 0, sizeof(int32_t) * N));
     std::vector<float> offf(hs.off.begin(), hs.off.end()), wf(hs.w.begin(), hs.w.end()),
         lbf(hs.lb.begin(), hs.lb.end()), ubf(hs.ub.begin(), hs.ub.end());
     if ((rc = up(offf, &a.off, err)) || (rc = up(wf, &a.w, err)) || (rc = up(lbf, &a.lb, err)) ||
@@ -783,7 +966,7 @@ class BatchEngineT final : public BatchEngine {
     ia.src_bs = src_bs;
     ia.src_rs = src_rs;
     ia.dst_k = dst_k;
-    hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, ia);
+    launch_psi(ia);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -808,7 +991,7 @@ class BatchEngineT final : public BatchEngine {
     int rc;
     for (int k = 0; k < cg_iters; ++k) {
       if ((rc = project_t(args_.cg_p, ny_, 1, args_.eta, 1, err))) return rc;  // eta = N' p, W = ||x0_j||^2 eta
-      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, qa);  // q = M p
+      launch_phi(qa);  // q = M p
       BENG_CHECK(hipGetLastError());
       hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_);
       BENG_CHECK(hipGetLastError());
@@ -833,9 +1016,9 @@ class BatchEngineT final : public BatchEngine {
 
   int launch_one(int k, std::string &err) override {
     if (k == 0)
-      hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, args_);
+      launch_phi(args_);
     else if (k == 1)
-      hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, args_);
+      launch_psi(args_);
     else
       hipLaunchKernelGGL(bdecide_kernel, dim3(1), dim3(64), 0, stream_, args_);
     BENG_CHECK(hipGetLastError());
@@ -843,9 +1026,9 @@ class BatchEngineT final : public BatchEngine {
   }
 
   int iteration(std::string &err) override {
-    hipLaunchKernelGGL((bphi_kernel<NX>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, args_);
+    launch_phi(args_);
     BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((bpsi_kernel<NX>), dim3(hs_->N), dim3(kPsiThreads), 0, stream_, args_);
+    launch_psi(args_);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL(bdecide_kernel, dim3(1), dim3(64), 0, stream_, args_);
     BENG_CHECK(hipGetLastError());
@@ -893,8 +1076,27 @@ class BatchEngineT final : public BatchEngine {
   const HostSetup *hs_ = nullptr;
   hipStream_t stream_ = nullptr;
   BArgs args_{};
+  // instantiations for the row tiles of a subsystem and the basis tiles per wave
+  void launch_phi(const BArgs &x) {
+    switch (nrt_) {
+      case 1: hipLaunchKernelGGL((bphi_kernel<NX, 1>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      case 2: hipLaunchKernelGGL((bphi_kernel<NX, 2>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      case 3: hipLaunchKernelGGL((bphi_kernel<NX, 3>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      default: hipLaunchKernelGGL((bphi_kernel<NX, 4>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+    }
+  }
+  void launch_psi(const BArgs &x) {
+    switch (mtw_) {
+      case 1: hipLaunchKernelGGL((bpsi_kernel<NX, 1>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+      case 2: hipLaunchKernelGGL((bpsi_kernel<NX, 2>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+      case 3: hipLaunchKernelGGL((bpsi_kernel<NX, 3>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+      default: hipLaunchKernelGGL((bpsi_kernel<NX, 4>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+    }
+  }
+  int nrt_ = 1, mtw_ = 1;
   int B_ = 0;
   int64_t ny_ = 0;  // N * rs
+  int n_units_ = 0;  // Psi-comp work units
   std::vector<void *> owned_;
 };
 

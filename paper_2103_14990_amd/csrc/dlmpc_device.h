@@ -116,10 +116,20 @@ struct BArgs {
   const int64_t *tile_off, *rt_ptr, *rt_tile;
   const int32_t *rt_col, *kdim, *tile_rsub;
   const int64_t *koff;      // [N+1] offsets of the k-space vectors (multiples of 32)
-  const int32_t *psi_order, *phi_order;  // [N] block -> subsystem dispatch orders
-  const int64_t *ncm_off;   // [N+1] column-major copy: k16(j) columns of ld64(j) rows
-  const int64_t *nrm_off;   // [N+1] row-major copy: D(j) rows of k32(j) entries
-  const __bf16 *ncm_hi, *ncm_lo, *nrm_hi, *nrm_lo;
+  const int32_t *phi_order;  // [N] block -> row subsystem (Phi-comp dispatch order)
+  // Psi-comp work units (heaviest first): column subsystem, row range [r0, r1), part index;
+  // per column subsystem: number of parts, first part slot and offset of its partial sums
+  // (split blocks only), arrival counters.
+  const int32_t *pu_j, *pu_r0, *pu_r1, *pu_p;
+  const int32_t *pj_n, *pj_first;
+  const int64_t *pj_off;
+  float *ppart;    // partial k-space sums [parts][k16][64]
+  double *ppod;    // partial offset terms of the second cold iteration [parts][64][8][nx]
+  int32_t *pcnt;   // [N]
+  // Null bases in matrix-core fragment order, bf16 hi and lo (see BatchEngineT::init):
+  const int64_t *ntf_off;   // [N+1] fragments of N_j' (Psi-comp left operand)
+  const int64_t *nf_off;    // [n_tiles+1] fragments of the rows of tile (j, m) (Phi-comp)
+  const __bf16 *ntf, *nf;
   const float *off;         // o_c, column-major per subsystem (leading dim ld4)
   const int64_t *off_ptr;
   const float *w, *lb, *ub; // [N*rs]

