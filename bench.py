@@ -133,6 +133,8 @@ def main() -> int:
     ap.add_argument("--single-steps", type=int, default=8, help="single-instance FP32 solves")
     ap.add_argument("--ref-steps", type=int, default=4, help="plain FP64 single-instance solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false",
+                    help="skip the 192-instance mixed-network group solve")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-launch timing of the batched kernels (for profiler runs)")
@@ -296,6 +298,39 @@ def main() -> int:
         prf.close()
     log(f"single fp32: {single}; plain fp64: {ref}")
 
+    # ---- instances of different networks in one launch per iteration chunk: 64 x {8x8, 16x16,
+    # 32x32 grids} (d = 2, T = 10, no bounds, x0 ~ N(0, I)), against the members one after another
+    mixed = {}
+    if args.mixed:
+        names = ("grid8", "grid16", "grid32")
+        mw = [W.workload(n) for n in names]
+        mp = [dlmpc.Problem.from_network(w.net, w.d, w.T, w.cost, rho=w.rho, eps=w.eps, max_iter=w.max_iter,
+                                         precision="fp32", device=0, max_batch=64) for w in mw]
+        mx = [torch.tensor(np.stack([w.x0(3000 + i) for i in range(64)]), dtype=torch.float64, device=dev)
+              for w in mw]
+        mu = [torch.zeros((64, w.net.n_sub * w.net.nu), dtype=torch.float64, device=dev) for w in mw]
+        grp = dlmpc.Group(mp)
+        args_g = ([64] * 3, [x.data_ptr() for x in mx], [u.data_ptr() for u in mu])
+        grp.solve_batch_device(*args_g)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, gst = grp.solve_batch_device(*args_g)
+        torch.cuda.synchronize()
+        eg = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        for p_, x_, u_ in zip(mp, mx, mu):
+            p_.solve_batch_device(64, x_.data_ptr(), u_.data_ptr())
+        torch.cuda.synchronize()
+        es = time.perf_counter() - t1
+        mixed = {"networks": list(names), "instances": 192, "group_ms": round(1e3 * eg, 3),
+                 "sequential_ms": round(1e3 * es, 3), "time_to_eps_ms": round(1e3 * eg / 192, 4),
+                 "iters_mean": {n: float(np.mean([q["iters"] for q in g])) for n, g in zip(names, gst)},
+                 "converged": sum(q["converged"] for g in gst for q in g)}
+        grp.close()
+        for p_ in mp:
+            p_.close()
+        log(f"mixed networks: {mixed}")
+
     # ---- roofline of the dominant batched kernel (HIP events around each launch)
     ab = batch_algorithmic_bytes(pr.info, N, rs, B)
     ku = pr.time_batch_kernels(B, x0[args.warmup].data_ptr(), 20)
@@ -327,6 +362,7 @@ def main() -> int:
         "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
         "converged": f"{conv}/{n_solves}", "fell_back": int(fell),
         "batched_cold": cold,
+        "mixed_networks": mixed,
         "single_fp32_cold": single,
         "plain_fp64_cold": ref,
         "speedup_vs_plain_fp64": round(ref["time_to_eps_ms_median"] / (ms_step / B), 2) if ref else None,

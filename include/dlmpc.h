@@ -286,6 +286,22 @@ int dlmpc_ws_predict(struct dlmpc_problem *p, int32_t S, const double *x0_dev, d
 int dlmpc_ws_save(struct dlmpc_problem *p, const char *path);
 int dlmpc_warmstart_load(struct dlmpc_problem *p, const char *path);
 
+/* ---- Groups: instances of several networks in one launch per iteration chunk.
+ * A group holds batched problems (each set up with max_batch > 0, all on one device); creation
+ * captures, for chunks of 1, 2, 4, ..., 32 iterations, one graph in which every member's batched
+ * iteration is an independent branch. dlmpc_group_solve_batch runs B[i] instances of member i
+ * (x0_dev[i] [B[i]][N_i*nx], u0_dev[i] [B[i]][N_i*nu], device; stats[i] [B[i]] or NULL) from the
+ * cold start with each member's own rho, eps and max_iter; every instance stops at its own
+ * convergence, and the launches continue until all members have stopped. Per-instance results
+ * equal those of dlmpc_solve_batch_device on the member alone. A member must not be used by
+ * another call while a group call runs; destroy the group before its members. Returns as
+ * dlmpc_solve_batch over all instances. */
+struct dlmpc_group;
+int dlmpc_group_create(struct dlmpc_problem *const *probs, int32_t n, struct dlmpc_group **out);
+int dlmpc_group_solve_batch(struct dlmpc_group *g, const int32_t *B, const double *const *x0_dev,
+                            double *const *u0_dev, dlmpc_stats *const *stats);
+void dlmpc_group_destroy(struct dlmpc_group *g);
+
 void dlmpc_destroy(struct dlmpc_problem *p);
 const char *dlmpc_status_string(int status);
 const char *dlmpc_last_error(void);

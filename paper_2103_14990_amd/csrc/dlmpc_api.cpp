@@ -926,4 +926,183 @@ void dlmpc_destroy(dlmpc_problem *p) {
   delete p;
 }
 
+// ------------------------------------------------------------------ groups of problems
+
+struct dlmpc_group {
+  std::vector<dlmpc_problem *> p;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph[dlmpc_problem::kGraphs] = {};
+  hipGraphExec_t gexec[dlmpc_problem::kGraphs] = {};
+  hipEvent_t ev_fork = nullptr, ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  Ctl *h_ctl = nullptr;  // pinned, one per member
+};
+
+namespace {
+
+void group_release(dlmpc_group *g) {
+  if (!g) return;
+  if (!g->p.empty()) (void)hipSetDevice(g->p[0]->opt.device);
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  for (int k = 0; k < dlmpc_problem::kGraphs; ++k) {
+    if (g->gexec[k]) (void)hipGraphExecDestroy(g->gexec[k]);
+    if (g->graph[k]) (void)hipGraphDestroy(g->graph[k]);
+  }
+  for (hipEvent_t e : g->ev_join)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {g->ev_fork, g->ev_done, g->ev_t0, g->ev_t1})
+    if (e) (void)hipEventDestroy(e);
+  if (g->h_ctl) (void)hipHostFree(g->h_ctl);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+}
+
+}  // namespace
+
+int dlmpc_group_create(dlmpc_problem *const *probs, int32_t n, dlmpc_group **out) {
+  if (!probs || n < 1 || !out) return fail(DLMPC_EINVAL, "need n >= 1 problems and an output handle");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!probs[i]) return fail(DLMPC_EINVAL, "NULL problem in group");
+    if (probs[i]->host_only || !probs[i]->beng) return fail(DLMPC_EINVAL, "group members need the batched engine (max_batch > 0)");
+    if (probs[i]->opt.device != probs[0]->opt.device) return fail(DLMPC_EINVAL, "group members must share one device");
+    for (int k = 0; k < i; ++k)
+      if (probs[k] == probs[i]) return fail(DLMPC_EINVAL, "a problem appears twice in the group");
+  }
+  auto g = std::make_unique<dlmpc_group>();
+  g->p.assign(probs, probs + n);
+  auto undo = [&](int code, const std::string &msg) {
+    group_release(g.get());
+    g->stream = nullptr;
+    return fail(code, msg);
+  };
+#define GRP_HIP(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return undo(DLMPC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  GRP_HIP(hipSetDevice(probs[0]->opt.device));
+  GRP_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+  GRP_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+  GRP_HIP(hipEventCreateWithFlags(&g->ev_done, hipEventDisableTiming));
+  GRP_HIP(hipEventCreate(&g->ev_t0));
+  GRP_HIP(hipEventCreate(&g->ev_t1));
+  g->ev_join.assign(n, nullptr);
+  for (auto &e : g->ev_join) GRP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  GRP_HIP(hipHostMalloc(reinterpret_cast<void **>(&g->h_ctl), sizeof(Ctl) * n, hipHostMallocDefault));
+  for (int i = 0; i < n; ++i) GRP_HIP(hipStreamSynchronize(probs[i]->stream));
+  // One graph per chunk size: fork to every member's stream, 2^k batched iterations each,
+  // join back (the members' kernels are independent branches of the graph).
+  for (int k = 0; k < dlmpc_problem::kGraphs; ++k) {
+    GRP_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    int rc = hipEventRecord(g->ev_fork, g->stream) == hipSuccess ? DLMPC_OK : DLMPC_EDEVICE;
+    std::string err = rc ? "hipEventRecord failed during capture" : "";
+    for (int i = 0; i < n && !rc; ++i) {
+      dlmpc_problem *q = probs[i];
+      if (hipStreamWaitEvent(q->stream, g->ev_fork, 0) != hipSuccess) {
+        rc = DLMPC_EDEVICE;
+        err = "hipStreamWaitEvent failed during capture";
+        break;
+      }
+      for (int it = 0; it < (1 << k) && !rc; ++it) rc = q->beng->iteration(err);
+      if (!rc && (hipEventRecord(g->ev_join[i], q->stream) != hipSuccess ||
+                  hipStreamWaitEvent(g->stream, g->ev_join[i], 0) != hipSuccess)) {
+        rc = DLMPC_EDEVICE;
+        err = "event join failed during capture";
+      }
+    }
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->stream, &gr);
+    if (rc || ec != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return undo(rc ? rc : DLMPC_EDEVICE, rc ? err : std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    }
+    g->graph[k] = gr;
+    GRP_HIP(hipGraphInstantiate(&g->gexec[k], g->graph[k], nullptr, nullptr, 0));
+  }
+#undef GRP_HIP
+  *out = g.release();
+  return DLMPC_OK;
+}
+
+int dlmpc_group_solve_batch(dlmpc_group *g, const int32_t *B, const double *const *x0_dev,
+                            double *const *u0_dev, dlmpc_stats *const *stats) {
+  const double t0 = now_ms();
+  if (!g || !B || !x0_dev || !u0_dev) return fail(DLMPC_EINVAL, "NULL argument");
+  const int n = int(g->p.size());
+  for (int i = 0; i < n; ++i) {
+    int rc = check_batch(g->p[i], B[i]);
+    if (rc) return rc;
+    if (!x0_dev[i] || !u0_dev[i]) return fail(DLMPC_EINVAL, "NULL device buffer for a group member");
+  }
+  API_HIP(hipSetDevice(g->p[0]->opt.device));
+  std::string err;
+  int max_iter = 0;
+  double eps = 0.0;
+  for (int i = 0; i < n; ++i) {
+    dlmpc_problem *q = g->p[i];
+    int rc = q->beng->precompute(x0_dev[i], B[i], q->opt.max_iter, q->opt.eps, 0, err);
+    if (rc) return fail(rc, err);
+    API_HIP(hipEventRecord(g->ev_join[i], q->stream));
+    API_HIP(hipStreamWaitEvent(g->stream, g->ev_join[i], 0));
+    max_iter = std::max(max_iter, q->opt.max_iter);
+    eps = std::max(eps, q->opt.eps);
+  }
+  API_HIP(hipEventRecord(g->ev_t0, g->stream));
+  ChunkPredictor pred;
+  int launched = 0, checks = 0, nchunk = 32;
+  bool all_stopped = false;
+  while (!all_stopped) {
+    nchunk = std::max(1, std::min(nchunk, max_iter - launched));
+    int rc = launch_graphs(g->gexec, g->stream, nchunk);
+    if (rc) return rc;
+    launched += nchunk;
+    ++checks;
+    for (int i = 0; i < n; ++i)
+      API_HIP(hipMemcpyAsync(&g->h_ctl[i], g->p[i]->beng->ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
+    API_HIP(hipStreamSynchronize(g->stream));
+    all_stopped = true;
+    double worst = 0.0, worst_d = 0.0;
+    int iters = 0;
+    for (int i = 0; i < n; ++i) {
+      const Ctl &c = g->h_ctl[i];
+      if (!c.stop) {
+        all_stopped = false;
+        if (c.last_rp > worst) worst = c.last_rp;
+        if (c.last_rd > worst_d) worst_d = c.last_rd;
+        iters = std::max(iters, c.iters);
+      }
+    }
+    if (all_stopped || launched >= max_iter) break;
+    nchunk = pred.next(iters, worst, worst_d, eps);
+  }
+  if (!all_stopped) return fail(DLMPC_EDEVICE, "grouped iteration did not reach its stop condition");
+  API_HIP(hipEventRecord(g->ev_t1, g->stream));
+  API_HIP(hipEventRecord(g->ev_done, g->stream));
+  float ms = 0.f;
+  bool all = true, numeric = false;
+  for (int i = 0; i < n; ++i) {
+    dlmpc_problem *q = g->p[i];
+    API_HIP(hipStreamWaitEvent(q->stream, g->ev_done, 0));
+    int rc = q->beng->output(u0_dev[i], err);
+    if (rc) return fail(rc, err);
+    API_HIP(hipMemcpyAsync(q->h_bctl, q->beng->ictl(), sizeof(dlmpc::BCtl) * B[i], hipMemcpyDeviceToHost, q->stream));
+    API_HIP(hipStreamSynchronize(q->stream));
+    if (i == 0) (void)hipEventElapsedTime(&ms, g->ev_t0, g->ev_t1);
+    for (int b = 0; b < B[i]; ++b) {
+      const dlmpc::BCtl &ic = q->h_bctl[b];
+      all = all && ic.converged;
+      numeric = numeric || ic.numeric;
+      if (stats && stats[i]) fill_stats(stats[i][b], ic, ms, checks, DLMPC_START_COLD, t0);
+    }
+  }
+  if (numeric) return fail(DLMPC_ENUMERIC, "NaN/Inf in a batched ADMM iterate");
+  return all ? DLMPC_OK : DLMPC_ENOCONV;
+}
+
+void dlmpc_group_destroy(dlmpc_group *g) {
+  if (!g) return;
+  group_release(g);
+  delete g;
+}
+
 }  // extern "C"

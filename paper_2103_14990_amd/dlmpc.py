@@ -98,6 +98,10 @@ EXPORTS = {
     "dlmpc_ws_predict": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dlmpc_ws_save": (C.c_int, [C.c_void_p, C.c_char_p]),
     "dlmpc_warmstart_load": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "dlmpc_group_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "dlmpc_group_solve_batch": (C.c_int, [C.c_void_p, _i32p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                          C.POINTER(C.POINTER(Stats))]),
+    "dlmpc_group_destroy": (None, [C.c_void_p]),
     "dlmpc_destroy": (None, [C.c_void_p]),
     "dlmpc_status_string": (C.c_char_p, [C.c_int]),
     "dlmpc_last_error": (C.c_char_p, []),
@@ -338,3 +342,40 @@ class Problem:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Group:
+    """Batched problems of different networks advanced together (dlmpc_group_*)."""
+
+    def __init__(self, problems: list):
+        self._lib = load()
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        self._h = C.c_void_p()
+        st = self._lib.dlmpc_group_create(arr, len(self.problems), C.byref(self._h))
+        if st != OK:
+            raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
+
+    def solve_batch_device(self, Bs: list[int], x0_devs: list[int], u0_devs: list[int]):
+        n = len(self.problems)
+        bs = (C.c_int32 * n)(*Bs)
+        xs = (C.c_void_p * n)(*x0_devs)
+        us = (C.c_void_p * n)(*u0_devs)
+        st_arrays = [(Stats * b)() for b in Bs]
+        sp = (C.POINTER(Stats) * n)(*[C.cast(a, C.POINTER(Stats)) for a in st_arrays])
+        s = self._lib.dlmpc_group_solve_batch(self._h, bs, xs, us, sp)
+        if s < 0:
+            raise DlmpcError(s, self._lib.dlmpc_last_error().decode())
+        return s, [[x.as_dict() for x in a] for a in st_arrays]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.dlmpc_group_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -124,3 +124,21 @@ def test_batch_argument_errors():
     pb = batch_problem(wl, max_batch=4)
     with pytest.raises(dlmpc.DlmpcError):
         pb.solve_batch(np.zeros((5, 20)))
+
+
+def test_star_network_split_column_block():
+    """A star of 40 subsystems (d = 1): the hub's column block is ~28x the mean basis size, so
+    its Psi-comp work is split into row ranges whose partial sums the last part adds in a
+    fixed order. Batched solves against the oracle."""
+    n = 40
+    net = W.swing_network("star40", n, np.array([[0, i] for i in range(1, n)]), 0)
+    cost = W.unit_cost(net)
+    wl = W.Workload("star40", net, 1, 5, cost, sigma=1.0)
+    pb = O.setup_from_network(net, 1, 5, cost)
+    pr = batch_problem(wl, max_batch=8)
+    x0s = np.stack([wl.x0(s) for s in (1, 3, 4)])
+    st, u0, stats = pr.solve_batch(x0s)
+    check_instances(pb, x0s, u0, stats, iter_slack=max(3, 20))
+    # deterministic: the split sums do not depend on which part finishes last
+    st2, u02, stats2 = pr.solve_batch(x0s)
+    assert np.array_equal(u0, u02) and [s["iters"] for s in stats] == [s["iters"] for s in stats2]
