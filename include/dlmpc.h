@@ -180,6 +180,19 @@ int dlmpc_solve(struct dlmpc_problem *p, const double *x0, const dlmpc_warm *war
 int dlmpc_solve_device(struct dlmpc_problem *p, const double *x0_dev, double *u0_dev,
                        double *phi_dev, dlmpc_stats *stats);
 
+/* FP64 certificate of the stopping iterate of the latest single-instance solve on this problem
+ * (dlmpc_solve or dlmpc_solve_device), recomputed on the device from the stored Phi, Psi, Lambda
+ * (promoted to FP64 in the FP32 tier) and x0. x0_dev: that solve's x0 on the device [N*nx], or
+ * NULL for the x0 of the latest dlmpc_solve (host entry). Fields (all >= 0): */
+typedef struct {
+  double eq;    /* max |Z_AB Psi - I| over the support and the (d+1)-hop ring of every column */
+  double pf;    /* max |Phi - Psi| */
+  double rp;    /* max over columns of ||Phi[:,c] - Psi[:,c]||_2 (the primal residual of Conv) */
+  double box;   /* largest bound violation of Phi x0 (0 when within the boxes) */
+  double stat;  /* max over columns of |N_j N_j' rho Lambda[:,c]| (Psi-step stationarity) */
+} dlmpc_cert;
+int dlmpc_certify(struct dlmpc_problem *p, const double *x0_dev, dlmpc_cert *out);
+
 /* Kernel timing for roofline measurement: runs `iters` ADMM iterations of the graph schedule
  * from x0_dev without early stop, each kernel launched on its own between HIP events on the
  * problem's stream, and writes the mean device time per launch in microseconds of each of

@@ -712,6 +712,137 @@ __global__ __launch_bounds__(kBlock) void export_kernel(const Tf *phi, const int
     }                                                                     \
   } while (0)
 
+// ------------------------------------------------------------------ FP64 certificate
+
+struct CertArgs {
+  const int64_t *eq_ptr;    // [N+1] entries (subsystems i of the support and ring) of column j
+  const int32_t *eq_sub;    // subsystem i
+  const int64_t *eq_tile;   // tile (j, i), or -1 when i is in the ring
+  const int64_t *eq_nptr;   // [entries+1] A neighbours of i (CSR order of A)
+  const int64_t *eq_ntile;  // tile (j, k) of neighbour k, or -1
+  const int64_t *eq_ablk;   // position of the block A_ik in the block-CSR arrays
+  const double *a_blk, *b_blk, *x0;
+  unsigned long long *out;  // [5] maxima as ordered bit patterns (all values >= 0)
+};
+
+// One block per subsystem b: Z_AB feasibility, |Phi - Psi| and Psi-step stationarity of column
+// block j = b, and the bound check of the rows of row subsystem m = b, all in FP64.
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void cert_kernel(KArgs<Tf> a, CertArgs c) {
+  extern __shared__ double tk[];  // [NX][k_j]
+  __shared__ double red[kBlock / 64][NX + 4];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rs = a.rs, T = a.T, nu = a.nu, ts = a.ts;
+  double m_eq = 0.0, m_pf = 0.0, m_box = 0.0, m_stat = 0.0, s2[NX];
+#pragma unroll
+  for (int q = 0; q < NX; ++q) s2[q] = 0.0;
+  // Z_AB Psi = I on the rows that can touch j's columns
+  const int64_t e0 = c.eq_ptr[j], e1 = c.eq_ptr[j + 1];
+  const int64_t per = int64_t(T) * NX * NX;
+  for (int64_t w = tid; w < (e1 - e0) * per; w += kBlock) {
+    const int64_t q = e0 + w / per;
+    const int rem = int(w % per), t = rem / (NX * NX), comp = (rem / NX) % NX, col = rem % NX;
+    const int i = c.eq_sub[q];
+    const int64_t ti = c.eq_tile[q];
+    double r = ti < 0 ? 0.0 : double(a.psi[ti * ts + (t * NX + comp) * NX + col]);
+    if (t == 0) {
+      if (i == j && comp == col) r -= 1.0;
+    } else {
+      for (int64_t n = c.eq_nptr[q]; n < c.eq_nptr[q + 1]; ++n) {
+        const int64_t tk_ = c.eq_ntile[n];
+        if (tk_ < 0) continue;
+        const double *A = c.a_blk + c.eq_ablk[n] * NX * NX;
+#pragma unroll
+        for (int cc = 0; cc < NX; ++cc) r -= A[comp * NX + cc] * double(a.psi[tk_ * ts + ((t - 1) * NX + cc) * NX + col]);
+      }
+      if (ti >= 0)
+        for (int u = 0; u < nu; ++u)
+          r -= c.b_blk[(int64_t(i) * NX + comp) * nu + u] * double(a.psi[ti * ts + (NX * T + (t - 1) * nu + u) * NX + col]);
+    }
+    m_eq = fmax(m_eq, fabs(r));
+  }
+  // Phi - Psi on j's support
+  const int64_t t0 = a.tile_off[j], t1 = a.tile_off[j + 1];
+  for (int64_t e = tid; e < (t1 - t0) * ts; e += kBlock) {
+    const int64_t idx = t0 * ts + e;
+    const double d = double(a.phi[idx]) - double(a.psi[idx]);
+    m_pf = fmax(m_pf, fabs(d));
+    s2[e % NX] += d * d;
+  }
+  // N_j N_j' (rho Lambda_c): coordinates first, then the rows
+  const int D = int(t1 - t0) * rs, ld = (D + 3) & ~3, k = a.kdim[j];
+  const Tf *Nj = a.nb + a.nb_off[j];
+  const double rho = double(a.rho);
+  for (int i = tid; i < k; i += kBlock)
+#pragma unroll
+    for (int col = 0; col < NX; ++col) {
+      double acc = 0.0;
+      for (int r = 0; r < D; ++r) acc += double(Nj[int64_t(i) * ld + r]) * rho * double(a.lam[t0 * ts + int64_t(r) * NX + col]);
+      tk[col * k + i] = acc;
+    }
+  __syncthreads();
+  for (int r = tid; r < D; r += kBlock)
+#pragma unroll
+    for (int col = 0; col < NX; ++col) {
+      double acc = 0.0;
+      for (int i = 0; i < k; ++i) acc += double(Nj[int64_t(i) * ld + r]) * tk[col * k + i];
+      m_stat = fmax(m_stat, fabs(acc));
+    }
+  // bounds of row subsystem m = j: y = Phi x0 recomputed from the tiles of m's row
+  const int m = j;
+  for (int l = tid; l < rs; l += kBlock) {
+    double y = 0.0;
+    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+      const int64_t tile = a.rt_tile[q];
+      const int jj = a.rt_col[q];
+#pragma unroll
+      for (int cc = 0; cc < NX; ++cc) y += double(a.phi[tile * ts + int64_t(l) * NX + cc]) * c.x0[jj * NX + cc];
+    }
+    const double lbv = double(a.lb[int64_t(m) * rs + l]), ubv = double(a.ub[int64_t(m) * rs + l]);
+    m_box = fmax(m_box, fmax(lbv - y, y - ubv));
+  }
+  // block maxima and column sums, then the device maxima
+  auto wmax = [](double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+  };
+  auto wsum_ = [](double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
+  m_eq = wmax(m_eq);
+  m_pf = wmax(m_pf);
+  m_box = wmax(m_box);
+  m_stat = wmax(m_stat);
+#pragma unroll
+  for (int q = 0; q < NX; ++q) s2[q] = wsum_(s2[q]);
+  if (lane == 0) {
+    red[wave][0] = m_eq;
+    red[wave][1] = m_pf;
+    red[wave][2] = m_box;
+    red[wave][3] = m_stat;
+#pragma unroll
+    for (int q = 0; q < NX; ++q) red[wave][4 + q] = s2[q];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, cs[NX];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) cs[q] = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      for (int q = 0; q < 4; ++q) v[q] = fmax(v[q], red[w][q]);
+      for (int q = 0; q < NX; ++q) cs[q] += red[w][4 + q];
+    }
+    double rp = 0.0;
+    for (int q = 0; q < NX; ++q) rp = fmax(rp, sqrt(cs[q]));
+    atomicMax(&c.out[0], as_bits(v[0]));
+    atomicMax(&c.out[1], as_bits(v[1]));
+    atomicMax(&c.out[2], as_bits(rp));
+    atomicMax(&c.out[3], as_bits(fmax(v[2], 0.0)));
+    atomicMax(&c.out[4], as_bits(v[3]));
+  }
+}
+
 template <typename Tf, int NX>
 class EngineT final : public Engine {
  public:
@@ -767,6 +898,7 @@ class EngineT final : public Engine {
       return DLMPC_EINVAL;
     }
     int rc2 = build_units(hs, err);
+    if (!rc2) rc2 = build_cert(hs, err);
     if (rc2) return rc2;
     return build_schedule(hs, err);
   }
@@ -942,6 +1074,63 @@ class EngineT final : public Engine {
     return DLMPC_OK;
   }
 
+  int certify(const double *x0_dev, double *out, std::string &err) override {
+    CertArgs c = cert_;
+    c.x0 = x0_dev;
+    ENG_CHECK(hipMemsetAsync(cert_out_, 0, 5 * sizeof(unsigned long long), stream_));
+    c.out = cert_out_;
+    const size_t lds = size_t(NX) * std::max(hs_->k_max, 1) * sizeof(double);
+    hipLaunchKernelGGL((cert_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds, stream_, args_, c);
+    ENG_CHECK(hipGetLastError());
+    unsigned long long h[5];
+    ENG_CHECK(hipMemcpyAsync(h, cert_out_, sizeof(h), hipMemcpyDeviceToHost, stream_));
+    ENG_CHECK(hipStreamSynchronize(stream_));
+    for (int q = 0; q < 5; ++q) {
+      double v;
+      std::memcpy(&v, &h[q], sizeof(v));
+      out[q] = v;
+    }
+    return DLMPC_OK;
+  }
+
+  // Lists for the certificate's Z_AB rows: per column subsystem j, the subsystems of its support
+  // and ring with their tiles and the tiles of their A neighbours.
+  int build_cert(const HostSetup &hs, std::string &err) {
+    const int N = hs.N;
+    std::vector<int64_t> eq_ptr(N + 1, 0), eq_tile, eq_nptr(1, 0), eq_ntile, eq_ablk;
+    std::vector<int32_t> eq_sub;
+    auto tile_of = [&](int j, int i) -> int64_t {
+      const auto &P = hs.patch[j];
+      const auto it = std::lower_bound(P.begin(), P.end(), i);
+      return (it != P.end() && *it == i) ? hs.tile_off[j] + (it - P.begin()) : -1;
+    };
+    for (int j = 0; j < N; ++j) {
+      std::vector<int32_t> rows(hs.patch[j].begin(), hs.patch[j].end());
+      for (int32_t i : hs.patch[j])
+        for (int64_t q = hs.a_rowptr[i]; q < hs.a_rowptr[i + 1]; ++q) rows.push_back(hs.a_colidx[q]);
+      std::sort(rows.begin(), rows.end());
+      rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+      for (int32_t i : rows) {
+        eq_sub.push_back(i);
+        eq_tile.push_back(tile_of(j, i));
+        for (int64_t q = hs.a_rowptr[i]; q < hs.a_rowptr[i + 1]; ++q) {
+          eq_ntile.push_back(tile_of(j, hs.a_colidx[q]));
+          eq_ablk.push_back(q);
+        }
+        eq_nptr.push_back(int64_t(eq_ntile.size()));
+      }
+      eq_ptr[j + 1] = int64_t(eq_sub.size());
+    }
+    int rc;
+    if ((rc = upload(eq_ptr, &cert_.eq_ptr, err)) || (rc = upload(eq_sub, &cert_.eq_sub, err)) ||
+        (rc = upload(eq_tile, &cert_.eq_tile, err)) || (rc = upload(eq_nptr, &cert_.eq_nptr, err)) ||
+        (rc = upload(eq_ntile, &cert_.eq_ntile, err)) || (rc = upload(eq_ablk, &cert_.eq_ablk, err)) ||
+        (rc = upload(hs.a_blocks, &cert_.a_blk, err)) || (rc = upload(hs.b_blocks, &cert_.b_blk, err)) ||
+        (rc = alloc(&cert_out_, 5, err)))
+      return rc;
+    return DLMPC_OK;
+  }
+
   Ctl *ctl() override { return args_.ctl; }
 
   ~EngineT() override {
@@ -989,6 +1178,8 @@ class EngineT final : public Engine {
   KArgs<Tf> args_{};
   const int64_t *map_ = nullptr;
   const double *w64_ = nullptr;
+  CertArgs cert_{};
+  unsigned long long *cert_out_ = nullptr;
   size_t lds_phi_ = 0, lds_psi_ = 0, lds_persist_ = 0, lds_p1_ = 0, lds_p2_ = 0;
   int n1_ = 0, n2_ = 0;
   PsiUnits<Tf> pu_{};

@@ -532,6 +532,22 @@ int dlmpc_solve_device(dlmpc_problem *p, const double *x0_dev, double *u0_dev, d
   return run_solve(p, x0_dev, nullptr, nullptr, u0_dev, phi_dev, stats, t0);
 }
 
+int dlmpc_certify(dlmpc_problem *p, const double *x0_dev, dlmpc_cert *out) {
+  if (!p || !out) return fail(DLMPC_EINVAL, "NULL argument");
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  API_HIP(hipSetDevice(p->opt.device));
+  std::string err;
+  double v[5];
+  const int rc = p->eng->certify(x0_dev ? x0_dev : p->d_x0, v, err);
+  if (rc) return fail(rc, err);
+  out->eq = v[0];
+  out->pf = v[1];
+  out->rp = v[2];
+  out->box = v[3];
+  out->stat = v[4];
+  return DLMPC_OK;
+}
+
 int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, double *us_per_launch) {
   if (!p || !x0_dev || iters < 1 || !us_per_launch) return fail(DLMPC_EINVAL, "bad argument");
   if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");

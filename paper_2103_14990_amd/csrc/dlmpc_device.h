@@ -93,6 +93,11 @@ class Engine {
   virtual int persistent_grid() const = 0;  // 0 when the device cannot co-schedule the grid
   virtual int output(double *u0_dev, std::string &err) = 0;
   virtual int export_phi(double *phi_dev, std::string &err) = 0;
+  // FP64 certificate of the current iterate for x0_dev: out[0] = max |Z_AB Psi - I| over the
+  // support and the (d+1)-hop ring of every column, out[1] = max |Phi - Psi|, out[2] = max over
+  // columns of ||Phi[:,c] - Psi[:,c]||_2, out[3] = largest bound violation of Phi x0, out[4] =
+  // max over columns of |N_j N_j' rho Lambda[:,c]| (Psi-step stationarity). Synchronises.
+  virtual int certify(const double *x0_dev, double *out, std::string &err) = 0;
   virtual Ctl *ctl() = 0;
 };
 

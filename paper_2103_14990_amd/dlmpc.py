@@ -64,6 +64,14 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Cert(C.Structure):
+    _fields_ = [("eq", C.c_double), ("pf", C.c_double), ("rp", C.c_double), ("box", C.c_double),
+                ("stat", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Info(C.Structure):
     _fields_ = [("R", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64), ("n_tiles", C.c_int64),
                 ("d_row_max", C.c_int32), ("d_col_max", C.c_int32), ("p_max", C.c_int32),
@@ -84,6 +92,7 @@ EXPORTS = {
     "dlmpc_column_block": (C.c_int, [C.c_void_p, C.c_int32, _i32p, _i64p, _dp, _dp]),
     "dlmpc_solve": (C.c_int, [C.c_void_p, _dp, C.POINTER(Warm), _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
+    "dlmpc_certify": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Cert)]),
     "dlmpc_time_kernels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, _dp]),
     "dlmpc_time_batch_kernels": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, _dp]),
     "dlmpc_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, C.POINTER(Stats)]),
@@ -313,6 +322,12 @@ class Problem:
 
     def warmstart_load(self, path: str):
         self._check(self._lib.dlmpc_warmstart_load(self._h, os.fsencode(path)))
+
+    def certify(self, x0_dev: int = 0) -> dict:
+        """FP64 certificate of the latest single-instance solve (x0_dev 0: the latest host x0)."""
+        c = Cert()
+        self._check(self._lib.dlmpc_certify(self._h, C.c_void_p(x0_dev) if x0_dev else None, C.byref(c)))
+        return c.as_dict()
 
     def time_kernels(self, x0_dev: int, iters: int) -> dict:
         """Mean microseconds per launch of each kernel of one iteration (no early stop)."""
