@@ -60,6 +60,8 @@ typedef enum {
                                             between Phi-comp and Psi-comp; the grid is sized to be
                                             co-resident, and a barrier wait that times out fails
                                             the solve with DLMPC_EDEVICE */
+#define DLMPC_FLAG_HOST_FACTOR 0x8u /* factor the column blocks with host threads instead of the
+                                       device kernels (host-only problems always do) */
 
 /* Networked plant. G_(A,B) is read off the block sparsity of A: subsystems i != j are
  * adjacent iff block A_ij or A_ji is present in the block-CSR with a nonzero entry. Every
@@ -134,13 +136,16 @@ typedef struct {
   int32_t k_max;        /* largest null-space dimension of a column block */
   int64_t sum_dcol_k;   /* sum over subsystems of D_col(j) * k_j (entries of the null bases) */
   int64_t sum_dcol2;    /* sum over subsystems of D_col(j)^2 */
-  double setup_ms;      /* host wall time of dlmpc_setup */
-  double factor_ms;     /* of which the FP64 factorisation of the column blocks */
+  double setup_ms;      /* wall time of dlmpc_setup up to the factorisation's end */
+  double factor_ms;     /* of which the FP64 factorisation of the column blocks (device
+                           factorisation: list building, transfers and both kernels) */
   int32_t schedule;     /* 0 = graph, 1 = persistent */
   int32_t persistent_grid; /* co-resident blocks of the persistent schedule (0 = unavailable) */
   double tune_graph_us;      /* per-iteration time measured at setup (0 if not measured) */
   double tune_persistent_us;
   int64_t sum_k;        /* sum over subsystems of k_j (null-space coordinates per instance) */
+  int32_t factor_device; /* 1 if the column blocks were factored on the device, 0 on the host */
+  int32_t pad0;
 } dlmpc_info;
 
 /* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the
@@ -148,9 +153,14 @@ typedef struct {
  * Z_AB (the SLS achievability operator: Phi_x[0] = I, Phi_x[t] = A Phi_x[t-1] + B Phi_u[t-1])
  * restricted to the support of j's columns: an orthonormal basis N_j of its null space and
  * the minimum-norm offsets o_c solving the block's equations for each column c of j, so that
- * the Psi-comp projection is psi = N_j N_j' v + o_c. Uploads the operators and allocates all
- * solve-time device memory. d >= 0, T >= 2. Returns DLMPC_EINFEASIBLE_LOCALITY when some
- * column has no localised trajectory. On success *out receives the handle. */
+ * the Psi-comp projection is psi = N_j N_j' v + o_c. The factorisation runs as two HIP kernels
+ * on opts->device (one workgroup per subsystem: pivoted Householder QR of the map from patch
+ * inputs to ring values, then of the simulated null-space trajectories) unless the problem is
+ * host-only or DLMPC_FLAG_HOST_FACTOR is set; both give the same N_j N_j' and o_c up to
+ * rounding. Uploads the operators and allocates all solve-time device memory. d >= 0, T >= 2.
+ * Returns DLMPC_EINFEASIBLE_LOCALITY when some column has no localised trajectory,
+ * DLMPC_ENUMERIC when a null basis loses rank, DLMPC_EINVAL when a column block is longer
+ * than 8000 rows for the device factorisation. On success *out receives the handle. */
 int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *cost,
                 const dlmpc_options *opts, struct dlmpc_problem **out);
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libdlmpc.so")
-SOURCES = ["setup_host.cpp", "admm_kernels.hip", "batch_kernels.hip", "warmstart_kernels.hip", "dlmpc_api.cpp"]
+SOURCES = ["setup_host.cpp", "setup_kernels.hip", "admm_kernels.hip", "batch_kernels.hip", "warmstart_kernels.hip", "dlmpc_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are disabled for all device code (see DESIGN notes on gfx950).

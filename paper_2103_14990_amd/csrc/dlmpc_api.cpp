@@ -414,8 +414,17 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
   p->opt = o;
   p->host_only = (o.flags & DLMPC_FLAG_HOST_ONLY) != 0;
   std::string err;
+  const auto t_setup = std::chrono::steady_clock::now();
   int rc = dlmpc::host_setup(sys, d, T, cost, p->hs, err);
   if (rc) return fail(rc, err);
+  // The column blocks are factored by device kernels unless the problem is host-only or the
+  // caller asks for the host factorisation.
+  if (p->host_only || (o.flags & DLMPC_FLAG_HOST_FACTOR))
+    rc = dlmpc::factor_host(p->hs, err);
+  else
+    rc = dlmpc::factor_device(p->hs, o.device, err);
+  if (rc) return fail(rc, err);
+  p->hs.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
   if (!p->host_only) {
     rc = setup_device(p.get());
     if (rc) {
@@ -444,6 +453,7 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   info->sum_dcol2 = h.sum_dcol2;
   info->setup_ms = h.setup_ms;
   info->factor_ms = h.factor_ms;
+  info->factor_device = h.factor_where;
   info->schedule = p->sched;
   info->persistent_grid = (p->eng ? p->eng->persistent_grid() : 0);
   info->tune_graph_us = p->tune_graph_us;

@@ -9,6 +9,11 @@
 
 namespace dlmpc {
 
+// Thresholds of the column-block factorisation (host and device alike).
+constexpr double kRankTol = 1e-10;   // relative pivot threshold of the rank-revealing QR of the ring map
+constexpr double kBasisTol = 1e-13;  // relative pivot threshold of the QR that orthonormalises S K
+constexpr double kFeasTol = 1e-9;    // absolute ring residual of a particular solution
+
 // Host-side result of the offline precomputation (Algorithm 1, first step).
 //
 // Packing ("tiles"): for every column subsystem j and every row subsystem m in its d-hop
@@ -55,6 +60,22 @@ struct HostSetup {
   int32_t p_max = 0, k_max = 0, d_row_max = 0, d_col_max = 0;
   int64_t sum_dcol_k = 0, sum_dcol2 = 0, sum_k = 0;
   double setup_ms = 0, factor_ms = 0;
+  int32_t factor_where = 0;  // 0 = host threads, 1 = device kernels
+};
+
+// Index lists for factoring the column blocks elsewhere than in the host loop: for each
+// subsystem j, the sparse patch dynamics A_PP (CSR over the p*nx patch states) and the ring
+// map G (CSR over the ng ring state rows that couple to the patch), with entries
+// (patch-state column, index into a_blocks). Row pointers are local to j's entry range.
+struct FactorLists {
+  std::vector<int32_t> aj;       // [N] position of j in P(j)
+  std::vector<int32_t> ng;       // [N] ring rows
+  std::vector<int64_t> app_rp0;  // [N] first row pointer of A_PP in rp
+  std::vector<int64_t> g_rp0;    // [N] first row pointer of G in rp
+  std::vector<int64_t> app_e0;   // [N] first entry of A_PP in ecol/eidx
+  std::vector<int64_t> g_e0;     // [N] first entry of G
+  std::vector<int32_t> rp;       // concatenated row pointers (p*nx+1 then ng+1 per j)
+  std::vector<int32_t> ecol, eidx;
 };
 
 inline int32_t padded_ld(int32_t D) { return (D + 3) & ~3; }
@@ -67,8 +88,24 @@ inline int64_t canon_row(const HostSetup &h, int32_t m, int32_t l) {
   return Nx * h.T + int64_t(lu / h.nu) * Nu + int64_t(m) * h.nu + (lu % h.nu);
 }
 
-// Builds everything above on the host in FP64. Returns a DLMPC_* status; err gets a message.
+// Builds everything above except the factorisation (kdim, nb, off) on the host. Returns a
+// DLMPC_* status; err gets a message.
 int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *cost,
                HostSetup &hs, std::string &err);
+
+// FP64 factorisation of every column block by host threads (fills kdim, nb_off, nb, off_ptr,
+// off and the sums).
+int factor_host(HostSetup &hs, std::string &err);
+
+// The same factorisation by HIP kernels on `device` (one workgroup per subsystem).
+int factor_device(HostSetup &hs, int device, std::string &err);
+
+// Index lists of the per-subsystem factorisation (graph work only).
+void factor_lists(const HostSetup &hs, FactorLists &fl);
+
+// Sets kdim, nb_off, off_ptr and the sums from ks; copies nbs/offs (D x k and D x nx
+// column-major per subsystem) into the padded arrays, or leaves them zero when empty.
+void pack_factors(HostSetup &hs, const std::vector<int> &ks, const std::vector<std::vector<double>> &nbs,
+                  const std::vector<std::vector<double>> &offs);
 
 }  // namespace dlmpc

@@ -30,8 +30,6 @@
 namespace dlmpc {
 namespace {
 
-constexpr double kRankTol = 1e-10;    // relative pivot threshold of the rank-revealing QR
-constexpr double kFeasTol = 1e-9;     // absolute ring residual of a particular solution
 
 // Column-major dense matrix.
 struct Dense {
@@ -130,6 +128,29 @@ struct BlockRef {
   int32_t col;
   const double *blk;  // nx x nx row-major
 };
+
+// Block rows of A (pointers into hs.a_blocks) and the undirected interconnection graph
+// G_(A,B): i ~ j when block A_ij or A_ji has a nonzero entry.
+void block_rows(const HostSetup &hs, std::vector<std::vector<BlockRef>> &arow,
+                std::vector<std::vector<int32_t>> &adj) {
+  const int32_t N = hs.N, nx = hs.nx;
+  for (int i = 0; i < N; ++i)
+    for (int64_t q = hs.a_rowptr[i]; q < hs.a_rowptr[i + 1]; ++q) {
+      const int32_t j = hs.a_colidx[q];
+      const double *blk = hs.a_blocks.data() + size_t(q) * nx * nx;
+      arow[i].push_back({j, blk});
+      bool nz = false;
+      for (int e = 0; e < nx * nx; ++e) nz |= (blk[e] != 0.0);
+      if (nz && j != i) {
+        adj[i].push_back(j);
+        adj[j].push_back(i);
+      }
+    }
+  for (auto &a : adj) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+}
 
 // Per-subsystem factorisation context (everything local to patch P(j)).
 struct PatchFactor {
@@ -258,7 +279,7 @@ struct PatchFactor {
       Dense Fs = SK;
       std::vector<double> tau2;
       std::vector<int> jp2;
-      const int r2 = qr_pivoted(Fs, tau2, jp2, 1e-13);
+      const int r2 = qr_pivoted(Fs, tau2, jp2, kBasisTol);
       if (r2 != k) {
         err = "null basis lost rank at subsystem " + std::to_string(j);
         return DLMPC_ENUMERIC;
@@ -394,34 +415,22 @@ int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *
   hs.b_blocks.assign(sys->b_blocks, sys->b_blocks + size_t(N) * nx * nu);
 
   // Block rows of A and the interconnection graph G_(A,B).
-  std::vector<std::vector<BlockRef>> arow(N);
-  std::vector<std::vector<int32_t>> adj(N);
   for (int i = 0; i < N; ++i) {
-    for (int64_t q = sys->a_rowptr[i]; q < sys->a_rowptr[i + 1]; ++q) {
-      const int32_t j = sys->a_colidx[q];
+    std::vector<int32_t> cols(sys->a_colidx + sys->a_rowptr[i], sys->a_colidx + sys->a_rowptr[i + 1]);
+    for (int32_t j : cols)
       if (j < 0 || j >= N) {
         err = "a_colidx out of range";
         return DLMPC_EINVAL;
       }
-      for (const BlockRef &br : arow[i])
-        if (br.col == j) {
-          err = "duplicate block in a row of A";
-          return DLMPC_EINVAL;
-        }
-      const double *blk = sys->a_blocks + size_t(q) * nx * nx;
-      arow[i].push_back({j, blk});
-      bool nz = false;
-      for (int e = 0; e < nx * nx; ++e) nz |= (blk[e] != 0.0);
-      if (nz && j != i) {
-        adj[i].push_back(j);
-        adj[j].push_back(i);
-      }
+    std::sort(cols.begin(), cols.end());
+    if (std::adjacent_find(cols.begin(), cols.end()) != cols.end()) {
+      err = "duplicate block in a row of A";
+      return DLMPC_EINVAL;
     }
   }
-  for (auto &a : adj) {
-    std::sort(a.begin(), a.end());
-    a.erase(std::unique(a.begin(), a.end()), a.end());
-  }
+  std::vector<std::vector<BlockRef>> arow(N);
+  std::vector<std::vector<int32_t>> adj(N);
+  block_rows(hs, arow, adj);
 
   // d-hop patches by breadth-first search.
   hs.patch.assign(N, {});
@@ -529,12 +538,51 @@ int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *
       }
     }
 
-  // Column-block factorisations, one task per subsystem.
+  hs.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return DLMPC_OK;
+}
+
+void pack_factors(HostSetup &hs, const std::vector<int> &ks, const std::vector<std::vector<double>> &nbs,
+                  const std::vector<std::vector<double>> &offs) {
+  const int32_t N = hs.N, nx = hs.nx;
+  hs.kdim = ks;
+  hs.nb_off.assign(N + 1, 0);
+  hs.off_ptr.assign(N + 1, 0);
+  for (int j = 0; j < N; ++j) {
+    const int64_t ld = padded_ld(int32_t(hs.patch[j].size()) * hs.rs);
+    hs.nb_off[j + 1] = hs.nb_off[j] + ld * ks[j];
+    hs.off_ptr[j + 1] = hs.off_ptr[j] + ld * nx;
+  }
+  hs.nb.assign(size_t(hs.nb_off[N]), 0.0);
+  hs.off.assign(size_t(hs.off_ptr[N]), 0.0);
+  hs.k_max = 0;
+  hs.sum_dcol_k = hs.sum_k = 0;
+  for (int j = 0; j < N; ++j) {
+    const int32_t D = int32_t(hs.patch[j].size()) * hs.rs, ld = padded_ld(D);
+    if (!nbs.empty())
+      for (int i = 0; i < ks[j]; ++i)
+        std::copy(nbs[j].begin() + size_t(i) * D, nbs[j].begin() + size_t(i + 1) * D,
+                  hs.nb.begin() + hs.nb_off[j] + size_t(i) * ld);
+    if (!offs.empty())
+      for (int c = 0; c < nx; ++c)
+        std::copy(offs[j].begin() + size_t(c) * D, offs[j].begin() + size_t(c + 1) * D,
+                  hs.off.begin() + hs.off_ptr[j] + size_t(c) * ld);
+    hs.k_max = std::max(hs.k_max, ks[j]);
+    hs.sum_dcol_k += int64_t(D) * ks[j];
+    hs.sum_k += ks[j];
+  }
+}
+
+int factor_host(HostSetup &hs, std::string &err) {
   const auto t_fac = std::chrono::steady_clock::now();
+  const int32_t N = hs.N, nx = hs.nx, nu = hs.nu, T = hs.T;
+  std::vector<std::vector<BlockRef>> arow(N);
+  std::vector<std::vector<int32_t>> adj(N);
+  block_rows(hs, arow, adj);
   std::vector<std::vector<double>> nbs(N), offs(N);
   std::vector<int> ks(N, 0), stat(N, DLMPC_OK);
   std::vector<std::string> errs(N);
-  PatchFactor pf{N, nx, nu, T, hs.rs, &arow, sys->b_blocks, &adj};
+  PatchFactor pf{N, nx, nu, T, hs.rs, &arow, hs.b_blocks.data(), &adj};
   std::atomic<int> next{0};
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   nth = std::min<unsigned>(nth, unsigned(N));
@@ -550,32 +598,86 @@ int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *
       err = errs[j];
       return stat[j];
     }
-  hs.kdim = ks;
-  hs.nb_off.assign(N + 1, 0);
-  hs.off_ptr.assign(N + 1, 0);
-  for (int j = 0; j < N; ++j) {
-    const int64_t ld = padded_ld(int32_t(hs.patch[j].size()) * hs.rs);
-    hs.nb_off[j + 1] = hs.nb_off[j] + ld * ks[j];
-    hs.off_ptr[j + 1] = hs.off_ptr[j] + ld * nx;
-  }
-  hs.nb.assign(size_t(hs.nb_off[N]), 0.0);
-  hs.off.assign(size_t(hs.off_ptr[N]), 0.0);
-  for (int j = 0; j < N; ++j) {
-    const int32_t D = int32_t(hs.patch[j].size()) * hs.rs, ld = padded_ld(D);
-    for (int i = 0; i < ks[j]; ++i)
-      std::copy(nbs[j].begin() + size_t(i) * D, nbs[j].begin() + size_t(i + 1) * D,
-                hs.nb.begin() + hs.nb_off[j] + size_t(i) * ld);
-    for (int c = 0; c < nx; ++c)
-      std::copy(offs[j].begin() + size_t(c) * D, offs[j].begin() + size_t(c + 1) * D,
-                hs.off.begin() + hs.off_ptr[j] + size_t(c) * ld);
-    hs.k_max = std::max(hs.k_max, ks[j]);
-    hs.sum_dcol_k += int64_t(D) * ks[j];
-    hs.sum_k += ks[j];
-  }
-  const auto t_end = std::chrono::steady_clock::now();
-  hs.factor_ms = std::chrono::duration<double, std::milli>(t_end - t_fac).count();
-  hs.setup_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+  pack_factors(hs, ks, nbs, offs);
+  hs.factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_fac).count();
+  hs.factor_where = 0;
   return DLMPC_OK;
+}
+
+void factor_lists(const HostSetup &hs, FactorLists &fl) {
+  const int32_t N = hs.N, nx = hs.nx;
+  std::vector<std::vector<BlockRef>> arow(N);
+  std::vector<std::vector<int32_t>> adj(N);
+  block_rows(hs, arow, adj);
+  fl = FactorLists();
+  fl.aj.resize(N);
+  fl.ng.resize(N);
+  fl.app_rp0.resize(N);
+  fl.g_rp0.resize(N);
+  fl.app_e0.resize(N);
+  fl.g_e0.resize(N);
+  std::vector<int> pos(N, -1);
+  for (int j = 0; j < N; ++j) {
+    const std::vector<int32_t> &P = hs.patch[j];
+    const int p = int(P.size());
+    for (int a = 0; a < p; ++a) pos[P[a]] = a;
+    fl.aj[j] = pos[j];
+    // A_PP: row a*nx+s, entries of the blocks of row P[a] whose column is in the patch.
+    fl.app_rp0[j] = int64_t(fl.rp.size());
+    fl.app_e0[j] = int64_t(fl.ecol.size());
+    int32_t cnt = 0;
+    fl.rp.push_back(0);
+    for (int a = 0; a < p; ++a)
+      for (int s = 0; s < nx; ++s) {
+        for (const BlockRef &br : arow[P[a]]) {
+          if (pos[br.col] < 0) continue;
+          const int64_t base = br.blk - hs.a_blocks.data();
+          for (int s2 = 0; s2 < nx; ++s2) {
+            fl.ecol.push_back(pos[br.col] * nx + s2);
+            fl.eidx.push_back(int32_t(base + s * nx + s2));
+            ++cnt;
+          }
+        }
+        fl.rp.push_back(cnt);
+      }
+    // Ring rows: states outside the patch whose A row has a nonzero entry on a patch state.
+    std::vector<int32_t> ring;
+    for (int a = 0; a < p; ++a)
+      for (int32_t q : adj[P[a]])
+        if (pos[q] < 0) ring.push_back(q);
+    std::sort(ring.begin(), ring.end());
+    ring.erase(std::unique(ring.begin(), ring.end()), ring.end());
+    fl.g_rp0[j] = int64_t(fl.rp.size());
+    fl.g_e0[j] = int64_t(fl.ecol.size());
+    cnt = 0;
+    int32_t ng = 0;
+    fl.rp.push_back(0);
+    for (int32_t q : ring)
+      for (int s = 0; s < nx; ++s) {
+        bool any = false;
+        const size_t mark = fl.ecol.size();
+        for (const BlockRef &br : arow[q]) {
+          if (pos[br.col] < 0) continue;
+          const int64_t base = br.blk - hs.a_blocks.data();
+          for (int s2 = 0; s2 < nx; ++s2) {
+            const double v = br.blk[s * nx + s2];
+            any |= (v != 0.0);
+            fl.ecol.push_back(pos[br.col] * nx + s2);
+            fl.eidx.push_back(int32_t(base + s * nx + s2));
+          }
+        }
+        if (!any) {
+          fl.ecol.resize(mark);
+          fl.eidx.resize(mark);
+          continue;
+        }
+        cnt += int32_t(fl.ecol.size() - mark);
+        fl.rp.push_back(cnt);
+        ++ng;
+      }
+    fl.ng[j] = ng;
+    for (int a = 0; a < p; ++a) pos[P[a]] = -1;
+  }
 }
 
 }  // namespace dlmpc

@@ -20,6 +20,8 @@ FP64, FP32 = 0, 1
 FLAG_HOST_ONLY = 0x1
 FLAG_SCHED_GRAPH = 0x2
 FLAG_SCHED_PERSISTENT = 0x4
+FLAG_HOST_FACTOR = 0x8
+FACTORS = {"device": 0, "host": FLAG_HOST_FACTOR}
 SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 TIMED_KERNELS = 4
@@ -78,7 +80,8 @@ class Info(C.Structure):
                 ("k_max", C.c_int32), ("sum_dcol_k", C.c_int64), ("sum_dcol2", C.c_int64),
                 ("setup_ms", C.c_double), ("factor_ms", C.c_double), ("schedule", C.c_int32),
                 ("persistent_grid", C.c_int32), ("tune_graph_us", C.c_double),
-                ("tune_persistent_us", C.c_double), ("sum_k", C.c_int64)]
+                ("tune_persistent_us", C.c_double), ("sum_k", C.c_int64),
+                ("factor_device", C.c_int32), ("pad0", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -179,7 +182,7 @@ class Problem:
                  rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500, precision: str = "fp64",
                  device: int = 0, stream: int | None = None, check_every: int = 0,
                  host_only: bool = False, schedule: str = "auto", max_batch: int = 0,
-                 warm_cg_iters: int = 0):
+                 warm_cg_iters: int = 0, factor: str = "device"):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -193,7 +196,7 @@ class Problem:
                     _ptr(keep["ul"]), _ptr(keep["uh"]))
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
-                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule], max_batch,
+                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule] | FACTORS[factor], max_batch,
                        warm_cg_iters)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
