@@ -1162,8 +1162,8 @@ class EngineT final : public Engine {
     *dst = reinterpret_cast<V *>(p);
     return DLMPC_OK;
   }
-  template <typename V>
-  int upload_conv(const std::vector<double> &src, V **dst, std::string &err) {
+  template <typename V, class Vec>
+  int upload_conv(const Vec &src, V **dst, std::string &err) {
     std::vector<Tf> tmp(src.begin(), src.end());
     Tf *p = nullptr;
     int rc = alloc(&p, tmp.size(), err);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,27 @@ namespace dlmpc {
 constexpr double kRankTol = 1e-10;   // relative pivot threshold of the rank-revealing QR of the ring map
 constexpr double kBasisTol = 1e-13;  // relative pivot threshold of the QR that orthonormalises S K
 constexpr double kFeasTol = 1e-9;    // absolute ring residual of a particular solution
+
+// Allocator whose resize() leaves doubles uninitialised (large arrays filled by a copy).
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+  template <class U>
+  void construct(U *p) noexcept {
+    ::new (static_cast<void *>(p)) U;
+  }
+  template <class U, class... Args>
+  void construct(U *p, Args &&...args) {
+    ::new (static_cast<void *>(p)) U(std::forward<Args>(args)...);
+  }
+};
+using BigVec = std::vector<double, NoInitAlloc<double>>;
 
 // Host-side result of the offline precomputation (Algorithm 1, first step).
 //
@@ -46,10 +68,10 @@ struct HostSetup {
   // D_col(j) rounded up to a multiple of 4 (zero rows below D_col(j)), at nb[nb_off[j]].
   std::vector<int32_t> kdim;        // [N]
   std::vector<int64_t> nb_off;      // [N+1]
-  std::vector<double> nb;
+  BigVec nb;
   // Offsets o_c: ld(j) x nx column-major (zero padded) at off[off_ptr[j]].
   std::vector<int64_t> off_ptr;     // [N+1]
-  std::vector<double> off;
+  BigVec off;
 
   // Row data in local order: w (cost weight), lb/ub (bounds on (Phi x0)_r), [N * rs].
   std::vector<double> w, lb, ub;
@@ -103,8 +125,9 @@ int factor_device(HostSetup &hs, int device, std::string &err);
 // Index lists of the per-subsystem factorisation (graph work only).
 void factor_lists(const HostSetup &hs, FactorLists &fl);
 
-// Sets kdim, nb_off, off_ptr and the sums from ks; copies nbs/offs (D x k and D x nx
-// column-major per subsystem) into the padded arrays, or leaves them zero when empty.
+// Sets kdim, nb_off, off_ptr and the sums from ks and sizes nb/off; copies nbs/offs (D x k and
+// D x nx column-major per subsystem) into the zero-padded arrays, or leaves the arrays
+// uninitialised when nbs/offs are empty (the caller fills every entry).
 void pack_factors(HostSetup &hs, const std::vector<int> &ks, const std::vector<std::vector<double>> &nbs,
                   const std::vector<std::vector<double>> &offs);
 

@@ -553,8 +553,12 @@ void pack_factors(HostSetup &hs, const std::vector<int> &ks, const std::vector<s
     hs.nb_off[j + 1] = hs.nb_off[j] + ld * ks[j];
     hs.off_ptr[j + 1] = hs.off_ptr[j] + ld * nx;
   }
-  hs.nb.assign(size_t(hs.nb_off[N]), 0.0);
-  hs.off.assign(size_t(hs.off_ptr[N]), 0.0);
+  hs.nb.clear();
+  hs.off.clear();
+  hs.nb.resize(size_t(hs.nb_off[N]));
+  hs.off.resize(size_t(hs.off_ptr[N]));
+  if (!nbs.empty()) std::fill(hs.nb.begin(), hs.nb.end(), 0.0);
+  if (!offs.empty()) std::fill(hs.off.begin(), hs.off.end(), 0.0);
   hs.k_max = 0;
   hs.sum_dcol_k = hs.sum_k = 0;
   for (int j = 0; j < N; ++j) {

@@ -31,9 +31,11 @@
 namespace dlmpc {
 namespace {
 
-constexpr int kFT = 256;           // threads per workgroup
-constexpr int kFW = kFT / 64;      // waves per workgroup
-constexpr int kMaxLdsRows = 8000;  // longest Householder vector staged in LDS (< 64 KiB)
+constexpr int kFT = 512;           // threads per workgroup
+constexpr int kFW = kFT / 64;      // waves per workgroup (row groups of the column passes)
+constexpr int kCC = 4;             // 64-column chunks per pass of reflect_cols
+constexpr int kRU = 2;             // rows per lane and load round of reflect_cols
+constexpr int kMaxLdsRows = 4000;  // longest Householder vector staged in LDS (32 KB)
 
 struct FacDesc {
   int64_t app_rp0, app_e0, g_rp0, g_e0;  // index lists
@@ -103,30 +105,161 @@ __device__ double block_max(double v, double *s_rv) {
   return m;
 }
 
+// Applies H = I - tau v v' (v_k = 1, v_i = s_v[i] for k < i < m) to columns [j0, j1) of C
+// (row-major, leading dimension ld, rows k..m-1). The columns go 64 to a wave (one per lane,
+// up to kCC chunks per pass) and the rows are split over the kFW waves; each lane keeps kRU
+// rows x kCC chunks of independent loads in flight. The partial products v'C meet in LDS
+// (s_part, kFW x kCC*64). With nrm2 non-null, nrm2[j] receives the squared norm of rows
+// k+1..m-1 of each updated column. Ends with a barrier.
+__device__ void reflect_cols(double *C, int ld, int m, int k, const double *s_v, double tau, int j0, int j1,
+                             double *nrm2, double *s_part) {
+  const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  for (int jb = j0; jb < j1; jb += kCC * 64) {
+    const int ncc = min(kCC, (j1 - jb + 63) / 64);
+    int col[kCC];
+    bool ok[kCC];
+#pragma unroll
+    for (int cc = 0; cc < kCC; ++cc) {
+      const int j = jb + cc * 64 + lane;
+      ok[cc] = cc < ncc && j < j1;
+      col[cc] = ok[cc] ? j : j0;  // idle lanes read a valid column and store nothing
+    }
+    double part[kCC];
+#pragma unroll
+    for (int cc = 0; cc < kCC; ++cc) part[cc] = 0.0;
+    int i = k + rg;
+    for (; i + (kRU - 1) * kFW < m; i += kRU * kFW) {
+      double v[kRU], x[kRU][kCC];
+#pragma unroll
+      for (int u = 0; u < kRU; ++u) {
+        const int iu = i + u * kFW;
+        v[u] = (iu == k) ? 1.0 : s_v[iu];
+        const double *r = C + int64_t(iu) * ld;
+#pragma unroll
+        for (int cc = 0; cc < kCC; ++cc)
+          if (cc < ncc) x[u][cc] = r[col[cc]];
+      }
+#pragma unroll
+      for (int u = 0; u < kRU; ++u)
+#pragma unroll
+        for (int cc = 0; cc < kCC; ++cc)
+          if (cc < ncc) part[cc] += v[u] * x[u][cc];
+    }
+    for (; i < m; i += kFW) {
+      const double v0 = (i == k) ? 1.0 : s_v[i];
+      const double *r0 = C + int64_t(i) * ld;
+#pragma unroll
+      for (int cc = 0; cc < kCC; ++cc)
+        if (cc < ncc) part[cc] += v0 * r0[col[cc]];
+    }
+#pragma unroll
+    for (int cc = 0; cc < kCC; ++cc)
+      if (cc < ncc) s_part[rg * (kCC * 64) + cc * 64 + lane] = part[cc];
+    __syncthreads();
+    double w[kCC];
+#pragma unroll
+    for (int cc = 0; cc < kCC; ++cc)
+      if (cc < ncc) {
+        double t = 0.0;
+        for (int g = 0; g < kFW; ++g) t += s_part[g * (kCC * 64) + cc * 64 + lane];
+        w[cc] = t * tau;
+      }
+    __syncthreads();
+    double q[kCC];
+#pragma unroll
+    for (int cc = 0; cc < kCC; ++cc) q[cc] = 0.0;
+    for (i = k + rg; i + (kRU - 1) * kFW < m; i += kRU * kFW) {
+      double v[kRU], x[kRU][kCC];
+#pragma unroll
+      for (int u = 0; u < kRU; ++u) {
+        const int iu = i + u * kFW;
+        v[u] = (iu == k) ? 1.0 : s_v[iu];
+        const double *r = C + int64_t(iu) * ld;
+#pragma unroll
+        for (int cc = 0; cc < kCC; ++cc)
+          if (cc < ncc) x[u][cc] = r[col[cc]];
+      }
+#pragma unroll
+      for (int u = 0; u < kRU; ++u) {
+        const int iu = i + u * kFW;
+        const double n0 = (iu == k) ? 0.0 : 1.0;
+        double *r = C + int64_t(iu) * ld;
+#pragma unroll
+        for (int cc = 0; cc < kCC; ++cc)
+          if (cc < ncc) {
+            const double y = x[u][cc] - w[cc] * v[u];
+            q[cc] += n0 * y * y;
+            if (ok[cc]) r[col[cc]] = y;
+          }
+      }
+    }
+    for (; i < m; i += kFW) {
+      const double v0 = (i == k) ? 1.0 : s_v[i];
+      const double n0 = (i == k) ? 0.0 : 1.0;
+      double *r0 = C + int64_t(i) * ld;
+#pragma unroll
+      for (int cc = 0; cc < kCC; ++cc)
+        if (cc < ncc) {
+          const double y = r0[col[cc]] - w[cc] * v0;
+          q[cc] += n0 * y * y;
+          if (ok[cc]) r0[col[cc]] = y;
+        }
+    }
+    if (nrm2) {
+#pragma unroll
+      for (int cc = 0; cc < kCC; ++cc)
+        if (cc < ncc) s_part[rg * (kCC * 64) + cc * 64 + lane] = q[cc];
+      __syncthreads();
+      if (rg == 0)
+#pragma unroll
+        for (int cc = 0; cc < kCC; ++cc)
+          if (ok[cc]) {
+            double t = 0.0;
+            for (int g = 0; g < kFW; ++g) t += s_part[g * (kCC * 64) + cc * 64 + lane];
+            nrm2[col[cc]] = t;
+          }
+    }
+    __syncthreads();
+  }
+}
+
 // Householder QR with column pivoting of the first n columns of F (m rows, row-major, leading
 // dimension ld), stopped at the first step whose largest remaining column norm is not above
 // rtol times the first pivot's. F receives R in its upper rows and the reflector vectors
 // (implicit unit leading entry) below the diagonal; column k of the result is input column
-// jpvt[k]. Norms of the trailing columns are recomputed in the same pass that updates them.
+// jpvt[k]. Norms of the trailing columns are recomputed in the pass that updates them.
 __device__ int qr_pivoted_dev(double *F, int m, int n, int ld, double rtol, double *tau, int *jpvt,
-                              double *nrm2, double *s_v, double *s_rv, int *s_ri) {
+                              double *nrm2, double *s_v, double *s_part, double *s_rv, int *s_ri) {
   const int tid = threadIdx.x;
-  for (int j = tid; j < n; j += kFT) {
-    double s0 = 0.0, s1 = 0.0;
-    int i = 0;
-    for (; i + 1 < m; i += 2) {
-      const double x0 = F[int64_t(i) * ld + j], x1 = F[int64_t(i + 1) * ld + j];
-      s0 += x0 * x0;
-      s1 += x1 * x1;
+  // Initial squared column norms: rows split over the waves, partial sums through LDS.
+  {
+    const int lane = tid & 63, rg = tid >> 6;
+    for (int jb = 0; jb < n; jb += 64) {
+      const int j = jb + lane;
+      double s0 = 0.0, s1 = 0.0;
+      if (j < n) {
+        int i = rg;
+        for (; i + kFW < m; i += 2 * kFW) {
+          const double x0 = F[int64_t(i) * ld + j], x1 = F[int64_t(i + kFW) * ld + j];
+          s0 += x0 * x0;
+          s1 += x1 * x1;
+        }
+        if (i < m) {
+          const double x0 = F[int64_t(i) * ld + j];
+          s0 += x0 * x0;
+        }
+      }
+      s_part[rg * 64 + lane] = s0 + s1;
+      __syncthreads();
+      if (rg == 0 && j < n) {
+        double t = 0.0;
+        for (int g = 0; g < kFW; ++g) t += s_part[g * 64 + lane];
+        nrm2[j] = t;
+        jpvt[j] = j;
+      }
+      __syncthreads();
     }
-    if (i < m) {
-      const double x0 = F[int64_t(i) * ld + j];
-      s0 += x0 * x0;
-    }
-    nrm2[j] = s0 + s1;
-    jpvt[j] = j;
   }
-  __syncthreads();
   const int kmax = min(m, n);
   double first = 0.0;
   int rank = 0;
@@ -177,62 +310,25 @@ __device__ int qr_pivoted_dev(double *F, int m, int n, int ld, double rtol, doub
       tau[k] = tk;
     }
     __syncthreads();
-    for (int j = k + 1 + tid; j < n; j += kFT) {
-      double *c = F + j;
-      double s0 = c[int64_t(k) * ld], s1 = 0.0;
-      int i = k + 1;
-      for (; i + 1 < m; i += 2) {
-        s0 += s_v[i] * c[int64_t(i) * ld];
-        s1 += s_v[i + 1] * c[int64_t(i + 1) * ld];
-      }
-      if (i < m) s0 += s_v[i] * c[int64_t(i) * ld];
-      const double s = (s0 + s1) * tk;
-      c[int64_t(k) * ld] -= s;
-      double q0 = 0.0, q1 = 0.0;
-      for (i = k + 1; i + 1 < m; i += 2) {
-        const double x0 = c[int64_t(i) * ld] - s * s_v[i];
-        const double x1 = c[int64_t(i + 1) * ld] - s * s_v[i + 1];
-        c[int64_t(i) * ld] = x0;
-        c[int64_t(i + 1) * ld] = x1;
-        q0 += x0 * x0;
-        q1 += x1 * x1;
-      }
-      if (i < m) {
-        const double x0 = c[int64_t(i) * ld] - s * s_v[i];
-        c[int64_t(i) * ld] = x0;
-        q0 += x0 * x0;
-      }
-      nrm2[j] = q0 + q1;
-    }
-    __syncthreads();
+    if (k + 1 < n) reflect_cols(F, ld, m, k, s_v, tk, k + 1, n, nrm2, s_part);
     rank = k + 1;
   }
   return rank;
 }
 
 // X <- H_0 H_1 ... H_{rank-1} X for the reflectors of qr_pivoted_dev held in F (m rows,
-// leading dimension ldf); X is m x nc row-major with leading dimension ldx.
+// leading dimension ldf); X is m x nc row-major with leading dimension ldx. With `unit`, X
+// starts as the first nc columns of the identity: column c is then left alone by H_k, k > c
+// (v_k vanishes above row k), so H_k only touches columns k..nc-1.
 __device__ void apply_q_dev(const double *F, int m, int ldf, const double *tau, int rank, double *X,
-                            int nc, int ldx, double *s_v) {
+                            int nc, int ldx, bool unit, double *s_v, double *s_part) {
   const int tid = threadIdx.x;
   for (int k = rank - 1; k >= 0; --k) {
+    const int c0 = unit ? k : 0;
+    if (c0 >= nc) continue;
     for (int i = k + 1 + tid; i < m; i += kFT) s_v[i] = F[int64_t(i) * ldf + k];
     __syncthreads();
-    const double tk = tau[k];
-    for (int j = tid; j < nc; j += kFT) {
-      double *c = X + j;
-      double s0 = c[int64_t(k) * ldx], s1 = 0.0;
-      int i = k + 1;
-      for (; i + 1 < m; i += 2) {
-        s0 += s_v[i] * c[int64_t(i) * ldx];
-        s1 += s_v[i + 1] * c[int64_t(i + 1) * ldx];
-      }
-      if (i < m) s0 += s_v[i] * c[int64_t(i) * ldx];
-      const double s = (s0 + s1) * tk;
-      c[int64_t(k) * ldx] -= s;
-      for (i = k + 1; i < m; ++i) c[int64_t(i) * ldx] -= s * s_v[i];
-    }
-    __syncthreads();
+    reflect_cols(X, ldx, m, k, s_v, tau[k], c0, nc, nullptr, s_part);
   }
 }
 
@@ -246,43 +342,54 @@ struct Patch {
   // Row of state s of patch member a at time t in the local trajectory order.
   __device__ int srow(int r, int t) const { return (r / nx) * rs + t * nx + r % nx; }
 
-  // Simulates column `col` of S (row-major, leading dimension lds) from the initial state
-  // e_{x0row} (zero when x0row < 0) under the inputs in column `col` of U (row-major, leading
-  // dimension ldu, rows t*ni + a*nu + q; zero inputs when U is null). Writes every state and
-  // input row of the trajectory. With `track`, computes the ring values G x[t], t = 0..T-2,
-  // stores them to ring[(t*ng+i)*ring_ld] when ring is non-null and returns their largest
-  // magnitude (NaN if any is NaN); returns 0 otherwise.
-  __device__ double simulate(double *S, int lds, int col, const double *U, int ldu, int ucol, int x0row,
-                             bool track, double *ring, int ring_ld) const {
-    double *c = S + col;
-    for (int r = 0; r < ns; ++r) c[int64_t(srow(r, 0)) * lds] = (r == x0row) ? 1.0 : 0.0;
-    double mx = 0.0;
-    for (int t = 0; t < T; ++t) {
-      if (track && t <= T - 2)
-        for (int i = 0; i < ng; ++i) {
-          double g = 0.0;
-          for (int q = grp[i]; q < grp[i + 1]; ++q) g += A[gidx[q]] * c[int64_t(srow(gcol[q], t)) * lds];
-          if (ring) ring[int64_t(t * ng + i) * ring_ld] = g;
-          mx = max_nan(mx, fabs(g));
-        }
-      if (t == T - 1) break;
-      for (int r = 0; r < ns; ++r) {
-        double v = 0.0;
-        for (int q = arp[r]; q < arp[r + 1]; ++q) v += A[aidx[q]] * c[int64_t(srow(acol[q], t)) * lds];
-        if (U) {
-          const int a = r / nx, s = r % nx;
-          for (int q = 0; q < nu; ++q)
-            v += B[(int64_t(mem[a]) * nx + s) * nu + q] * U[int64_t(t * ni + a * nu + q) * ldu + ucol];
-        }
-        c[int64_t(srow(r, t + 1)) * lds] = v;
+  // Simulates columns [c0, c1) of S (row-major, leading dimension lds): column c starts from
+  // e_{x0base + c - off0} when c >= off0 (zero state otherwise) under the inputs in column c of
+  // U (row-major, leading dimension lds, rows t*ni + a*nu + q; zero inputs when U is null),
+  // and every state and input row of its trajectory is written. For the columns c >= off0 the
+  // ring values G x[t], t = 0..T-2, are computed, stored to ring[(t*ng+i)*ring_ld + c - off0]
+  // when ring is non-null, and the largest magnitude over them (NaN if any is NaN) is
+  // returned to every thread. Lanes take columns, the waves split the rows of each time step.
+  __device__ double simulate(double *S, int lds, int c0, int c1, const double *U, int off0, int x0base,
+                             double *ring, int ring_ld, double *s_rv) const {
+    const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    for (int cb = c0; cb < c1; cb += 64) {
+      const int c = cb + lane;
+      if (c >= c1) continue;
+      const int x0row = (c >= off0) ? x0base + c - off0 : -1;
+      for (int r = rg; r < ns; r += kFW) S[int64_t(srow(r, 0)) * lds + c] = (r == x0row) ? 1.0 : 0.0;
+      for (int e = rg; e < (T - 1) * ni; e += kFW) {
+        const int t = e / ni, a = (e % ni) / nu, q = e % nu;
+        S[int64_t(a * rs + nx * T + t * nu + q) * lds + c] = U ? U[int64_t(e) * lds + c] : 0.0;
       }
     }
-    for (int t = 0; t + 1 < T; ++t)
-      for (int a = 0; a < p; ++a)
-        for (int q = 0; q < nu; ++q)
-          c[int64_t(a * rs + nx * T + t * nu + q) * lds] =
-              U ? U[int64_t(t * ni + a * nu + q) * ldu + ucol] : 0.0;
-    return mx;
+    __syncthreads();
+    double mx = 0.0;
+    for (int t = 0; t < T; ++t) {
+      for (int cb = c0; cb < c1; cb += 64) {
+        const int c = cb + lane;
+        if (c >= c1) continue;
+        if (c >= off0 && t <= T - 2)
+          for (int i = rg; i < ng; i += kFW) {
+            double g = 0.0;
+            for (int q = grp[i]; q < grp[i + 1]; ++q) g += A[gidx[q]] * S[int64_t(srow(gcol[q], t)) * lds + c];
+            if (ring) ring[int64_t(t * ng + i) * ring_ld + c - off0] = g;
+            mx = max_nan(mx, fabs(g));
+          }
+        if (t == T - 1) continue;
+        for (int r = rg; r < ns; r += kFW) {
+          double v = 0.0;
+          for (int q = arp[r]; q < arp[r + 1]; ++q) v += A[aidx[q]] * S[int64_t(srow(acol[q], t)) * lds + c];
+          if (U) {
+            const int a = r / nx, s = r % nx;
+            for (int q = 0; q < nu; ++q)
+              v += B[(int64_t(mem[a]) * nx + s) * nu + q] * U[int64_t(t * ni + a * nu + q) * lds + c];
+          }
+          S[int64_t(srow(r, t + 1)) * lds + c] = v;
+        }
+      }
+      __syncthreads();
+    }
+    return block_max(mx, s_rv);
   }
 };
 
@@ -311,6 +418,7 @@ __device__ Patch make_patch(const FacArgs &a, const FacDesc &d) {
 // Phase 1: assemble M' and factor it; rank[j] = numerical rank.
 __global__ __launch_bounds__(kFT) void fac_ring_qr_kernel(FacArgs a) {
   extern __shared__ double s_v[];
+  __shared__ double s_part[kFW * kCC * 64];
   __shared__ double s_rv[kFW];
   __shared__ int s_ri[kFW];
   const int j = a.order[blockIdx.x];
@@ -347,13 +455,14 @@ __global__ __launch_bounds__(kFT) void fac_ring_qr_kernel(FacArgs a) {
     W = Wn;
     Wn = t;
   }
-  const int r = qr_pivoted_dev(F, mu, mc, mc, kRankTol, tau, jpvt, nrm, s_v, s_rv, s_ri);
+  const int r = qr_pivoted_dev(F, mu, mc, mc, kRankTol, tau, jpvt, nrm, s_v, s_part, s_rv, s_ri);
   if (tid == 0) a.rank[j] = r;
 }
 
 // Phase 2: null basis N_j and offsets o_c from the factored M'.
 __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
   extern __shared__ double s_v[];
+  __shared__ double s_part[kFW * kCC * 64];
   __shared__ double s_rv[kFW];
   __shared__ int s_ri[kFW];
   const int j = a.order[blockIdx.x];
@@ -373,8 +482,7 @@ __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
   int *jp2 = a.iwsb + d.ib_off;
 
   // Ring values of the free responses x_0 = e_c (scratch trajectories in the offset columns).
-  if (tid < nx) P.simulate(S, ncol, k + tid, nullptr, 0, 0, d.aj * nx + tid, true, ringv + tid, nx);
-  __syncthreads();
+  P.simulate(S, ncol, k, ncol, nullptr, k, d.aj * nx, ringv, nx, s_rv);
   for (int e = tid; e < r * nx; e += kFT) {
     const int i = e / nx, c = e % nx;
     rhs[e] = -ringv[int64_t(jpvt[i]) * nx + c];
@@ -395,15 +503,9 @@ __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
     __syncthreads();
   }
   // X = Q [I_k-part | w; 0] = [K | u_c].
-  apply_q_dev(F, mu, mc, tau, r, X, ncol, ncol, s_v);
+  apply_q_dev(F, mu, mc, tau, r, X, ncol, ncol, false, s_v, s_part);
   // Trajectories: S K (zero initial state) and psi_c (initial state e_c, inputs u_c).
-  double res = 0.0;
-  for (int c = tid; c < ncol; c += kFT) {
-    const bool is_off = c >= k;
-    const double m = P.simulate(S, ncol, c, X, ncol, c, is_off ? d.aj * nx + (c - k) : -1, is_off, nullptr, 0);
-    res = max_nan(res, m);
-  }
-  res = block_max(res, s_rv);
+  const double res = P.simulate(S, ncol, 0, ncol, X, k, d.aj * nx, nullptr, 0, s_rv);
   if (!(res <= kFeasTol)) {
     if (tid == 0) {
       a.status[j] = DLMPC_EINFEASIBLE_LOCALITY;
@@ -412,7 +514,7 @@ __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
     return;
   }
   if (k > 0) {
-    const int r2 = qr_pivoted_dev(S, D, k, ncol, kBasisTol, tau2, jp2, nrm2, s_v, s_rv, s_ri);
+    const int r2 = qr_pivoted_dev(S, D, k, ncol, kBasisTol, tau2, jp2, nrm2, s_v, s_part, s_rv, s_ri);
     if (r2 != k) {
       if (tid == 0) a.status[j] = DLMPC_ENUMERIC;
       return;
@@ -422,7 +524,7 @@ __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
       Nw[e] = (i == c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    apply_q_dev(S, D, ncol, tau2, k, Nw, k, k, s_v);
+    apply_q_dev(S, D, ncol, tau2, k, Nw, k, k, true, s_v, s_part);
     // t = N' psi_c
     for (int e = tid; e < k * nx; e += kFT) {
       const int c = e / nx, cc = e % nx;
