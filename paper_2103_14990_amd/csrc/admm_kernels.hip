@@ -843,6 +843,13 @@ __global__ __launch_bounds__(kBlock) void cert_kernel(KArgs<Tf> a, CertArgs c) {
   }
 }
 
+// dst = src converted to Tf (device arrays of n values).
+template <typename Tf>
+__global__ void convert_kernel(const double *__restrict__ src, Tf *__restrict__ dst, int64_t n) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+    dst[e] = Tf(src[e]);
+}
+
 template <typename Tf, int NX>
 class EngineT final : public Engine {
  public:
@@ -877,7 +884,18 @@ class EngineT final : public Engine {
       if ((rc = upload(so, &a.psi_order, err))) return rc;
     }
     if ((rc = upload(hs.csr_map, &map_, err))) return rc;
-    if ((rc = upload_conv(hs.nb, &a.nb, err))) return rc;
+    if (hs.d_nb) {
+      // bases on the device (device factorisation): convert there
+      const int64_t n = hs.nb_off[hs.N];
+      Tf *p = nullptr;
+      if ((rc = alloc(&p, size_t(n), err))) return rc;
+      hipLaunchKernelGGL(convert_kernel<Tf>, dim3(2048), dim3(256), 0, stream_, hs.d_nb, p, n);
+      ENG_CHECK(hipGetLastError());
+      ENG_CHECK(hipStreamSynchronize(stream_));
+      a.nb = p;
+    } else if ((rc = upload_conv(hs.nb, &a.nb, err))) {
+      return rc;
+    }
     if ((rc = upload_conv(hs.off, &a.off, err))) return rc;
     if ((rc = upload_conv(hs.w, &a.w, err))) return rc;
     if ((rc = upload_conv(hs.lb, &a.lb, err))) return rc;

@@ -756,6 +756,42 @@ __global__ __launch_bounds__(256) void bexport_y_kernel(BArgs a, double *out, in
     }                                                                     \
   } while (0)
 
+// Null bases from the device factorisation (FP64, column-major, padded leading dimension) into
+// the fragment orders ntf and nf (bf16 hi at [l*8+e], lo 512 further; layouts as built on the
+// host from the same bases). Block (j, y) strides over the k_j x D_col(j) entries of N_j.
+__global__ void bfrag_kernel(const double *__restrict__ nb, const int64_t *__restrict__ nb_off,
+                             const int32_t *__restrict__ kdim, const int64_t *__restrict__ tile_off,
+                             const int64_t *__restrict__ ntf_off, const int64_t *__restrict__ nf_off, int rs,
+                             __bf16 *__restrict__ ntf, __bf16 *__restrict__ nf) {
+  const int j = blockIdx.x;
+  const int64_t t0 = tile_off[j];
+  const int D = int(tile_off[j + 1] - t0) * rs, k = kdim[j], ld = (D + 3) & ~3;
+  const int nkt_c = (D + kKC - 1) / kKC * kKC / 32, nkt_r = ((k + 31) & ~31) / 32;
+  const double *Nj = nb + nb_off[j];
+  for (int64_t e = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; e < int64_t(k) * D;
+       e += int64_t(gridDim.y) * blockDim.x) {
+    const int i = int(e / D), r = int(e % D);
+    const float x = float(Nj[int64_t(i) * ld + r]);
+    const __bf16 h = static_cast<__bf16>(x);
+    const __bf16 lo = static_cast<__bf16>(x - static_cast<float>(h));
+    {  // ntf: M = basis i, K = row r
+      const int mt = i / 16, kt = r / 32, kk = r % 32;
+      const int l = (i % 16) + 16 * (kk / 8), el = kk % 8;
+      const int64_t at = ntf_off[j] + (int64_t(mt) * nkt_c + kt) * 1024 + l * 8 + el;
+      ntf[at] = h;
+      ntf[at + 512] = lo;
+    }
+    {  // nf: M = row of the tile, K = basis i
+      const int t = r / rs, rr = r % rs;
+      const int rt = rr / 16, kt = i / 32, kk = i % 32;
+      const int l = (rr % 16) + 16 * (kk / 8), el = kk % 8;
+      const int64_t at = nf_off[t0 + t] + (int64_t(rt) * nkt_r + kt) * 1024 + l * 8 + el;
+      nf[at] = h;
+      nf[at + 512] = lo;
+    }
+  }
+}
+
 template <int NX>
 class BatchEngineT final : public BatchEngine {
  public:
@@ -850,8 +886,27 @@ class BatchEngineT final : public BatchEngine {
     for (int j = 0; j < N; ++j) fo[j] = j;
     std::stable_sort(fo.begin(), fo.end(), [&](int x, int y) { return hs.patch[x].size() > hs.patch[y].size(); });
     const __bf16 z = static_cast<__bf16>(0.f);
-    std::vector<__bf16> ntf(ntf_off[N], z), nf(nf_off[hs.n_tiles], z);
-    for (int j = 0; j < N; ++j) {
+    int rc;
+    if (hs.d_nb) {
+      // bases on the device: build the fragments there
+      __bf16 *d_ntf = nullptr, *d_nf = nullptr;
+      const int64_t *d_nboff = nullptr, *d_ntfoff = nullptr, *d_nfoff = nullptr, *d_toff = nullptr;
+      const int32_t *d_k = nullptr;
+      if ((rc = al(&d_ntf, size_t(ntf_off[N]), err)) || (rc = al(&d_nf, size_t(nf_off[hs.n_tiles]), err)) ||
+          (rc = up(hs.nb_off, &d_nboff, err)) || (rc = up(ntf_off, &d_ntfoff, err)) ||
+          (rc = up(nf_off, &d_nfoff, err)) || (rc = up(hs.tile_off, &d_toff, err)) || (rc = up(hs.kdim, &d_k, err)))
+        return rc;
+      BENG_CHECK(hipMemset(d_ntf, 0, sizeof(__bf16) * std::max<int64_t>(ntf_off[N], 1)));
+      BENG_CHECK(hipMemset(d_nf, 0, sizeof(__bf16) * std::max<int64_t>(nf_off[hs.n_tiles], 1)));
+      hipLaunchKernelGGL(bfrag_kernel, dim3(N, 16), dim3(256), 0, nullptr, hs.d_nb, d_nboff, d_k, d_toff,
+                         d_ntfoff, d_nfoff, hs.rs, d_ntf, d_nf);
+      BENG_CHECK(hipGetLastError());
+      BENG_CHECK(hipDeviceSynchronize());
+      a.ntf = d_ntf;
+      a.nf = d_nf;
+    }
+    std::vector<__bf16> ntf(hs.d_nb ? 0 : ntf_off[N], z), nf(hs.d_nb ? 0 : nf_off[hs.n_tiles], z);
+    for (int j = 0; j < N && !hs.d_nb; ++j) {
       const int D = int(hs.patch[j].size()) * hs.rs, k = hs.kdim[j], ld = padded_ld(D);
       const int nkt_c = (D + kKC - 1) / kKC * kKC / 32, nkt_r = ((k + 31) & ~31) / 32;
       const double *Nj = hs.nb.data() + hs.nb_off[j];
@@ -886,12 +941,11 @@ class BatchEngineT final : public BatchEngine {
           on2[size_t(j) * NX + c] += o * o;
         }
     }
-    int rc;
+    if (!hs.d_nb && ((rc = up(ntf, &a.ntf, err)) || (rc = up(nf, &a.nf, err)))) return rc;
     if ((rc = up(hs.tile_off, &a.tile_off, err)) || (rc = up(hs.rt_ptr, &a.rt_ptr, err)) ||
         (rc = up(hs.rt_tile, &a.rt_tile, err)) || (rc = up(hs.rt_col, &a.rt_col, err)) ||
         (rc = up(hs.kdim, &a.kdim, err)) || (rc = up(hs.tile_rsub, &a.tile_rsub, err)) ||
         (rc = up(koff, &a.koff, err)) || (rc = up(ntf_off, &a.ntf_off, err)) || (rc = up(nf_off, &a.nf_off, err)) ||
-        (rc = up(ntf, &a.ntf, err)) || (rc = up(nf, &a.nf, err)) ||
         (rc = up(hs.off_ptr, &a.off_ptr, err)) || (rc = up(on2, &a.onorm2, err)) ||
         (rc = up(hs.w, &a.w64, err)) || (rc = up(fo, &a.phi_order, err)) || (rc = up(pu_j, &a.pu_j, err)) ||
         (rc = up(pu_r0, &a.pu_r0, err)) || (rc = up(pu_r1, &a.pu_r1, err)) || (rc = up(pu_p, &a.pu_p, err)) ||

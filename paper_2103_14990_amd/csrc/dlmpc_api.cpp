@@ -95,6 +95,7 @@ void release_device(dlmpc_problem *p) {
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   p->h_ctl = nullptr;
   p->stream = nullptr;
+  dlmpc::free_factors_device(p->hs);
 }
 
 int choose_schedule(dlmpc_problem *p);
@@ -423,7 +424,10 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
     rc = dlmpc::factor_host(p->hs, err);
   else
     rc = dlmpc::factor_device(p->hs, o.device, err);
-  if (rc) return fail(rc, err);
+  if (rc) {
+    dlmpc::free_factors_device(p->hs);
+    return fail(rc, err);
+  }
   p->hs.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
   if (!p->host_only) {
     rc = setup_device(p.get());
@@ -487,7 +491,13 @@ int dlmpc_column_block(const dlmpc_problem *p, int32_t j, int32_t *D_out, int64_
       for (int l = 0; l < h.rs; ++l) rows[a * h.rs + l] = dlmpc::canon_row(h, h.patch[j][a], l);
   const int k = h.kdim[j];
   const int ld = dlmpc::padded_ld(D);
-  const double *Nj = h.nb.data() + h.nb_off[j];
+  std::vector<double> nbj;
+  if (P) {
+    std::string err;
+    const int rc = dlmpc::fetch_basis(h, j, nbj, err);
+    if (rc) return fail(rc, err);
+  }
+  const double *Nj = nbj.data();
   if (P)
     for (int r = 0; r < D; ++r)
       for (int c = 0; c < D; ++c) {

@@ -68,7 +68,7 @@ struct HostSetup {
   // D_col(j) rounded up to a multiple of 4 (zero rows below D_col(j)), at nb[nb_off[j]].
   std::vector<int32_t> kdim;        // [N]
   std::vector<int64_t> nb_off;      // [N+1]
-  BigVec nb;
+  BigVec nb;                        // empty when the bases stay on the device (d_nb)
   // Offsets o_c: ld(j) x nx column-major (zero padded) at off[off_ptr[j]].
   std::vector<int64_t> off_ptr;     // [N+1]
   BigVec off;
@@ -83,6 +83,10 @@ struct HostSetup {
   int64_t sum_dcol_k = 0, sum_dcol2 = 0, sum_k = 0;
   double setup_ms = 0, factor_ms = 0;
   int32_t factor_where = 0;  // 0 = host threads, 1 = device kernels
+  // Device factorisation: the padded N_j array (same layout as nb, FP64) stays on the device
+  // (owned here, released by free_factors_device); nb is then left empty.
+  double *d_nb = nullptr;
+  int32_t d_nb_device = -1;
 };
 
 // Index lists for factoring the column blocks elsewhere than in the host loop: for each
@@ -119,8 +123,16 @@ int host_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost *
 // off and the sums).
 int factor_host(HostSetup &hs, std::string &err);
 
-// The same factorisation by HIP kernels on `device` (one workgroup per subsystem).
+// The same factorisation by HIP kernels on `device` (one workgroup per subsystem). The
+// offsets come back to hs.off; the bases stay on the device in hs.d_nb.
 int factor_device(HostSetup &hs, int device, std::string &err);
+
+// Releases hs.d_nb (no-op when null).
+void free_factors_device(HostSetup &hs);
+
+// Copies N_j (D x k_j column-major, leading dimension padded_ld(D)) to host memory `out`
+// from hs.nb or hs.d_nb. Returns a DLMPC_* status.
+int fetch_basis(const HostSetup &hs, int32_t j, std::vector<double> &out, std::string &err);
 
 // Index lists of the per-subsystem factorisation (graph work only).
 void factor_lists(const HostSetup &hs, FactorLists &fl);

@@ -708,6 +708,7 @@ int factor_device(HostSetup &hs, int device, std::string &err) {
     ks[j] = int(mu - rank[j]);
   }
   pack_factors(hs, ks, {}, {});
+  hs.nb = BigVec();  // the bases stay on the device
   int64_t wb_tot = 0, ib_tot = 0;
   for (int j = 0; j < N; ++j) {
     FacDesc &d = desc[j];
@@ -724,9 +725,12 @@ int factor_device(HostSetup &hs, int device, std::string &err) {
   int32_t *iws2;
   FAC_HIP(B.alloc(&ws2, size_t(wb_tot)), "workspace");
   FAC_HIP(B.alloc(&iws2, size_t(ib_tot)), "workspace");
-  FAC_HIP(B.alloc(&d_nb, hs.nb.size()), "alloc");
+  const size_t nb_len = size_t(hs.nb_off[N]);
+  FAC_HIP(hipMalloc(reinterpret_cast<void **>(&d_nb), std::max<size_t>(nb_len, 1) * sizeof(double)), "alloc");
+  hs.d_nb = d_nb;  // owned by hs from here on (released with the problem, or below on error)
+  hs.d_nb_device = device;
   FAC_HIP(B.alloc(&d_off, hs.off.size()), "alloc");
-  FAC_HIP(hipMemsetAsync(d_nb, 0, std::max<size_t>(hs.nb.size(), 1) * 8, st), "memset");
+  FAC_HIP(hipMemsetAsync(d_nb, 0, std::max<size_t>(nb_len, 1) * 8, st), "memset");
   FAC_HIP(hipMemsetAsync(d_off, 0, std::max<size_t>(hs.off.size(), 1) * 8, st), "memset");
   FAC_HIP(hipMemsetAsync(d_status, 0xff, size_t(N) * 4, st), "memset");
   FAC_HIP(up(d_desc, desc.data(), size_t(N) * sizeof(FacDesc)), "upload");
@@ -740,8 +744,6 @@ int factor_device(HostSetup &hs, int device, std::string &err) {
   std::vector<double> resid(N);
   FAC_HIP(hipMemcpyAsync(status.data(), d_status, size_t(N) * 4, hipMemcpyDeviceToHost, st), "download");
   FAC_HIP(hipMemcpyAsync(resid.data(), d_resid, size_t(N) * 8, hipMemcpyDeviceToHost, st), "download");
-  if (!hs.nb.empty())
-    FAC_HIP(hipMemcpyAsync(hs.nb.data(), d_nb, hs.nb.size() * 8, hipMemcpyDeviceToHost, st), "download");
   if (!hs.off.empty())
     FAC_HIP(hipMemcpyAsync(hs.off.data(), d_off, hs.off.size() * 8, hipMemcpyDeviceToHost, st), "download");
   FAC_HIP(hipStreamSynchronize(st), "phase 2");
@@ -763,6 +765,38 @@ int factor_device(HostSetup &hs, int device, std::string &err) {
   }
   hs.factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   hs.factor_where = 1;
+  return DLMPC_OK;
+}
+
+void free_factors_device(HostSetup &hs) {
+  if (!hs.d_nb) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (hs.d_nb_device >= 0) (void)hipSetDevice(hs.d_nb_device);
+  (void)hipFree(hs.d_nb);
+  if (cur >= 0) (void)hipSetDevice(cur);
+  hs.d_nb = nullptr;
+  hs.d_nb_device = -1;
+}
+
+int fetch_basis(const HostSetup &hs, int32_t j, std::vector<double> &out, std::string &err) {
+  const size_t len = size_t(hs.nb_off[j + 1] - hs.nb_off[j]);
+  out.resize(len);
+  if (len == 0) return DLMPC_OK;
+  if (!hs.nb.empty()) {
+    std::copy(hs.nb.begin() + hs.nb_off[j], hs.nb.begin() + hs.nb_off[j + 1], out.begin());
+    return DLMPC_OK;
+  }
+  if (!hs.d_nb) {
+    err = "no null bases";
+    return DLMPC_EINVAL;
+  }
+  hipError_t e = hipSetDevice(hs.d_nb_device);
+  if (e == hipSuccess) e = hipMemcpy(out.data(), hs.d_nb + hs.nb_off[j], len * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    err = std::string("fetching a null basis: ") + hipGetErrorString(e);
+    return DLMPC_EDEVICE;
+  }
   return DLMPC_OK;
 }
 
