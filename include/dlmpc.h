@@ -99,6 +99,9 @@ typedef struct {
   int32_t max_batch;   /* 0, or 1..64: also set up the batched engine for up to this many x0
                           per dlmpc_solve_batch call (FP32 precision only) */
   int32_t warm_cg_iters; /* CG steps of the trajectory warm start (0: 12) */
+  double factor_chol_tol; /* device factorisation: a Cholesky QR pivot of S K below this
+                             fraction of the largest diagonal of (S K)'(S K) switches that
+                             subsystem to the Householder QR (0: 1e-10; 1 or more: always) */
 } dlmpc_options;
 
 /* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
@@ -145,7 +148,8 @@ typedef struct {
   double tune_persistent_us;
   int64_t sum_k;        /* sum over subsystems of k_j (null-space coordinates per instance) */
   int32_t factor_device; /* 1 if the column blocks were factored on the device, 0 on the host */
-  int32_t pad0;
+  int32_t factor_fallbacks; /* device factorisation: subsystems whose null basis came from the
+                               Householder QR because Cholesky QR of S K met a tiny pivot */
 } dlmpc_info;
 
 /* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the
@@ -155,8 +159,9 @@ typedef struct {
  * the minimum-norm offsets o_c solving the block's equations for each column c of j, so that
  * the Psi-comp projection is psi = N_j N_j' v + o_c. The factorisation runs as two HIP kernels
  * on opts->device (one workgroup per subsystem: pivoted Householder QR of the map from patch
- * inputs to ring values, then of the simulated null-space trajectories) unless the problem is
- * host-only or DLMPC_FLAG_HOST_FACTOR is set; both give the same N_j N_j' and o_c up to
+ * inputs to ring values, then Cholesky QR, applied twice, of the simulated null-space
+ * trajectories, with a Householder QR instead when a Cholesky pivot is tiny) unless the problem
+ * is host-only or DLMPC_FLAG_HOST_FACTOR is set; both give the same N_j N_j' and o_c up to
  * rounding. Uploads the operators and allocates all solve-time device memory. d >= 0, T >= 2.
  * Returns DLMPC_EINFEASIBLE_LOCALITY when some column has no localised trajectory,
  * DLMPC_ENUMERIC when a null basis loses rank, DLMPC_EINVAL when a column block is longer

@@ -411,6 +411,7 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
     return fail(DLMPC_EINVAL, "options: need rho > 0, eps > 0, max_iter >= 0, check_every >= 0");
   if (o.precision != DLMPC_FP64 && o.precision != DLMPC_FP32) return fail(DLMPC_EINVAL, "unknown precision");
   if (o.max_batch < 0 || o.max_batch > 64) return fail(DLMPC_EINVAL, "max_batch must be in 0..64");
+  if (!(o.factor_chol_tol >= 0.0)) return fail(DLMPC_EINVAL, "factor_chol_tol must be >= 0");
   auto p = std::make_unique<dlmpc_problem>();
   p->opt = o;
   p->host_only = (o.flags & DLMPC_FLAG_HOST_ONLY) != 0;
@@ -423,7 +424,7 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
   if (p->host_only || (o.flags & DLMPC_FLAG_HOST_FACTOR))
     rc = dlmpc::factor_host(p->hs, err);
   else
-    rc = dlmpc::factor_device(p->hs, o.device, err);
+    rc = dlmpc::factor_device(p->hs, o.device, o.factor_chol_tol > 0.0 ? o.factor_chol_tol : 1e-10, err);
   if (rc) {
     dlmpc::free_factors_device(p->hs);
     return fail(rc, err);
@@ -458,6 +459,7 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   info->setup_ms = h.setup_ms;
   info->factor_ms = h.factor_ms;
   info->factor_device = h.factor_where;
+  info->factor_fallbacks = h.factor_fallbacks;
   info->schedule = p->sched;
   info->persistent_grid = (p->eng ? p->eng->persistent_grid() : 0);
   info->tune_graph_us = p->tune_graph_us;

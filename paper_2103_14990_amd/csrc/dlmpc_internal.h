@@ -83,6 +83,7 @@ struct HostSetup {
   int64_t sum_dcol_k = 0, sum_dcol2 = 0, sum_k = 0;
   double setup_ms = 0, factor_ms = 0;
   int32_t factor_where = 0;  // 0 = host threads, 1 = device kernels
+  int32_t factor_fallbacks = 0;  // device: subsystems whose basis needed the Householder QR
   // Device factorisation: the padded N_j array (same layout as nb, FP64) stays on the device
   // (owned here, released by free_factors_device); nb is then left empty.
   double *d_nb = nullptr;
@@ -125,7 +126,7 @@ int factor_host(HostSetup &hs, std::string &err);
 
 // The same factorisation by HIP kernels on `device` (one workgroup per subsystem). The
 // offsets come back to hs.off; the bases stay on the device in hs.d_nb.
-int factor_device(HostSetup &hs, int device, std::string &err);
+int factor_device(HostSetup &hs, int device, double chol_tol, std::string &err);
 
 // Releases hs.d_nb (no-op when null).
 void free_factors_device(HostSetup &hs);

@@ -11,8 +11,11 @@
 //            r (relative threshold kRankTol) -> k = dim null(M) = mu - r;
 //   phase 2: K = Q [0; I_k] (orthonormal basis of null(M)); the minimum-norm inputs u_c solving
 //            M u = -(free response of x_0 = e_c on the ring) by forward substitution with R'
-//            and Q; trajectories S K and psi_c = S(e_c, u_c) by simulating the patch; N_j from
-//            a second pivoted Householder QR of S K (rank k required); o_c = psi_c - N N' psi_c.
+//            and Q; trajectories S K and psi_c = S(e_c, u_c) by simulating the patch; N_j by
+//            Cholesky QR applied twice to S K (its input rows are K itself, so its smallest
+//            singular value is at least 1; GEMM-shaped, in 64-column panels), or by a second
+//            pivoted Householder QR (rank k required) when a Cholesky pivot falls below a
+//            set fraction of the largest diagonal; o_c = psi_c - N N' psi_c.
 // The host only builds index lists (patches, ring rows, sparse A entries); every floating-point
 // step runs here. Layout: every per-subsystem matrix is row-major in a global workspace, one
 // thread per column, so a wave's loads of one row are contiguous (64 consecutive doubles).
@@ -33,8 +36,11 @@ namespace {
 
 constexpr int kFT = 512;           // threads per workgroup
 constexpr int kFW = kFT / 64;      // waves per workgroup (row groups of the column passes)
-constexpr int kCC = 4;             // 64-column chunks per pass of reflect_cols
-constexpr int kRU = 2;             // rows per lane and load round of reflect_cols
+constexpr int kCC = 1;             // 64-column chunks per pass of reflect_cols
+constexpr int kRU = 4;             // rows per lane and load round of reflect_cols
+constexpr int kTS = 32 * 65;       // one staged GEMM operand: 32 inner x 64, rows padded to 65
+constexpr int kLdsMin = 2 * kTS;   // doubles of dynamic LDS the GEMM and 64 x 64 Cholesky need
+constexpr int kFallbackOk = 1;     // phase 2 status: done, with the Householder basis
 constexpr int kMaxLdsRows = 4000;  // longest Householder vector staged in LDS (32 KB)
 
 struct FacDesc {
@@ -62,9 +68,10 @@ struct FacArgs {
   int32_t *iwsb;   // phase 2 pivots
   double *nb, *off;
   int32_t *rank;    // [N] phase 1 result
-  int32_t *status;  // [N] phase 2 result (DLMPC_OK or an error)
+  int32_t *status;  // [N] phase 2 result (DLMPC_OK, kFallbackOk, or an error)
   double *resid;    // [N] ring residual of the particular solutions
   int32_t nx, nu, T, rs;
+  double chol_tol;  // smallest Cholesky QR pivot relative to the largest diagonal of Y'Y
 };
 
 // Largest value over the workgroup, ties to the smallest index; uniform result.
@@ -332,6 +339,143 @@ __device__ void apply_q_dev(const double *F, int m, int ldf, const double *tau, 
   }
 }
 
+// C (M x Nn, row-major ldc) = beta C + alpha A B' with A(i, l) and B(j, l), l < L, read as
+// A[l*lda + i] and B[l*ldb + j] (TN) or A[i*lda + l] and B[j*ldb + l] (NT). 64 x 64 output
+// tiles, 4 x 2 outputs per thread; 32 values of l of both operands staged in LDS (s_t, 2 kTS
+// doubles) per round. lower: tiles above the diagonal are skipped and only j <= i is written.
+// beta = 0 does not read C. A tile's operands are read completely before it is written, so C
+// may alias A or B when Nn <= 64 (one column tile). Ends with a barrier.
+template <bool TN>
+__device__ void gemm_dev(int M, int Nn, int L, double alpha, const double *A, int lda, const double *B, int ldb,
+                         double beta, double *C, int ldc, bool lower, double *s_t) {
+  const int tid = threadIdx.x, ta = tid >> 5, tb = tid & 31;
+  for (int i0 = 0; i0 < M; i0 += 64)
+    for (int j0 = 0; j0 < Nn; j0 += 64) {
+      if (lower && j0 > i0 + 63) continue;
+      double acc[4][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = 0.0;
+      for (int l0 = 0; l0 < L; l0 += 32) {
+#pragma unroll
+        for (int u = 0; u < 2048 / kFT; ++u) {  // 64 x 32 values of each operand
+          const int e = tid + kFT * u;
+          const int ii = TN ? (e & 63) : (e >> 5), ll = TN ? (e >> 6) : (e & 31);
+          const int i = i0 + ii, j = j0 + ii, l = l0 + ll;
+          const bool lin = l < L;
+          s_t[ll * 65 + ii] = (lin && i < M) ? (TN ? A[int64_t(l) * lda + i] : A[int64_t(i) * lda + l]) : 0.0;
+          s_t[kTS + ll * 65 + ii] = (lin && j < Nn) ? (TN ? B[int64_t(l) * ldb + j] : B[int64_t(j) * ldb + l]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int ll = 0; ll < 32; ++ll) {
+          const double *ra = s_t + ll * 65 + 4 * ta, *rb = s_t + kTS + ll * 65 + 2 * tb;
+          const double a0 = ra[0], a1 = ra[1], a2 = ra[2], a3 = ra[3], b0 = rb[0], b1 = rb[1];
+          acc[0][0] += a0 * b0;
+          acc[0][1] += a0 * b1;
+          acc[1][0] += a1 * b0;
+          acc[1][1] += a1 * b1;
+          acc[2][0] += a2 * b0;
+          acc[2][1] += a2 * b1;
+          acc[3][0] += a3 * b0;
+          acc[3][1] += a3 * b1;
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          const int i = i0 + 4 * ta + q, j = j0 + 2 * tb + w;
+          if (i < M && j < Nn && (!lower || j <= i)) {
+            double *c = C + int64_t(i) * ldc + j;
+            *c = (beta == 0.0) ? alpha * acc[q][w] : beta * *c + alpha * acc[q][w];
+          }
+        }
+    }
+  __syncthreads();
+}
+
+// Cholesky factor of the nb x nb (nb <= 64) diagonal block at (jb, jb) of G (row-major,
+// leading dimension ldg; lower triangle used and overwritten with L), and the inverse of that
+// factor written to Li (64 x 64 row-major, zero above the diagonal). Both triangles live packed
+// in LDS (s_t: L at i(i+1)/2 + l, inverse 2080 further). Returns false, uniformly, when a pivot
+// is not above tol.
+__device__ bool chol_inv64(double *G, int ldg, int jb, int nb, double *Li, double tol, double *s_t) {
+  const int tid = threadIdx.x;
+  double *sl = s_t, *si = s_t + 2080;
+  for (int e = tid; e < nb * nb; e += kFT) {
+    const int i = e / nb, l = e % nb;
+    if (l <= i) sl[i * (i + 1) / 2 + l] = G[int64_t(jb + i) * ldg + jb + l];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double pv = sl[j * (j + 1) / 2 + j];
+    if (!(pv > tol) || !(pv < INFINITY)) return false;
+    const double dj = sqrt(pv);
+    for (int i = j + 1 + tid; i < nb; i += kFT) sl[i * (i + 1) / 2 + j] /= dj;
+    __syncthreads();
+    if (tid == 0) sl[j * (j + 1) / 2 + j] = dj;
+    const int n = nb - j - 1;
+    for (int e = tid; e < n * n; e += kFT) {
+      const int i = j + 1 + e / n, l = j + 1 + e % n;
+      if (l <= i) sl[i * (i + 1) / 2 + l] -= sl[i * (i + 1) / 2 + j] * sl[l * (l + 1) / 2 + j];
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < nb; ++i) {
+    for (int c = tid; c <= i; c += kFT) {
+      double t = (c == i) ? 1.0 : 0.0;
+      for (int l = c; l < i; ++l) t -= sl[i * (i + 1) / 2 + l] * si[l * (l + 1) / 2 + c];
+      si[i * (i + 1) / 2 + c] = t / sl[i * (i + 1) / 2 + i];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 64 * 64; e += kFT) {
+    const int i = e >> 6, l = e & 63;
+    Li[e] = (i < nb && l <= i) ? si[i * (i + 1) / 2 + l] : 0.0;
+    if (i < nb && l <= i) G[int64_t(jb + i) * ldg + jb + l] = sl[i * (i + 1) / 2 + l];
+  }
+  __syncthreads();
+  return true;
+}
+
+// Q (m x k, row-major ldq) = Y L^{-T}, an orthonormal basis of range(Y) for Y (m x k, row-major
+// ldy) with Y'Y = L L' (Cholesky QR): Gram by gemm_dev, Cholesky in 64-column panels (panel
+// factor and inverse in LDS, L21 = G21 L11^{-T} and G22 -= L21 L21' by gemm_dev), then
+// Q_B = (Y_B - Q_<B L_B,<B') L_BB^{-T} panel by panel. G: k x k workspace; Lb: ceil(k/64)
+// blocks of 64 x 64. Y and Q must not alias. Returns false, uniformly, when a pivot is not
+// above tol times the largest diagonal entry of Y'Y.
+__device__ bool cholqr_dev(const double *Y, int ldy, int m, int k, double *Q, int ldq, double *G, double *Lb,
+                           double tol, double *s_t, double *s_rv) {
+  const int tid = threadIdx.x;
+  gemm_dev<true>(k, k, m, 1.0, Y, ldy, Y, ldy, 0.0, G, k, true, s_t);
+  double md = 0.0;
+  for (int i = tid; i < k; i += kFT) md = max_nan(md, G[int64_t(i) * k + i]);
+  md = block_max(md, s_rv);
+  if (!(md > 0.0) || !(md < INFINITY)) return false;
+  for (int jb = 0; jb < k; jb += 64) {
+    const int nb = min(64, k - jb), rest = k - jb - nb;
+    double *Li = Lb + int64_t(jb / 64) * 4096;
+    if (!chol_inv64(G, k, jb, nb, Li, tol * md, s_t)) return false;
+    if (rest > 0) {
+      double *G21 = G + int64_t(jb + nb) * k + jb;
+      gemm_dev<false>(rest, nb, nb, 1.0, G21, k, Li, 64, 0.0, G21, k, false, s_t);
+      gemm_dev<false>(rest, rest, nb, -1.0, G21, k, G21, k, 1.0, G21 + nb, k, true, s_t);
+    }
+  }
+  for (int jb = 0; jb < k; jb += 64) {
+    const int nb = min(64, k - jb);
+    for (int64_t e = tid; e < int64_t(m) * nb; e += kFT) {
+      const int i = int(e / nb), c = int(e % nb);
+      Q[int64_t(i) * ldq + jb + c] = Y[int64_t(i) * ldy + jb + c];
+    }
+    __syncthreads();
+    if (jb > 0) gemm_dev<false>(m, nb, jb, -1.0, Q, ldq, G + int64_t(jb) * k, k, 1.0, Q + jb, ldq, false, s_t);
+    gemm_dev<false>(m, nb, nb, 1.0, Q + jb, ldq, Lb + int64_t(jb / 64) * 4096, 64, 0.0, Q + jb, ldq, false, s_t);
+  }
+  return true;
+}
+
 struct Patch {
   const double *A, *B;
   const int32_t *arp, *acol, *aidx;  // A_PP (CSR over patch states)
@@ -479,6 +623,7 @@ __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
   double *Nw = S + int64_t(D) * ncol;
   double *tau2 = Nw + int64_t(D) * k, *nrm2 = tau2 + k;
   double *ringv = nrm2 + k, *rhs = ringv + int64_t(mc) * nx, *tv = rhs + int64_t(r) * nx;
+  double *Q2 = tv + int64_t(k) * nx, *Gk = Q2 + int64_t(D) * k, *Lb = Gk + int64_t(k) * k;
   int *jp2 = a.iwsb + d.ib_off;
 
   // Ring values of the free responses x_0 = e_c (scratch trajectories in the offset columns).
@@ -513,28 +658,36 @@ __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
     }
     return;
   }
+  // N_j: Cholesky QR twice (S K -> Nw -> Q2); Householder QR of S K when a pivot is too small.
+  const double *Nb = Q2;
   if (k > 0) {
-    const int r2 = qr_pivoted_dev(S, D, k, ncol, kBasisTol, tau2, jp2, nrm2, s_v, s_part, s_rv, s_ri);
-    if (r2 != k) {
-      if (tid == 0) a.status[j] = DLMPC_ENUMERIC;
-      return;
+    bool ok = cholqr_dev(S, ncol, D, k, Nw, k, Gk, Lb, a.chol_tol, s_v, s_rv);
+    if (ok) ok = cholqr_dev(Nw, k, D, k, Q2, k, Gk, Lb, a.chol_tol, s_v, s_rv);
+    if (!ok) {
+      const int r2 = qr_pivoted_dev(S, D, k, ncol, kBasisTol, tau2, jp2, nrm2, s_v, s_part, s_rv, s_ri);
+      if (r2 != k) {
+        if (tid == 0) a.status[j] = DLMPC_ENUMERIC;
+        return;
+      }
+      for (int64_t e = tid; e < int64_t(D) * k; e += kFT) {
+        const int i = int(e / k), c = int(e % k);
+        Nw[e] = (i == c) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      apply_q_dev(S, D, ncol, tau2, k, Nw, k, k, true, s_v, s_part);
+      Nb = Nw;
+      if (tid == 0) a.status[j] = kFallbackOk;
     }
-    for (int64_t e = tid; e < int64_t(D) * k; e += kFT) {
-      const int i = int(e / k), c = int(e % k);
-      Nw[e] = (i == c) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    apply_q_dev(S, D, ncol, tau2, k, Nw, k, k, true, s_v, s_part);
     // t = N' psi_c
     for (int e = tid; e < k * nx; e += kFT) {
       const int c = e / nx, cc = e % nx;
       double s0 = 0.0, s1 = 0.0;
       int i = 0;
       for (; i + 1 < D; i += 2) {
-        s0 += Nw[int64_t(i) * k + c] * S[int64_t(i) * ncol + k + cc];
-        s1 += Nw[int64_t(i + 1) * k + c] * S[int64_t(i + 1) * ncol + k + cc];
+        s0 += Nb[int64_t(i) * k + c] * S[int64_t(i) * ncol + k + cc];
+        s1 += Nb[int64_t(i + 1) * k + c] * S[int64_t(i + 1) * ncol + k + cc];
       }
-      if (i < D) s0 += Nw[int64_t(i) * k + c] * S[int64_t(i) * ncol + k + cc];
+      if (i < D) s0 += Nb[int64_t(i) * k + c] * S[int64_t(i) * ncol + k + cc];
       tv[e] = s0 + s1;
     }
     __syncthreads();
@@ -543,15 +696,15 @@ __global__ __launch_bounds__(kFT) void fac_basis_kernel(FacArgs a) {
   for (int i = tid; i < D; i += kFT)
     for (int cc = 0; cc < nx; ++cc) {
       double s = 0.0;
-      for (int c = 0; c < k; ++c) s += Nw[int64_t(i) * k + c] * tv[c * nx + cc];
+      for (int c = 0; c < k; ++c) s += Nb[int64_t(i) * k + c] * tv[c * nx + cc];
       a.off[d.off_off + int64_t(cc) * ld + i] = S[int64_t(i) * ncol + k + cc] - s;
     }
   for (int64_t e = tid; e < int64_t(D) * k; e += kFT) {
     const int c = int(e / D), i = int(e % D);
-    a.nb[d.nb_off + int64_t(c) * ld + i] = Nw[int64_t(i) * k + c];
+    a.nb[d.nb_off + int64_t(c) * ld + i] = Nb[int64_t(i) * k + c];
   }
   if (tid == 0) {
-    a.status[j] = DLMPC_OK;
+    if (Nb != Nw) a.status[j] = DLMPC_OK;
     a.resid[j] = res;
   }
 }
@@ -574,7 +727,7 @@ struct DevBufs {
 
 }  // namespace
 
-int factor_device(HostSetup &hs, int device, std::string &err) {
+int factor_device(HostSetup &hs, int device, double chol_tol, std::string &err) {
   const auto t0 = std::chrono::steady_clock::now();
   const int32_t N = hs.N, nx = hs.nx, nu = hs.nu, T = hs.T;
   if (hs.a_blocks.size() >= size_t(INT_MAX)) {
@@ -690,7 +843,8 @@ int factor_device(HostSetup &hs, int device, std::string &err) {
   a.nu = nu;
   a.T = T;
   a.rs = hs.rs;
-  const size_t lds = size_t(vmax) * sizeof(double);
+  a.chol_tol = chol_tol;
+  const size_t lds = size_t(std::max(vmax, kLdsMin)) * sizeof(double);
   hipLaunchKernelGGL(fac_ring_qr_kernel, dim3(N), dim3(kFT), lds, st, a);
   FAC_HIP(hipGetLastError(), "phase 1 launch");
   std::vector<int32_t> rank(N);
@@ -715,7 +869,8 @@ int factor_device(HostSetup &hs, int device, std::string &err) {
     const int64_t mu = int64_t(hs.patch[j].size()) * nu * (T - 1), mc = int64_t(d.ng) * (T - 1);
     const int64_t D = int64_t(d.p) * hs.rs, k = ks[j], ncol = k + nx, r = rank[j];
     d.wb_off = wb_tot;
-    wb_tot += mu * ncol + D * ncol + D * k + 2 * k + mc * nx + r * nx + k * nx;
+    wb_tot += mu * ncol + D * ncol + D * k + 2 * k + mc * nx + r * nx + k * nx + D * k + k * k +
+              (k + 63) / 64 * 4096;
     d.ib_off = ib_tot;
     ib_tot += k;
     d.nb_off = hs.nb_off[j];
@@ -748,7 +903,12 @@ int factor_device(HostSetup &hs, int device, std::string &err) {
     FAC_HIP(hipMemcpyAsync(hs.off.data(), d_off, hs.off.size() * 8, hipMemcpyDeviceToHost, st), "download");
   FAC_HIP(hipStreamSynchronize(st), "phase 2");
 #undef FAC_HIP
+  hs.factor_fallbacks = 0;
   for (int j = 0; j < N; ++j) {
+    if (status[j] == kFallbackOk) {
+      ++hs.factor_fallbacks;
+      continue;
+    }
     if (status[j] == DLMPC_EINFEASIBLE_LOCALITY) {
       err = "column of subsystem " + std::to_string(j) +
             " has no trajectory inside its d-hop patch (ring residual " + std::to_string(resid[j]) + ")";

@@ -49,7 +49,7 @@ class Options(C.Structure):
     _fields_ = [("rho", C.c_double), ("eps", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("flags", C.c_uint32), ("max_batch", C.c_int32),
-                ("warm_cg_iters", C.c_int32)]
+                ("warm_cg_iters", C.c_int32), ("factor_chol_tol", C.c_double)]
 
 
 class Warm(C.Structure):
@@ -81,7 +81,7 @@ class Info(C.Structure):
                 ("setup_ms", C.c_double), ("factor_ms", C.c_double), ("schedule", C.c_int32),
                 ("persistent_grid", C.c_int32), ("tune_graph_us", C.c_double),
                 ("tune_persistent_us", C.c_double), ("sum_k", C.c_int64),
-                ("factor_device", C.c_int32), ("pad0", C.c_int32)]
+                ("factor_device", C.c_int32), ("factor_fallbacks", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -182,7 +182,7 @@ class Problem:
                  rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500, precision: str = "fp64",
                  device: int = 0, stream: int | None = None, check_every: int = 0,
                  host_only: bool = False, schedule: str = "auto", max_batch: int = 0,
-                 warm_cg_iters: int = 0, factor: str = "device"):
+                 warm_cg_iters: int = 0, factor: str = "device", factor_chol_tol: float = 0.0):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -197,7 +197,7 @@ class Problem:
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
                        (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule] | FACTORS[factor], max_batch,
-                       warm_cg_iters)
+                       warm_cg_iters, factor_chol_tol)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
             raise DlmpcError(st, self._lib.dlmpc_last_error().decode())

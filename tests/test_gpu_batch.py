@@ -29,12 +29,16 @@ def check_instances(pb, x0s, u0, stats, n_check=None, iter_slack=3):
     idx = range(len(x0s)) if n_check is None else np.linspace(0, len(x0s) - 1, n_check).astype(int)
     for i in idx:
         ref = O.solve(pb, x0s[i], RHO, EPS, MAXIT)
+        assert stats[i]["converged"] == int(ref.converged)
+        assert abs(stats[i]["iters"] - ref.iters) <= iter_slack
+        if stats[i]["iters"] != ref.iters:
+            # an eps-stopped iterate is fixed only to O(eps): compare with the oracle's iterate
+            # after the same number of iterations
+            ref = O.solve(pb, x0s[i], RHO, 0.0, stats[i]["iters"])
         e = rel(u0[i], ref.u0) if np.abs(ref.u0).max() > 0 else float(np.abs(u0[i]).max())
         je = abs(stats[i]["objective"] - ref.J) / max(ref.J, 1e-300)
         print(f"  instance {i}: iters {stats[i]['iters']} (oracle {ref.iters}) u0 rel {e:.2e} J rel {je:.2e}",
               flush=True)
-        assert stats[i]["converged"] == int(ref.converged)
-        assert abs(stats[i]["iters"] - ref.iters) <= iter_slack
         assert e < 1e-4
         assert je < 1e-5 or ref.J == 0.0
 

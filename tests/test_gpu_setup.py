@@ -39,7 +39,8 @@ def test_device_factor_matches_oracle(name):
     wl = W.workload(name)
     pr = _dev(wl.net, wl.d, wl.T, wl.cost)
     pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
-    print(f"  {name}: factor {pr.info['factor_ms']:.1f} ms, k_max {pr.info['k_max']}", flush=True)
+    print(f"  {name}: factor {pr.info['factor_ms']:.1f} ms, k_max {pr.info['k_max']}, "
+          f"fallbacks {pr.info['factor_fallbacks']}", flush=True)
     _compare_blocks(pr, pb, range(wl.net.n_sub), 1e-10, 1e-9)
     ks = [len(b.rows) - b.rank for b in pb.blocks]
     assert pr.info["k_max"] == max(ks) and pr.info["sum_k"] == sum(ks)
@@ -72,6 +73,31 @@ def test_device_factor_infeasible_locality():
     assert e.value.status == dlmpc.EINFEASIBLE_LOCALITY
 
 
+@pytest.mark.parametrize("name", ["chain10", "grid16_box"])
+def test_device_factor_householder_path(name):
+    """factor_chol_tol = 1 sends every subsystem through the Householder QR of S K (the path
+    taken when a Cholesky QR pivot is tiny): same blocks as the oracle."""
+    wl = W.workload(name)
+    pr = _dev(wl.net, wl.d, wl.T, wl.cost, factor_chol_tol=1.0)
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
+    assert pr.info["factor_fallbacks"] == wl.net.n_sub
+    _compare_blocks(pr, pb, range(wl.net.n_sub), 1e-10, 1e-9)
+    pr.close()
+
+
+def test_device_factor_unstable_plant():
+    """A scaled by 3 (spectral radius 3), T = 14: trajectories grow ~1e5-fold; blocks still
+    match the oracle."""
+    net = W.chain(6)
+    net.a_blocks = net.a_blocks * 3.0
+    cost = W.unit_cost(net)
+    pr = _dev(net, 1, 14, cost)
+    pb = O.setup_from_network(net, 1, 14, cost)
+    print(f"  Householder fallbacks: {pr.info['factor_fallbacks']} of 6", flush=True)
+    _compare_blocks(pr, pb, range(6), 1e-9, 1e-8)
+    pr.close()
+
+
 def test_device_factor_whole_graph_patch():
     """d >= diameter: one patch is the whole network (no ring equations, M empty)."""
     net = W.chain(5)
@@ -94,6 +120,7 @@ def test_device_factor_full_size_mesh_matches_host():
           f"problem {t_dev * 1e3:.0f} ms), host {host.info['factor_ms']:.1f} ms", flush=True)
     for key in ("k_max", "sum_k", "sum_dcol_k", "nnz", "d_col_max"):
         assert dev.info[key] == host.info[key], key
+    assert dev.info["factor_fallbacks"] == 0  # Cholesky QR throughout
     N = wl.net.n_sub
     rng = np.random.default_rng(0)
     dcol = np.asarray([len(dev.column_block(j, want_P=False)[0]) for j in range(N)])
