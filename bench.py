@@ -138,6 +138,9 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-launch timing of the batched kernels (for profiler runs)")
+    ap.add_argument("--setup-only", action="store_true",
+                    help="only problem creation (device factorisation of the column blocks, engine layouts), "
+                         "twice, for profiler runs")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -171,6 +174,17 @@ def main() -> int:
         log(f"setup {precision} (max_batch {max_batch}): {time.perf_counter() - t:.1f} s")
         return p
 
+    if args.setup_only:
+        rec = []
+        for _ in range(2):
+            t = time.perf_counter()
+            p = make("fp32", B)
+            rec.append({"problem_ms": round(1e3 * (time.perf_counter() - t), 1),
+                        "setup_ms": round(p.info["setup_ms"], 1), "factor_ms": round(p.info["factor_ms"], 1),
+                        "factor_device": p.info["factor_device"], "factor_fallbacks": p.info["factor_fallbacks"]})
+            p.close()
+        print(json.dumps({"workload": args.workload, "setup": rec}), flush=True)
+        return 0
     pr = make("fp32", B)
     if args.kernels_only:
         xk = torch.tensor(np.stack([wl.x0(1000 + i) for i in range(B)]), dtype=torch.float64, device=dev)
@@ -368,6 +382,7 @@ def main() -> int:
         "speedup_vs_plain_fp64": round(ref["time_to_eps_ms_median"] / (ms_step / B), 2) if ref else None,
         "warm_start_training": train,
         "setup_ms": round(pr.info["setup_ms"], 1),
+        "factor_ms": round(pr.info["factor_ms"], 1),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
