@@ -278,6 +278,34 @@ int dlmpc_solve_batch_ex(struct dlmpc_problem *p, int32_t B, const double *x0_de
                          int32_t start, const double *start_dev, double *y_out_dev,
                          double *alpha_out_dev, dlmpc_stats *stats);
 
+/* Counters of a streamed solve (dlmpc_solve_stream). */
+typedef struct {
+  int32_t joins;               /* times new instances entered free slots (the first fill included) */
+  int32_t checks;              /* host checks of the per-instance stop flags */
+  int64_t slot_iterations;     /* iterations launched times slots in use */
+  int64_t instance_iterations; /* sum over instances of their warm-started iterations */
+  int32_t fell_back;           /* instances re-solved from the cold start */
+  int32_t pad;
+  double t_stream_ms;          /* device time from the first fill to the last stop */
+} dlmpc_stream_info;
+
+/* n independent instances of this network (any n >= 1) streamed through the batched engine's
+ * max_batch slots, each from the learned start (needs the warm-start network): every
+ * check_iters iterations (0: 4) the host reads the per-instance stop flags, writes u(0) of the
+ * instances that stopped to their rows of u0_dev, and once at least refill_min slots are free
+ * (0: half the slots; or the last instances are waiting; or no slot is busy) starts the next
+ * instances in them: network inference, simulation, CG and the start projections run for the
+ * joining slots only while the others keep their state, and the joiners enter the running
+ * iteration with their own iteration count. Per instance the arithmetic is that of
+ * dlmpc_solve_batch_ex with the learned start (same start, same iterates, same stopping rule),
+ * whatever slot and moment it joins; instances that end unconverged are solved again from the
+ * cold start. x0_dev [n][N*nx], u0_dev [n][N*nu] device buffers; stats [n] and info may be NULL.
+ * Returns DLMPC_OK, or DLMPC_ENOCONV if some instance did not converge even from the cold
+ * start. */
+int dlmpc_solve_stream(struct dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev,
+                       int32_t refill_min, int32_t check_iters, dlmpc_stats *stats,
+                       dlmpc_stream_info *info);
+
 /* ---- Learned warm start: one network per subsystem g (separate FP32 weights), input the x0
  * entries of the subsystems within d hops of g (ascending subsystem order, each nx entries,
  * zero-padded to IN = p_max*nx) divided by x_scale; two GELU hidden layers of width `hidden`;

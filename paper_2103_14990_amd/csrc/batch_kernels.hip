@@ -81,11 +81,15 @@ __device__ __forceinline__ T wsum(T v) {
 
 template <int NX>
 __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double *x0, int B, int warm,
-                                                          int max_iter, double eps) {
-  const int m = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+                                                          int max_iter, double eps, const int32_t *slots,
+                                                          const int32_t *xsrc, int reset) {
+  // instance blockIdx.y: slot slots[y] (or y), initial state row xsrc[y] (or y) of x0; reset:
+  // the solve starts here (global control block reset); otherwise the slot joins a running one
+  const int m = blockIdx.x, y = blockIdx.y, tid = threadIdx.x;
+  const int b = slots ? slots[y] : y;
   const int rs = a.rs;
   const int64_t nxs = int64_t(a.N) * NX;
-  const double *xb = x0 + int64_t(b) * nxs;
+  const double *xb = x0 + int64_t(xsrc ? xsrc[y] : y) * nxs;
   if (tid < NX) a.x0[int64_t(b) * nxs + m * NX + tid] = static_cast<float>(xb[m * NX + tid]);
   if (tid == 0) {
     double sm = 0.0, sn = 0.0;
@@ -126,10 +130,12 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
     ic.stop = 0;
     ic.converged = 0;
     ic.numeric = 0;
+    ic.it0 = reset ? 0 : a.ctl->iters;
     ic.last_rp = ic.last_rd = INFINITY;
     ic.objective = 0.0;
     a.slot[2 * b] = a.slot[2 * b + 1] = 0ull;
-    if (b == 0) {
+    if (!reset && y == 0) a.ctl->stop = 0;  // a running solve resumes with the new slots
+    if (reset && y == 0) {
       Ctl *c = a.ctl;
       c->iters = 0;
       c->stop = 0;
@@ -501,6 +507,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
         const float en = acc[t][nt][e];
         float wv;
         if (initp) {
+          if (a.imask && !a.imask[b]) continue;
           a.dst_k[ki] = en;
           if (a.wmode == 0) continue;
           wv = xj * (a.wmode == 2 ? a.tau[ki] + en : en);
@@ -585,7 +592,7 @@ __global__ __launch_bounds__(64) void bdecide_kernel(BArgs a) {
     if (!ic.stop) {
       const double rp = __longlong_as_double(static_cast<long long>(a.slot[2 * b]));
       const double rd = __longlong_as_double(static_cast<long long>(a.slot[2 * b + 1]));
-      ic.iters = it;
+      ic.iters = it - ic.it0;
       ic.last_rp = rp;
       ic.last_rd = rd;
       if (!(rp == rp) || !(rd == rd) || isinf(rp) || isinf(rd)) {
@@ -594,7 +601,7 @@ __global__ __launch_bounds__(64) void bdecide_kernel(BArgs a) {
       } else if (rp <= c->eps && rd <= c->eps) {
         ic.converged = 1;
         ic.stop = 1;
-      } else if (it >= c->max_iter) {
+      } else if (ic.iters >= c->max_iter) {
         ic.stop = 1;
       }
       if (!ic.stop) {
@@ -615,9 +622,12 @@ __global__ __launch_bounds__(64) void bdecide_kernel(BArgs a) {
 }
 
 template <int NX>
-__global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0) {
+__global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0, const int32_t *slots,
+                                                      const int32_t *dst) {
+  // slot slots[x] (or x) into row dst[x] (or x) of u0
   __shared__ double red[4];
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = slots ? slots[blockIdx.x] : blockIdx.x, tid = threadIdx.x;
+  const int64_t orow = dst ? dst[blockIdx.x] : blockIdx.x;
   const int64_t ny = int64_t(a.N) * a.rs;
   const float *sb = a.s + b;  // row i of instance b at sb[i * Bmax]
   double acc = 0.0;
@@ -628,7 +638,7 @@ __global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0) {
   if (tid == 0) a.ictl[b].objective = (red[0] + red[1]) + (red[2] + red[3]);
   for (int i = tid; i < a.N * a.nu; i += 256) {
     const int m = i / a.nu, q = i - m * a.nu;
-    u0[int64_t(b) * a.N * a.nu + i] = double(sb[(int64_t(m) * a.rs + NX * a.T + q) * a.Bmax]);
+    u0[orow * a.N * a.nu + i] = double(sb[(int64_t(m) * a.rs + NX * a.T + q) * a.Bmax]);
   }
 }
 
@@ -648,8 +658,8 @@ __global__ __launch_bounds__(256) void btraj_load_kernel(BArgs a, const double *
 // State rows of yhat: x_0 = x0, x_{t+1} = sum_j A_ij x_j(t) + B_i u_i(t), one block per
 // instance, one time step per barrier interval.
 template <int NX>
-__global__ __launch_bounds__(256) void bsim_kernel(BArgs a) {
-  const int b = blockIdx.x, tid = threadIdx.x;
+__global__ __launch_bounds__(256) void bsim_kernel(BArgs a, const int32_t *slots) {
+  const int b = slots ? slots[blockIdx.x] : blockIdx.x, tid = threadIdx.x;
   const int rs = a.rs, nu = a.nu, N = a.N;
   float *y = a.yhat + int64_t(b) * N * rs;
   const float *x0 = a.x0 + int64_t(b) * N * NX;
@@ -693,10 +703,12 @@ __device__ __forceinline__ double block_sum1024(double v, double *red) {
   return s;
 }
 
-// r = yhat - b, p = r, x = 0, rr = r'r; alpha^0 = -2 w yhat / rho into the previous plane.
-__global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a) {
+// r = yhat - b, p = r, x = 0, rr = r'r; alpha^0 = -2 w yhat / rho into plane `pl` (the one the
+// next iteration reads as its previous iterate).
+__global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *slots, int pl) {
   __shared__ double red[16];
-  const int b = blockIdx.x;
+  const int b = slots ? slots[blockIdx.x] : blockIdx.x;
+  float *alpha = a.alpha + int64_t(pl) * a.Bmax * a.N * a.rs;
   const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < ny; i += 1024) {
@@ -705,7 +717,7 @@ __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a) {
     a.cg_r[o + i] = r;
     a.cg_p[o + i] = r;
     a.cg_x[o + i] = 0.f;
-    a.alpha[i * a.Bmax + b] = -2.f * a.w[i] * y / a.rho;
+    alpha[i * a.Bmax + b] = -2.f * a.w[i] * y / a.rho;
     acc += double(r) * double(r);
   }
   acc = block_sum1024(acc, red);
@@ -713,9 +725,9 @@ __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a) {
 }
 
 // One CG step per instance after cg_q = M cg_p.
-__global__ __launch_bounds__(1024) void bcg_step_kernel(BArgs a) {
+__global__ __launch_bounds__(1024) void bcg_step_kernel(BArgs a, const int32_t *slots) {
   __shared__ double red[16];
-  const int b = blockIdx.x;
+  const int b = slots ? slots[blockIdx.x] : blockIdx.x;
   const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
   const double rr = a.cg_rr[b];
   double pq = 0.0;
@@ -743,6 +755,15 @@ __global__ __launch_bounds__(256) void bexport_y_kernel(BArgs a, double *out, in
     const int64_t b = i / ny;
     out[i] = double(a.s[(i - b * ny) * a.Bmax + b]);
   }
+}
+
+// Rows of src ([S][ny], FP32) into rows slots[0..S) of dst ([Bmax][ny]).
+__global__ __launch_bounds__(256) void bscatter_rows_kernel(const float *src, const int32_t *slots, int64_t ny,
+                                                            float *dst) {
+  const int y = blockIdx.x;
+  const float *s = src + int64_t(y) * ny;
+  float *d = dst + int64_t(slots[y]) * ny;
+  for (int64_t i = int64_t(blockIdx.y) * 256 + threadIdx.x; i < ny; i += int64_t(gridDim.y) * 256) d[i] = s[i];
 }
 
 // ------------------------------------------------------------------ engine
@@ -967,7 +988,9 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&a.nrm, size_t(bmax) * N, err)) || (rc = al(&a.bvec, size_t(bmax) * ny, err)) ||
         (rc = al(&a.s, size_t(bmax) * ny, err)) || (rc = al(&a.x0, size_t(bmax) * N * NX, err)) ||
         (rc = al(&a.ictl, size_t(bmax), err)) || (rc = al(&a.slot, 2 * size_t(bmax), err)) ||
-        (rc = al(&a.ctl, 1, err)))
+        (rc = al(&a.ctl, 1, err)) || (rc = al(&d_slots_, size_t(bmax), err)) ||
+        (rc = al(&d_xsrc_, size_t(bmax), err)) || (rc = al(&d_mask_, size_t(bmax), err)) ||
+        (rc = al(&d_oslots_, size_t(bmax), err)) || (rc = al(&d_odst_, size_t(bmax), err)))
       return rc;
     // trajectory warm start: vectors and the plant in FP32
     a.Bw = (bmax + 15) & ~15;
@@ -1005,15 +1028,16 @@ class BatchEngineT final : public BatchEngine {
     }
     B_ = B;
     hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, B), dim3(256), 0, stream_, args_, x0_dev, B,
-                       warm ? 1 : 0, max_iter, eps);
+                       warm ? 1 : 0, max_iter, eps, nullptr, nullptr, 1);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
 
   // dst_k = N_j' src for every column subsystem j and instance; wmode 1 also writes the
   // product operand W = ||x0_j||^2 dst_k, wmode 2 W = ||x0_j||^2 (tau + dst_k).
-  int project_t(const float *src, int64_t src_bs, int64_t src_rs, float *dst_k, int wmode, std::string &err) {
-    BArgs ia = args_;
+  int project_t(const float *src, int64_t src_bs, int64_t src_rs, float *dst_k, int wmode, std::string &err,
+                const BArgs *base = nullptr) {
+    BArgs ia = base ? *base : args_;
     ia.init_pass = 1;
     ia.wmode = wmode;
     ia.src = src;
@@ -1036,9 +1060,9 @@ class BatchEngineT final : public BatchEngine {
       hipLaunchKernelGGL(btraj_load_kernel, dim3(1024), dim3(256), 0, stream_, args_, y0_dev, B_);
       BENG_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_);
+    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, nullptr);
     BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(bcg_init_kernel, dim3(B_), dim3(1024), 0, stream_, args_);
+    hipLaunchKernelGGL(bcg_init_kernel, dim3(B_), dim3(1024), 0, stream_, args_, nullptr, 0);
     BENG_CHECK(hipGetLastError());
     BArgs qa = args_;
     qa.phi_mode = 1;
@@ -1047,7 +1071,7 @@ class BatchEngineT final : public BatchEngine {
       if ((rc = project_t(args_.cg_p, ny_, 1, args_.eta, 1, err))) return rc;  // eta = N' p, W = ||x0_j||^2 eta
       launch_phi(qa);  // q = M p
       BENG_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_);
+      hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_, nullptr);
       BENG_CHECK(hipGetLastError());
     }
     if ((rc = project_t(args_.cg_x, ny_, 1, args_.tau, 0, err))) return rc;  // tau = N' beta
@@ -1055,6 +1079,78 @@ class BatchEngineT final : public BatchEngine {
   }
 
   float *yhat() override { return args_.yhat; }
+
+  int stream_start(const double *x0_dev, const int32_t *slots, const int32_t *xsrc, int S, const float *ypred,
+                   int cg_iters, bool first, int iters, int max_iter, double eps, std::string &err) override {
+    const int Bm = args_.Bmax;
+    if (S < 1 || S > Bm) {
+      err = "stream_start: slot count out of range";
+      return DLMPC_EINVAL;
+    }
+    // staging in the engine (the copies are ordered on the stream; the host rewrites these
+    // vectors only after the stream has drained)
+    st_slots_.assign(slots, slots + S);
+    st_xsrc_.assign(xsrc, xsrc + S);
+    st_mask_.assign(Bm, 0);
+    for (int i = 0; i < S; ++i) {
+      if (slots[i] < 0 || slots[i] >= Bm || st_mask_[slots[i]]) {
+        err = "stream_start: bad or repeated slot";
+        return DLMPC_EINVAL;
+      }
+      if (first && slots[i] != i) {
+        err = "stream_start: the initial fill takes slots 0..S-1";
+        return DLMPC_EINVAL;
+      }
+      st_mask_[slots[i]] = 1;
+    }
+    BENG_CHECK(hipMemcpyAsync(d_slots_, st_slots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    BENG_CHECK(hipMemcpyAsync(d_xsrc_, st_xsrc_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    BENG_CHECK(hipMemcpyAsync(d_mask_, st_mask_.data(), sizeof(int32_t) * Bm, hipMemcpyHostToDevice, stream_));
+    if (first) B_ = S;
+    hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, S), dim3(256), 0, stream_, args_, x0_dev, S, 1,
+                       max_iter, eps, d_slots_, d_xsrc_, first ? 1 : 0);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bscatter_rows_kernel, dim3(S, 16), dim3(256), 0, stream_, ypred, d_slots_, ny_, args_.yhat);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, d_slots_);
+    BENG_CHECK(hipGetLastError());
+    const int pl = first ? 0 : (iters & 1);  // the plane iteration iters + 1 reads as previous
+    hipLaunchKernelGGL(bcg_init_kernel, dim3(S), dim3(1024), 0, stream_, args_, d_slots_, pl);
+    BENG_CHECK(hipGetLastError());
+    BArgs ma = args_;
+    ma.imask = d_mask_;  // set-up passes write only the new slots
+    BArgs qa = ma;
+    qa.phi_mode = 1;
+    int rc;
+    for (int k = 0; k < cg_iters; ++k) {
+      if ((rc = project_t(args_.cg_p, ny_, 1, args_.eta, 1, err, &ma))) return rc;
+      launch_phi(qa);
+      BENG_CHECK(hipGetLastError());
+      hipLaunchKernelGGL(bcg_step_kernel, dim3(S), dim3(1024), 0, stream_, args_, d_slots_);
+      BENG_CHECK(hipGetLastError());
+    }
+    if ((rc = project_t(args_.cg_x, ny_, 1, args_.tau, 0, err, &ma))) return rc;
+    return project_t(args_.alpha + int64_t(pl) * Bm * ny_, 1, Bm, args_.eta, 2, err, &ma);
+  }
+
+  int output_slots(double *u0_dev, const int32_t *slots, const int32_t *dst, int S, std::string &err) override {
+    if (S < 1 || S > args_.Bmax) {
+      err = "output_slots: slot count out of range";
+      return DLMPC_EINVAL;
+    }
+    for (int i = 0; i < S; ++i)
+      if (slots[i] < 0 || slots[i] >= args_.Bmax) {
+        err = "output_slots: bad slot";
+        return DLMPC_EINVAL;
+      }
+    st_oslots_.assign(slots, slots + S);
+    st_odst_.assign(dst, dst + S);
+    BENG_CHECK(hipMemcpyAsync(d_oslots_, st_oslots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    BENG_CHECK(hipMemcpyAsync(d_odst_, st_odst_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, u0_dev, d_oslots_, d_odst_);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
 
   int export_y(double *y_dev, std::string &err) override {
     hipLaunchKernelGGL(bexport_y_kernel, dim3(1024), dim3(256), 0, stream_, args_, y_dev, B_);
@@ -1090,7 +1186,7 @@ class BatchEngineT final : public BatchEngine {
   }
 
   int output(double *u0_dev, std::string &err) override {
-    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, u0_dev);
+    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, u0_dev, nullptr, nullptr);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -1150,6 +1246,9 @@ class BatchEngineT final : public BatchEngine {
   int nrt_ = 1, mtw_ = 1;
   int B_ = 0;
   int64_t ny_ = 0;  // N * rs
+  // streamed solves: slot lists on the device and their host staging
+  int32_t *d_slots_ = nullptr, *d_xsrc_ = nullptr, *d_mask_ = nullptr, *d_oslots_ = nullptr, *d_odst_ = nullptr;
+  std::vector<int32_t> st_slots_, st_xsrc_, st_mask_, st_oslots_, st_odst_;
   int n_units_ = 0;  // Psi-comp work units
   std::vector<void *> owned_;
 };

@@ -44,6 +44,7 @@ struct dlmpc_problem {
   double *d_fx0 = nullptr, *d_fu0 = nullptr, *d_falpha = nullptr, *d_fy = nullptr;
   int cg_iters = 12;
   hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
+  float *d_sy = nullptr;  // streamed solves: predicted trajectories of the joining instances [Bmax][R]
 };
 
 namespace {
@@ -79,6 +80,8 @@ void release_device(dlmpc_problem *p) {
   for (double *d : {p->d_bx0, p->d_bu0, p->d_fx0, p->d_fu0, p->d_falpha, p->d_fy})
     if (d) (void)hipFree(d);
   p->d_fx0 = p->d_fu0 = p->d_falpha = p->d_fy = nullptr;
+  if (p->d_sy) (void)hipFree(p->d_sy);
+  p->d_sy = nullptr;
   for (hipEvent_t e : {p->ev_w0, p->ev_w1})
     if (e) (void)hipEventDestroy(e);
   p->ev_w0 = p->ev_w1 = nullptr;
@@ -837,6 +840,142 @@ int dlmpc_solve_batch_ex(dlmpc_problem *p, int32_t B, const double *x0_dev, doub
     return fail(DLMPC_EINVAL, "no warm-start network (dlmpc_ws_init or dlmpc_warmstart_load)");
   API_HIP(hipSetDevice(p->opt.device));
   return run_batch(p, B, x0_dev, u0_dev, start, start_dev, y_out_dev, alpha_out_dev, stats, t0);
+}
+
+int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,
+                       int32_t check_iters, dlmpc_stats *stats, dlmpc_stream_info *info) {
+  const double t0 = now_ms();
+  int rc = check_batch(p, 1);
+  if (rc) return rc;
+  if (!x0_dev || !u0_dev || n < 1) return fail(DLMPC_EINVAL, "need n >= 1 and non-NULL x0_dev, u0_dev");
+  if (!p->ws) return fail(DLMPC_EINVAL, "no warm-start network (dlmpc_ws_init or dlmpc_warmstart_load)");
+  if (check_iters < 0 || refill_min < 0) return fail(DLMPC_EINVAL, "refill_min and check_iters must be >= 0");
+  API_HIP(hipSetDevice(p->opt.device));
+  const HostSetup &h = p->hs;
+  const size_t nxs = size_t(h.N) * h.nx, nus = size_t(h.N) * h.nu, R = size_t(h.N) * h.rs;
+  const int Bm = p->beng->bmax(), Bs = std::min<int>(Bm, n);
+  if (refill_min == 0) refill_min = std::max(1, Bs / 2);
+  refill_min = std::min(refill_min, Bs);
+  const int K = check_iters > 0 ? check_iters : 4;
+  if (!p->d_sy) API_HIP(hipMalloc(&p->d_sy, sizeof(float) * size_t(Bm) * R));
+  std::string err;
+  std::vector<int32_t> inst(Bs, -1);  // instance in each slot (-1: free)
+  std::vector<dlmpc::BCtl> fin(n);     // final control block of every instance
+  int next = 0, active = 0, joins = 0, checks = 0;
+  int64_t slot_iters = 0;  // slot-iterations launched (active or idle)
+  // New instances next.. into the given slots: network inference, then the trajectory start.
+  auto join = [&](std::vector<int32_t> slots, bool first, int iters) -> int {
+    const int S = int(slots.size());
+    std::vector<int32_t> xsrc(S);
+    for (int i = 0; i < S; ++i) xsrc[i] = next + i;
+    for (int s0 = 0; s0 < S; s0 += p->ws->Smax) {
+      const int c = std::min(p->ws->Smax, S - s0);
+      const int r = p->ws->predict(c, x0_dev + size_t(next + s0) * nxs, p->d_sy + size_t(s0) * R, err);
+      if (r) return fail(r, err);
+    }
+    const int r = p->beng->stream_start(x0_dev, slots.data(), xsrc.data(), S, p->d_sy, p->cg_iters, first, iters,
+                                        p->opt.max_iter, p->opt.eps, err);
+    if (r) return fail(r, err);
+    for (int i = 0; i < S; ++i) inst[slots[i]] = next + i;
+    next += S;
+    active += S;
+    ++joins;
+    return DLMPC_OK;
+  };
+  {
+    std::vector<int32_t> s0(Bs);
+    for (int b = 0; b < Bs; ++b) s0[b] = b;
+    if ((rc = join(s0, true, 0))) return rc;
+  }
+  API_HIP(hipEventRecord(p->ev_t0, p->stream));
+  Ctl *d_ctl = p->beng->ctl();
+  // Bound on the loop: every join brings at least one instance, and every instance stops
+  // within max_iter iterations of its join.
+  const int64_t guard = (int64_t(n) + 1) * (p->opt.max_iter + K);
+  int64_t launched = 0;
+  while (active > 0) {
+    rc = launch_graphs(p->bgexec, p->stream, K);
+    if (rc) return rc;
+    launched += K;
+    slot_iters += int64_t(K) * Bs;
+    ++checks;
+    API_HIP(hipMemcpyAsync(&p->h_ctl[1], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipStreamSynchronize(p->stream));
+    const int iters = p->h_ctl[1].iters;
+    std::vector<int32_t> done_s, done_i, free_s;
+    for (int b = 0; b < Bs; ++b) {
+      if (inst[b] >= 0 && p->h_bctl[b].stop) {
+        done_s.push_back(b);
+        done_i.push_back(inst[b]);
+      }
+    }
+    if (!done_s.empty()) {
+      if ((rc = p->beng->output_slots(u0_dev, done_s.data(), done_i.data(), int(done_s.size()), err)))
+        return fail(rc, err);
+      API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
+      API_HIP(hipStreamSynchronize(p->stream));
+      for (size_t q = 0; q < done_s.size(); ++q) {
+        fin[done_i[q]] = p->h_bctl[done_s[q]];
+        inst[done_s[q]] = -1;
+      }
+      active -= int(done_s.size());
+    }
+    for (int b = 0; b < Bs; ++b)
+      if (inst[b] < 0) free_s.push_back(b);
+    const int want = std::min<int>(int(free_s.size()), n - next);
+    if (want > 0 && (int(free_s.size()) >= refill_min || active == 0 || next + want == n)) {
+      free_s.resize(want);
+      if ((rc = join(free_s, false, iters))) return rc;
+    }
+    if (launched > guard) return fail(DLMPC_EDEVICE, "streamed solve did not drain");
+  }
+  API_HIP(hipEventRecord(p->ev_t1, p->stream));
+  API_HIP(hipStreamSynchronize(p->stream));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
+  for (int i = 0; i < n; ++i)
+    if (stats) fill_stats(stats[i], fin[i], ms, checks, DLMPC_START_LEARNED, t0);
+  // Instances the warm start left unconverged (or with a NaN/Inf): cold batched solves.
+  std::vector<int> redo;
+  for (int i = 0; i < n; ++i)
+    if (!fin[i].converged || fin[i].numeric) redo.push_back(i);
+  for (size_t r0 = 0; r0 < redo.size(); r0 += size_t(Bm)) {
+    const int F = int(std::min(redo.size() - r0, size_t(Bm)));
+    for (int f = 0; f < F; ++f)
+      API_HIP(hipMemcpyAsync(p->d_fx0 + f * nxs, x0_dev + size_t(redo[r0 + f]) * nxs, nxs * sizeof(double),
+                             hipMemcpyDeviceToDevice, p->stream));
+    float ms2 = 0.f, mw2 = 0.f;
+    int checks2 = 0;
+    rc = run_batch_once(p, F, p->d_fx0, DLMPC_START_COLD, nullptr, p->d_fu0, nullptr, nullptr, &ms2, &mw2, &checks2);
+    if (rc) return rc;
+    for (int f = 0; f < F; ++f) {
+      const int i = redo[r0 + f];
+      API_HIP(hipMemcpyAsync(u0_dev + size_t(i) * nus, p->d_fu0 + f * nus, nus * sizeof(double),
+                             hipMemcpyDeviceToDevice, p->stream));
+      dlmpc::BCtl ic = p->h_bctl[f];
+      ic.iters += fin[i].iters;
+      fin[i] = ic;
+      if (stats) {
+        fill_stats(stats[i], ic, ms + ms2, checks + checks2, DLMPC_START_LEARNED, t0);
+        stats[i].fell_back = 1;
+      }
+    }
+  }
+  API_HIP(hipStreamSynchronize(p->stream));
+  if (info) {
+    info->joins = joins;
+    info->checks = checks;
+    info->slot_iterations = slot_iters;
+    int64_t used = 0;
+    for (int i = 0; i < n; ++i) used += fin[i].iters;
+    info->instance_iterations = used;
+    info->fell_back = int32_t(redo.size());
+    info->t_stream_ms = ms;
+  }
+  int conv = 0;
+  for (int i = 0; i < n; ++i) conv += fin[i].converged;
+  return conv == n ? DLMPC_OK : DLMPC_ENOCONV;
 }
 
 namespace {

@@ -112,6 +112,7 @@ std::unique_ptr<Engine> make_engine(int precision, int nx);
 
 struct BCtl {  // per-instance control block
   int32_t iters, stop, converged, numeric;
+  int32_t it0, pad;  // global iteration count when the instance entered its slot
   double last_rp, last_rd, objective;
 };
 
@@ -153,6 +154,7 @@ struct BArgs {
   // init_pass 1: bpsi_kernel writes dst_k = N_j' src (row vectors [Bmax][N*rs]) per instance;
   // phi_mode 1: bphi_kernel writes cg_q = sum_{j in P(m)} ||x0_j||^2 N_j eta_j (rows of m).
   int32_t init_pass, phi_mode, wmode;
+  const int32_t *imask;     // set-up passes: write only instances b with imask[b] != 0 (null: all)
   const float *src;
   int64_t src_bs, src_rs;   // element (b, row) of src at b * src_bs + row * src_rs
   float *dst_k;
@@ -195,6 +197,16 @@ class BatchEngine {
   // One kernel of an iteration: 0 bphi_kernel, 1 bpsi_kernel, 2 bdecide_kernel.
   virtual int launch_one(int k, std::string &err) = 0;
   virtual int output(double *u0_dev, std::string &err) = 0;
+  // Streamed solves (warm starts only). Slots slots[0..S) take the instances xsrc[0..S) of
+  // x0_dev ([*][N*nx]); their input-row predictions are ypred [S][N*rs] (FP32, device). first:
+  // the initial fill (resets the solve, batch = S, slots 0..S-1); otherwise the slots join the
+  // running solve at the current iteration count `iters` (their start goes to the multiplier
+  // plane the next iteration reads).
+  virtual int stream_start(const double *x0_dev, const int32_t *slots, const int32_t *xsrc, int S,
+                           const float *ypred, int cg_iters, bool first, int iters, int max_iter, double eps,
+                           std::string &err) = 0;
+  // u(0) and objective of slots[0..S) into rows dst[0..S) of u0_dev ([*][N*nu]).
+  virtual int output_slots(double *u0_dev, const int32_t *slots, const int32_t *dst, int S, std::string &err) = 0;
   virtual Ctl *ctl() = 0;
   virtual BCtl *ictl() = 0;
   virtual int bmax() const = 0;

@@ -74,6 +74,15 @@ class Cert(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class StreamInfo(C.Structure):
+    _fields_ = [("joins", C.c_int32), ("checks", C.c_int32), ("slot_iterations", C.c_int64),
+                ("instance_iterations", C.c_int64), ("fell_back", C.c_int32), ("pad", C.c_int32),
+                ("t_stream_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
 class Info(C.Structure):
     _fields_ = [("R", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64), ("n_tiles", C.c_int64),
                 ("d_row_max", C.c_int32), ("d_col_max", C.c_int32), ("p_max", C.c_int32),
@@ -100,6 +109,8 @@ EXPORTS = {
     "dlmpc_time_batch_kernels": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, _dp]),
     "dlmpc_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, _dp, _dp, C.POINTER(Stats)]),
     "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
+    "dlmpc_solve_stream": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p]),
     "dlmpc_solve_batch_ex": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_ws_init": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_double, C.c_double]),
@@ -286,6 +297,17 @@ class Problem:
             self._h, B, C.c_void_p(x0_dev), C.c_void_p(u0_dev), STARTS[start], opt(start_dev),
             opt(y_out_dev), opt(alpha_out_dev), st))
         return s, [x.as_dict() for x in st]
+
+    def solve_stream(self, n: int, x0_dev: int, u0_dev: int, refill_min: int = 0,
+                     check_iters: int = 0) -> tuple[int, list[dict], dict]:
+        """n instances streamed through the batched engine's slots from the learned start
+        (device pointers of float64 [n][N*nx] and [n][N*nu]); returns (status, per-instance
+        stats, stream counters)."""
+        st = (Stats * n)()
+        info = StreamInfo()
+        s = self._check(self._lib.dlmpc_solve_stream(self._h, n, C.c_void_p(x0_dev), C.c_void_p(u0_dev),
+                                                      refill_min, check_iters, st, C.byref(info)))
+        return s, [x.as_dict() for x in st], info.as_dict()
 
     # ---- learned warm start
     def ws_init(self, hidden: int, max_samples: int, seed: int = 0, x_scale: float = 1.0,
