@@ -127,6 +127,12 @@ def main() -> int:
     ap.add_argument("--workload", default="irregular1024_box")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--start", default="learned", choices=["learned", "cold"])
+    ap.add_argument("--stream", type=int, default=256,
+                    help="learned start: instances per step streamed through the --batch slots "
+                         "(0: one batch of --batch instances per step)")
+    ap.add_argument("--refill-min", type=int, default=0, help="free slots before new instances join (0: half)")
+    ap.add_argument("--check-iters", type=int, default=0, help="iterations between host checks (0: 4)")
+    ap.add_argument("--cg-iters", type=int, default=0, help="CG steps of the trajectory start (0: library default 12)")
     ap.add_argument("--train-solves", type=int, default=8192)
     ap.add_argument("--train-steps", type=int, default=10000)
     ap.add_argument("--hidden", type=int, default=64)
@@ -170,7 +176,7 @@ def main() -> int:
         t = time.perf_counter()
         p = dlmpc.Problem.from_network(net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps,
                                        max_iter=wl.max_iter, precision=precision, device=0,
-                                       stream=stream.cuda_stream, max_batch=max_batch)
+                                       stream=stream.cuda_stream, max_batch=max_batch, warm_cg_iters=args.cg_iters)
         log(f"setup {precision} (max_batch {max_batch}): {time.perf_counter() - t:.1f} s")
         return p
 
@@ -233,50 +239,80 @@ def main() -> int:
         log(f"warm-start network: {train}")
         del xt, yt, ut
 
-    # ---- timed steps: one batch of B fresh x0 each
+    # ---- timed steps: a stream of S fresh x0 through the B slots (learned start), or one batch
+    # of B fresh x0
+    S = args.stream if args.start == "learned" and args.stream > 0 else 0
+    per = S if S else B
     n_steps = args.warmup + args.steps
-    seeds = [1000 + i for i in range(n_steps * B)]
+    seeds = [1000 + i for i in range(n_steps * per)]
     x0 = torch.tensor(np.stack([wl.x0(s) for s in seeds]), dtype=torch.float64,
-                      device=dev).view(n_steps, B, n_x)
-    u0 = torch.zeros((n_steps, B, n_u), dtype=torch.float64, device=dev)
+                      device=dev).view(n_steps, per, n_x)
+    u0 = torch.zeros((n_steps, per, n_u), dtype=torch.float64, device=dev)
+
+    def run_step(i, uu, start):
+        """One step's instances: streamed, or batches of B; returns (stats, stream counters)."""
+        if S and start == "learned":
+            _, s, info = pr.solve_stream(per, x0[i].data_ptr(), uu[i].data_ptr(), args.refill_min,
+                                         args.check_iters)
+            return s, info
+        s = []
+        for b0 in range(0, per, B):
+            _, q = batch_solve(x0[i][b0:b0 + B], uu[i][b0:b0 + B], start)
+            s += q
+        return s, None
+
     for i in range(args.warmup):
-        batch_solve(x0[i], u0[i], args.start)
+        run_step(i, u0, args.start)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
+    stats, sinfo = [], []
     for i in range(args.warmup, n_steps):
-        _, s = batch_solve(x0[i], u0[i], args.start)
+        s, info = run_step(i, u0, args.start)
         stats += s
+        if info:
+            sinfo.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     iters = [s["iters"] for s in stats]
     conv = sum(1 for s in stats if s["converged"])
     fell = sum(s["fell_back"] for s in stats)
-    n_solves = args.steps * B
-    log(f"timed {args.steps} batches of {B} in {elapsed:.3f} s; iters mean {np.mean(iters):.1f} "
+    n_solves = args.steps * per
+    log(f"timed {args.steps} steps of {per} instances in {elapsed:.3f} s; iters mean {np.mean(iters):.1f} "
         f"max {max(iters)}; converged {conv}/{n_solves}; fell back {fell}")
+    stream_rec = {}
+    if sinfo:
+        stream_rec = {"slots": B, "instances_per_step": per,
+                  "joins_per_step": float(np.mean([q["joins"] for q in sinfo])),
+                  "slot_use": round(sum(q["instance_iterations"] for q in sinfo) /
+                                    sum(q["slot_iterations"] for q in sinfo), 4),
+                  "refill_min": args.refill_min or B // 2, "check_iters": args.check_iters or 4}
 
-    # ---- the same batches from the cold start (when the headline is warm)
-    cold = {}
-    if args.start != "cold":
+    def compare(start, label):
+        """The timed instances again, in batches of B from `start`: time per solve, iterations,
+        and u(0) against the headline's."""
         uc = torch.zeros_like(u0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sc = []
         for i in range(args.warmup, n_steps):
-            _, s = batch_solve(x0[i], uc[i], "cold")
-            sc += s
+            for b0 in range(0, per, B):
+                _, q = batch_solve(x0[i][b0:b0 + B], uc[i][b0:b0 + B], start)
+                sc += q
         torch.cuda.synchronize()
         ec = time.perf_counter() - t1
-        ok = [k for k, s in enumerate(sc) if s["converged"]]
+        ok = [k for k, q in enumerate(sc) if q["converged"]]
         ud = (u0[args.warmup:] - uc[args.warmup:]).reshape(n_solves, n_u).abs().amax(dim=1)
         un = uc[args.warmup:].reshape(n_solves, n_u).abs().amax(dim=1)
-        cold = {"time_to_eps_ms": round(1e3 * ec / n_solves, 4),
-                "iters_mean": float(np.mean([s["iters"] for s in sc])),
-                "iter_per_s": round(sum(s["iters"] for s in sc) / ec, 1),
-                "converged": f"{len(ok)}/{n_solves}",
-                "u0_rel_diff_warm_vs_cold_max": float((ud[ok] / un[ok]).max().item()) if ok else None}
-        log(f"batched cold: {cold}")
+        rec = {"time_to_eps_ms": round(1e3 * ec / n_solves, 4),
+               "iters_mean": float(np.mean([q["iters"] for q in sc])),
+               "iter_per_s": round(sum(q["iters"] for q in sc) / ec, 1),
+               "converged": f"{len(ok)}/{n_solves}",
+               f"u0_rel_diff_headline_vs_{label}_max": float((ud[ok] / un[ok]).max().item()) if ok else None}
+        log(f"batched {label}: {rec}")
+        return rec
+
+    batched_learned = compare("learned", "batched_learned") if S else {}
+    cold = compare("cold", "cold") if args.start != "cold" else {}
 
     # ---- single-instance solves on the first x0 of the first timed batch
     xs = x0[args.warmup]
@@ -370,16 +406,19 @@ def main() -> int:
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_sub": N, "d": wl.d, "T": wl.T, "rho": wl.rho,
                    "eps": wl.eps, "max_iter": wl.max_iter, "x0_sigma": wl.sigma,
-                   "instances_per_step": B, "x0_seeds": [seeds[args.warmup * B], seeds[-1]],
+                   "instances_per_step": per, "slots": B, "mode": "stream" if S else "batch",
+                   "x0_seeds": [seeds[args.warmup * per], seeds[-1]],
                    "precision": "fp32 (split-bf16 matrix-core products)", "start": args.start},
-        "time_to_eps_ms": round(ms_step / B, 4),
+        "time_to_eps_ms": round(ms_step / per, 4),
         "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
         "converged": f"{conv}/{n_solves}", "fell_back": int(fell),
+        "stream": stream_rec,
+        "batched_learned": batched_learned,
         "batched_cold": cold,
         "mixed_networks": mixed,
         "single_fp32_cold": single,
         "plain_fp64_cold": ref,
-        "speedup_vs_plain_fp64": round(ref["time_to_eps_ms_median"] / (ms_step / B), 2) if ref else None,
+        "speedup_vs_plain_fp64": round(ref["time_to_eps_ms_median"] / (ms_step / per), 2) if ref else None,
         "warm_start_training": train,
         "setup_ms": round(pr.info["setup_ms"], 1),
         "factor_ms": round(pr.info["factor_ms"], 1),

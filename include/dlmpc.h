@@ -294,9 +294,10 @@ typedef struct {
  * check_iters iterations (0: 4) the host reads the per-instance stop flags, writes u(0) of the
  * instances that stopped to their rows of u0_dev, and once at least refill_min slots are free
  * (0: half the slots; or the last instances are waiting; or no slot is busy) starts the next
- * instances in them: network inference, simulation, CG and the start projections run for the
- * joining slots only while the others keep their state, and the joiners enter the running
- * iteration with their own iteration count. Per instance the arithmetic is that of
+ * instances in them: network inference and simulation at once, then the CG steps and the start
+ * projections of their trajectory start inside the following iterations, in the joiners'
+ * columns of the same basis products (no pass over the bases of their own), after which each
+ * joiner iterates with its own iteration count. Per instance the arithmetic is that of
  * dlmpc_solve_batch_ex with the learned start (same start, same iterates, same stopping rule),
  * whatever slot and moment it joins; instances that end unconverged are solved again from the
  * cold start. x0_dev [n][N*nx], u0_dev [n][N*nu] device buffers; stats [n] and info may be NULL.

@@ -82,7 +82,7 @@ __device__ __forceinline__ T wsum(T v) {
 template <int NX>
 __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double *x0, int B, int warm,
                                                           int max_iter, double eps, const int32_t *slots,
-                                                          const int32_t *xsrc, int reset) {
+                                                          const int32_t *xsrc, int reset, int join, int cg_k) {
   // instance blockIdx.y: slot slots[y] (or y), initial state row xsrc[y] (or y) of x0; reset:
   // the solve starts here (global control block reset); otherwise the slot joins a running one
   const int m = blockIdx.x, y = blockIdx.y, tid = threadIdx.x;
@@ -131,6 +131,8 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
     ic.converged = 0;
     ic.numeric = 0;
     ic.it0 = reset ? 0 : a.ctl->iters;
+    a.phase[b] = join ? 0 : -1;
+    if (y == 0) a.ctl->cg_k = cg_k;
     ic.last_rp = ic.last_rd = INFINITY;
     ic.objective = 0.0;
     a.slot[2 * b] = a.slot[2 * b + 1] = 0ull;
@@ -265,6 +267,13 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
     }
     return;
   }
+  // streamed joins whose start is at a CG step: this product is q = M p
+  for (int idx = tid; idx < rs * B; idx += blockDim.x) {
+    const int l = idx / B, b = idx - l * B;
+    const int ph = a.phase[b];
+    if (ph >= 1 && ph <= a.ctl->cg_k && !a.ictl[b].stop)
+      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = Ct[0][l][b] + Ct[1][l][b];
+  }
   // Row update: thread (instance b, row group lg) handles rows lg, lg + 8, ... of m, and the
   // sum of (alpha - alpha_prev)^2 over m's rows (the residual term Psi-comp needs) per instance.
   constexpr int kLG = kPhiThreads / 64;
@@ -272,7 +281,7 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   const int cur = it & 1, prev = cur ^ 1;
   const int b = tid & 63, lg = tid >> 6;
   double dl = 0.0;
-  if (b < B && !a.ictl[b].stop) {
+  if (b < B && !a.ictl[b].stop && a.phase[b] < 0) {
     const float n = a.nrm[int64_t(b) * a.N + m];
     for (int l = lg; l < rs; l += kLG) {
       const int64_t o = int64_t(m) * rs + l;
@@ -295,7 +304,7 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   }
   red[lg][b] = dl;
   __syncthreads();
-  if (tid < B && !a.ictl[tid].stop) {
+  if (tid < B && !a.ictl[tid].stop && a.phase[tid] < 0) {
     double sum = 0.0;
 #pragma unroll
     for (int g = 0; g < kLG; ++g) sum += red[g][tid];
@@ -340,6 +349,11 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
   // their own strides
   // staging: instance sb (fastest across the wave), rows 8 sub .. 8 sub + 7 of the chunk
   const int sb = tid & 63, sub = tid >> 6;
+  // streamed joins (iteration passes): the lane's instance may stage its CG vector instead
+  // (cg_p at phases 0..cg_k-1, beta = cg_x at phase cg_k; at cg_k + 1 alpha^0, in both planes)
+  const int sph = (!initp && sb < B) ? a.phase[sb] : -1;
+  const float *jsrc = (sph >= 0 && sph < a.ctl->cg_k) ? a.cg_p : a.cg_x;
+  const bool jstage = sph >= 0 && sph <= a.ctl->cg_k;
 
   if (!warm && it == 1 && !initp) {  // alpha^1 = 0: Psi^1 = o, residuals ||o_c||, eta stays 0
     if (part == 0 && tid < B && !a.ictl[tid].stop) {
@@ -373,7 +387,9 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
       const bool ok = sact && rr < D;
       const int rc = ok ? rr : 0;
       const int ta = rc / rs, l = rc - ta * rs;
-      const float x = stage_src[int64_t(ok ? sb : 0) * a.src_bs + (int64_t(s_rsub[ta]) * rs + l) * a.src_rs];
+      const int64_t row = int64_t(s_rsub[ta]) * rs + l;
+      const float x = jstage ? jsrc[int64_t(ok ? sb : 0) * a.N * rs + row]
+                             : stage_src[int64_t(ok ? sb : 0) * a.src_bs + row * a.src_rs];
       v[e] = ok ? x : 0.f;
     }
   };
@@ -506,8 +522,19 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
         const float xj = a.xn[int64_t(b) * a.N + j];
         const float en = acc[t][nt][e];
         float wv;
-        if (initp) {
-          if (a.imask && !a.imask[b]) continue;
+        const int ph = initp ? -1 : a.phase[b];
+        if (ph >= 0) {  // streamed join: the start's projections, as the set-up passes do them
+          if (ph < a.ctl->cg_k) {
+            a.eta[ki] = en;
+            wv = xj * en;
+          } else if (ph == a.ctl->cg_k) {
+            a.tau[ki] = en;
+            continue;
+          } else {
+            a.eta[ki] = en;
+            wv = xj * (a.tau[ki] + en);
+          }
+        } else if (initp) {
           a.dst_k[ki] = en;
           if (a.wmode == 0) continue;
           wv = xj * (a.wmode == 2 ? a.tau[ki] + en : en);
@@ -541,7 +568,7 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
 #pragma unroll
   for (int c = 0; c < NX; ++c) red_od[sb][sub][c] = od[c];
   __syncthreads();
-  if (tid < B && !a.ictl[tid].stop) {
+  if (tid < B && !a.ictl[tid].stop && a.phase[tid] < 0) {
     const int b = tid;
     double se = 0.0, sd = 0.0, sdl = 0.0;
     for (int w = 0; w < kPsiWaves; ++w) {
@@ -589,7 +616,12 @@ __global__ __launch_bounds__(64) void bdecide_kernel(BArgs a) {
   const int B = c->batch;
   if (b < B) {
     BCtl &ic = a.ictl[b];
-    if (!ic.stop) {
+    if (!ic.stop && a.phase[b] >= 0) {  // streamed join: its start runs; no decision yet
+      if (++a.phase[b] > a.ctl->cg_k + 1) {
+        a.phase[b] = -1;
+        ic.it0 = it;  // its first ADMM iteration is the next one
+      }
+    } else if (!ic.stop) {
       const double rp = __longlong_as_double(static_cast<long long>(a.slot[2 * b]));
       const double rd = __longlong_as_double(static_cast<long long>(a.slot[2 * b + 1]));
       ic.iters = it - ic.it0;
@@ -708,7 +740,8 @@ __device__ __forceinline__ double block_sum1024(double v, double *red) {
 __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *slots, int pl) {
   __shared__ double red[16];
   const int b = slots ? slots[blockIdx.x] : blockIdx.x;
-  float *alpha = a.alpha + int64_t(pl) * a.Bmax * a.N * a.rs;
+  const int64_t plane = int64_t(a.Bmax) * a.N * a.rs;
+  float *alpha = a.alpha + int64_t(pl < 0 ? 0 : pl) * plane;
   const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < ny; i += 1024) {
@@ -717,7 +750,9 @@ __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *
     a.cg_r[o + i] = r;
     a.cg_p[o + i] = r;
     a.cg_x[o + i] = 0.f;
-    alpha[i * a.Bmax + b] = -2.f * a.w[i] * y / a.rho;
+    const float a0 = -2.f * a.w[i] * y / a.rho;
+    alpha[i * a.Bmax + b] = a0;
+    if (pl < 0) alpha[plane + i * a.Bmax + b] = a0;  // both planes: read by whichever iteration starts
     acc += double(r) * double(r);
   }
   acc = block_sum1024(acc, red);
@@ -725,9 +760,15 @@ __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *
 }
 
 // One CG step per instance after cg_q = M cg_p.
-__global__ __launch_bounds__(1024) void bcg_step_kernel(BArgs a, const int32_t *slots) {
+__global__ __launch_bounds__(1024) void bcg_step_kernel(BArgs a, const int32_t *slots, int gate) {
+  // gate: inside the iteration, only instances whose Phi-comp just wrote q = M p (phase 1..cg_k)
   __shared__ double red[16];
   const int b = slots ? slots[blockIdx.x] : blockIdx.x;
+  if (gate) {
+    if (a.ctl->stop || b >= a.ctl->batch || a.ictl[b].stop) return;
+    const int ph = a.phase[b];
+    if (ph < 1 || ph > a.ctl->cg_k) return;
+  }
   const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
   const double rr = a.cg_rr[b];
   double pq = 0.0;
@@ -989,9 +1030,15 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&a.s, size_t(bmax) * ny, err)) || (rc = al(&a.x0, size_t(bmax) * N * NX, err)) ||
         (rc = al(&a.ictl, size_t(bmax), err)) || (rc = al(&a.slot, 2 * size_t(bmax), err)) ||
         (rc = al(&a.ctl, 1, err)) || (rc = al(&d_slots_, size_t(bmax), err)) ||
-        (rc = al(&d_xsrc_, size_t(bmax), err)) || (rc = al(&d_mask_, size_t(bmax), err)) ||
-        (rc = al(&d_oslots_, size_t(bmax), err)) || (rc = al(&d_odst_, size_t(bmax), err)))
+        (rc = al(&d_xsrc_, size_t(bmax), err)) ||
+        (rc = al(&d_oslots_, size_t(bmax), err)) || (rc = al(&d_odst_, size_t(bmax), err)) ||
+        (rc = al(&a.phase, size_t(bmax), err)))
       return rc;
+    {
+      const std::vector<int32_t> adm(bmax, -1);  // every slot in the ADMM iteration
+      BENG_CHECK(hipMemcpy(a.phase, adm.data(), sizeof(int32_t) * bmax, hipMemcpyHostToDevice));
+    }
+
     // trajectory warm start: vectors and the plant in FP32
     a.Bw = (bmax + 15) & ~15;
     if ((rc = al(&a.w_hi, size_t(a.Bw) * a.ktot, err)) || (rc = al(&a.w_lo, size_t(a.Bw) * a.ktot, err)) ||
@@ -1028,7 +1075,7 @@ class BatchEngineT final : public BatchEngine {
     }
     B_ = B;
     hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, B), dim3(256), 0, stream_, args_, x0_dev, B,
-                       warm ? 1 : 0, max_iter, eps, nullptr, nullptr, 1);
+                       warm ? 1 : 0, max_iter, eps, nullptr, nullptr, 1, 0, 0);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -1071,7 +1118,7 @@ class BatchEngineT final : public BatchEngine {
       if ((rc = project_t(args_.cg_p, ny_, 1, args_.eta, 1, err))) return rc;  // eta = N' p, W = ||x0_j||^2 eta
       launch_phi(qa);  // q = M p
       BENG_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_, nullptr);
+      hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_, nullptr, 0);
       BENG_CHECK(hipGetLastError());
     }
     if ((rc = project_t(args_.cg_x, ny_, 1, args_.tau, 0, err))) return rc;  // tau = N' beta
@@ -1081,7 +1128,7 @@ class BatchEngineT final : public BatchEngine {
   float *yhat() override { return args_.yhat; }
 
   int stream_start(const double *x0_dev, const int32_t *slots, const int32_t *xsrc, int S, const float *ypred,
-                   int cg_iters, bool first, int iters, int max_iter, double eps, std::string &err) override {
+                   int cg_iters, bool first, int max_iter, double eps, std::string &err) override {
     const int Bm = args_.Bmax;
     if (S < 1 || S > Bm) {
       err = "stream_start: slot count out of range";
@@ -1105,32 +1152,18 @@ class BatchEngineT final : public BatchEngine {
     }
     BENG_CHECK(hipMemcpyAsync(d_slots_, st_slots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
     BENG_CHECK(hipMemcpyAsync(d_xsrc_, st_xsrc_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
-    BENG_CHECK(hipMemcpyAsync(d_mask_, st_mask_.data(), sizeof(int32_t) * Bm, hipMemcpyHostToDevice, stream_));
     if (first) B_ = S;
     hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, S), dim3(256), 0, stream_, args_, x0_dev, S, 1,
-                       max_iter, eps, d_slots_, d_xsrc_, first ? 1 : 0);
+                       max_iter, eps, d_slots_, d_xsrc_, first ? 1 : 0, 1, cg_iters);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL(bscatter_rows_kernel, dim3(S, 16), dim3(256), 0, stream_, ypred, d_slots_, ny_, args_.yhat);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL((bsim_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, d_slots_);
     BENG_CHECK(hipGetLastError());
-    const int pl = first ? 0 : (iters & 1);  // the plane iteration iters + 1 reads as previous
-    hipLaunchKernelGGL(bcg_init_kernel, dim3(S), dim3(1024), 0, stream_, args_, d_slots_, pl);
+    // the CG steps and the start projections run inside the following iterations (phases)
+    hipLaunchKernelGGL(bcg_init_kernel, dim3(S), dim3(1024), 0, stream_, args_, d_slots_, -1);
     BENG_CHECK(hipGetLastError());
-    BArgs ma = args_;
-    ma.imask = d_mask_;  // set-up passes write only the new slots
-    BArgs qa = ma;
-    qa.phi_mode = 1;
-    int rc;
-    for (int k = 0; k < cg_iters; ++k) {
-      if ((rc = project_t(args_.cg_p, ny_, 1, args_.eta, 1, err, &ma))) return rc;
-      launch_phi(qa);
-      BENG_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(bcg_step_kernel, dim3(S), dim3(1024), 0, stream_, args_, d_slots_);
-      BENG_CHECK(hipGetLastError());
-    }
-    if ((rc = project_t(args_.cg_x, ny_, 1, args_.tau, 0, err, &ma))) return rc;
-    return project_t(args_.alpha + int64_t(pl) * Bm * ny_, 1, Bm, args_.eta, 2, err, &ma);
+    return DLMPC_OK;
   }
 
   int output_slots(double *u0_dev, const int32_t *slots, const int32_t *dst, int S, std::string &err) override {
@@ -1177,6 +1210,9 @@ class BatchEngineT final : public BatchEngine {
 
   int iteration(std::string &err) override {
     launch_phi(args_);
+    BENG_CHECK(hipGetLastError());
+    // CG steps of streamed joins (a no-op for instances in the ADMM iteration)
+    hipLaunchKernelGGL(bcg_step_kernel, dim3(args_.Bmax), dim3(1024), 0, stream_, args_, nullptr, 1);
     BENG_CHECK(hipGetLastError());
     launch_psi(args_);
     BENG_CHECK(hipGetLastError());
@@ -1247,7 +1283,7 @@ class BatchEngineT final : public BatchEngine {
   int B_ = 0;
   int64_t ny_ = 0;  // N * rs
   // streamed solves: slot lists on the device and their host staging
-  int32_t *d_slots_ = nullptr, *d_xsrc_ = nullptr, *d_mask_ = nullptr, *d_oslots_ = nullptr, *d_odst_ = nullptr;
+  int32_t *d_slots_ = nullptr, *d_xsrc_ = nullptr, *d_oslots_ = nullptr, *d_odst_ = nullptr;
   std::vector<int32_t> st_slots_, st_xsrc_, st_mask_, st_oslots_, st_odst_;
   int n_units_ = 0;  // Psi-comp work units
   std::vector<void *> owned_;

@@ -864,7 +864,7 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   int next = 0, active = 0, joins = 0, checks = 0;
   int64_t slot_iters = 0;  // slot-iterations launched (active or idle)
   // New instances next.. into the given slots: network inference, then the trajectory start.
-  auto join = [&](std::vector<int32_t> slots, bool first, int iters) -> int {
+  auto join = [&](std::vector<int32_t> slots, bool first) -> int {
     const int S = int(slots.size());
     std::vector<int32_t> xsrc(S);
     for (int i = 0; i < S; ++i) xsrc[i] = next + i;
@@ -873,7 +873,7 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
       const int r = p->ws->predict(c, x0_dev + size_t(next + s0) * nxs, p->d_sy + size_t(s0) * R, err);
       if (r) return fail(r, err);
     }
-    const int r = p->beng->stream_start(x0_dev, slots.data(), xsrc.data(), S, p->d_sy, p->cg_iters, first, iters,
+    const int r = p->beng->stream_start(x0_dev, slots.data(), xsrc.data(), S, p->d_sy, p->cg_iters, first,
                                         p->opt.max_iter, p->opt.eps, err);
     if (r) return fail(r, err);
     for (int i = 0; i < S; ++i) inst[slots[i]] = next + i;
@@ -885,7 +885,7 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   {
     std::vector<int32_t> s0(Bs);
     for (int b = 0; b < Bs; ++b) s0[b] = b;
-    if ((rc = join(s0, true, 0))) return rc;
+    if ((rc = join(s0, true))) return rc;
   }
   API_HIP(hipEventRecord(p->ev_t0, p->stream));
   Ctl *d_ctl = p->beng->ctl();
@@ -902,7 +902,6 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
     API_HIP(hipMemcpyAsync(&p->h_ctl[1], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
     API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
     API_HIP(hipStreamSynchronize(p->stream));
-    const int iters = p->h_ctl[1].iters;
     std::vector<int32_t> done_s, done_i, free_s;
     for (int b = 0; b < Bs; ++b) {
       if (inst[b] >= 0 && p->h_bctl[b].stop) {
@@ -926,7 +925,7 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
     const int want = std::min<int>(int(free_s.size()), n - next);
     if (want > 0 && (int(free_s.size()) >= refill_min || active == 0 || next + want == n)) {
       free_s.resize(want);
-      if ((rc = join(free_s, false, iters))) return rc;
+      if ((rc = join(free_s, false))) return rc;
     }
     if (launched > guard) return fail(DLMPC_EDEVICE, "streamed solve did not drain");
   }

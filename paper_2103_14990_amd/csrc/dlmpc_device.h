@@ -33,6 +33,7 @@ struct Ctl {
   // batched engine: instances of the current solve and its start (kernels captured in graphs
   // read these here, not from their launch arguments)
   int32_t batch, warm;
+  int32_t cg_k, pad3;  // CG steps of the streamed joins' trajectory start
 };
 
 // Static work lists of the persistent schedule: block b runs Phi-comp for
@@ -154,7 +155,12 @@ struct BArgs {
   // init_pass 1: bpsi_kernel writes dst_k = N_j' src (row vectors [Bmax][N*rs]) per instance;
   // phi_mode 1: bphi_kernel writes cg_q = sum_{j in P(m)} ||x0_j||^2 N_j eta_j (rows of m).
   int32_t init_pass, phi_mode, wmode;
-  const int32_t *imask;     // set-up passes: write only instances b with imask[b] != 0 (null: all)
+  // Streamed joins: phase[b] < 0 for an instance in the ADMM iteration; 0..cg_k+1 while its
+  // trajectory start runs inside the iterations (its column of the products serves the start:
+  // phase 0..cg_k-1 Psi-comp stages cg_p (eta = N'p, W = ||x0_j||^2 eta), 1..cg_k Phi-comp
+  // writes q = M p and a CG step follows, cg_k stages beta (tau = N'beta), cg_k+1 stages
+  // alpha^0 (eta, W = ||x0_j||^2 (tau + eta)); then the ADMM iteration starts).
+  int32_t *phase;  // (the number of CG steps, cg_k, is ctl->cg_k)
   const float *src;
   int64_t src_bs, src_rs;   // element (b, row) of src at b * src_bs + row * src_rs
   float *dst_k;
@@ -200,10 +206,10 @@ class BatchEngine {
   // Streamed solves (warm starts only). Slots slots[0..S) take the instances xsrc[0..S) of
   // x0_dev ([*][N*nx]); their input-row predictions are ypred [S][N*rs] (FP32, device). first:
   // the initial fill (resets the solve, batch = S, slots 0..S-1); otherwise the slots join the
-  // running solve at the current iteration count `iters` (their start goes to the multiplier
-  // plane the next iteration reads).
+  // running solve. The joiners' trajectory start (cg_iters CG steps and the start projections)
+  // then runs inside the following iterations, in their columns of the same products.
   virtual int stream_start(const double *x0_dev, const int32_t *slots, const int32_t *xsrc, int S,
-                           const float *ypred, int cg_iters, bool first, int iters, int max_iter, double eps,
+                           const float *ypred, int cg_iters, bool first, int max_iter, double eps,
                            std::string &err) = 0;
   // u(0) and objective of slots[0..S) into rows dst[0..S) of u0_dev ([*][N*nu]).
   virtual int output_slots(double *u0_dev, const int32_t *slots, const int32_t *dst, int S, std::string &err) = 0;
