@@ -130,7 +130,7 @@ def main() -> int:
     ap.add_argument("--stream", type=int, default=256,
                     help="learned start: instances per step streamed through the --batch slots "
                          "(0: one batch of --batch instances per step)")
-    ap.add_argument("--refill-min", type=int, default=0, help="free slots before new instances join (0: half)")
+    ap.add_argument("--refill-min", type=int, default=0, help="free slots before new instances join (0: an eighth)")
     ap.add_argument("--check-iters", type=int, default=0, help="iterations between host checks (0: 4)")
     ap.add_argument("--cg-iters", type=int, default=0, help="CG steps of the trajectory start (0: library default 12)")
     ap.add_argument("--train-solves", type=int, default=8192)
@@ -261,18 +261,31 @@ def main() -> int:
             s += q
         return s, None
 
-    for i in range(args.warmup):
-        run_step(i, u0, args.start)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     stats, sinfo = [], []
-    for i in range(args.warmup, n_steps):
-        s, info = run_step(i, u0, args.start)
-        stats += s
-        if info:
-            sinfo.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    if S:
+        # one stream over all timed steps (steps x S instances in order, no drain between
+        # steps); the warm-up steps are a stream of their own before it
+        w = args.warmup * per
+        if w:
+            pr.solve_stream(w, x0[:args.warmup].data_ptr(), u0[:args.warmup].data_ptr(), args.refill_min,
+                            args.check_iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, stats, info = pr.solve_stream(args.steps * per, x0[args.warmup:].data_ptr(), u0[args.warmup:].data_ptr(),
+                                         args.refill_min, args.check_iters)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        sinfo.append(info)
+    else:
+        for i in range(args.warmup):
+            run_step(i, u0, args.start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.warmup, n_steps):
+            s, _ = run_step(i, u0, args.start)
+            stats += s
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     iters = [s["iters"] for s in stats]
     conv = sum(1 for s in stats if s["converged"])
     fell = sum(s["fell_back"] for s in stats)
@@ -281,11 +294,11 @@ def main() -> int:
         f"max {max(iters)}; converged {conv}/{n_solves}; fell back {fell}")
     stream_rec = {}
     if sinfo:
-        stream_rec = {"slots": B, "instances_per_step": per,
-                  "joins_per_step": float(np.mean([q["joins"] for q in sinfo])),
+        stream_rec = {"slots": B, "instances_per_step": per, "instances_streamed": args.steps * per,
+                  "joins": int(sum(q["joins"] for q in sinfo)),
                   "slot_use": round(sum(q["instance_iterations"] for q in sinfo) /
                                     sum(q["slot_iterations"] for q in sinfo), 4),
-                  "refill_min": args.refill_min or B // 2, "check_iters": args.check_iters or 4}
+                  "refill_min": args.refill_min or max(1, B // 8), "check_iters": args.check_iters or 4}
 
     def compare(start, label):
         """The timed instances again, in batches of B from `start`: time per solve, iterations,

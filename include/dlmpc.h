@@ -293,7 +293,7 @@ typedef struct {
  * max_batch slots, each from the learned start (needs the warm-start network): every
  * check_iters iterations (0: 4) the host reads the per-instance stop flags, writes u(0) of the
  * instances that stopped to their rows of u0_dev, and once at least refill_min slots are free
- * (0: half the slots; or the last instances are waiting; or no slot is busy) starts the next
+ * (0: an eighth of the slots; or the last instances are waiting; or no slot is busy) starts the next
  * instances in them: network inference and simulation at once, then the CG steps and the start
  * projections of their trajectory start inside the following iterations, in the joiners'
  * columns of the same basis products (no pass over the bases of their own), after which each

@@ -1208,12 +1208,13 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
-  int iteration(std::string &err) override {
+  int iteration(std::string &err, bool joins) override {
     launch_phi(args_);
     BENG_CHECK(hipGetLastError());
-    // CG steps of streamed joins (a no-op for instances in the ADMM iteration)
-    hipLaunchKernelGGL(bcg_step_kernel, dim3(args_.Bmax), dim3(1024), 0, stream_, args_, nullptr, 1);
-    BENG_CHECK(hipGetLastError());
+    if (joins) {  // CG steps of streamed joins (a no-op for instances in the ADMM iteration)
+      hipLaunchKernelGGL(bcg_step_kernel, dim3(args_.Bmax), dim3(1024), 0, stream_, args_, nullptr, 1);
+      BENG_CHECK(hipGetLastError());
+    }
     launch_psi(args_);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL(bdecide_kernel, dim3(1), dim3(64), 0, stream_, args_);

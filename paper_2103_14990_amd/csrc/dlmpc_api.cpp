@@ -37,6 +37,8 @@ struct dlmpc_problem {
   std::unique_ptr<dlmpc::BatchEngine> beng;
   hipGraph_t bgraph[kGraphs] = {};
   hipGraphExec_t bgexec[kGraphs] = {};
+  hipGraph_t sgraph[kGraphs] = {};      // iterations with the CG step of streamed joins
+  hipGraphExec_t sgexec[kGraphs] = {};
   double *d_bx0 = nullptr, *d_bu0 = nullptr;
   dlmpc::BCtl *h_bctl = nullptr;
   // learned warm start: network, predicted multipliers [Bmax][R], cold re-solve staging
@@ -71,6 +73,10 @@ void release_device(dlmpc_problem *p) {
     if (p->graph[g]) (void)hipGraphDestroy(p->graph[g]);
     if (p->bgexec[g]) (void)hipGraphExecDestroy(p->bgexec[g]);
     if (p->bgraph[g]) (void)hipGraphDestroy(p->bgraph[g]);
+    if (p->sgexec[g]) (void)hipGraphExecDestroy(p->sgexec[g]);
+    if (p->sgraph[g]) (void)hipGraphDestroy(p->sgraph[g]);
+    p->sgexec[g] = nullptr;
+    p->sgraph[g] = nullptr;
     p->gexec[g] = nullptr;
     p->graph[g] = nullptr;
     p->bgexec[g] = nullptr;
@@ -174,20 +180,23 @@ int setup_batch(dlmpc_problem *p) {
   API_HIP(hipMalloc(&p->d_fu0, sizeof(double) * size_t(B) * hs.N * hs.nu));
   API_HIP(hipEventCreate(&p->ev_w0));
   API_HIP(hipEventCreate(&p->ev_w1));
-  for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
-    API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < (1 << g); ++i) {
-      rc = p->beng->iteration(err);
-      if (rc) {
-        hipGraph_t gr = nullptr;
-        (void)hipStreamEndCapture(p->stream, &gr);
-        if (gr) (void)hipGraphDestroy(gr);
-        return fail(rc, err);
+  for (int joins = 0; joins < 2; ++joins)
+    for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
+      API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < (1 << g); ++i) {
+        rc = p->beng->iteration(err, joins != 0);
+        if (rc) {
+          hipGraph_t gr = nullptr;
+          (void)hipStreamEndCapture(p->stream, &gr);
+          if (gr) (void)hipGraphDestroy(gr);
+          return fail(rc, err);
+        }
       }
+      hipGraph_t &gr = joins ? p->sgraph[g] : p->bgraph[g];
+      hipGraphExec_t &ex = joins ? p->sgexec[g] : p->bgexec[g];
+      API_HIP(hipStreamEndCapture(p->stream, &gr));
+      API_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
     }
-    API_HIP(hipStreamEndCapture(p->stream, &p->bgraph[g]));
-    API_HIP(hipGraphInstantiate(&p->bgexec[g], p->bgraph[g], nullptr, nullptr, 0));
-  }
   API_HIP(hipStreamSynchronize(p->stream));
   return DLMPC_OK;
 }
@@ -854,7 +863,7 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   const HostSetup &h = p->hs;
   const size_t nxs = size_t(h.N) * h.nx, nus = size_t(h.N) * h.nu, R = size_t(h.N) * h.rs;
   const int Bm = p->beng->bmax(), Bs = std::min<int>(Bm, n);
-  if (refill_min == 0) refill_min = std::max(1, Bs / 2);
+  if (refill_min == 0) refill_min = std::max(1, Bs / 8);
   refill_min = std::min(refill_min, Bs);
   const int K = check_iters > 0 ? check_iters : 4;
   if (!p->d_sy) API_HIP(hipMalloc(&p->d_sy, sizeof(float) * size_t(Bm) * R));
@@ -894,7 +903,7 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   const int64_t guard = (int64_t(n) + 1) * (p->opt.max_iter + K);
   int64_t launched = 0;
   while (active > 0) {
-    rc = launch_graphs(p->bgexec, p->stream, K);
+    rc = launch_graphs(p->sgexec, p->stream, K);
     if (rc) return rc;
     launched += K;
     slot_iters += int64_t(K) * Bs;

@@ -199,7 +199,8 @@ class BatchEngine {
   // Current row multipliers alpha and trajectory rows (Phi x0) of every instance, [B][N*rs].
   virtual int export_alpha(double *alpha_dev, std::string &err) = 0;
   virtual int export_y(double *y_dev, std::string &err) = 0;
-  virtual int iteration(std::string &err) = 0;  // capturable
+  // One iteration (capturable); with `joins`, also the CG step of streamed joins.
+  virtual int iteration(std::string &err, bool joins = false) = 0;
   // One kernel of an iteration: 0 bphi_kernel, 1 bpsi_kernel, 2 bdecide_kernel.
   virtual int launch_one(int k, std::string &err) = 0;
   virtual int output(double *u0_dev, std::string &err) = 0;
