@@ -1082,9 +1082,8 @@ class BatchEngineT final : public BatchEngine {
 
   // dst_k = N_j' src for every column subsystem j and instance; wmode 1 also writes the
   // product operand W = ||x0_j||^2 dst_k, wmode 2 W = ||x0_j||^2 (tau + dst_k).
-  int project_t(const float *src, int64_t src_bs, int64_t src_rs, float *dst_k, int wmode, std::string &err,
-                const BArgs *base = nullptr) {
-    BArgs ia = base ? *base : args_;
+  int project_t(const float *src, int64_t src_bs, int64_t src_rs, float *dst_k, int wmode, std::string &err) {
+    BArgs ia = args_;
     ia.init_pass = 1;
     ia.wmode = wmode;
     ia.src = src;
