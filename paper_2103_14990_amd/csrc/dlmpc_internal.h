@@ -13,7 +13,7 @@ namespace dlmpc {
 // Thresholds of the column-block factorisation (host and device alike).
 constexpr double kRankTol = 1e-10;   // relative pivot threshold of the rank-revealing QR of the ring map
 constexpr double kBasisTol = 1e-13;  // relative pivot threshold of the QR that orthonormalises S K
-constexpr double kFeasTol = 1e-9;    // absolute ring residual of a particular solution
+constexpr double kFeasTol = 1e-9;    // ring residual of a particular solution over max(1, its largest entry)
 
 // Allocator whose resize() leaves doubles uninitialised (large arrays filled by a copy).
 template <class T>

@@ -308,12 +308,15 @@ struct PatchFactor {
       }
       Dense psi(D, 1), cons(std::max(mc, 1), 1);
       simulate(App, Bp, G, X0, u, p, &psi, ng > 0 ? &cons : nullptr);
-      double resid = 0.0;
+      // ring residual relative to the size of the trajectory (rounding grows with it)
+      double resid = 0.0, size = 1.0;
       if (ng > 0)
         for (int i = 0; i < mc; ++i) resid = std::max(resid, std::fabs(cons(i, 0)));
+      for (int rr = 0; rr < D; ++rr) size = std::max(size, std::fabs(psi(rr, 0)));
+      resid /= size;
       if (!(resid <= kFeasTol)) {
         err = "column " + std::to_string(j * nx + c) + " of subsystem " + std::to_string(j) +
-              " has no trajectory inside its d-hop patch (ring residual " + std::to_string(resid) + ")";
+              " has no trajectory inside its d-hop patch (relative ring residual " + std::to_string(resid) + ")";
         return DLMPC_EINFEASIBLE_LOCALITY;
       }
       // o_c = psi - N (N' psi)

@@ -69,7 +69,7 @@ struct FacArgs {
   double *nb, *off;
   int32_t *rank;    // [N] phase 1 result
   int32_t *status;  // [N] phase 2 result (DLMPC_OK, kFallbackOk, or an error)
-  double *resid;    // [N] ring residual of the particular solutions
+  double *resid;    // [N] ring residual of the particular solutions over their size
   int32_t nx, nu, T, rs;
   double chol_tol;  // smallest Cholesky QR pivot relative to the largest diagonal of Y'Y
 };
@@ -492,9 +492,11 @@ struct Patch {
   // and every state and input row of its trajectory is written. For the columns c >= off0 the
   // ring values G x[t], t = 0..T-2, are computed, stored to ring[(t*ng+i)*ring_ld + c - off0]
   // when ring is non-null, and the largest magnitude over them (NaN if any is NaN) is
-  // returned to every thread. Lanes take columns, the waves split the rows of each time step.
+  // returned to every thread, divided by max(1, largest magnitude of those columns' entries).
+  // Lanes take columns, the waves split the rows of each time step.
   __device__ double simulate(double *S, int lds, int c0, int c1, const double *U, int off0, int x0base,
                              double *ring, int ring_ld, double *s_rv) const {
+    double sz = 1.0;  // size of the tracked trajectories
     const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
     for (int cb = c0; cb < c1; cb += 64) {
       const int c = cb + lane;
@@ -503,7 +505,9 @@ struct Patch {
       for (int r = rg; r < ns; r += kFW) S[int64_t(srow(r, 0)) * lds + c] = (r == x0row) ? 1.0 : 0.0;
       for (int e = rg; e < (T - 1) * ni; e += kFW) {
         const int t = e / ni, a = (e % ni) / nu, q = e % nu;
-        S[int64_t(a * rs + nx * T + t * nu + q) * lds + c] = U ? U[int64_t(e) * lds + c] : 0.0;
+        const double uv = U ? U[int64_t(e) * lds + c] : 0.0;
+        S[int64_t(a * rs + nx * T + t * nu + q) * lds + c] = uv;
+        if (c >= off0) sz = max_nan(sz, fabs(uv));
       }
     }
     __syncthreads();
@@ -529,11 +533,14 @@ struct Patch {
               v += B[(int64_t(mem[a]) * nx + s) * nu + q] * U[int64_t(t * ni + a * nu + q) * lds + c];
           }
           S[int64_t(srow(r, t + 1)) * lds + c] = v;
+          if (c >= off0) sz = max_nan(sz, fabs(v));
         }
       }
       __syncthreads();
     }
-    return block_max(mx, s_rv);
+    mx = block_max(mx, s_rv);
+    sz = block_max(sz, s_rv);
+    return mx / sz;
   }
 };
 
@@ -911,7 +918,7 @@ int factor_device(HostSetup &hs, int device, double chol_tol, std::string &err) 
     }
     if (status[j] == DLMPC_EINFEASIBLE_LOCALITY) {
       err = "column of subsystem " + std::to_string(j) +
-            " has no trajectory inside its d-hop patch (ring residual " + std::to_string(resid[j]) + ")";
+            " has no trajectory inside its d-hop patch (relative ring residual " + std::to_string(resid[j]) + ")";
       return DLMPC_EINFEASIBLE_LOCALITY;
     }
     if (status[j] == DLMPC_ENUMERIC) {

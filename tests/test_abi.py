@@ -96,6 +96,19 @@ def test_infeasible_locality_status():
     assert e.value.status == dlmpc.EINFEASIBLE_LOCALITY
 
 
+@pytest.mark.parametrize("fac,T", [(4.0, 12), (3.0, 16)])
+def test_unstable_plant_blocks_match_oracle(fac, T):
+    """A scaled by fac (spectral radius fac): the particular trajectories grow ~fac^T-fold and
+    their ring residuals with them; feasibility is judged relative to the trajectory's size, so
+    the blocks exist and match the oracle's SVD (conditioning costs accuracy: 1e-9 / 1e-8)."""
+    net = W.chain(6)
+    net.a_blocks = net.a_blocks * fac
+    cost = W.unit_cost(net)
+    pb = O.setup_from_network(net, 1, T, cost)
+    assert pb.feasible
+    _compare_blocks(_host(net, 1, T, cost), pb, range(6), 1e-9, 1e-8)
+
+
 def test_whole_graph_patch_has_no_ring():
     """d >= diameter: one patch is the whole network (no ring equations)."""
     net = W.chain(5)
