@@ -316,8 +316,10 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
 
 // One block per column subsystem j: eta_j = N_j' A_j over K-chunks of its support rows staged
 // (as bf16 hi/lo) in LDS; wave w owns the M tiles w, w + 8, ... of the basis vectors.
+// Two 8-wave blocks per CU (four waves per SIMD, 128 registers per lane, a few of them spilled)
+// while a wave has at most 3 tiles, one block otherwise.
 template <int NX, int MTW>
-__global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
+__global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW <= 3 ? 4 : 2))) void bpsi_kernel(BArgs a) {
   if (a.ctl->stop) return;
   __shared__ __align__(16) __bf16 sh_hi[kBMax][kKC + 8];
   __shared__ __align__(16) __bf16 sh_lo[kBMax][kKC + 8];
@@ -423,19 +425,16 @@ __global__ __launch_bounds__(kPsiThreads) void bpsi_kernel(BArgs a) {
 #pragma unroll
     for (int ks = 0; ks < kKC / 32; ++ks) {
       const int kr = ks * 32 + 8 * (lane >> 4);
-      bf16x8 bh[kNT], bl[kNT];
+      // one instance tile's staged operand at a time (fewer live registers than all four)
 #pragma unroll
       for (int nt = 0; nt < kNT; ++nt) {
-        bh[nt] = *reinterpret_cast<const bf16x8 *>(&sh_hi[nt * 16 + (lane & 15)][kr]);
-        bl[nt] = *reinterpret_cast<const bf16x8 *>(&sh_lo[nt * 16 + (lane & 15)][kr]);
-      }
+        if (nt * 16 >= B) break;
+        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sh_hi[nt * 16 + (lane & 15)][kr]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sh_lo[nt * 16 + (lane & 15)][kr]);
 #pragma unroll
-      for (int t = 0; t < MTW; ++t) {
-        if (wave + kPsiWaves * t >= nmt) break;
-#pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) {
-          if (nt * 16 >= B) break;
-          acc[t][nt] = mfma3(ah[ks][t], al[ks][t], bh[nt], bl[nt], acc[t][nt]);
+        for (int t = 0; t < MTW; ++t) {
+          if (wave + kPsiWaves * t >= nmt) break;
+          acc[t][nt] = mfma3(ah[ks][t], al[ks][t], bh, bl, acc[t][nt]);
         }
       }
     }
