@@ -4,13 +4,15 @@
 Workload: the 1024-subsystem irregular mesh (32x32 grid, 30% of edges dropped, 51 chords;
 d = 3, T = 15, |theta| <= 0.8, |u| <= 2), x0 = 0.15 N(0, I), rho = 5, eps = 1e-4.
 
-A step is one batch of 64 MPC solves to eps (Algorithm 1 loop body for 64 distinct x0 already
-resident in HBM: per-step precompute, the start construction, ADMM iterations of Algorithm 2
-until every instance passes the convergence check, u(0) read out) in FP32 with the learned
-warm start; the warm-start network is trained beforehand (untimed) on cold solves that the
-same engine generates. Alongside: the same batches from the cold start, single-instance FP32
-and the plain FP64 cold-start GPU solve on the same x0, the roofline of the dominant kernel
-(HIP events around each launch), and the CPU oracle timed on a bounded sample.
+A step is 256 MPC solves to eps (Algorithm 1 loop body for distinct x0 already resident in
+HBM: per-solve precompute, the start construction, ADMM iterations of Algorithm 2 until the
+instance passes the convergence check, u(0) read out) in FP32 with the learned warm start, all
+timed steps streamed as one stream through 64 slots; the warm-start network is trained
+beforehand (untimed) on cold solves that the same engine generates. Alongside: the same
+instances in batches of 64 from the learned and the cold start, single-instance FP32 and the
+plain FP64 cold-start GPU solve on the same x0, the reduced-operator tier (basis rounded once
+to bf16) against the split-operand solves, the roofline of the dominant kernel (HIP events
+around each launch), and the CPU oracle timed on a bounded sample.
 
 Prints one JSON line: value = ADMM iterations per second over the timed steps (instance
 iterations, whole job); time_to_eps_ms = device-and-host wall time per MPC solve.
@@ -41,16 +43,16 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def batch_algorithmic_bytes(info: dict, n_sub: int, rs: int, B: int) -> dict:
+def batch_algorithmic_bytes(info: dict, n_sub: int, rs: int, B: int, basis_bytes: int = 4) -> dict:
     """Bytes each batched kernel must move per launch for B instances (lower bound: every
-    array touched once). The null bases are stored as bf16 hi + lo (4 B per entry) and read
-    once per kernel: sum_j D_col(j) k_j entries. FP32 vectors: alpha, s, b over the R rows,
+    array touched once). The null bases are stored as bf16 hi + lo (4 B per entry; 2 B in the
+    tier that rounds them once to bf16) and read once per kernel: sum_j D_col(j) k_j entries. FP32 vectors: alpha, s, b over the R rows,
     tau / eta / W (bf16 hi + lo) over sum_j k_j coordinates, per instance.
     bpsi_kernel: bases + alpha (read) + tau, eta (read, write) + W (write) + row-subsystem sums.
     bphi_kernel: bases + W (read) + alpha_prev, b (read), alpha, s (write) + w, lb, ub.
     """
     dk, sk, R = info["sum_dcol_k"], info["sum_k"], n_sub * rs
-    nb = 4 * dk
+    nb = basis_bytes * dk
     bpsi = nb + 4 * B * R + 16 * B * sk + 4 * B * sk + 8 * B * n_sub
     bphi = nb + 4 * B * sk + 16 * B * R + 12 * R + 8 * B * n_sub
     return {"bphi_kernel": bphi, "bpsi_kernel": bpsi, "bdecide_kernel": 0, "iteration": bphi + bpsi}
@@ -139,6 +141,8 @@ def main() -> int:
     ap.add_argument("--single-steps", type=int, default=8, help="single-instance FP32 solves")
     ap.add_argument("--ref-steps", type=int, default=4, help="plain FP64 single-instance solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16-tier", dest="bf16_tier", action="store_false",
+                    help="skip the reduced-operator tier (basis rounded once to bf16) comparison")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the 192-instance mixed-network group solve")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -361,6 +365,57 @@ def main() -> int:
         prf.close()
     log(f"single fp32: {single}; plain fp64: {ref}")
 
+    # ---- reduced-operator tier (basis rounded once to bf16): the first timed step's instances
+    # in batches of B from the cold start at eps = 1e-3 (above the tier's dual-residual floor on
+    # this mesh), against the split-operand tier at the same eps and at the headline eps, and
+    # the plain FP64 solves above; per-launch kernel times
+    tier = {}
+    if args.bf16_tier:
+        eps_t = 1e-3
+
+        def timed_batches(p_, uu):
+            p_.solve_batch_ex(min(B, per), xs.data_ptr(), uu.data_ptr(), "cold")  # untimed first use
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sq = []
+            for b0 in range(0, per, B):
+                sq += p_.solve_batch_ex(min(B, per - b0), xs[b0:].data_ptr(), uu[b0:].data_ptr(), "cold")[1]
+            torch.cuda.synchronize()
+            return sq, time.perf_counter() - t1
+
+        def tier_problem(precision):
+            return dlmpc.Problem.from_network(net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=eps_t,
+                                              max_iter=wl.max_iter, precision=precision, device=0,
+                                              stream=stream.cuda_stream, max_batch=B)
+
+        def urel(a_, b_):
+            return ((a_ - b_).abs().amax(dim=1) / b_.abs().amax(dim=1)).max().item()
+
+        p16, p32 = tier_problem("fp32_bf16"), tier_problem("fp32")
+        u16, u32, u4 = (torch.zeros((per, n_u), dtype=torch.float64, device=dev) for _ in range(3))
+        s16, e16 = timed_batches(p16, u16)
+        s32, e32 = timed_batches(p32, u32)
+        s4, _ = timed_batches(pr, u4)
+        k16 = p16.time_batch_kernels(B, xs.data_ptr(), 20)
+        ab16 = batch_algorithmic_bytes(pr.info, N, rs, B, basis_bytes=2)
+        tier = {"eps": eps_t, "instances": per, "start": "cold",
+                "time_to_eps_ms": round(1e3 * e16 / per, 4),
+                "iters_mean": float(np.mean([q["iters"] for q in s16])),
+                "converged": f"{sum(q['converged'] for q in s16)}/{per}",
+                "split_operands_same_eps": {"time_to_eps_ms": round(1e3 * e32 / per, 4),
+                                            "iters_mean": float(np.mean([q["iters"] for q in s32]))},
+                "u0_rel_diff_vs_split_operands_same_eps_max": urel(u16, u32),
+                "u0_rel_diff_vs_split_operands_headline_eps_max": urel(u16, u4),
+                "per_kernel": {k: {"us": round(v, 2),
+                                   "GB/s": round(ab16[k] / (v * 1e-6) / 1e9, 1) if ab16[k] else None}
+                               for k, v in k16.items()}}
+        if ref:
+            kr = len(ref["iters"])
+            tier["u0_rel_diff_vs_fp64_max"] = urel(u16[:kr], uf)
+        p16.close()
+        p32.close()
+        log(f"bf16 operator tier: {tier}")
+
     # ---- instances of different networks in one launch per iteration chunk: 64 x {8x8, 16x16,
     # 32x32 grids} (d = 2, T = 10, no bounds, x0 ~ N(0, I)), against the members one after another
     mixed = {}
@@ -431,6 +486,7 @@ def main() -> int:
         "mixed_networks": mixed,
         "single_fp32_cold": single,
         "plain_fp64_cold": ref,
+        "bf16_operator_tier": tier,
         "speedup_vs_plain_fp64": round(ref["time_to_eps_ms_median"] / (ms_step / per), 2) if ref else None,
         "warm_start_training": train,
         "setup_ms": round(pr.info["setup_ms"], 1),

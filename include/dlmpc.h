@@ -46,8 +46,19 @@ enum {
 };
 
 typedef enum {
-  DLMPC_FP64 = 0, /* state, operators and reductions in double */
-  DLMPC_FP32 = 1  /* state and operators in float; setup and outputs stay double */
+  DLMPC_FP64 = 0,     /* state, operators and reductions in double */
+  DLMPC_FP32 = 1,     /* state and operators in float; setup and outputs stay double. Batched
+                         solves: matrix-core products with both operands split into bf16 hi + lo
+                         and float accumulation (float-level products) */
+  DLMPC_FP32_BF16 = 2 /* reduced-operator tier: as DLMPC_FP32, except that the batched solves'
+                         basis operands are rounded once to bf16 (two matrix-core products per
+                         tile instead of three, half the basis bytes). The rounded basis is not
+                         exactly orthonormal: the iterate keeps moving by an amount set by bf16
+                         rounding, so the dual residual settles on a floor that depends on the
+                         network (4e-4 to 7e-3 on the grids and meshes tested) and eps must lie
+                         above it, else the solve runs to max_iter (DLMPC_ENOCONV); u(0) and J
+                         then carry an error of the order of eps and of bf16 rounding.
+                         Single-instance solves run as DLMPC_FP32. */
 } dlmpc_precision;
 
 /* Setup flags (dlmpc_options.flags). */
@@ -97,7 +108,7 @@ typedef struct {
   void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
   uint32_t flags;      /* DLMPC_FLAG_* */
   int32_t max_batch;   /* 0, or 1..64: also set up the batched engine for up to this many x0
-                          per dlmpc_solve_batch call (FP32 precision only) */
+                          per dlmpc_solve_batch call (FP32 or FP32_BF16 precision) */
   int32_t warm_cg_iters; /* CG steps of the trajectory warm start (0: 12) */
   double factor_chol_tol; /* device factorisation: a Cholesky QR pivot of S K below this
                              fraction of the largest diagonal of (S K)'(S K) switches that

@@ -1221,7 +1221,7 @@ std::unique_ptr<Engine> make_for_nx(int nx) {
 
 std::unique_ptr<Engine> make_engine(int precision, int nx) {
   if (precision == DLMPC_FP64) return make_for_nx<double>(nx);
-  if (precision == DLMPC_FP32) return make_for_nx<float>(nx);
+  if (precision == DLMPC_FP32 || precision == DLMPC_FP32_BF16) return make_for_nx<float>(nx);
   return nullptr;
 }
 

@@ -68,6 +68,17 @@ __device__ __forceinline__ f32x4 mfma3(const bf16x8 &ah, const bf16x8 &al, const
   return c;
 }
 
+// A*B with A = ah (the operand rounded once to bf16), B = bh + bl.
+__device__ __forceinline__ f32x4 mfma2(const bf16x8 &ah, const bf16x8 &bh, const bf16x8 &bl, f32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  return c;
+}
+
+// Values per basis fragment block: bf16 hi and lo of 64 lanes x 8 (split operands), or hi only.
+template <bool SPLIT>
+constexpr int frag_block() { return SPLIT ? 1024 : 512; }
+
 __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 
 template <typename T>
@@ -177,8 +188,10 @@ __global__ __launch_bounds__(256) void bexport_alpha_kernel(BArgs a, double *out
 // hi/lo, written by bpsi_kernel) once per block; the rows of N_j that belong to m (fragment
 // order) are the left operand. The (tile, k-step) sequence of a wave is one flat loop whose
 // next step's operands are in flight while the current step's products run.
-template <int NX, int NRT>
+// SPLIT: basis fragments as bf16 hi + lo (three products per tile); otherwise hi only (two).
+template <int NX, int NRT, bool SPLIT>
 __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
+  constexpr int kFB = frag_block<SPLIT>();
   if (a.ctl->stop) return;
   __shared__ float Ct[2][64][kBMax + 1];
   __shared__ double red[kPhiThreads / 64][kBMax];
@@ -212,11 +225,11 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
       const int64_t wi = ((s_w8[t] + 4 * kt + (lane >> 4)) * a.Bw + b) * 8;
       ph = load8(a.w_hi + wi);
       pl = load8(a.w_lo + wi);
-      const int64_t fb = s_fb[t] + lane * 8 + int64_t(kt) * 1024, stride = int64_t(s_nkt[t]) * 1024;
+      const int64_t fb = s_fb[t] + lane * 8 + int64_t(kt) * kFB, stride = int64_t(s_nkt[t]) * kFB;
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt) {  // rows past rs are zero in the fragments
         qh[rt] = load8(a.nf + fb + rt * stride);
-        ql[rt] = load8(a.nf + fb + rt * stride + 512);
+        if constexpr (SPLIT) ql[rt] = load8(a.nf + fb + rt * stride + 512);
       }
     };
     // two operand sets used alternately: the loads of one are in flight while the products of
@@ -244,13 +257,15 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
       load_step(t, kt, wh2, wl2, ah2, al2);
       __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
 #pragma unroll
-      for (int rt = 0; rt < NRT; ++rt) acc[rt] = mfma3(ah[rt], al[rt], wh, wl, acc[rt]);
+      for (int rt = 0; rt < NRT; ++rt)
+        acc[rt] = SPLIT ? mfma3(ah[rt], al[rt], wh, wl, acc[rt]) : mfma2(ah[rt], wh, wl, acc[rt]);
       if (!more) break;
       more = advance();
       load_step(t, kt, wh, wl, ah, al);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int rt = 0; rt < NRT; ++rt) acc[rt] = mfma3(ah2[rt], al2[rt], wh2, wl2, acc[rt]);
+      for (int rt = 0; rt < NRT; ++rt)
+        acc[rt] = SPLIT ? mfma3(ah2[rt], al2[rt], wh2, wl2, acc[rt]) : mfma2(ah2[rt], wh2, wl2, acc[rt]);
       if (!more) break;
     }
   }
@@ -317,9 +332,11 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
 // One block per column subsystem j: eta_j = N_j' A_j over K-chunks of its support rows staged
 // (as bf16 hi/lo) in LDS; wave w owns the M tiles w, w + 8, ... of the basis vectors.
 // Two 8-wave blocks per CU (four waves per SIMD, 128 registers per lane, a few of them spilled)
-// while a wave has at most 3 tiles, one block otherwise.
-template <int NX, int MTW>
+// while a wave has at most 3 tiles, one block otherwise. SPLIT: basis fragments as bf16 hi + lo
+// (three products per tile); otherwise hi only (two).
+template <int NX, int MTW, bool SPLIT>
 __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW <= 3 ? 4 : 2))) void bpsi_kernel(BArgs a) {
+  constexpr int kFB = frag_block<SPLIT>();
   if (a.ctl->stop) return;
   __shared__ __align__(16) __bf16 sh_hi[kBMax][kKC + 8];
   __shared__ __align__(16) __bf16 sh_lo[kBMax][kKC + 8];
@@ -405,9 +422,9 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
 #pragma unroll
       for (int t = 0; t < MTW; ++t) {
         const int mt = min(wave + kPsiWaves * t, nmt - 1);  // tiles past nmt: loaded, unused
-        const int64_t ai = a.ntf_off[j] + (int64_t(mt) * nkt + (r0 >> 5) + ks) * 1024 + lane * 8;
+        const int64_t ai = a.ntf_off[j] + (int64_t(mt) * nkt + (r0 >> 5) + ks) * kFB + lane * 8;
         ah[ks][t] = load8(a.ntf + ai);
-        al[ks][t] = load8(a.ntf + ai + 512);
+        if constexpr (SPLIT) al[ks][t] = load8(a.ntf + ai + 512);
       }
     __builtin_amdgcn_sched_barrier(0);  // fragments in flight before the staging barrier
 #pragma unroll
@@ -434,7 +451,7 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
 #pragma unroll
         for (int t = 0; t < MTW; ++t) {
           if (wave + kPsiWaves * t >= nmt) break;
-          acc[t][nt] = mfma3(ah[ks][t], al[ks][t], bh, bl, acc[t][nt]);
+          acc[t][nt] = SPLIT ? mfma3(ah[ks][t], al[ks][t], bh, bl, acc[t][nt]) : mfma2(ah[ks][t], bh, bl, acc[t][nt]);
         }
       }
     }
@@ -818,12 +835,14 @@ __global__ __launch_bounds__(256) void bscatter_rows_kernel(const float *src, co
   } while (0)
 
 // Null bases from the device factorisation (FP64, column-major, padded leading dimension) into
-// the fragment orders ntf and nf (bf16 hi at [l*8+e], lo 512 further; layouts as built on the
-// host from the same bases). Block (j, y) strides over the k_j x D_col(j) entries of N_j.
+// the fragment orders ntf and nf (bf16 hi at [l*8+e], with split operands lo 512 further;
+// layouts as built on the host from the same bases). Block (j, y) strides over the
+// k_j x D_col(j) entries of N_j.
 __global__ void bfrag_kernel(const double *__restrict__ nb, const int64_t *__restrict__ nb_off,
                              const int32_t *__restrict__ kdim, const int64_t *__restrict__ tile_off,
                              const int64_t *__restrict__ ntf_off, const int64_t *__restrict__ nf_off, int rs,
-                             __bf16 *__restrict__ ntf, __bf16 *__restrict__ nf) {
+                             int split, __bf16 *__restrict__ ntf, __bf16 *__restrict__ nf) {
+  const int fb = split ? 1024 : 512;
   const int j = blockIdx.x;
   const int64_t t0 = tile_off[j];
   const int D = int(tile_off[j + 1] - t0) * rs, k = kdim[j], ld = (D + 3) & ~3;
@@ -838,17 +857,17 @@ __global__ void bfrag_kernel(const double *__restrict__ nb, const int64_t *__res
     {  // ntf: M = basis i, K = row r
       const int mt = i / 16, kt = r / 32, kk = r % 32;
       const int l = (i % 16) + 16 * (kk / 8), el = kk % 8;
-      const int64_t at = ntf_off[j] + (int64_t(mt) * nkt_c + kt) * 1024 + l * 8 + el;
+      const int64_t at = ntf_off[j] + (int64_t(mt) * nkt_c + kt) * fb + l * 8 + el;
       ntf[at] = h;
-      ntf[at + 512] = lo;
+      if (split) ntf[at + 512] = lo;
     }
     {  // nf: M = row of the tile, K = basis i
       const int t = r / rs, rr = r % rs;
       const int rt = rr / 16, kt = i / 32, kk = i % 32;
       const int l = (rr % 16) + 16 * (kk / 8), el = kk % 8;
-      const int64_t at = nf_off[t0 + t] + (int64_t(rt) * nkt_r + kt) * 1024 + l * 8 + el;
+      const int64_t at = nf_off[t0 + t] + (int64_t(rt) * nkt_r + kt) * fb + l * 8 + el;
       nf[at] = h;
-      nf[at + 512] = lo;
+      if (split) nf[at + 512] = lo;
     }
   }
 }
@@ -856,7 +875,7 @@ __global__ void bfrag_kernel(const double *__restrict__ nb, const int64_t *__res
 template <int NX>
 class BatchEngineT final : public BatchEngine {
  public:
-  int init(const HostSetup &hs, double rho, int bmax, hipStream_t s, std::string &err) override {
+  int init(const HostSetup &hs, double rho, int bmax, bool split, hipStream_t s, std::string &err) override {
     if (bmax < 1 || bmax > kBMax) {
       err = "max_batch must be in 1..64";
       return DLMPC_EINVAL;
@@ -865,6 +884,8 @@ class BatchEngineT final : public BatchEngine {
       err = "batched engine needs k_j <= 512, nx*T + nu*(T-1) <= 64 and d-hop patches of <= 64 subsystems";
       return DLMPC_EINVAL;
     }
+    split_ = split;
+    const int64_t fb = split ? 1024 : 512;
     nrt_ = (hs.rs + 15) / 16;
     mtw_ = std::max(1, ((hs.k_max + 15) / 16 + kPsiWaves - 1) / kPsiWaves);
     hs_ = &hs;
@@ -878,13 +899,14 @@ class BatchEngineT final : public BatchEngine {
     a.Bmax = bmax;
     a.rho = float(rho);
     const int N = hs.N;
-    // Null bases in matrix-core fragment order (bf16 hi and lo of one fragment adjacent, 1024
-    // values): a wave's load of one fragment is one contiguous 1 KB block per half.
+    // Null bases in matrix-core fragment order (bf16 hi and lo of one fragment adjacent, fb =
+    // 1024 values; hi only, fb = 512, when the operands are rounded once): a wave's load of one
+    // fragment is one contiguous 1 KB block per half.
     //  ntf (left operand of N_j' alpha): fragment (M-tile mt of 16 basis vectors, K-step kt of
-    //      32 support rows) of j at ntf_off[j] + (mt * nkt + kt) * 1024, lane l, element e:
+    //      32 support rows) of j at ntf_off[j] + (mt * nkt + kt) * fb, lane l, element e:
     //      N_j[32 kt + 8 (l / 16) + e][16 mt + l % 16];
     //  nf (left operand of N_j W_j for the rows of one tile (j, m)): fragment (row tile rt of 16
-    //      rows of m, K-step kt of 32 basis vectors) at nf_off[tile] + (rt * nkt + kt) * 1024:
+    //      rows of m, K-step kt of 32 basis vectors) at nf_off[tile] + (rt * nkt + kt) * fb:
     //      N_j[ro + 16 rt + l % 16][32 kt + 8 (l / 16) + e]; zero outside N_j.
     const int nrt = (hs.rs + 15) / 16;
     std::vector<int64_t> koff(N + 1, 0), ntf_off(N + 1, 0), nf_off(hs.n_tiles + 1, 0);
@@ -892,10 +914,10 @@ class BatchEngineT final : public BatchEngine {
       const int64_t D = int64_t(hs.patch[j].size()) * hs.rs, k = hs.kdim[j];
       const int64_t k32 = (k + 31) & ~31;
       koff[j + 1] = koff[j] + k32;
-      ntf_off[j + 1] = ntf_off[j] + ((k + 15) & ~15) / 16 * ((D + kKC - 1) / kKC * kKC / 32) * 1024;
+      ntf_off[j + 1] = ntf_off[j] + ((k + 15) & ~15) / 16 * ((D + kKC - 1) / kKC * kKC / 32) * fb;
       for (size_t t = 0; t < hs.patch[j].size(); ++t) {
         const int64_t tile = hs.tile_off[j] + int64_t(t);
-        nf_off[tile + 1] = nf_off[tile] + int64_t(nrt) * (k32 / 32) * 1024;
+        nf_off[tile + 1] = nf_off[tile] + int64_t(nrt) * (k32 / 32) * fb;
       }
     }
     a.ktot = koff[N];
@@ -960,7 +982,7 @@ class BatchEngineT final : public BatchEngine {
       BENG_CHECK(hipMemset(d_ntf, 0, sizeof(__bf16) * std::max<int64_t>(ntf_off[N], 1)));
       BENG_CHECK(hipMemset(d_nf, 0, sizeof(__bf16) * std::max<int64_t>(nf_off[hs.n_tiles], 1)));
       hipLaunchKernelGGL(bfrag_kernel, dim3(N, 16), dim3(256), 0, nullptr, hs.d_nb, d_nboff, d_k, d_toff,
-                         d_ntfoff, d_nfoff, hs.rs, d_ntf, d_nf);
+                         d_ntfoff, d_nfoff, hs.rs, int(split), d_ntf, d_nf);
       BENG_CHECK(hipGetLastError());
       BENG_CHECK(hipDeviceSynchronize());
       a.ntf = d_ntf;
@@ -975,7 +997,7 @@ class BatchEngineT final : public BatchEngine {
         const float x = float(v);
         const __bf16 h = static_cast<__bf16>(x);
         dst[at] = h;
-        dst[at + 512] = static_cast<__bf16>(x - static_cast<float>(h));
+        if (split) dst[at + 512] = static_cast<__bf16>(x - static_cast<float>(h));
       };
       for (int i = 0; i < k; ++i)
         for (int r = 0; r < D; ++r) {
@@ -983,13 +1005,13 @@ class BatchEngineT final : public BatchEngine {
           {  // ntf: M = basis i, K = row r
             const int mt = i / 16, kt = r / 32, kk = r % 32;
             const int l = (i % 16) + 16 * (kk / 8), e = kk % 8;
-            put(ntf, ntf_off[j] + (int64_t(mt) * nkt_c + kt) * 1024 + l * 8 + e, v);
+            put(ntf, ntf_off[j] + (int64_t(mt) * nkt_c + kt) * fb + l * 8 + e, v);
           }
           {  // nf: M = row of the tile, K = basis i
             const int t = r / hs.rs, rr = r % hs.rs;
             const int rt = rr / 16, kt = i / 32, kk = i % 32;
             const int l = (rr % 16) + 16 * (kk / 8), e = kk % 8;
-            put(nf, nf_off[hs.tile_off[j] + t] + (int64_t(rt) * nkt_r + kt) * 1024 + l * 8 + e, v);
+            put(nf, nf_off[hs.tile_off[j] + t] + (int64_t(rt) * nkt_r + kt) * fb + l * 8 + e, v);
           }
         }
     }
@@ -1263,22 +1285,37 @@ class BatchEngineT final : public BatchEngine {
   BArgs args_{};
   // instantiations for the row tiles of a subsystem and the basis tiles per wave
   void launch_phi(const BArgs &x) {
-    switch (nrt_) {
-      case 1: hipLaunchKernelGGL((bphi_kernel<NX, 1>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
-      case 2: hipLaunchKernelGGL((bphi_kernel<NX, 2>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
-      case 3: hipLaunchKernelGGL((bphi_kernel<NX, 3>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
-      default: hipLaunchKernelGGL((bphi_kernel<NX, 4>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
-    }
+    if (split_)
+      launch_phi_t<true>(x);
+    else
+      launch_phi_t<false>(x);
   }
   void launch_psi(const BArgs &x) {
+    if (split_)
+      launch_psi_t<true>(x);
+    else
+      launch_psi_t<false>(x);
+  }
+  template <bool SPLIT>
+  void launch_phi_t(const BArgs &x) {
+    switch (nrt_) {
+      case 1: hipLaunchKernelGGL((bphi_kernel<NX, 1, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      case 2: hipLaunchKernelGGL((bphi_kernel<NX, 2, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      case 3: hipLaunchKernelGGL((bphi_kernel<NX, 3, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      default: hipLaunchKernelGGL((bphi_kernel<NX, 4, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+    }
+  }
+  template <bool SPLIT>
+  void launch_psi_t(const BArgs &x) {
     switch (mtw_) {
-      case 1: hipLaunchKernelGGL((bpsi_kernel<NX, 1>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
-      case 2: hipLaunchKernelGGL((bpsi_kernel<NX, 2>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
-      case 3: hipLaunchKernelGGL((bpsi_kernel<NX, 3>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
-      default: hipLaunchKernelGGL((bpsi_kernel<NX, 4>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+      case 1: hipLaunchKernelGGL((bpsi_kernel<NX, 1, SPLIT>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+      case 2: hipLaunchKernelGGL((bpsi_kernel<NX, 2, SPLIT>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+      case 3: hipLaunchKernelGGL((bpsi_kernel<NX, 3, SPLIT>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+      default: hipLaunchKernelGGL((bpsi_kernel<NX, 4, SPLIT>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
     }
   }
   int nrt_ = 1, mtw_ = 1;
+  bool split_ = true;  // basis operands as bf16 hi + lo
   int B_ = 0;
   int64_t ny_ = 0;  // N * rs
   // streamed solves: slot lists on the device and their host staging

@@ -163,10 +163,11 @@ int setup_device(dlmpc_problem *p) {
 int setup_batch(dlmpc_problem *p) {
   const HostSetup &hs = p->hs;
   std::string err;
-  if (p->opt.precision != DLMPC_FP32) return fail(DLMPC_EINVAL, "the batched engine runs in FP32 precision");
+  if (p->opt.precision != DLMPC_FP32 && p->opt.precision != DLMPC_FP32_BF16)
+    return fail(DLMPC_EINVAL, "the batched engine runs in FP32 or FP32_BF16 precision");
   p->beng = dlmpc::make_batch_engine(hs.nx);
   if (!p->beng) return fail(DLMPC_EINVAL, "batched engine: nx must be 1..4");
-  int rc = p->beng->init(hs, p->opt.rho, p->opt.max_batch, p->stream, err);
+  int rc = p->beng->init(hs, p->opt.rho, p->opt.max_batch, p->opt.precision == DLMPC_FP32, p->stream, err);
   if (rc) return fail(rc, err);
   const int B = p->opt.max_batch;
   API_HIP(hipMalloc(&p->d_bx0, sizeof(double) * size_t(B) * hs.N * hs.nx));
@@ -421,7 +422,8 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
   if (o.max_iter == 0) o.max_iter = 500;
   if (!(o.rho > 0.0) || !std::isfinite(o.rho) || !(o.eps > 0.0) || o.max_iter < 0 || o.check_every < 0)
     return fail(DLMPC_EINVAL, "options: need rho > 0, eps > 0, max_iter >= 0, check_every >= 0");
-  if (o.precision != DLMPC_FP64 && o.precision != DLMPC_FP32) return fail(DLMPC_EINVAL, "unknown precision");
+  if (o.precision != DLMPC_FP64 && o.precision != DLMPC_FP32 && o.precision != DLMPC_FP32_BF16)
+    return fail(DLMPC_EINVAL, "unknown precision");
   if (o.max_batch < 0 || o.max_batch > 64) return fail(DLMPC_EINVAL, "max_batch must be in 0..64");
   if (!(o.factor_chol_tol >= 0.0)) return fail(DLMPC_EINVAL, "factor_chol_tol must be >= 0");
   auto p = std::make_unique<dlmpc_problem>();

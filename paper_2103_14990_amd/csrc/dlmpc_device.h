@@ -182,7 +182,8 @@ struct BArgs {
 class BatchEngine {
  public:
   virtual ~BatchEngine() = default;
-  virtual int init(const HostSetup &hs, double rho, int bmax, hipStream_t s, std::string &err) = 0;
+  // split: basis operands as bf16 hi + lo (FP32-level products); otherwise rounded once to bf16
+  virtual int init(const HostSetup &hs, double rho, int bmax, bool split, hipStream_t s, std::string &err) = 0;
   // Per-solve set-up of B instances; warm != 0 selects the iteration of a warm start (one of
   // the start_* calls below must follow before the first iteration).
   virtual int precompute(const double *x0_dev, int B, int max_iter, double eps, int warm,

@@ -16,14 +16,14 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libdlmpc.so")
 
 OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EINFEASIBLE_LOCALITY, ENUMERIC = 0, 1, -1, -2, -3, -4, -5
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_BF16 = 0, 1, 2
 FLAG_HOST_ONLY = 0x1
 FLAG_SCHED_GRAPH = 0x2
 FLAG_SCHED_PERSISTENT = 0x4
 FLAG_HOST_FACTOR = 0x8
 FACTORS = {"device": 0, "host": FLAG_HOST_FACTOR}
 SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
-PRECISIONS = {"fp64": FP64, "fp32": FP32}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16": FP32_BF16}
 TIMED_KERNELS = 4
 KERNEL_NAMES = ("phi_kernel", "psi_pass1_kernel", "psi_pass2_kernel", "conv_kernel")
 BATCH_KERNEL_NAMES = ("bphi_kernel", "bpsi_kernel", "bdecide_kernel")

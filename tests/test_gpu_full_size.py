@@ -91,3 +91,83 @@ def test_grid32_batch_matches_oracle():
         # FP32-tier rounding moves the stopping iterate of a ~200-iteration run by a few
         assert abs(stats[i]["iters"] - rec["iters"]) <= max(5, 0.05 * rec["iters"])
         assert err < 1e-4 and jerr < 1e-5
+
+
+def test_bench_configuration_batched_and_streamed(golden, wl):
+    """The launch configuration of the throughput measurement at full size: FP32 state,
+    split-bf16 matrix-core products, 64 slots. A cold batched solve of 64 instances (the two with
+    stored oracle values among them) meets the reduced-precision bar against the oracle; then,
+    with a briefly trained warm-start network, a streamed solve of 96 instances equals the
+    batched learned solves of the same instances bit for bit, and each learned solve sits within
+    the warm-start bar (both stop on the eps rule from different initial points) of the cold
+    solve of the same x0."""
+    import torch
+    G, nu = wl.net.n_sub, wl.net.nu
+    rs = wl.net.nx * wl.T + nu * (wl.T - 1)
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps,
+                                    max_iter=wl.max_iter, precision="fp32", max_batch=64)
+    gseeds = [r["seed"] for r in golden["records"]]
+    seeds = gseeds + [6000 + i for i in range(64 - len(gseeds))]
+    xd = torch.tensor(np.stack([wl.x0(s) for s in seeds]), dtype=torch.float64, device="cuda")
+    ud = torch.zeros((64, G * nu), dtype=torch.float64, device="cuda")
+    yd = torch.zeros((64, G * rs), dtype=torch.float64, device="cuda")
+    st, sc = pr.solve_batch_ex(64, xd.data_ptr(), ud.data_ptr(), "cold", 0, yd.data_ptr())
+    assert st == dlmpc.OK
+    for i, rec in enumerate(golden["records"]):
+        ref = np.array(rec["u0"])
+        err = np.abs(ud[i].cpu().numpy() - ref).max() / np.abs(ref).max()
+        jerr = abs(sc[i]["objective"] - rec["J"]) / rec["J"]
+        print(f"  batched cold seed {rec['seed']}: iters {sc[i]['iters']} (oracle {rec['iters']}) "
+              f"u0 rel {err:.2e} J rel {jerr:.2e}", flush=True)
+        assert abs(sc[i]["iters"] - rec["iters"]) <= max(5, 0.05 * rec["iters"])
+        assert err < 1e-4 and jerr < 1e-5
+
+    ys = float(yd.view(64, G, rs)[:, :, wl.net.nx * wl.T:].std().item())
+    pr.ws_init(32, 64, seed=1, x_scale=wl.sigma, y_scale=ys)
+    for _ in range(300):
+        pr.ws_train_step(64, xd.data_ptr(), yd.data_ptr(), 2e-3)
+    n = 96  # the 64 instances above, then 32 more: joins into freed slots
+    xs = torch.cat([xd, torch.tensor(np.stack([wl.x0(7000 + i) for i in range(n - 64)]),
+                                     dtype=torch.float64, device="cuda")])
+    us = torch.zeros((n, G * nu), dtype=torch.float64, device="cuda")
+    st, ss, info = pr.solve_stream(n, xs.data_ptr(), us.data_ptr())
+    ub = torch.zeros_like(us)
+    sb = []
+    for s0 in range(0, n, 64):
+        c = min(64, n - s0)
+        stb, s = pr.solve_batch_ex(c, xs[s0:].data_ptr(), ub[s0:].data_ptr(), "learned")
+        sb += s
+    it_s = [s["iters"] for s in ss]
+    print(f"  streamed {n}: iterations mean {np.mean(it_s):.1f} (cold {np.mean([s['iters'] for s in sc]):.1f}), "
+          f"joins {info['joins']}, fell back {info['fell_back']}", flush=True)
+    assert st == dlmpc.OK and all(s["converged"] for s in ss)
+    assert torch.equal(us, ub)
+    assert it_s == [s["iters"] for s in sb]
+    assert info["joins"] > 1
+    e = (us[:64] - ud).abs().amax(dim=1) / ud.abs().amax(dim=1)
+    print(f"  learned vs cold u0 rel max {float(e.max()):.2e}", flush=True)
+    assert float(e.max()) < 5e-3
+    pr.close()
+
+
+def test_bf16_operator_tier_full_size(golden, wl):
+    """Reduced-operator tier (basis rounded once to bf16) at full size with eps = 1e-3 (above
+    its dual-residual floor here): every one of 64 instances converges, and the instances with
+    stored oracle values meet 8 u_bf16 (u_bf16 = 2^-8) on u(0) and J against the oracle's
+    eps = 1e-4 solution."""
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=1e-3,
+                                    max_iter=wl.max_iter, precision="fp32_bf16", max_batch=64)
+    seeds = [r["seed"] for r in golden["records"]]
+    seeds += [6000 + i for i in range(64 - len(seeds))]
+    st, u0, stats = pr.solve_batch(np.stack([wl.x0(s) for s in seeds]))
+    print(f"  bf16 tier: iterations mean {np.mean([q['iters'] for q in stats]):.1f}", flush=True)
+    assert st == dlmpc.OK
+    ub = 2.0 ** -8
+    for i, rec in enumerate(golden["records"]):
+        ref = np.array(rec["u0"])
+        err = np.abs(u0[i] - ref).max() / np.abs(ref).max()
+        jerr = abs(stats[i]["objective"] - rec["J"]) / rec["J"]
+        print(f"  seed {rec['seed']}: iters {stats[i]['iters']} (oracle {rec['iters']}) u0 rel {err:.2e} "
+              f"J rel {jerr:.2e}", flush=True)
+        assert err < 8 * ub and jerr < 8 * ub
+    pr.close()
