@@ -142,6 +142,21 @@ def test_invalid_arguments(bad):
     assert e.value.status == dlmpc.EINVAL
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_bf16"])
+def test_precision_values_accepted(precision):
+    wl = W.workload("chain10")
+    pr = _host(wl, precision=precision)
+    assert pr.precision == precision
+    pr.close()
+
+
+def test_unknown_precision_rejected(monkeypatch):
+    monkeypatch.setitem(dlmpc.PRECISIONS, "unknown", 3)
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        _host(W.workload("chain10"), precision="unknown")
+    assert e.value.status == dlmpc.EINVAL
+
+
 def test_host_only_problem_refuses_solve():
     wl = W.workload("chain10")
     pr = _host(wl)
