@@ -172,7 +172,7 @@ def test_bf16_operator_tier_error_report(name):
     assert n16 >= 60
     ub = 2.0 ** -8
     worst = [0.0, 0.0]
-    for i in range(0, 64, 9):
+    for i in range(0, 64, 21):  # four samples: each oracle solve takes seconds here
         ref = O.solve(pb, x0s[i], RHO, EPS, MAXIT)
         if not ref.converged or not s16[i]["converged"]:
             continue
