@@ -148,6 +148,8 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-launch timing of the batched kernels (for profiler runs)")
+    ap.add_argument("--kernels-precision", default="fp32", choices=["fp32", "fp32_bf16"],
+                    help="--kernels-only: split-operand kernels (fp32) or the reduced-operator tier")
     ap.add_argument("--setup-only", action="store_true",
                     help="only problem creation (device factorisation of the column blocks, engine layouts), "
                          "twice, for profiler runs")
@@ -195,11 +197,12 @@ def main() -> int:
             p.close()
         print(json.dumps({"workload": args.workload, "setup": rec}), flush=True)
         return 0
-    pr = make("fp32", B)
+    pr = make(args.kernels_precision if args.kernels_only else "fp32", B)
     if args.kernels_only:
         xk = torch.tensor(np.stack([wl.x0(1000 + i) for i in range(B)]), dtype=torch.float64, device=dev)
         ku = pr.time_batch_kernels(B, xk.data_ptr(), 20)
-        print(json.dumps({"kernels_us": ku, "instances": B, "timed_iterations": 20}), flush=True)
+        print(json.dumps({"kernels_us": ku, "instances": B, "timed_iterations": 20,
+                          "precision": args.kernels_precision}), flush=True)
         pr.close()
         return 0
 
