@@ -302,7 +302,7 @@ typedef struct {
 
 /* n independent instances of this network (any n >= 1) streamed through the batched engine's
  * max_batch slots, each from the learned start (needs the warm-start network): every
- * check_iters iterations (0: 4) the host reads the per-instance stop flags, writes u(0) of the
+ * check_iters iterations (0: 16) the host reads the per-instance stop flags, writes u(0) of the
  * instances that stopped to their rows of u0_dev, and once at least refill_min slots are free
  * (0: an eighth of the slots; or the last instances are waiting; or no slot is busy) starts the next
  * instances in them: network inference and simulation at once, then the CG steps and the start

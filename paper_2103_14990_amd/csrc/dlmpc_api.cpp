@@ -867,7 +867,10 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   const int Bm = p->beng->bmax(), Bs = std::min<int>(Bm, n);
   if (refill_min == 0) refill_min = std::max(1, Bs / 8);
   refill_min = std::min(refill_min, Bs);
-  const int K = check_iters > 0 ? check_iters : 4;
+  // Every check leaves the device idle for one host round trip (stop flags read, u(0) of the
+  // stopped instances written, joiners started): 16 iterations between checks measured faster
+  // than 2..12 or 32 on the 1024 mesh with 64 slots (the iterates do not depend on it).
+  const int K = check_iters > 0 ? check_iters : 16;
   if (!p->d_sy) API_HIP(hipMalloc(&p->d_sy, sizeof(float) * size_t(Bm) * R));
   std::string err;
   std::vector<int32_t> inst(Bs, -1);  // instance in each slot (-1: free)

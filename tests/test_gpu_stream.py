@@ -59,7 +59,7 @@ def _batched_reference(torch, pr, xd, B):
 
 @pytest.mark.parametrize("name,n,B,refill_min,check_iters", [
     ("grid8", 57, 16, 4, 3),       # many joins, a few slots at a time
-    ("grid8", 40, 16, 0, 0),       # defaults: half the slots, checks every 4 iterations
+    ("grid8", 40, 16, 0, 0),       # defaults: an eighth of the slots, checks every 16 iterations
     ("grid16_box", 37, 8, 2, 5),   # active bounds
     ("grid8", 5, 16, 0, 0),        # fewer instances than slots: one fill, no join
 ])
