@@ -69,6 +69,14 @@ def test_host_setup_matches_oracle(name):
     # null-space dimensions agree with the oracle's SVD rank
     ks = [len(b.rows) - b.rank for b in pb.blocks]
     assert pr.info["k_max"] == max(ks)
+    # the unit counts behind the kernels' algorithmic bytes: basis entries sum_j D_col(j) k_j,
+    # coordinates sum_j k_j and dense-projector entries sum_j D_col(j)^2, with k_j read off the
+    # oracle's projector as its trace (its rank, independent of the SVD rank count above)
+    kt = [int(round(float(np.trace(b.P)))) for b in pb.blocks]
+    assert kt == ks
+    assert pr.info["sum_k"] == sum(kt)
+    assert pr.info["sum_dcol_k"] == sum(len(b.rows) * k for b, k in zip(pb.blocks, kt))
+    assert pr.info["sum_dcol2"] == sum(len(b.rows) ** 2 for b in pb.blocks)
 
 
 @pytest.mark.parametrize("nx,nu,d,T,seed", [(1, 1, 1, 4, 0), (3, 2, 1, 3, 1), (2, 2, 2, 4, 2)])
