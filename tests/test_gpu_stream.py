@@ -22,12 +22,12 @@ def torch():
     return t
 
 
-def _trained(torch, name, max_batch, n_train=256, steps=300):
+def _trained(torch, name, max_batch, n_train=256, steps=300, precision="fp32", eps=EPS):
     """Problem with a warm-start network trained briefly on cold solves (the comparison holds
     for any weights; training only makes the starts realistic)."""
     wl = W.workload(name)
-    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=500,
-                                    precision="fp32", max_batch=max_batch, warm_cg_iters=CG)
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=eps, max_iter=500,
+                                    precision=precision, max_batch=max_batch, warm_cg_iters=CG)
     G, rs = wl.net.n_sub, wl.net.nx * wl.T + wl.net.nu * (wl.T - 1)
     xd = torch.tensor(np.stack([wl.x0(10**6 + i) for i in range(n_train)]), dtype=torch.float64, device="cuda")
     yd = torch.zeros((n_train, G * rs), dtype=torch.float64, device="cuda")
@@ -57,14 +57,15 @@ def _batched_reference(torch, pr, xd, B):
     return u, stats
 
 
-@pytest.mark.parametrize("name,n,B,refill_min,check_iters", [
-    ("grid8", 57, 16, 4, 3),       # many joins, a few slots at a time
-    ("grid8", 40, 16, 0, 0),       # defaults: an eighth of the slots, checks every 16 iterations
-    ("grid16_box", 37, 8, 2, 5),   # active bounds
-    ("grid8", 5, 16, 0, 0),        # fewer instances than slots: one fill, no join
+@pytest.mark.parametrize("name,n,B,refill_min,check_iters,precision", [
+    ("grid8", 57, 16, 4, 3, "fp32"),       # many joins, a few slots at a time
+    ("grid8", 40, 16, 0, 0, "fp32"),       # defaults: an eighth of the slots, checks every 16 iterations
+    ("grid16_box", 37, 8, 2, 5, "fp32"),   # active bounds
+    ("grid8", 5, 16, 0, 0, "fp32"),        # fewer instances than slots: one fill, no join
+    ("grid16_box", 37, 8, 2, 5, "fp32_bf16"),  # reduced-operator tier (eps 1e-3, above its floor)
 ])
-def test_stream_equals_batched_learned_solves(torch, name, n, B, refill_min, check_iters):
-    wl, pr = _trained(torch, name, B)
+def test_stream_equals_batched_learned_solves(torch, name, n, B, refill_min, check_iters, precision):
+    wl, pr = _trained(torch, name, B, precision=precision, eps=EPS if precision == "fp32" else 1e-3)
     x0s = np.stack([wl.x0(3000 + i) for i in range(n)])
     xd = torch.tensor(x0s, dtype=torch.float64, device="cuda")
     us = torch.zeros((n, pr.n_sub * pr.nu), dtype=torch.float64, device="cuda")
