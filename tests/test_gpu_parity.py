@@ -141,14 +141,16 @@ def test_deterministic(grid16_box):
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
-@pytest.mark.parametrize("nx,nu,T,seed", [(1, 1, 4, 0), (3, 2, 3, 1), (4, 1, 3, 3)])
-def test_generic_shapes_fp64(nx, nu, T, seed, schedule):
+# (nx > nu plants of this graph are not localisable at d = 1 for T = 3: the oracle finds no
+# solution of the ring equations, so those shapes run at d = 2)
+@pytest.mark.parametrize("nx,nu,d,T,seed", [(1, 1, 1, 4, 0), (3, 2, 2, 3, 1), (4, 1, 2, 3, 3)])
+def test_generic_shapes_fp64(nx, nu, d, T, seed, schedule):
     edges = np.array([(0, 1), (1, 2), (2, 3), (3, 4), (1, 4), (4, 5), (5, 6)])
     net = W.generic_network(7, edges, nx, nu, seed)
-    wl = W.Workload("generic", net, 1, T, W.unit_cost(net), sigma=1.0)
-    pb = O.setup_from_network(net, 1, T, wl.cost)
+    wl = W.Workload("generic", net, d, T, W.unit_cost(net), sigma=1.0)
+    pb = O.setup_from_network(net, d, T, wl.cost)
     if not pb.feasible:
-        pytest.skip("random plant not localisable at d = 1")
+        pytest.skip(f"random plant not localisable at d = {d}")
     case = Case(wl, schedule=schedule)
     x0 = wl.x0(7)
     ores = O.solve(case.pb, x0, RHO, EPS, MAXIT)
