@@ -208,3 +208,58 @@ def projection_by_kkt(H: np.ndarray, v: np.ndarray, e: np.ndarray) -> np.ndarray
     K = np.block([[np.eye(n), H.T], [H, np.zeros((m, m))]])
     sol = np.linalg.lstsq(K, np.concatenate([v, e]), rcond=None)[0]
     return sol[:n]
+
+
+def admm_entry_space(A, B, n_sub, nx, nu, d, T, w, x0, rho, n_iter, lb=None, ub=None):
+    """Algorithm 2 run a second way, to pin the oracle's iteration and its stopping rule.
+
+    The unknowns are the supported entries z of Phi (one vector over all columns, as in
+    ``dense_sls``); achievability is E z = f built by simulating the plant. Phi-comp solves
+    each row's problem min w (phi.x)^2 + (rho/2)||phi - v||^2 (lb <= phi.x <= ub) as linear
+    systems: the unconstrained stationarity system, and when its phi.x leaves the box the
+    equality-constrained KKT system with phi.x on the violated bound. Psi-comp is the
+    minimum-norm correction onto {E z = f} for all columns at once (pseudo-inverse of E),
+    not a per-column projector. Residuals are summed per column with ``np.bincount``.
+
+    Runs exactly ``n_iter`` iterations from Psi^0 = Lambda^0 = 0 and returns the per-iteration
+    per-column residuals (primal ||Phi - Psi||, dual ||Psi^{k+1} - Psi^k||), each
+    [n_iter, N_x], and the final (Phi, Psi, Lambda) entry vectors with ``var_rc``.
+    """
+    x0 = np.asarray(x0, float)
+    sls = dense_sls(A, B, n_sub, nx, nu, d, T, x0)
+    R, Nx = sls.R, n_sub * nx
+    rows, cols = sls.var_rc[:, 0], sls.var_rc[:, 1]
+    lb = np.full(R, -np.inf) if lb is None else np.asarray(lb, float)
+    ub = np.full(R, np.inf) if ub is None else np.asarray(ub, float)
+    w = np.asarray(w, float)
+    E_pinv = np.linalg.pinv(sls.E, rcond=1e-12)
+    by_row = [np.flatnonzero(rows == r) for r in range(R)]
+    nvar = len(rows)
+    psi, lam = np.zeros(nvar), np.zeros(nvar)
+    rp_hist, rd_hist = np.zeros((n_iter, Nx)), np.zeros((n_iter, Nx))
+    phi = np.zeros(nvar)
+    for k in range(n_iter):
+        v = psi - lam
+        phi = v.copy()
+        for r, idx in enumerate(by_row):
+            if idx.size == 0:
+                continue
+            x = x0[cols[idx]]
+            if not np.any(x):
+                continue  # the row cost vanishes: phi = v
+            n = idx.size
+            H = 2.0 * w[r] * np.outer(x, x) + rho * np.eye(n)
+            p = np.linalg.solve(H, rho * v[idx])
+            s = x @ p
+            bound = lb[r] if s < lb[r] else (ub[r] if s > ub[r] else None)
+            if bound is not None:  # min (rho/2)||phi - v||^2 + w bound^2 s.t. x.phi = bound
+                K = np.block([[rho * np.eye(n), x[:, None]], [x[None, :], np.zeros((1, 1))]])
+                p = np.linalg.solve(K, np.concatenate([rho * v[idx], [bound]]))[:n]
+            phi[idx] = p
+        u = phi + lam
+        psi_new = u - E_pinv @ (sls.E @ u - sls.f)
+        lam = lam + phi - psi_new
+        rp_hist[k] = np.sqrt(np.bincount(cols, weights=(phi - psi_new) ** 2, minlength=Nx))
+        rd_hist[k] = np.sqrt(np.bincount(cols, weights=(psi_new - psi) ** 2, minlength=Nx))
+        psi = psi_new
+    return rp_hist, rd_hist, (phi, psi, lam, sls.var_rc)

@@ -291,8 +291,12 @@ class Result:
 
 
 def solve(pb: Problem, x0: np.ndarray, rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500,
-          psi0: np.ndarray | None = None, lam0: np.ndarray | None = None) -> Result:
-    """Algorithm 2 from Psi^0 = psi0 (default 0) and Lambda^0 = lam0 (default 0)."""
+          psi0: np.ndarray | None = None, lam0: np.ndarray | None = None,
+          progress=None) -> Result:
+    """Algorithm 2 from Psi^0 = psi0 (default 0) and Lambda^0 = lam0 (default 0).
+
+    ``progress``, if given, is called as progress(k, r_primal, r_dual) after every iteration
+    (reporting only; it cannot change the iteration)."""
     R, Nx = pb.lay.R, pb.lay.Nx
     Psi = np.zeros((R, Nx)) if psi0 is None else np.array(psi0, dtype=np.float64)
     Lam = np.zeros((R, Nx)) if lam0 is None else np.array(lam0, dtype=np.float64)
@@ -307,6 +311,8 @@ def solve(pb: Problem, x0: np.ndarray, rho: float = 5.0, eps: float = 1e-4, max_
         Psi = Psi_new
         it += 1
         rp, rd = float(rpc.max()), float(rdc.max())
+        if progress is not None:
+            progress(it, rp, rd)
         if rp <= eps and rd <= eps:
             conv = True
             break

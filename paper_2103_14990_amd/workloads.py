@@ -268,7 +268,40 @@ class Workload:
     max_iter: int = 500
 
     def x0(self, seed: int) -> np.ndarray:
-        return x0(self.net, seed, self.sigma)
+        """sigma * z with z ~ N(0, I) from ``default_rng(seed)``; on a constrained workload a
+        draw whose uncontrollable first step leaves the box (see ``first_step_outside_box``)
+        is replaced by the next draw of the same generator, so every returned x0 passes that
+        check and a draw that passes is returned unchanged."""
+        if not self.cost.constrained:
+            return x0(self.net, seed, self.sigma)
+        rng = np.random.default_rng(seed)
+        for _ in range(1000):
+            v = self.sigma * rng.standard_normal(self.net.n_sub * self.net.nx)
+            if not first_step_outside_box(self.net, self.cost, v):
+                return v
+        raise RuntimeError(f"no x0 within the box after 1000 draws (seed {seed})")
+
+
+def first_step_outside_box(net: Network, cost: Cost, x: np.ndarray) -> bool:
+    """True if some state that no input reaches in one step (a zero row of B) leaves its bound
+    at t = 1: x_s(1) = (A x)_s for such a state whatever u(0) is, so the instance of eq. (MPC)
+    is infeasible. (On the swing plant this is theta_i(1) = theta_i(0) + dt omega_i(0).)"""
+    if cost.x_lo is None and cost.x_hi is None:
+        return False
+    nx = net.nx
+    for i in range(net.n_sub):
+        free = ~np.any(net.b_blocks[i] != 0, axis=1)  # states of i with no input
+        if not free.any():
+            continue
+        ax = np.zeros(nx)
+        for p in range(net.a_rowptr[i], net.a_rowptr[i + 1]):
+            j = int(net.a_colidx[p])
+            ax += net.a_blocks[p] @ x[j * nx:(j + 1) * nx]
+        lo = -np.inf if cost.x_lo is None else cost.x_lo[i * nx:(i + 1) * nx]
+        hi = np.inf if cost.x_hi is None else cost.x_hi[i * nx:(i + 1) * nx]
+        if np.any(free & ((ax < lo) | (ax > hi))):
+            return True
+    return False
 
 
 # Scale of x0 for the box-constrained workloads. With |theta| <= 0.8 and x0 ~ N(0, 1) the

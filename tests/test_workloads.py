@@ -46,3 +46,23 @@ def test_swing_plant_blocks():
     assert np.allclose(A[1::2, 0::2].sum(axis=1), 0.0)
     B = net.dense_B()
     assert np.allclose(B[1::2].diagonal(), dt) and np.all(B[0::2] == 0)
+
+
+def test_box_x0_first_step_inside_box():
+    """On the box-constrained workloads theta_i(1) = theta_i(0) + dt omega_i(0) is beyond any
+    input; every x0 the workloads hand out (bench, stored full-size values, held-out, training
+    seeds) keeps it inside the box, and a passing draw is returned unchanged."""
+    for name, seeds in (("irregular1024_box", list(range(1000, 1100)) + list(range(2000, 2200))
+                         + list(range(2280, 7400, 7)) + list(range(10**6, 10**6 + 300))),
+                        ("grid16_box", list(range(1000, 1100)) + list(range(2000, 2200)))):
+        wl = W.workload(name)
+        for s in seeds:
+            x = wl.x0(s)
+            assert not W.first_step_outside_box(wl.net, wl.cost, x), (name, s)
+            th1 = x[0::2] + W.DT * x[1::2]
+            assert np.abs(th1).max() <= 0.8
+    wl = W.workload("irregular1024_box")
+    raw = W.x0(wl.net, 4605, wl.sigma)  # the one draw of the bench range that leaves the box
+    assert W.first_step_outside_box(wl.net, wl.cost, raw)
+    assert not np.array_equal(wl.x0(4605), raw)
+    assert np.array_equal(wl.x0(1000), W.x0(wl.net, 1000, wl.sigma))
