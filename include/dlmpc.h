@@ -73,6 +73,8 @@ typedef enum {
                                             the solve with DLMPC_EDEVICE */
 #define DLMPC_FLAG_HOST_FACTOR 0x8u /* factor the column blocks with host threads instead of the
                                        device kernels (host-only problems always do) */
+#define DLMPC_FLAG_NO_CHECK 0x10u  /* skip the FP64 check of the stopping iterate that every solve
+                                      otherwise runs (stats kkt, eq_resid, u0_check are then 0) */
 
 /* Networked plant. G_(A,B) is read off the block sparsity of A: subsystems i != j are
  * adjacent iff block A_ij or A_ji is present in the block-CSR with a nonzero entry. Every
@@ -113,6 +115,13 @@ typedef struct {
   double factor_chol_tol; /* device factorisation: a Cholesky QR pivot of S K below this
                              fraction of the largest diagonal of (S K)'(S K) switches that
                              subsystem to the Householder QR (0: 1e-10; 1 or more: always) */
+  double warm_eps_scale; /* batched and streamed solves from a warm start (trajectory, learned,
+                            alpha) stop on the eps rule with eps * warm_eps_scale, in (0, 1]
+                            (0: 1/3). The eps rule bounds the residuals, not the distance to the
+                            optimum: from a warm start the stopping iterate was measured up to
+                            3x farther from the optimum than the cold start's at the same eps,
+                            and within the cold start's distance at eps/3. Cold runs, including
+                            the cold fallback of a warm-started instance, use eps. */
 } dlmpc_options;
 
 /* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
@@ -137,6 +146,20 @@ typedef struct {
   int32_t fell_back;      /* 1 if the warm-started run did not converge and the instance was
                              solved again from the cold start (iters then counts both runs) */
   double t_warm_ms;       /* device time of the warm-start network inference (learned start) */
+  /* FP64 check of the stopping iterate (recomputed on the device in double; skipped with
+   * DLMPC_FLAG_NO_CHECK). Single-instance solves: the certificate of dlmpc_certify, with
+   * eq_resid = its eq (max |Z_AB Psi - I|) and kkt = the largest of its rp, box and stat and of
+   * r_dual. Batched and streamed solves (compact state): the trajectory y = Phi x0 of the
+   * stopping iterate is recomputed in FP64 from the instance's state with the FP64 null bases and
+   * offsets; eq_resid = max |Z_AB y - [x0; 0; ...]| (initial state and dynamics of the returned
+   * trajectory), u0_check = max |u(0) returned - u(0) of that y| (the rounding of the reduced-
+   * precision iteration in u(0)), kkt = the largest of eq_resid, the bound violation of y,
+   * r_primal and r_dual. */
+  double kkt;
+  double eq_resid;
+  double u0_check;
+  double t_precompute_ms; /* device time of the per-solve precompute (Algorithm 1, with x0) */
+  double t_check_ms;      /* device time of the FP64 check (per instance share for streams) */
 } dlmpc_stats;
 
 typedef struct {

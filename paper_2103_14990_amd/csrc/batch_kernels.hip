@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
   for (int64_t i = a.koff[m] + tid; i < a.koff[m + 1]; i += 256) {
     a.tau[i * a.Bmax + b] = 0.f;
     a.eta[i * a.Bmax + b] = 0.f;
+    a.eta[(a.ktot + i) * a.Bmax + b] = 0.f;
   }
   if (m == 0 && tid == 0) {
     BCtl &ic = a.ictl[b];
@@ -518,6 +519,7 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
     if (tid == 0) a.pcnt[j] = 0;  // ready for the next launch
   }
   // eta_new, tau and the k-space residual terms; lane holds basis rows 4 (lane/16) + e of tile.
+  const int64_t eplane = a.ktot * a.Bmax;
   double e2[kNT], d2[kNT];
 #pragma unroll
   for (int nt = 0; nt < kNT; ++nt) e2[nt] = d2[nt] = 0.0;
@@ -534,6 +536,8 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
         const int i = mtile * 16 + 4 * (lane >> 4) + e;
         if (i >= k) continue;
         const int64_t ki = (a.koff[j] + i) * a.Bmax + b;  // instance-minor: lanes b coalesce
+        // eta planes by iteration parity: the current iterate's, and the previous one's
+        const int64_t kc = ki + (cur ? eplane : 0), kp = ki + (cur ? 0 : eplane);
         const int64_t wi = (((a.koff[j] + i) >> 3) * a.Bw + b) * 8 + (i & 7);
         const float xj = a.xn[int64_t(b) * a.N + j];
         const float en = acc[t][nt][e];
@@ -541,13 +545,14 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
         const int ph = initp ? -1 : a.phase[b];
         if (ph >= 0) {  // streamed join: the start's projections, as the set-up passes do them
           if (ph < a.ctl->cg_k) {
-            a.eta[ki] = en;
+            a.eta[kc] = en;
             wv = xj * en;
           } else if (ph == a.ctl->cg_k) {
             a.tau[ki] = en;
             continue;
-          } else {
-            a.eta[ki] = en;
+          } else {  // eta^0 into both planes: the joiner's first iteration may have either parity
+            a.eta[kc] = en;
+            a.eta[kp] = en;
             wv = xj * (a.tau[ki] + en);
           }
         } else if (initp) {
@@ -555,9 +560,9 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
           if (a.wmode == 0) continue;
           wv = xj * (a.wmode == 2 ? a.tau[ki] + en : en);
         } else {
-          const float eo = a.eta[ki];
+          const float eo = a.eta[kp];
           const float tn = a.tau[ki] + en;
-          a.eta[ki] = en;
+          a.eta[kc] = en;
           a.tau[ki] = tn;
           e2[nt] += double(en) * double(en);
           d2[nt] += double(en - eo) * double(en - eo);
@@ -687,6 +692,156 @@ __global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0, const
   for (int i = tid; i < a.N * a.nu; i += 256) {
     const int m = i / a.nu, q = i - m * a.nu;
     u0[orow * a.N * a.nu + i] = double(sb[(int64_t(m) * a.rs + NX * a.T + q) * a.Bmax]);
+  }
+}
+
+// ------------------------------------------------------------------ FP64 check of the stopping iterate
+
+// Trajectory y = Phi^{k+1} x0 of each instance recomputed in FP64 from its compact stopping
+// state (the FP32 values taken as exact): with g the global stopping iteration, alpha^{k+1} in
+// plane g & 1 and alpha^k in the other, eta likewise and tau = tau^{k+1}, row r of subsystem m
+//   a_r = c b_r + sum_{j in P(m)} ||x0_j||^2 [N_j (tau^k + eta^k)]_r - n_r alpha^k_r,
+//   tau^k = tau^{k+1} - eta^{k+1},  b_r = sum_{j in P(m)} sum_c x0_c o_c[r],
+//   y_r = a_r + n_r alpha^{k+1}_r   (the Phi-comp row value, Phi row = v + alpha x_r),
+// with the FP64 bases and offsets and c as in bphi_kernel. One block per row subsystem m;
+// thread (instance i of the slot list, row group lg) accumulates rows lg, lg + 8, ... of m.
+constexpr int kChkThreads = 512;
+constexpr int kChkRows = (64 + kChkThreads / 64 - 1) / (kChkThreads / 64);  // rs <= 64
+
+template <int NX>
+__global__ __launch_bounds__(kChkThreads) void bcheck_y_kernel(BArgs a, const double *x0, const int32_t *slots,
+                                                               const int32_t *xsrc, int S) {
+  const int m = blockIdx.x, tid = threadIdx.x, bi = tid & 63, lg = tid >> 6;
+  constexpr int kLG = kChkThreads / 64;
+  if (bi >= S) return;
+  const int b = slots ? slots[bi] : bi;
+  const double *xb = x0 + int64_t(xsrc ? xsrc[bi] : bi) * a.N * NX;
+  const int rs = a.rs;
+  const BCtl &ic = a.ictl[b];
+  const int g = ic.it0 + ic.iters;
+  const int cur = g & 1;
+  const bool warm = a.ctl->warm != 0;
+  const double coef = warm ? 1.0 : (g == 1 ? 0.0 : (g == 2 ? 2.0 : 1.0));
+  const bool use_w = warm || g >= 3;
+  const int64_t plane = int64_t(a.Bmax) * a.N * rs, eplane = a.ktot * a.Bmax;
+  const float *tau = a.tau + b;
+  const float *ec = a.eta + (cur ? eplane : 0) + b, *ep = a.eta + (cur ? 0 : eplane) + b;
+  double acc[kChkRows];
+#pragma unroll
+  for (int q = 0; q < kChkRows; ++q) acc[q] = 0.0;
+  double n_r = 0.0;
+  for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+    const int j = a.rt_col[q];
+    const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
+    const int ld = (D + 3) & ~3;
+    const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
+    double xj2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) xj2 += xb[j * NX + c] * xb[j * NX + c];
+    n_r += xj2;
+    const double *off = a.off64 + a.off_ptr[j] + ro;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const double xc = coef * xb[j * NX + c];
+#pragma unroll
+      for (int q2 = 0; q2 < kChkRows; ++q2) {
+        const int l = lg + kLG * q2;
+        if (l < rs) acc[q2] += xc * off[int64_t(c) * ld + l];
+      }
+    }
+    if (!use_w) continue;
+    const double *Nj = a.nb64 + a.nb_off[j] + ro;
+    const int64_t k0 = a.koff[j];
+    const int k = a.kdim[j];
+    for (int i = 0; i < k; ++i) {
+      const int64_t ki = (k0 + i) * a.Bmax;
+      const double w = xj2 * ((double(tau[ki]) - double(ec[ki])) + double(ep[ki]));
+      const double *col = Nj + int64_t(i) * ld;
+#pragma unroll
+      for (int q2 = 0; q2 < kChkRows; ++q2) {
+        const int l = lg + kLG * q2;
+        if (l < rs) acc[q2] += col[l] * w;
+      }
+    }
+  }
+  double *y = a.y64 + int64_t(b) * a.N * rs + int64_t(m) * rs;
+#pragma unroll
+  for (int q2 = 0; q2 < kChkRows; ++q2) {
+    const int l = lg + kLG * q2;
+    if (l >= rs) continue;
+    const int64_t rb = (int64_t(m) * rs + l) * a.Bmax + b;
+    const double apv = a.alpha[(cur ? 0 : plane) + rb], acv = a.alpha[(cur ? plane : 0) + rb];
+    y[l] = (acc[q2] - n_r * apv) + n_r * acv;
+  }
+}
+
+// Per instance from y64: largest |x_0 - x0| and |x_{t+1} - A x_t - B u_t| (Z_AB y - [x0; 0]),
+// largest bound violation, largest |u(0) returned (the FP32 row values) - u(0) of y64|, and
+// sum_r w_r y_r^2. One block per instance.
+template <int NX>
+__global__ __launch_bounds__(256) void bcheck_red_kernel(BArgs a, const double *x0, const int32_t *slots,
+                                                         const int32_t *xsrc, int S) {
+  __shared__ double r_eq[4], r_box[4], r_u[4], r_j[4];
+  const int bi = blockIdx.x, tid = threadIdx.x;
+  const int b = slots ? slots[bi] : bi;
+  const double *xb = x0 + int64_t(xsrc ? xsrc[bi] : bi) * a.N * NX;
+  const int rs = a.rs, nu = a.nu, T = a.T;
+  const double *y = a.y64 + int64_t(b) * a.N * rs;
+  double eq = 0.0, box = 0.0, ud = 0.0, jv = 0.0;
+  for (int m = tid; m < a.N; m += 256) {
+    const double *ym = y + int64_t(m) * rs;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) eq = fmax(eq, fabs(ym[c] - xb[m * NX + c]));
+    for (int t = 0; t + 1 < T; ++t) {
+      double v[NX];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v[c] = ym[(t + 1) * NX + c];
+      for (int64_t q = a.a_rowptr[m]; q < a.a_rowptr[m + 1]; ++q) {
+        const double *blk = a.a64 + q * NX * NX;
+        const double *xj = y + int64_t(a.a_colidx[q]) * rs + t * NX;
+#pragma unroll
+        for (int c = 0; c < NX; ++c)
+#pragma unroll
+          for (int c2 = 0; c2 < NX; ++c2) v[c] -= blk[c * NX + c2] * xj[c2];
+      }
+      const double *bb = a.b64 + int64_t(m) * NX * nu;
+      for (int q = 0; q < nu; ++q)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) v[c] -= bb[c * nu + q] * ym[NX * T + t * nu + q];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) eq = fmax(eq, fabs(v[c]));
+    }
+    for (int l = 0; l < rs; ++l) {
+      const int64_t o = int64_t(m) * rs + l;
+      const double yv = ym[l];
+      box = fmax(box, fmax(a.lb64[o] - yv, yv - a.ub64[o]));
+      jv += a.w64[o] * yv * yv;
+    }
+    for (int q = 0; q < nu; ++q) {
+      const int64_t o = int64_t(m) * rs + NX * T + q;
+      ud = fmax(ud, fabs(double(a.s[o * a.Bmax + b]) - ym[NX * T + q]));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    eq = fmax(eq, __shfl_xor(eq, o, 64));
+    box = fmax(box, __shfl_xor(box, o, 64));
+    ud = fmax(ud, __shfl_xor(ud, o, 64));
+    jv += __shfl_xor(jv, o, 64);
+  }
+  if ((tid & 63) == 0) {
+    r_eq[tid >> 6] = eq;
+    r_box[tid >> 6] = box;
+    r_u[tid >> 6] = ud;
+    r_j[tid >> 6] = jv;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    BCtl &ic = a.ictl[b];
+    ic.eq_resid = fmax(fmax(r_eq[0], r_eq[1]), fmax(r_eq[2], r_eq[3]));
+    ic.box = fmax(0.0, fmax(fmax(r_box[0], r_box[1]), fmax(r_box[2], r_box[3])));
+    ic.u0dev = fmax(fmax(r_u[0], r_u[1]), fmax(r_u[2], r_u[3]));
+    ic.objective64 = (r_j[0] + r_j[1]) + (r_j[2] + r_j[3]);
   }
 }
 
@@ -1046,7 +1201,7 @@ class BatchEngineT final : public BatchEngine {
       return rc;
     const size_t ny = size_t(N) * hs.rs;
     if ((rc = al(&a.alpha, 2 * size_t(bmax) * ny, err)) || (rc = al(&a.tau, size_t(bmax) * a.ktot, err)) ||
-        (rc = al(&a.eta, size_t(bmax) * a.ktot, err)) || (rc = al(&a.xn, size_t(bmax) * N, err)) ||
+        (rc = al(&a.eta, 2 * size_t(bmax) * a.ktot, err)) || (rc = al(&a.xn, size_t(bmax) * N, err)) ||
         (rc = al(&a.nrm, size_t(bmax) * N, err)) || (rc = al(&a.bvec, size_t(bmax) * ny, err)) ||
         (rc = al(&a.s, size_t(bmax) * ny, err)) || (rc = al(&a.x0, size_t(bmax) * N * NX, err)) ||
         (rc = al(&a.ictl, size_t(bmax), err)) || (rc = al(&a.slot, 2 * size_t(bmax), err)) ||
@@ -1076,6 +1231,26 @@ class BatchEngineT final : public BatchEngine {
     std::vector<float> ablk(hs.a_blocks.begin(), hs.a_blocks.end()), bblk(hs.b_blocks.begin(), hs.b_blocks.end());
     if ((rc = up(hs.a_rowptr, &a.a_rowptr, err)) || (rc = up(hs.a_colidx, &a.a_colidx, err)) ||
         (rc = up(ablk, &a.a_blk, err)) || (rc = up(bblk, &a.b_blk, err)))
+      return rc;
+    // FP64 check of the stopping iterate: bases (the device factorisation's, or uploaded),
+    // offsets, bounds, plant blocks, trajectory scratch
+    if (hs.d_nb) {
+      a.nb64 = hs.d_nb;
+    } else {
+      double *d = nullptr;
+      if ((rc = al(&d, hs.nb.size(), err))) return rc;
+      if (!hs.nb.empty()) BENG_CHECK(hipMemcpy(d, hs.nb.data(), hs.nb.size() * sizeof(double), hipMemcpyHostToDevice));
+      a.nb64 = d;
+    }
+    {
+      double *d = nullptr;
+      if ((rc = al(&d, hs.off.size(), err))) return rc;
+      if (!hs.off.empty()) BENG_CHECK(hipMemcpy(d, hs.off.data(), hs.off.size() * sizeof(double), hipMemcpyHostToDevice));
+      a.off64 = d;
+    }
+    if ((rc = up(hs.nb_off, &a.nb_off, err)) || (rc = up(hs.lb, &a.lb64, err)) || (rc = up(hs.ub, &a.ub64, err)) ||
+        (rc = up(hs.a_blocks, &a.a64, err)) || (rc = up(hs.b_blocks, &a.b64, err)) ||
+        (rc = al(&a.y64, size_t(bmax) * ny, err)))
       return rc;
     a.init_pass = 0;
     a.wmode = 0;
@@ -1248,6 +1423,30 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
+  int check(const double *x0_dev, std::string &err) override {
+    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(kChkThreads), 0, stream_, args_, x0_dev, nullptr,
+                       nullptr, B_);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
+                       B_);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int check_slots(const double *x0_dev, int S, std::string &err) override {
+    if (S < 1 || S > int(st_oslots_.size())) {
+      err = "check_slots: slot count out of range";
+      return DLMPC_EINVAL;
+    }
+    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(kChkThreads), 0, stream_, args_, x0_dev,
+                       d_oslots_, d_odst_, S);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, x0_dev, d_oslots_, d_odst_,
+                       S);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
   Ctl *ctl() override { return args_.ctl; }
   BCtl *ictl() override { return args_.ictl; }
   int bmax() const override { return args_.Bmax; }
@@ -1325,7 +1524,27 @@ class BatchEngineT final : public BatchEngine {
   std::vector<void *> owned_;
 };
 
+// flag[0] = 1 if some entry of x[0..n) is NaN or +-Inf (flag cleared by the caller).
+__global__ __launch_bounds__(256) void finite_kernel(const double *__restrict__ x, int64_t n, int32_t *flag) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    if (!isfinite(x[i])) flag[0] = 1;
+}
+
 }  // namespace
+
+int device_all_finite(const double *x_dev, int64_t n, int32_t *flag_dev, int32_t *flag_host, hipStream_t s,
+                      bool *ok, std::string &err) {
+  BENG_CHECK(hipMemsetAsync(flag_dev, 0, sizeof(int32_t), s));
+  const int grid = int(std::min<int64_t>(1024, (n + 255) / 256));
+  if (n > 0) {
+    hipLaunchKernelGGL(finite_kernel, dim3(std::max(grid, 1)), dim3(256), 0, s, x_dev, n, flag_dev);
+    BENG_CHECK(hipGetLastError());
+  }
+  BENG_CHECK(hipMemcpyAsync(flag_host, flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BENG_CHECK(hipStreamSynchronize(s));
+  *ok = flag_host[0] == 0;
+  return DLMPC_OK;
+}
 
 std::unique_ptr<BatchEngine> make_batch_engine(int nx) {
   switch (nx) {

@@ -46,7 +46,11 @@ struct dlmpc_problem {
   double *d_fx0 = nullptr, *d_fu0 = nullptr, *d_falpha = nullptr, *d_fy = nullptr;
   int cg_iters = 12;
   hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
-  float *d_sy = nullptr;  // streamed solves: predicted trajectories of the joining instances [Bmax][R]
+  float *d_sy = nullptr;
+  // per-solve precompute and FP64 check timing; device finiteness flag of x0 (device entries)
+  hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr, ev_c0 = nullptr, ev_c1 = nullptr;
+  int32_t *d_flag = nullptr, *h_flag = nullptr;
+  double warm_eps = 1e-4;  // eps of warm-started batched and streamed runs  // streamed solves: predicted trajectories of the joining instances [Bmax][R]
 };
 
 namespace {
@@ -95,8 +99,12 @@ void release_device(dlmpc_problem *p) {
   p->beng.reset();
   p->h_bctl = nullptr;
   p->d_bx0 = p->d_bu0 = nullptr;
-  for (hipEvent_t e : {p->ev_ctl[0], p->ev_ctl[1], p->ev_t0, p->ev_t1})
+  for (hipEvent_t e : {p->ev_ctl[0], p->ev_ctl[1], p->ev_t0, p->ev_t1, p->ev_p0, p->ev_p1, p->ev_c0, p->ev_c1})
     if (e) (void)hipEventDestroy(e);
+  p->ev_p0 = p->ev_p1 = p->ev_c0 = p->ev_c1 = nullptr;
+  if (p->d_flag) (void)hipFree(p->d_flag);
+  if (p->h_flag) (void)hipHostFree(p->h_flag);
+  p->d_flag = p->h_flag = nullptr;
   if (p->h_ctl) (void)hipHostFree(p->h_ctl);
   for (double *d : {p->d_x0, p->d_u0, p->d_phi, p->d_warm})
     if (d) (void)hipFree(d);
@@ -136,6 +144,9 @@ int setup_device(dlmpc_problem *p) {
   for (auto *e : {&p->ev_ctl[0], &p->ev_ctl[1]}) API_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   API_HIP(hipEventCreate(&p->ev_t0));
   API_HIP(hipEventCreate(&p->ev_t1));
+  for (auto *e : {&p->ev_p0, &p->ev_p1, &p->ev_c0, &p->ev_c1}) API_HIP(hipEventCreate(e));
+  API_HIP(hipMalloc(&p->d_flag, sizeof(int32_t)));
+  API_HIP(hipHostMalloc(reinterpret_cast<void **>(&p->h_flag), sizeof(int32_t), hipHostMallocDefault));
   // Iteration graphs of 2^g iterations; every launch after the device-side stop is a no-op.
   p->K = p->opt.check_every > 0 ? std::min(p->opt.check_every, p->opt.max_iter) : 32;
   for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
@@ -319,8 +330,10 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
               double *u0_dev, double *phi_dev, dlmpc_stats *stats, double t_host0_ms) {
   std::string err;
   const int max_iter = p->opt.max_iter;
+  API_HIP(hipEventRecord(p->ev_p0, p->stream));
   int rc = p->eng->precompute(x0_dev, wpsi, wlam, max_iter, p->opt.eps, err);
   if (rc) return fail(rc, err);
+  API_HIP(hipEventRecord(p->ev_p1, p->stream));
   API_HIP(hipEventRecord(p->ev_t0, p->stream));
   int launched = 0, launches = 0;
   bool stopped = false;
@@ -365,9 +378,26 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
   API_HIP(hipMemcpyAsync(&p->h_ctl[0], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
   API_HIP(hipStreamSynchronize(p->stream));
   const Ctl &c = p->h_ctl[0];
+  // FP64 certificate of the stopping iterate (synchronises)
+  double cert[5] = {0, 0, 0, 0, 0};
+  float mc = 0.f;
+  if (!(p->opt.flags & DLMPC_FLAG_NO_CHECK) && !c.bar_fail) {
+    API_HIP(hipEventRecord(p->ev_c0, p->stream));
+    rc = p->eng->certify(x0_dev, cert, err);
+    if (rc) return fail(rc, err);
+    API_HIP(hipEventRecord(p->ev_c1, p->stream));
+    API_HIP(hipEventSynchronize(p->ev_c1));
+    (void)hipEventElapsedTime(&mc, p->ev_c0, p->ev_c1);
+  }
   if (stats) {
-    float ms = 0.f;
+    float ms = 0.f, mp = 0.f;
     (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
+    (void)hipEventElapsedTime(&mp, p->ev_p0, p->ev_p1);
+    stats->eq_resid = cert[0];
+    stats->kkt = std::max(std::max(cert[2], cert[3]), std::max(cert[4], double(c.last_rd)));
+    stats->u0_check = 0.0;
+    stats->t_precompute_ms = mp;
+    stats->t_check_ms = mc;
     stats->iters = c.iters;
     stats->converged = c.converged;
     stats->r_primal = c.last_rp;
@@ -390,6 +420,15 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// n initial states on the device (x0_dev [n][N*nx]) must be finite: DLMPC_EINVAL otherwise.
+int check_x0_device(dlmpc_problem *p, const double *x0_dev, int64_t n) {
+  std::string err;
+  bool ok = false;
+  const int rc = dlmpc::device_all_finite(x0_dev, n * p->hs.N * p->hs.nx, p->d_flag, p->h_flag, p->stream, &ok, err);
+  if (rc) return fail(rc, err);
+  return ok ? DLMPC_OK : fail(DLMPC_EINVAL, "x0 has a NaN/Inf entry");
 }
 
 }  // namespace
@@ -426,8 +465,12 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
     return fail(DLMPC_EINVAL, "unknown precision");
   if (o.max_batch < 0 || o.max_batch > 64) return fail(DLMPC_EINVAL, "max_batch must be in 0..64");
   if (!(o.factor_chol_tol >= 0.0)) return fail(DLMPC_EINVAL, "factor_chol_tol must be >= 0");
+  if (o.warm_eps_scale == 0.0) o.warm_eps_scale = 1.0 / 3.0;
+  if (!(o.warm_eps_scale > 0.0 && o.warm_eps_scale <= 1.0))
+    return fail(DLMPC_EINVAL, "warm_eps_scale must be in (0, 1]");
   auto p = std::make_unique<dlmpc_problem>();
   p->opt = o;
+  p->warm_eps = o.eps * o.warm_eps_scale;
   p->host_only = (o.flags & DLMPC_FLAG_HOST_ONLY) != 0;
   std::string err;
   const auto t_setup = std::chrono::steady_clock::now();
@@ -565,6 +608,8 @@ int dlmpc_solve_device(dlmpc_problem *p, const double *x0_dev, double *u0_dev, d
   if (!p || !x0_dev || !u0_dev) return fail(DLMPC_EINVAL, "NULL argument");
   if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
   API_HIP(hipSetDevice(p->opt.device));
+  int rc = check_x0_device(p, x0_dev, 1);
+  if (rc) return rc;
   return run_solve(p, x0_dev, nullptr, nullptr, u0_dev, phi_dev, stats, t0);
 }
 
@@ -663,14 +708,21 @@ namespace {
 // y_out_dev / alpha_out_dev (or NULL) get the stopping trajectories and multipliers.
 // *t_warm_ms is the device time of the start construction. Returns DLMPC_OK or a negative
 // status (per-instance outcomes are left to the caller).
+// Device times of a batched run (ms): iteration phase, start construction, precompute, FP64 check.
+struct RunTimes {
+  float iter = 0.f, warm = 0.f, pre = 0.f, check = 0.f;
+};
+
 int run_batch_once(dlmpc_problem *p, int B, const double *x0_dev, int start, const double *start_dev,
-                   double *u0_dev, double *y_out_dev, double *alpha_out_dev, float *t_iter_ms, float *t_warm_ms,
-                   int *checks_out) {
+                   double *u0_dev, double *y_out_dev, double *alpha_out_dev, RunTimes *times, int *checks_out) {
   std::string err;
   const int max_iter = p->opt.max_iter;
   const HostSetup &h = p->hs;
-  int rc = p->beng->precompute(x0_dev, B, max_iter, p->opt.eps, start != DLMPC_START_COLD ? 1 : 0, err);
+  const double eps = start != DLMPC_START_COLD ? p->warm_eps : p->opt.eps;
+  API_HIP(hipEventRecord(p->ev_p0, p->stream));
+  int rc = p->beng->precompute(x0_dev, B, max_iter, eps, start != DLMPC_START_COLD ? 1 : 0, err);
   if (rc) return fail(rc, err);
+  API_HIP(hipEventRecord(p->ev_p1, p->stream));
   API_HIP(hipEventRecord(p->ev_w0, p->stream));
   if (start == DLMPC_START_ALPHA) {
     rc = p->beng->start_alpha(start_dev, err);
@@ -706,7 +758,7 @@ int run_batch_once(dlmpc_problem *p, int B, const double *x0_dev, int start, con
       break;
     }
     if (launched >= max_iter) break;
-    n = p->opt.check_every > 0 ? p->K : pred.next(c.iters, c.last_rp, c.last_rd, p->opt.eps);
+    n = p->opt.check_every > 0 ? p->K : pred.next(c.iters, c.last_rp, c.last_rd, eps);
   }
   if (!stopped) return fail(DLMPC_EDEVICE, "batched iteration did not reach its stop condition");
   API_HIP(hipEventRecord(p->ev_t1, p->stream));
@@ -714,18 +766,29 @@ int run_batch_once(dlmpc_problem *p, int B, const double *x0_dev, int start, con
   if (!rc && alpha_out_dev) rc = p->beng->export_alpha(alpha_out_dev, err);
   if (!rc && y_out_dev) rc = p->beng->export_y(y_out_dev, err);
   if (rc) return fail(rc, err);
+  const bool check = !(p->opt.flags & DLMPC_FLAG_NO_CHECK);
+  API_HIP(hipEventRecord(p->ev_c0, p->stream));
+  if (check && (rc = p->beng->check(x0_dev, err))) return fail(rc, err);
+  API_HIP(hipEventRecord(p->ev_c1, p->stream));
   API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * B, hipMemcpyDeviceToHost, p->stream));
   API_HIP(hipStreamSynchronize(p->stream));
-  float ms = 0.f, mw = 0.f;
+  float ms = 0.f, mw = 0.f, mp = 0.f, mc = 0.f;
   (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
   (void)hipEventElapsedTime(&mw, p->ev_w0, p->ev_w1);
-  *t_iter_ms = ms;
-  *t_warm_ms = start == DLMPC_START_COLD ? 0.f : mw;
+  (void)hipEventElapsedTime(&mp, p->ev_p0, p->ev_p1);
+  (void)hipEventElapsedTime(&mc, p->ev_c0, p->ev_c1);
+  times->iter = ms;
+  times->warm = start == DLMPC_START_COLD ? 0.f : mw;
+  times->pre = mp;
+  times->check = check ? mc : 0.f;
   *checks_out = checks;
   return DLMPC_OK;
 }
 
 void fill_stats(dlmpc_stats &st, const dlmpc::BCtl &ic, float ms, int checks, int start, double t0) {
+  st.eq_resid = ic.eq_resid;
+  st.u0_check = ic.u0dev;
+  st.kkt = std::max(std::max(ic.eq_resid, ic.box), std::max(ic.last_rp, ic.last_rd));
   st.iters = ic.iters;
   st.converged = ic.converged;
   st.r_primal = ic.last_rp;
@@ -746,10 +809,11 @@ int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, int
               double *y_out_dev, double *alpha_out_dev, dlmpc_stats *stats, double t0) {
   const HostSetup &h = p->hs;
   const size_t nxs = size_t(h.N) * h.nx, nus = size_t(h.N) * h.nu, R = size_t(h.N) * h.rs;
-  float ms = 0.f, mw = 0.f;
+  RunTimes tm;
   int checks = 0;
-  int rc = run_batch_once(p, B, x0_dev, start, start_dev, u0_dev, y_out_dev, alpha_out_dev, &ms, &mw, &checks);
+  int rc = run_batch_once(p, B, x0_dev, start, start_dev, u0_dev, y_out_dev, alpha_out_dev, &tm, &checks);
   if (rc) return rc;
+  const float ms = tm.iter, mw = tm.warm;
   std::vector<dlmpc::BCtl> first(p->h_bctl, p->h_bctl + B);
   std::vector<int> redo;
   for (int b = 0; b < B; ++b)
@@ -762,11 +826,14 @@ int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, int
     for (int f = 0; f < F; ++f)
       API_HIP(hipMemcpyAsync(p->d_fx0 + f * nxs, x0_dev + redo[f] * nxs, nxs * sizeof(double),
                              hipMemcpyDeviceToDevice, p->stream));
-    float ms2 = 0.f, mw2 = 0.f;
+    RunTimes tm2;
     int checks2 = 0;
     rc = run_batch_once(p, F, p->d_fx0, DLMPC_START_COLD, nullptr, p->d_fu0, y_out_dev ? p->d_fy : nullptr,
-                        alpha_out_dev ? p->d_falpha : nullptr, &ms2, &mw2, &checks2);
+                        alpha_out_dev ? p->d_falpha : nullptr, &tm2, &checks2);
     if (rc) return rc;
+    const float ms2 = tm2.iter;
+    tm.pre += tm2.pre;
+    tm.check += tm2.check;
     for (int f = 0; f < F; ++f) {
       const int b = redo[f];
       API_HIP(hipMemcpyAsync(u0_dev + b * nus, p->d_fu0 + f * nus, nus * sizeof(double), hipMemcpyDeviceToDevice,
@@ -793,6 +860,8 @@ int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, int
     numeric = numeric || first[b].numeric;
     if (stats) {
       stats[b].t_warm_ms = mw;
+      stats[b].t_precompute_ms = tm.pre;
+      stats[b].t_check_ms = tm.check;
       stats[b].t_solve_ms = now_ms() - t0;
     }
   }
@@ -833,6 +902,7 @@ int dlmpc_solve_batch_device(dlmpc_problem *p, int32_t B, const double *x0_dev, 
   if (rc) return rc;
   if (!x0_dev || !u0_dev) return fail(DLMPC_EINVAL, "NULL argument");
   API_HIP(hipSetDevice(p->opt.device));
+  if ((rc = check_x0_device(p, x0_dev, B))) return rc;
   return run_batch(p, B, x0_dev, u0_dev, DLMPC_START_COLD, nullptr, nullptr, nullptr, stats, t0);
 }
 
@@ -850,6 +920,7 @@ int dlmpc_solve_batch_ex(dlmpc_problem *p, int32_t B, const double *x0_dev, doub
   if (start == DLMPC_START_LEARNED && !p->ws)
     return fail(DLMPC_EINVAL, "no warm-start network (dlmpc_ws_init or dlmpc_warmstart_load)");
   API_HIP(hipSetDevice(p->opt.device));
+  if ((rc = check_x0_device(p, x0_dev, B))) return rc;
   return run_batch(p, B, x0_dev, u0_dev, start, start_dev, y_out_dev, alpha_out_dev, stats, t0);
 }
 
@@ -862,6 +933,9 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   if (!p->ws) return fail(DLMPC_EINVAL, "no warm-start network (dlmpc_ws_init or dlmpc_warmstart_load)");
   if (check_iters < 0 || refill_min < 0) return fail(DLMPC_EINVAL, "refill_min and check_iters must be >= 0");
   API_HIP(hipSetDevice(p->opt.device));
+  if ((rc = check_x0_device(p, x0_dev, n))) return rc;
+  const bool check = !(p->opt.flags & DLMPC_FLAG_NO_CHECK);
+  double t_check = 0.0, t_pre = 0.0;  // device ms over the whole stream
   const HostSetup &h = p->hs;
   const size_t nxs = size_t(h.N) * h.nx, nus = size_t(h.N) * h.nu, R = size_t(h.N) * h.rs;
   const int Bm = p->beng->bmax(), Bs = std::min<int>(Bm, n);
@@ -888,7 +962,7 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
       if (r) return fail(r, err);
     }
     const int r = p->beng->stream_start(x0_dev, slots.data(), xsrc.data(), S, p->d_sy, p->cg_iters, first,
-                                        p->opt.max_iter, p->opt.eps, err);
+                                        p->opt.max_iter, p->warm_eps, err);
     if (r) return fail(r, err);
     for (int i = 0; i < S; ++i) inst[slots[i]] = next + i;
     next += S;
@@ -926,8 +1000,18 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
     if (!done_s.empty()) {
       if ((rc = p->beng->output_slots(u0_dev, done_s.data(), done_i.data(), int(done_s.size()), err)))
         return fail(rc, err);
+      if (check) {
+        API_HIP(hipEventRecord(p->ev_c0, p->stream));
+        if ((rc = p->beng->check_slots(x0_dev, int(done_s.size()), err))) return fail(rc, err);
+        API_HIP(hipEventRecord(p->ev_c1, p->stream));
+      }
       API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
       API_HIP(hipStreamSynchronize(p->stream));
+      if (check) {
+        float mc = 0.f;
+        (void)hipEventElapsedTime(&mc, p->ev_c0, p->ev_c1);
+        t_check += mc;
+      }
       for (size_t q = 0; q < done_s.size(); ++q) {
         fin[done_i[q]] = p->h_bctl[done_s[q]];
         inst[done_s[q]] = -1;
@@ -958,10 +1042,13 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
     for (int f = 0; f < F; ++f)
       API_HIP(hipMemcpyAsync(p->d_fx0 + f * nxs, x0_dev + size_t(redo[r0 + f]) * nxs, nxs * sizeof(double),
                              hipMemcpyDeviceToDevice, p->stream));
-    float ms2 = 0.f, mw2 = 0.f;
+    RunTimes tm2;
     int checks2 = 0;
-    rc = run_batch_once(p, F, p->d_fx0, DLMPC_START_COLD, nullptr, p->d_fu0, nullptr, nullptr, &ms2, &mw2, &checks2);
+    rc = run_batch_once(p, F, p->d_fx0, DLMPC_START_COLD, nullptr, p->d_fu0, nullptr, nullptr, &tm2, &checks2);
     if (rc) return rc;
+    const float ms2 = tm2.iter;
+    t_check += tm2.check;
+    t_pre += tm2.pre;
     for (int f = 0; f < F; ++f) {
       const int i = redo[r0 + f];
       API_HIP(hipMemcpyAsync(u0_dev + size_t(i) * nus, p->d_fu0 + f * nus, nus * sizeof(double),
@@ -987,7 +1074,16 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
     info->t_stream_ms = ms;
   }
   int conv = 0;
-  for (int i = 0; i < n; ++i) conv += fin[i].converged;
+  bool numeric = false;
+  for (int i = 0; i < n; ++i) {
+    conv += fin[i].converged;
+    numeric = numeric || fin[i].numeric;
+    if (stats) {
+      stats[i].t_check_ms = t_check / n;
+      stats[i].t_precompute_ms = t_pre / n;
+    }
+  }
+  if (numeric) return fail(DLMPC_ENUMERIC, "NaN/Inf in a streamed ADMM iterate (also after the cold fallback)");
   return conv == n ? DLMPC_OK : DLMPC_ENOCONV;
 }
 
@@ -1275,6 +1371,7 @@ int dlmpc_group_solve_batch(dlmpc_group *g, const int32_t *B, const double *cons
     API_HIP(hipStreamWaitEvent(q->stream, g->ev_done, 0));
     int rc = q->beng->output(u0_dev[i], err);
     if (rc) return fail(rc, err);
+    if (!(q->opt.flags & DLMPC_FLAG_NO_CHECK) && (rc = q->beng->check(x0_dev[i], err))) return fail(rc, err);
     API_HIP(hipMemcpyAsync(q->h_bctl, q->beng->ictl(), sizeof(dlmpc::BCtl) * B[i], hipMemcpyDeviceToHost, q->stream));
     API_HIP(hipStreamSynchronize(q->stream));
     if (i == 0) (void)hipEventElapsedTime(&ms, g->ev_t0, g->ev_t1);

@@ -115,6 +115,10 @@ struct BCtl {  // per-instance control block
   int32_t iters, stop, converged, numeric;
   int32_t it0, pad;  // global iteration count when the instance entered its slot
   double last_rp, last_rd, objective;
+  // FP64 check of the stopping iterate (bcheck kernels): trajectory y = Phi x0 recomputed in FP64
+  // from the compact state; largest |Z_AB y - [x0; 0]| (dynamics and initial state), largest
+  // bound violation of y, largest |u(0) returned - u(0) of y|, sum_r w_r y_r^2
+  double eq_resid, box, u0dev, objective64;
 };
 
 struct BArgs {
@@ -143,7 +147,8 @@ struct BArgs {
   const double *w64;
   const double *onorm2;     // [N*nx] ||o_c||^2
   float *alpha;             // [2][N*rs][Bmax] (iteration parity; instance index fastest)
-  float *tau, *eta;         // [Ktot][Bmax] (instance index fastest)
+  float *tau;               // [Ktot][Bmax] (instance index fastest)
+  float *eta;               // [2][Ktot][Bmax] (iteration parity, as alpha)
   float *xn, *nrm;          // [Bmax][N] ||x0_j||^2 and ||x_r||^2 of row subsystem m
   float *bvec, *s;          // [N*rs][Bmax]
   float *x0;                // [Bmax][N*nx]
@@ -177,6 +182,12 @@ struct BArgs {
   const int64_t *a_rowptr;
   const int32_t *a_colidx;
   const float *a_blk, *b_blk;  // plant blocks (row-major nx x nx, nx x nu)
+  // FP64 check of the stopping iterate: null bases (column-major, leading dimension D rounded
+  // up to 4, at nb64 + nb_off[j]), offsets, bounds, plant blocks, and the recomputed
+  // trajectories y64 [Bmax][N*rs]
+  const double *nb64, *off64, *lb64, *ub64, *a64, *b64;
+  const int64_t *nb_off;
+  double *y64;
 };
 
 class BatchEngine {
@@ -205,6 +216,13 @@ class BatchEngine {
   // One kernel of an iteration: 0 bphi_kernel, 1 bpsi_kernel, 2 bdecide_kernel.
   virtual int launch_one(int k, std::string &err) = 0;
   virtual int output(double *u0_dev, std::string &err) = 0;
+  // FP64 check of the stopping iterate of every instance of the batch (x0_dev [B][N*nx], the
+  // solve's FP64 initial states): results in the per-instance control blocks (BCtl eq_resid,
+  // box, u0dev, objective64).
+  virtual int check(const double *x0_dev, std::string &err) = 0;
+  // The same for the slots of the latest output_slots call (instance dst[i] of x0_dev in
+  // slot slots[i]).
+  virtual int check_slots(const double *x0_dev, int S, std::string &err) = 0;
   // Streamed solves (warm starts only). Slots slots[0..S) take the instances xsrc[0..S) of
   // x0_dev ([*][N*nx]); their input-row predictions are ypred [S][N*rs] (FP32, device). first:
   // the initial fill (resets the solve, batch = S, slots 0..S-1); otherwise the slots join the
@@ -221,6 +239,11 @@ class BatchEngine {
 };
 
 std::unique_ptr<BatchEngine> make_batch_engine(int nx);
+
+// *ok = every entry of x_dev[0..n) is finite (device check on stream s, synchronised; flag_dev
+// one device int, flag_host one pinned host int). Returns a DLMPC_* status.
+int device_all_finite(const double *x_dev, int64_t n, int32_t *flag_dev, int32_t *flag_host, hipStream_t s,
+                      bool *ok, std::string &err);
 
 // ----------------------------------------------------------------------------- learned warm start
 // One network per subsystem g (separate weights): x = x0 of the members of P(g) in ascending

@@ -6,8 +6,11 @@ loudly otherwise — there is no fallback implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -21,6 +24,7 @@ FLAG_HOST_ONLY = 0x1
 FLAG_SCHED_GRAPH = 0x2
 FLAG_SCHED_PERSISTENT = 0x4
 FLAG_HOST_FACTOR = 0x8
+FLAG_NO_CHECK = 0x10
 FACTORS = {"device": 0, "host": FLAG_HOST_FACTOR}
 SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16": FP32_BF16}
@@ -49,7 +53,8 @@ class Options(C.Structure):
     _fields_ = [("rho", C.c_double), ("eps", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("precision", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("flags", C.c_uint32), ("max_batch", C.c_int32),
-                ("warm_cg_iters", C.c_int32), ("factor_chol_tol", C.c_double)]
+                ("warm_cg_iters", C.c_int32), ("factor_chol_tol", C.c_double),
+                ("warm_eps_scale", C.c_double)]
 
 
 class Warm(C.Structure):
@@ -60,7 +65,9 @@ class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_primal", C.c_double),
                 ("r_dual", C.c_double), ("objective", C.c_double), ("t_solve_ms", C.c_double),
                 ("t_iter_ms", C.c_double), ("graph_launches", C.c_int32), ("schedule", C.c_int32),
-                ("start", C.c_int32), ("fell_back", C.c_int32), ("t_warm_ms", C.c_double)]
+                ("start", C.c_int32), ("fell_back", C.c_int32), ("t_warm_ms", C.c_double),
+                ("kkt", C.c_double), ("eq_resid", C.c_double), ("u0_check", C.c_double),
+                ("t_precompute_ms", C.c_double), ("t_check_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -131,6 +138,17 @@ EXPORTS = {
 }
 
 _lib: C.CDLL | None = None
+# Live handles, released at interpreter exit before the HIP runtime goes away (the hook is
+# registered when the library is loaded, i.e. after torch's own exit hooks, so it runs first).
+_LIVE: "weakref.WeakSet" = weakref.WeakSet()
+
+
+def _close_all():
+    for obj in sorted(list(_LIVE), key=lambda o: 0 if isinstance(o, Group) else 1):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def load(path: str | None = None) -> C.CDLL:
@@ -154,6 +172,7 @@ def load(path: str | None = None) -> C.CDLL:
         fn.argtypes = args
     if path is None:
         _lib = lib
+        atexit.register(_close_all)
     return lib
 
 
@@ -193,7 +212,8 @@ class Problem:
                  rho: float = 5.0, eps: float = 1e-4, max_iter: int = 500, precision: str = "fp64",
                  device: int = 0, stream: int | None = None, check_every: int = 0,
                  host_only: bool = False, schedule: str = "auto", max_batch: int = 0,
-                 warm_cg_iters: int = 0, factor: str = "device", factor_chol_tol: float = 0.0):
+                 warm_cg_iters: int = 0, factor: str = "device", factor_chol_tol: float = 0.0,
+                 warm_eps_scale: float = 0.0, check: bool = True):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -207,8 +227,9 @@ class Problem:
                     _ptr(keep["ul"]), _ptr(keep["uh"]))
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
-                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule] | FACTORS[factor], max_batch,
-                       warm_cg_iters, factor_chol_tol)
+                       (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule] | FACTORS[factor]
+                       | (0 if check else FLAG_NO_CHECK), max_batch,
+                       warm_cg_iters, factor_chol_tol, warm_eps_scale)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
             raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
@@ -217,6 +238,7 @@ class Problem:
         inf = Info()
         self._check(self._lib.dlmpc_query(self._h, C.byref(inf)))
         self.info = inf.as_dict()
+        _LIVE.add(self)
 
     @classmethod
     def from_network(cls, net, d: int, T: int, cost, **kw) -> "Problem":
@@ -372,6 +394,8 @@ class Problem:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():  # the exit hook has closed every live handle
+            return
         try:
             self.close()
         except Exception:
@@ -395,6 +419,7 @@ class Group:
         st = self._lib.dlmpc_group_create(arr, len(self.problems), C.byref(self._h))
         if st != OK:
             raise DlmpcError(st, self._lib.dlmpc_last_error().decode())
+        _LIVE.add(self)
 
     def solve_batch_device(self, Bs: list[int], x0_devs: list[int], u0_devs: list[int]):
         n = len(self.problems)
@@ -414,6 +439,8 @@ class Group:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():  # the exit hook has closed every live handle
+            return
         try:
             self.close()
         except Exception:

@@ -1,0 +1,165 @@
+"""FP64 check of the stopping iterate in every solve mode, and x0 validation on the device
+entries (needs a GPU).
+
+Batched and streamed solves recompute the trajectory y = Phi x0 of each instance's stopping
+iterate in FP64 on the device from its compact state (Algorithm 1: u(t) is read from Phi), and
+report eq_resid = max |Z_AB y - [x0; 0]| (initial state and dynamics of the returned trajectory),
+u0_check = max |u(0) returned - u(0) of that y| and kkt (the largest of eq_resid, the bound
+violation of y and the two stopping residuals). Against the FP64 oracle run to the same
+iteration count: Z_AB (Phi x0) - [x0; 0] of the oracle's Phi has the same size (both equal
+Z_AB (Phi - Psi) x0 up to rounding, since Z_AB Psi = I), the returned u(0) is within the FP32
+tier's rounding of the FP64 trajectory, and the stream reports the values of the batched learned
+solves of the same instances (same iterates). Single-instance solves report the certificate
+of dlmpc_certify.
+"""
+import numpy as np
+import pytest
+
+from oracle import dlmpc_oracle as O
+from paper_2103_14990_amd import dlmpc
+from paper_2103_14990_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RHO, EPS, MAXIT = 5.0, 1e-4, 500
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _cases():
+    net = W.chain(10)
+    tight = W.box_cost(net, theta_max=0.8, u_max=0.3)
+    return {"chain10_tight": (W.Workload("chain10_tight", net, 1, 5, tight, sigma=0.4), [4, 9, 11, 13]),
+            "grid8": (W.workload("grid8"), [3000 + i for i in range(6)])}
+
+
+def _dyn_resid(pb, y, x0):
+    Z = O.build_zab(pb.A, pb.B, pb.lay.T)
+    rhs = np.zeros(Z.shape[0])
+    rhs[:pb.lay.Nx] = x0
+    return float(np.abs(Z @ y - rhs).max())
+
+
+@pytest.mark.parametrize("name", ["chain10_tight", "grid8"])
+def test_batched_check_against_oracle(torch, name):
+    wl, seeds = _cases()[name]
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                    precision="fp32", max_batch=8)
+    x0s = np.stack([wl.x0(s) for s in seeds])
+    st, u0, stats = pr.solve_batch(x0s)
+    assert st in (dlmpc.OK, dlmpc.ENOCONV)
+    for i, x0 in enumerate(x0s):
+        s = stats[i]
+        ref = O.solve(pb, x0, RHO, 0.0, s["iters"])  # the oracle's iterate after as many iterations
+        eq_o = _dyn_resid(pb, ref.y, x0)
+        box_o = float(max(np.max(pb.lb - ref.y), np.max(ref.y - pb.ub), 0.0))
+        scale = np.abs(ref.u0).max()
+        print(f"  {name} seed {seeds[i]}: iters {s['iters']} eq_resid gpu {s['eq_resid']:.3e} oracle {eq_o:.3e} "
+              f"u0_check {s['u0_check']:.2e} kkt {s['kkt']:.2e} box oracle {box_o:.1e} "
+              f"t_check {s['t_check_ms']:.3f} ms t_pre {s['t_precompute_ms']:.3f} ms", flush=True)
+        assert s["eq_resid"] > 0.0
+        assert abs(s["eq_resid"] - eq_o) <= 0.05 * eq_o + 1e-6
+        assert s["u0_check"] <= 1e-5 * scale
+        assert np.abs(u0[i] - ref.u0).max() <= 1e-4 * scale  # the reduced-precision bar
+        assert s["kkt"] >= max(s["eq_resid"], s["r_primal"], s["r_dual"])
+        assert s["kkt"] <= max(s["eq_resid"], s["r_primal"], s["r_dual"]) + 1e-6
+        assert s["t_check_ms"] > 0.0 and s["t_precompute_ms"] > 0.0
+
+
+def test_check_can_be_skipped():
+    wl, seeds = _cases()["grid8"]
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                    precision="fp32", max_batch=4, check=False)
+    _, _, stats = pr.solve_batch(np.stack([wl.x0(s) for s in seeds[:4]]))
+    assert all(s["eq_resid"] == 0.0 and s["u0_check"] == 0.0 and s["t_check_ms"] == 0.0 for s in stats)
+
+
+def test_single_instance_stats_carry_certificate():
+    wl, seeds = _cases()["chain10_tight"]
+    for precision in ("fp64", "fp32"):
+        pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                        precision=precision)
+        r = pr.solve(wl.x0(seeds[0]))
+        c = pr.certify()
+        s = r.stats
+        print(f"  {precision}: eq_resid {s['eq_resid']:.2e} kkt {s['kkt']:.2e} cert {c} "
+              f"t_check {s['t_check_ms']:.3f} ms", flush=True)
+        assert s["eq_resid"] == c["eq"]
+        assert s["kkt"] == max(c["rp"], c["box"], c["stat"], s["r_dual"])
+        assert s["t_check_ms"] > 0.0
+
+
+def test_stream_check_equals_batched(torch):
+    """Streamed instances follow the batched learned iterates bit for bit, so their FP64 checks
+    are equal too."""
+    wl = W.workload("grid8")
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                    precision="fp32", max_batch=16)
+    G, nx, nu = wl.net.n_sub, wl.net.nx, wl.net.nu
+    rs = nx * wl.T + nu * (wl.T - 1)
+    n_train = 64
+    xt = torch.tensor(np.stack([wl.x0(10**6 + i) for i in range(n_train)]), dtype=torch.float64, device="cuda")
+    yt = torch.zeros((n_train, G * rs), dtype=torch.float64, device="cuda")
+    ut = torch.zeros((n_train, G * nu), dtype=torch.float64, device="cuda")
+    for s0 in range(0, n_train, 16):
+        pr.solve_batch_ex(16, xt[s0:].data_ptr(), ut[s0:].data_ptr(), "cold", 0, yt[s0:].data_ptr())
+    pr.ws_init(16, 16, seed=1, x_scale=1.0, y_scale=float(yt.std().item()))
+    for k in range(200):
+        pr.ws_train_step(16, xt[(k % 4) * 16:].data_ptr(), yt[(k % 4) * 16:].data_ptr(), 2e-3)
+    n = 40
+    xs = torch.tensor(np.stack([wl.x0(4000 + i) for i in range(n)]), dtype=torch.float64, device="cuda")
+    us = torch.zeros((n, G * nu), dtype=torch.float64, device="cuda")
+    _, ss, info = pr.solve_stream(n, xs.data_ptr(), us.data_ptr())
+    ub = torch.zeros_like(us)
+    sb = []
+    for s0 in range(0, n, 16):
+        sb += pr.solve_batch_ex(min(16, n - s0), xs[s0:].data_ptr(), ub[s0:].data_ptr(), "learned")[1]
+    assert torch.equal(us, ub)
+    for a, b in zip(ss, sb):
+        assert a["iters"] == b["iters"]
+        assert a["eq_resid"] == b["eq_resid"] and a["u0_check"] == b["u0_check"] and a["kkt"] == b["kkt"]
+        assert a["eq_resid"] > 0.0
+    assert info["joins"] > 1
+
+
+def test_nonfinite_x0_rejected_on_device_entries(torch):
+    wl, seeds = _cases()["grid8"]
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                    precision="fp32", max_batch=4)
+    G, nu = wl.net.n_sub, wl.net.nu
+    x = torch.tensor(np.stack([wl.x0(s) for s in seeds[:4]]), dtype=torch.float64, device="cuda")
+    u = torch.zeros((4, G * nu), dtype=torch.float64, device="cuda")
+    for bad in (float("nan"), float("inf")):
+        xb = x.clone()
+        xb[2, 7] = bad
+        with pytest.raises(dlmpc.DlmpcError) as e:
+            pr.solve_device(xb[2].data_ptr(), u[0].data_ptr())
+        assert e.value.status == dlmpc.EINVAL
+        with pytest.raises(dlmpc.DlmpcError) as e:
+            pr.solve_batch_device(4, xb.data_ptr(), u.data_ptr())
+        assert e.value.status == dlmpc.EINVAL
+        with pytest.raises(dlmpc.DlmpcError) as e:
+            pr.solve_batch_ex(4, xb.data_ptr(), u.data_ptr(), "cold")
+        assert e.value.status == dlmpc.EINVAL
+    # the finite rows still solve
+    st, _ = pr.solve_batch_device(4, x.data_ptr(), u.data_ptr())
+    assert st == dlmpc.OK
+
+
+def test_nonfinite_x0_rejected_by_stream(torch):
+    wl, seeds = _cases()["grid8"]
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                    precision="fp32", max_batch=4)
+    pr.ws_init(8, 4, seed=1)
+    G, nu = wl.net.n_sub, wl.net.nu
+    x = torch.tensor(np.stack([wl.x0(s) for s in seeds[:6]]), dtype=torch.float64, device="cuda")
+    x[5, 0] = float("nan")
+    u = torch.zeros((6, G * nu), dtype=torch.float64, device="cuda")
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        pr.solve_stream(6, x.data_ptr(), u.data_ptr())
+    assert e.value.status == dlmpc.EINVAL
