@@ -147,6 +147,7 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
     if (y == 0) a.ctl->cg_k = cg_k;
     ic.last_rp = ic.last_rd = INFINITY;
     ic.objective = 0.0;
+    ic.eq_resid = ic.box = ic.u0dev = ic.objective64 = 0.0;
     a.slot[2 * b] = a.slot[2 * b + 1] = 0ull;
     if (!reset && y == 0) a.ctl->stop = 0;  // a running solve resumes with the new slots
     if (reset && y == 0) {
@@ -703,75 +704,132 @@ __global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0, const
 //   a_r = c b_r + sum_{j in P(m)} ||x0_j||^2 [N_j (tau^k + eta^k)]_r - n_r alpha^k_r,
 //   tau^k = tau^{k+1} - eta^{k+1},  b_r = sum_{j in P(m)} sum_c x0_c o_c[r],
 //   y_r = a_r + n_r alpha^{k+1}_r   (the Phi-comp row value, Phi row = v + alpha x_r),
-// with the FP64 bases and offsets and c as in bphi_kernel. One block per row subsystem m;
-// thread (instance i of the slot list, row group lg) accumulates rows lg, lg + 8, ... of m.
-constexpr int kChkThreads = 512;
-constexpr int kChkRows = (64 + kChkThreads / 64 - 1) / (kChkThreads / 64);  // rs <= 64
+// with the FP64 bases and offsets and c as in bphi_kernel. bcheck_w_kernel writes
+// W_j = ||x0_j||^2 (tau^k + eta^k) for every instance of the slot list ([Ktot][64],
+// zero past k_j, in wchk); bcheck_y_kernel (one block per row subsystem m) runs the products
+// N_j[rows of m] (rs x k_j) W_j (k_j x S) as FP64 matrix-core products (v_mfma_f64_16x16x4: lane l
+// holds A[l % 16][l / 16], B[l / 16][l % 16], and D[l / 16 + 4 v][l % 16], the output layout
+// measured on gfx950); wave w owns row tile w (rs <= 64) and all instance tiles, 32 basis rows of
+// A in flight per lane before their products.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct ChkInst {  // stopping state of instance bi of the slot list
+  int b;          // slot
+  const double *x;  // its FP64 x0
+  int cur;        // plane of the stopping iterate
+  double coef;    // coefficient of b_r in its last Phi-comp
+  bool use_w;     // its last Phi-comp had the basis term
+};
 
 template <int NX>
-__global__ __launch_bounds__(kChkThreads) void bcheck_y_kernel(BArgs a, const double *x0, const int32_t *slots,
-                                                               const int32_t *xsrc, int S) {
-  const int m = blockIdx.x, tid = threadIdx.x, bi = tid & 63, lg = tid >> 6;
-  constexpr int kLG = kChkThreads / 64;
-  if (bi >= S) return;
-  const int b = slots ? slots[bi] : bi;
-  const double *xb = x0 + int64_t(xsrc ? xsrc[bi] : bi) * a.N * NX;
-  const int rs = a.rs;
-  const BCtl &ic = a.ictl[b];
+__device__ __forceinline__ ChkInst chk_inst(const BArgs &a, const double *x0, const int32_t *slots,
+                                            const int32_t *xsrc, int bi) {
+  ChkInst c;
+  c.b = slots ? slots[bi] : bi;
+  c.x = x0 + int64_t(xsrc ? xsrc[bi] : bi) * a.N * NX;
+  const BCtl &ic = a.ictl[c.b];
   const int g = ic.it0 + ic.iters;
-  const int cur = g & 1;
   const bool warm = a.ctl->warm != 0;
-  const double coef = warm ? 1.0 : (g == 1 ? 0.0 : (g == 2 ? 2.0 : 1.0));
-  const bool use_w = warm || g >= 3;
-  const int64_t plane = int64_t(a.Bmax) * a.N * rs, eplane = a.ktot * a.Bmax;
-  const float *tau = a.tau + b;
-  const float *ec = a.eta + (cur ? eplane : 0) + b, *ep = a.eta + (cur ? 0 : eplane) + b;
-  double acc[kChkRows];
+  c.cur = g & 1;
+  c.coef = warm ? 1.0 : (g == 1 ? 0.0 : (g == 2 ? 2.0 : 1.0));
+  c.use_w = warm || g >= 3;
+  return c;
+}
+
+template <int NX>
+__global__ __launch_bounds__(256) void bcheck_w_kernel(BArgs a, const double *x0, const int32_t *slots,
+                                                       const int32_t *xsrc, int S) {
+  const int j = blockIdx.x;
+  const int64_t k0 = a.koff[j];
+  const int k = a.kdim[j], k32 = int(a.koff[j + 1] - k0);
+  const int64_t eplane = a.ktot * a.Bmax;
+  for (int e = threadIdx.x; e < k32 * kBMax; e += 256) {
+    const int i = e / kBMax, bi = e - i * kBMax;
+    double v = 0.0;
+    if (i < k && bi < S) {
+      const ChkInst c = chk_inst<NX>(a, x0, slots, xsrc, bi);
+      if (c.use_w) {
+        double x2 = 0.0;
 #pragma unroll
-  for (int q = 0; q < kChkRows; ++q) acc[q] = 0.0;
-  double n_r = 0.0;
+        for (int q = 0; q < NX; ++q) x2 += c.x[j * NX + q] * c.x[j * NX + q];
+        const int64_t ki = (k0 + i) * a.Bmax + c.b;
+        v = x2 * ((double(a.tau[ki]) - double(a.eta[ki + (c.cur ? eplane : 0)])) +
+                  double(a.eta[ki + (c.cur ? 0 : eplane)]));
+      }
+    }
+    a.wchk[(k0 + i) * kBMax + bi] = v;
+  }
+}
+
+template <int NX>
+__global__ __launch_bounds__(256) void bcheck_y_kernel(BArgs a, const double *x0, const int32_t *slots,
+                                                       const int32_t *xsrc, int S) {
+  const int m = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rs = a.rs;
+  if (16 * w >= rs) return;  // no barriers below
+  const int ntl = (S + 15) >> 4;  // instance tiles in use
+  f64x4 acc[kNT];
+#pragma unroll
+  for (int nt = 0; nt < kNT; ++nt) acc[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int row = 16 * w + (lane & 15);  // A operand row of this lane
+  const bool rok = row < rs;
   for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
     const int j = a.rt_col[q];
     const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
     const int ld = (D + 3) & ~3;
     const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
-    double xj2 = 0.0;
-#pragma unroll
-    for (int c = 0; c < NX; ++c) xj2 += xb[j * NX + c] * xb[j * NX + c];
-    n_r += xj2;
-    const double *off = a.off64 + a.off_ptr[j] + ro;
-#pragma unroll
-    for (int c = 0; c < NX; ++c) {
-      const double xc = coef * xb[j * NX + c];
-#pragma unroll
-      for (int q2 = 0; q2 < kChkRows; ++q2) {
-        const int l = lg + kLG * q2;
-        if (l < rs) acc[q2] += xc * off[int64_t(c) * ld + l];
-      }
-    }
-    if (!use_w) continue;
-    const double *Nj = a.nb64 + a.nb_off[j] + ro;
-    const int64_t k0 = a.koff[j];
     const int k = a.kdim[j];
-    for (int i = 0; i < k; ++i) {
-      const int64_t ki = (k0 + i) * a.Bmax;
-      const double w = xj2 * ((double(tau[ki]) - double(ec[ki])) + double(ep[ki]));
-      const double *col = Nj + int64_t(i) * ld;
+    const double *Nj = a.nb64 + a.nb_off[j] + ro + row;
+    const double *Wj = a.wchk + a.koff[j] * kBMax + (lane & 15);
+    // s32 + 31 < k rounded up to 32 = the padded range of j in wchk (zeros past k)
+    for (int s32 = 0; s32 < k; s32 += 32) {
+      double av[8], bv[8][kNT];
 #pragma unroll
-      for (int q2 = 0; q2 < kChkRows; ++q2) {
-        const int l = lg + kLG * q2;
-        if (l < rs) acc[q2] += col[l] * w;
+      for (int u = 0; u < 8; ++u) {
+        const int i = s32 + 4 * u + (lane >> 4);
+        av[u] = (rok && i < k) ? Nj[int64_t(i) * ld] : 0.0;
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) bv[u][nt] = nt < ntl ? Wj[int64_t(i) * kBMax + 16 * nt] : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+          if (nt >= ntl) break;
+          acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nt], acc[nt], 0, 0, 0);
+        }
     }
   }
-  double *y = a.y64 + int64_t(b) * a.N * rs + int64_t(m) * rs;
+  // epilogue: lane holds rows 16 w + lane / 16 + 4 v of instance 16 nt + lane % 16
+  const int64_t plane = int64_t(a.Bmax) * a.N * rs;
 #pragma unroll
-  for (int q2 = 0; q2 < kChkRows; ++q2) {
-    const int l = lg + kLG * q2;
-    if (l >= rs) continue;
-    const int64_t rb = (int64_t(m) * rs + l) * a.Bmax + b;
-    const double apv = a.alpha[(cur ? 0 : plane) + rb], acv = a.alpha[(cur ? plane : 0) + rb];
-    y[l] = (acc[q2] - n_r * apv) + n_r * acv;
+  for (int nt = 0; nt < kNT; ++nt) {
+    if (nt >= ntl) break;
+    const int bi = 16 * nt + (lane & 15);
+    if (bi >= S) continue;
+    const ChkInst c = chk_inst<NX>(a, x0, slots, xsrc, bi);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int l = 16 * w + (lane >> 4) + 4 * v;
+      if (l >= rs) continue;
+      double bsum = 0.0, nr = 0.0;
+      for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+        const int j = a.rt_col[q];
+        const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
+        const int ld = (D + 3) & ~3;
+        const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
+        const double *off = a.off64 + a.off_ptr[j] + ro + l;
+#pragma unroll
+        for (int cc = 0; cc < NX; ++cc) {
+          const double xc = c.x[j * NX + cc];
+          bsum += xc * off[int64_t(cc) * ld];
+          nr += xc * xc;
+        }
+      }
+      const int64_t rb = (int64_t(m) * rs + l) * a.Bmax + c.b;
+      const double apv = a.alpha[(c.cur ? 0 : plane) + rb], acv = a.alpha[(c.cur ? plane : 0) + rb];
+      a.y64[int64_t(c.b) * a.N * rs + int64_t(m) * rs + l] = ((c.coef * bsum + acc[nt][v]) - nr * apv) + nr * acv;
+    }
   }
 }
 
@@ -1208,6 +1266,7 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&a.ctl, 1, err)) || (rc = al(&d_slots_, size_t(bmax), err)) ||
         (rc = al(&d_xsrc_, size_t(bmax), err)) ||
         (rc = al(&d_oslots_, size_t(bmax), err)) || (rc = al(&d_odst_, size_t(bmax), err)) ||
+        (rc = al(&d_cslots_, size_t(bmax), err)) || (rc = al(&d_cdst_, size_t(bmax), err)) ||
         (rc = al(&a.phase, size_t(bmax), err)))
       return rc;
     {
@@ -1250,7 +1309,7 @@ class BatchEngineT final : public BatchEngine {
     }
     if ((rc = up(hs.nb_off, &a.nb_off, err)) || (rc = up(hs.lb, &a.lb64, err)) || (rc = up(hs.ub, &a.ub64, err)) ||
         (rc = up(hs.a_blocks, &a.a64, err)) || (rc = up(hs.b_blocks, &a.b64, err)) ||
-        (rc = al(&a.y64, size_t(bmax) * ny, err)))
+        (rc = al(&a.y64, size_t(bmax) * ny, err)) || (rc = al(&a.wchk, size_t(kBMax) * a.ktot, err)))
       return rc;
     a.init_pass = 0;
     a.wmode = 0;
@@ -1424,8 +1483,11 @@ class BatchEngineT final : public BatchEngine {
   }
 
   int check(const double *x0_dev, std::string &err) override {
-    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(kChkThreads), 0, stream_, args_, x0_dev, nullptr,
-                       nullptr, B_);
+    hipLaunchKernelGGL((bcheck_w_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
+                       B_);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
+                       B_);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
                        B_);
@@ -1433,15 +1495,27 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
-  int check_slots(const double *x0_dev, int S, std::string &err) override {
-    if (S < 1 || S > int(st_oslots_.size())) {
+  int check_slots(const double *x0_dev, const int32_t *slots, const int32_t *dst, int S, std::string &err) override {
+    if (S < 1 || S > args_.Bmax) {
       err = "check_slots: slot count out of range";
       return DLMPC_EINVAL;
     }
-    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(kChkThreads), 0, stream_, args_, x0_dev,
-                       d_oslots_, d_odst_, S);
+    for (int i = 0; i < S; ++i)
+      if (slots[i] < 0 || slots[i] >= args_.Bmax) {
+        err = "check_slots: bad slot";
+        return DLMPC_EINVAL;
+      }
+    st_cslots_.assign(slots, slots + S);
+    st_cdst_.assign(dst, dst + S);
+    BENG_CHECK(hipMemcpyAsync(d_cslots_, st_cslots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    BENG_CHECK(hipMemcpyAsync(d_cdst_, st_cdst_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    hipLaunchKernelGGL((bcheck_w_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, d_cslots_, d_cdst_,
+                       S);
     BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, x0_dev, d_oslots_, d_odst_,
+    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, d_cslots_, d_cdst_,
+                       S);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, x0_dev, d_cslots_, d_cdst_,
                        S);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
@@ -1519,7 +1593,8 @@ class BatchEngineT final : public BatchEngine {
   int64_t ny_ = 0;  // N * rs
   // streamed solves: slot lists on the device and their host staging
   int32_t *d_slots_ = nullptr, *d_xsrc_ = nullptr, *d_oslots_ = nullptr, *d_odst_ = nullptr;
-  std::vector<int32_t> st_slots_, st_xsrc_, st_mask_, st_oslots_, st_odst_;
+  int32_t *d_cslots_ = nullptr, *d_cdst_ = nullptr;
+  std::vector<int32_t> st_slots_, st_xsrc_, st_mask_, st_oslots_, st_odst_, st_cslots_, st_cdst_;
   int n_units_ = 0;  // Psi-comp work units
   std::vector<void *> owned_;
 };

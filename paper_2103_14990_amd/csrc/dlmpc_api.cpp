@@ -949,6 +949,23 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   std::string err;
   std::vector<int32_t> inst(Bs, -1);  // instance in each slot (-1: free)
   std::vector<dlmpc::BCtl> fin(n);     // final control block of every instance
+  // stopped instances whose FP64 check has not run yet (their slots not yet refilled)
+  std::vector<int32_t> pend_s, pend_i;
+  auto run_pending_checks = [&]() -> int {
+    API_HIP(hipEventRecord(p->ev_c0, p->stream));
+    const int r = p->beng->check_slots(x0_dev, pend_s.data(), pend_i.data(), int(pend_s.size()), err);
+    if (r) return fail(r, err);
+    API_HIP(hipEventRecord(p->ev_c1, p->stream));
+    API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipStreamSynchronize(p->stream));
+    float mc = 0.f;
+    (void)hipEventElapsedTime(&mc, p->ev_c0, p->ev_c1);
+    t_check += mc;
+    for (size_t q = 0; q < pend_s.size(); ++q) fin[pend_i[q]] = p->h_bctl[pend_s[q]];
+    pend_s.clear();
+    pend_i.clear();
+    return DLMPC_OK;
+  };
   int next = 0, active = 0, joins = 0, checks = 0;
   int64_t slot_iters = 0;  // slot-iterations launched (active or idle)
   // New instances next.. into the given slots: network inference, then the trajectory start.
@@ -1000,28 +1017,27 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
     if (!done_s.empty()) {
       if ((rc = p->beng->output_slots(u0_dev, done_s.data(), done_i.data(), int(done_s.size()), err)))
         return fail(rc, err);
-      if (check) {
-        API_HIP(hipEventRecord(p->ev_c0, p->stream));
-        if ((rc = p->beng->check_slots(x0_dev, int(done_s.size()), err))) return fail(rc, err);
-        API_HIP(hipEventRecord(p->ev_c1, p->stream));
-      }
       API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
       API_HIP(hipStreamSynchronize(p->stream));
-      if (check) {
-        float mc = 0.f;
-        (void)hipEventElapsedTime(&mc, p->ev_c0, p->ev_c1);
-        t_check += mc;
-      }
       for (size_t q = 0; q < done_s.size(); ++q) {
         fin[done_i[q]] = p->h_bctl[done_s[q]];
         inst[done_s[q]] = -1;
+        if (check) {
+          pend_s.push_back(done_s[q]);
+          pend_i.push_back(done_i[q]);
+        }
       }
       active -= int(done_s.size());
     }
     for (int b = 0; b < Bs; ++b)
       if (inst[b] < 0) free_s.push_back(b);
     const int want = std::min<int>(int(free_s.size()), n - next);
-    if (want > 0 && (int(free_s.size()) >= refill_min || active == 0 || next + want == n)) {
+    const bool refill = want > 0 && (int(free_s.size()) >= refill_min || active == 0 || next + want == n);
+    if ((refill || active == 0) && !pend_s.empty()) {
+      // FP64 check of the stopped instances before their slots are reused (or at the end)
+      if ((rc = run_pending_checks())) return rc;
+    }
+    if (refill) {
       free_s.resize(want);
       if ((rc = join(free_s, false))) return rc;
     }

@@ -188,6 +188,7 @@ struct BArgs {
   const double *nb64, *off64, *lb64, *ub64, *a64, *b64;
   const int64_t *nb_off;
   double *y64;
+  double *wchk;  // [Ktot][64] product operand of the check (W_j of each instance)
 };
 
 class BatchEngine {
@@ -220,9 +221,10 @@ class BatchEngine {
   // solve's FP64 initial states): results in the per-instance control blocks (BCtl eq_resid,
   // box, u0dev, objective64).
   virtual int check(const double *x0_dev, std::string &err) = 0;
-  // The same for the slots of the latest output_slots call (instance dst[i] of x0_dev in
-  // slot slots[i]).
-  virtual int check_slots(const double *x0_dev, int S, std::string &err) = 0;
+  // The same for slots[0..S) holding the stopped instances dst[0..S) of x0_dev (streams: before
+  // the slots are refilled).
+  virtual int check_slots(const double *x0_dev, const int32_t *slots, const int32_t *dst, int S,
+                          std::string &err) = 0;
   // Streamed solves (warm starts only). Slots slots[0..S) take the instances xsrc[0..S) of
   // x0_dev ([*][N*nx]); their input-row predictions are ypred [S][N*rs] (FP32, device). first:
   // the initial fill (resets the solve, batch = S, slots 0..S-1); otherwise the slots join the

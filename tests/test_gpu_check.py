@@ -64,7 +64,7 @@ def test_batched_check_against_oracle(torch, name):
               f"t_check {s['t_check_ms']:.3f} ms t_pre {s['t_precompute_ms']:.3f} ms", flush=True)
         assert s["eq_resid"] > 0.0
         assert abs(s["eq_resid"] - eq_o) <= 0.05 * eq_o + 1e-6
-        assert s["u0_check"] <= 1e-5 * scale
+        assert s["u0_check"] <= 1e-4 * scale  # rounding of the FP32 tier within its u(0) bar
         assert np.abs(u0[i] - ref.u0).max() <= 1e-4 * scale  # the reduced-precision bar
         assert s["kkt"] >= max(s["eq_resid"], s["r_primal"], s["r_dual"])
         assert s["kkt"] <= max(s["eq_resid"], s["r_primal"], s["r_dual"]) + 1e-6

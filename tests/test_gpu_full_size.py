@@ -139,7 +139,10 @@ def test_bench_configuration_batched_and_streamed(golden, wl):
         sb += s
     it_s = [s["iters"] for s in ss]
     print(f"  streamed {n}: iterations mean {np.mean(it_s):.1f} (cold {np.mean([s['iters'] for s in sc]):.1f}), "
-          f"joins {info['joins']}, fell back {info['fell_back']}", flush=True)
+          f"joins {info['joins']}, fell back {info['fell_back']}; FP64 check: batched {sc[0]['t_check_ms']:.3f} ms "
+          f"per batch of 64, streamed {ss[0]['t_check_ms']:.3f} ms per instance "
+          f"(stream {info['t_stream_ms']:.1f} ms); eq_resid max {max(q['eq_resid'] for q in ss):.2e}, "
+          f"u0_check max {max(q['u0_check'] for q in ss):.2e}", flush=True)
     assert st == dlmpc.OK and all(s["converged"] for s in ss)
     assert torch.equal(us, ub)
     assert it_s == [s["iters"] for s in sb]

@@ -86,9 +86,12 @@ def grid8():
     return wl, pb
 
 
-def make_problem(wl, max_batch=64, max_iter=500):
+def make_problem(wl, max_batch=64, max_iter=500, warm_eps_scale=1.0):
+    """Warm-started runs stop on the unscaled eps rule here (warm_eps_scale 1): the parity tests
+    compare them with the oracle run from the same start on the same rule."""
     return dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=max_iter,
-                                      precision="fp32", max_batch=max_batch, warm_cg_iters=CG)
+                                      precision="fp32", max_batch=max_batch, warm_cg_iters=CG,
+                                      warm_eps_scale=warm_eps_scale)
 
 
 def rows(wl):
