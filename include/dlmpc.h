@@ -341,6 +341,21 @@ int dlmpc_solve_stream(struct dlmpc_problem *p, int32_t n, const double *x0_dev,
                        int32_t refill_min, int32_t check_iters, dlmpc_stats *stats,
                        dlmpc_stream_info *info);
 
+/* dlmpc_solve_stream without any device allocation, for callers that cannot allocate device
+ * memory during a call (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the staging of the joining instances' predicted trajectories lives in a static
+ * device array of the library (16 MiB, 4194304 floats, one copy per GPU, held until the process
+ * ends) instead of a buffer that dlmpc_solve_stream allocates on its first call. The call needs
+ * max_batch * N * (nx*T + nu*(T-1)) <= 4194304 (the 1024-subsystem mesh with T = 15 and 64 slots
+ * takes 2883584) and otherwise returns DLMPC_EINVAL before any device work. Every other buffer
+ * it uses belongs to the problem (allocated by dlmpc_setup / dlmpc_ws_init). Arguments, results
+ * and statuses as dlmpc_solve_stream, with identical results. Calls on one GPU share that GPU's
+ * array: calls that overlap in time on one GPU (from different threads, or on different
+ * problems' streams) race on it and must be serialised by the caller. */
+int dlmpc_solve_stream_noalloc(struct dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev,
+                               int32_t refill_min, int32_t check_iters, dlmpc_stats *stats,
+                               dlmpc_stream_info *info);
+
 /* ---- Learned warm start: one network per subsystem g (separate FP32 weights), input the x0
  * entries of the subsystems within d hops of g (ascending subsystem order, each nx entries,
  * zero-padded to IN = p_max*nx) divided by x_scale; two GELU hidden layers of width `hidden`;

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1606,6 +1607,34 @@ __global__ __launch_bounds__(256) void finite_kernel(const double *__restrict__ 
 }
 
 }  // namespace
+
+// Prediction staging of the allocation-free stream entry (dlmpc_solve_stream_noalloc): a
+// file-scope device array, one copy per device, held until the process ends. Host code never
+// passes `scratch` itself to a kernel (in host code the name is a stand-in, not a device
+// address): it takes the device address of each device's copy once, with that device current.
+constexpr size_t kStreamScratchFloats = size_t(4) << 20;  // 16 MiB
+static __device__ __align__(256) float scratch[kStreamScratchFloats];
+
+int stream_scratch(float **ptr, size_t *cap_floats, std::string &err) {
+  static std::mutex mu;
+  static std::vector<float *> addr;  // per device ordinal (nullptr until taken)
+  int dev = -1;
+  BENG_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev >= int(addr.size())) addr.resize(size_t(dev) + 1, nullptr);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return DLMPC_EDEVICE;
+    }
+    addr[dev] = static_cast<float *>(p);
+  }
+  *ptr = addr[dev];
+  *cap_floats = kStreamScratchFloats;
+  return DLMPC_OK;
+}
 
 int device_all_finite(const double *x_dev, int64_t n, int32_t *flag_dev, int32_t *flag_host, hipStream_t s,
                       bool *ok, std::string &err) {

@@ -924,16 +924,24 @@ int dlmpc_solve_batch_ex(dlmpc_problem *p, int32_t B, const double *x0_dev, doub
   return run_batch(p, B, x0_dev, u0_dev, start, start_dev, y_out_dev, alpha_out_dev, stats, t0);
 }
 
-int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,
-                       int32_t check_iters, dlmpc_stats *stats, dlmpc_stream_info *info) {
-  const double t0 = now_ms();
+namespace {
+
+int check_stream_args(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,
+                      int32_t check_iters) {
   int rc = check_batch(p, 1);
   if (rc) return rc;
   if (!x0_dev || !u0_dev || n < 1) return fail(DLMPC_EINVAL, "need n >= 1 and non-NULL x0_dev, u0_dev");
   if (!p->ws) return fail(DLMPC_EINVAL, "no warm-start network (dlmpc_ws_init or dlmpc_warmstart_load)");
   if (check_iters < 0 || refill_min < 0) return fail(DLMPC_EINVAL, "refill_min and check_iters must be >= 0");
-  API_HIP(hipSetDevice(p->opt.device));
-  if ((rc = check_x0_device(p, x0_dev, n))) return rc;
+  return DLMPC_OK;
+}
+
+// The streamed solve; sy: staging of the joiners' predicted trajectories, max_batch * N * rs
+// floats on the problem's device (the caller checked the arguments and made the device current).
+int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,
+               int32_t check_iters, dlmpc_stats *stats, dlmpc_stream_info *info, float *sy, double t0) {
+  int rc = check_x0_device(p, x0_dev, n);
+  if (rc) return rc;
   const bool check = !(p->opt.flags & DLMPC_FLAG_NO_CHECK);
   double t_check = 0.0, t_pre = 0.0;  // device ms over the whole stream
   const HostSetup &h = p->hs;
@@ -945,7 +953,6 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   // stopped instances written, joiners started): 16 iterations between checks measured faster
   // than 2..12 or 32 on the 1024 mesh with 64 slots (the iterates do not depend on it).
   const int K = check_iters > 0 ? check_iters : 16;
-  if (!p->d_sy) API_HIP(hipMalloc(&p->d_sy, sizeof(float) * size_t(Bm) * R));
   std::string err;
   std::vector<int32_t> inst(Bs, -1);  // instance in each slot (-1: free)
   std::vector<dlmpc::BCtl> fin(n);     // final control block of every instance
@@ -975,10 +982,10 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
     for (int i = 0; i < S; ++i) xsrc[i] = next + i;
     for (int s0 = 0; s0 < S; s0 += p->ws->Smax) {
       const int c = std::min(p->ws->Smax, S - s0);
-      const int r = p->ws->predict(c, x0_dev + size_t(next + s0) * nxs, p->d_sy + size_t(s0) * R, err);
+      const int r = p->ws->predict(c, x0_dev + size_t(next + s0) * nxs, sy + size_t(s0) * R, err);
       if (r) return fail(r, err);
     }
-    const int r = p->beng->stream_start(x0_dev, slots.data(), xsrc.data(), S, p->d_sy, p->cg_iters, first,
+    const int r = p->beng->stream_start(x0_dev, slots.data(), xsrc.data(), S, sy, p->cg_iters, first,
                                         p->opt.max_iter, p->warm_eps, err);
     if (r) return fail(r, err);
     for (int i = 0; i < S; ++i) inst[slots[i]] = next + i;
@@ -1101,6 +1108,38 @@ int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double
   }
   if (numeric) return fail(DLMPC_ENUMERIC, "NaN/Inf in a streamed ADMM iterate (also after the cold fallback)");
   return conv == n ? DLMPC_OK : DLMPC_ENOCONV;
+}
+
+}  // namespace
+
+int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,
+                       int32_t check_iters, dlmpc_stats *stats, dlmpc_stream_info *info) {
+  const double t0 = now_ms();
+  int rc = check_stream_args(p, n, x0_dev, u0_dev, refill_min, check_iters);
+  if (rc) return rc;
+  API_HIP(hipSetDevice(p->opt.device));
+  const size_t sy_len = size_t(p->beng->bmax()) * p->hs.N * p->hs.rs;
+  if (!p->d_sy) API_HIP(hipMalloc(&p->d_sy, sizeof(float) * sy_len));
+  return run_stream(p, n, x0_dev, u0_dev, refill_min, check_iters, stats, info, p->d_sy, t0);
+}
+
+int dlmpc_solve_stream_noalloc(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev,
+                               int32_t refill_min, int32_t check_iters, dlmpc_stats *stats,
+                               dlmpc_stream_info *info) {
+  const double t0 = now_ms();
+  int rc = check_stream_args(p, n, x0_dev, u0_dev, refill_min, check_iters);
+  if (rc) return rc;
+  API_HIP(hipSetDevice(p->opt.device));
+  const size_t sy_len = size_t(p->beng->bmax()) * p->hs.N * p->hs.rs;
+  float *sy = nullptr;
+  size_t cap = 0;
+  std::string err;
+  if ((rc = dlmpc::stream_scratch(&sy, &cap, err))) return fail(rc, err);
+  if (sy_len > cap)
+    return fail(DLMPC_EINVAL, "dlmpc_solve_stream_noalloc: max_batch * N * (nx*T + nu*(T-1)) = " +
+                                  std::to_string(sy_len) + " exceeds the static staging of " + std::to_string(cap) +
+                                  " floats");
+  return run_stream(p, n, x0_dev, u0_dev, refill_min, check_iters, stats, info, sy, t0);
 }
 
 namespace {

@@ -242,6 +242,10 @@ class BatchEngine {
 
 std::unique_ptr<BatchEngine> make_batch_engine(int nx);
 
+// Device address of the current device's copy of the stream entry's static prediction
+// staging (taken once per device) and its size in floats. Returns a DLMPC_* status.
+int stream_scratch(float **ptr, size_t *cap_floats, std::string &err);
+
 // *ok = every entry of x_dev[0..n) is finite (device check on stream s, synchronised; flag_dev
 // one device int, flag_host one pinned host int). Returns a DLMPC_* status.
 int device_all_finite(const double *x_dev, int64_t n, int32_t *flag_dev, int32_t *flag_host, hipStream_t s,

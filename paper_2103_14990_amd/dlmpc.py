@@ -118,6 +118,8 @@ EXPORTS = {
     "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_solve_stream": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p]),
+    "dlmpc_solve_stream_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                             C.c_void_p, C.c_void_p]),
     "dlmpc_solve_batch_ex": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_ws_init": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_double, C.c_double]),
@@ -329,6 +331,16 @@ class Problem:
         info = StreamInfo()
         s = self._check(self._lib.dlmpc_solve_stream(self._h, n, C.c_void_p(x0_dev), C.c_void_p(u0_dev),
                                                       refill_min, check_iters, st, C.byref(info)))
+        return s, [x.as_dict() for x in st], info.as_dict()
+
+    def solve_stream_noalloc(self, n: int, x0_dev: int, u0_dev: int, refill_min: int = 0,
+                             check_iters: int = 0) -> tuple[int, list[dict], dict]:
+        """solve_stream without device allocation (static staging array of the library; calls
+        that overlap on one GPU race on it)."""
+        st = (Stats * n)()
+        info = StreamInfo()
+        s = self._check(self._lib.dlmpc_solve_stream_noalloc(self._h, n, C.c_void_p(x0_dev), C.c_void_p(u0_dev),
+                                                              refill_min, check_iters, st, C.byref(info)))
         return s, [x.as_dict() for x in st], info.as_dict()
 
     # ---- learned warm start
