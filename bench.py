@@ -2,17 +2,24 @@
 """Benchmark of the DLMPC-ADMM hot path on one MI355X.
 
 Workload: the 1024-subsystem irregular mesh (32x32 grid, 30% of edges dropped, 51 chords;
-d = 3, T = 15, |theta| <= 0.8, |u| <= 2), x0 = 0.15 N(0, I), rho = 5, eps = 1e-4.
+d = 3, T = 15, |theta| <= 0.8, |u| <= 2), x0 = 0.15 N(0, I) (draws whose uncontrollable first
+step leaves the box replaced), rho = 5, eps = 1e-4.
 
 A step is 256 MPC solves to eps (Algorithm 1 loop body for distinct x0 already resident in
 HBM: per-solve precompute, the start construction, ADMM iterations of Algorithm 2 until the
-instance passes the convergence check, u(0) read out) in FP32 with the learned warm start, all
-timed steps streamed as one stream through 64 slots; the warm-start network is trained
-beforehand (untimed) on cold solves that the same engine generates. Alongside: the same
-instances in batches of 64 from the learned and the cold start, single-instance FP32 and the
-plain FP64 cold-start GPU solve on the same x0, the reduced-operator tier (basis rounded once
-to bf16) against the split-operand solves, the roofline of the dominant kernel (HIP events
-around each launch), and the CPU oracle timed on a bounded sample.
+instance passes the convergence check, u(0) read out, the FP64 check of the stopping iterate)
+with FP32 state and split-bf16 matrix-core products, from the learned warm start (stopping at
+eps * warm_eps_scale, the library default 1/2, so that the learned u(0) lands no farther from
+the exact optimum than the cold start's), all timed steps streamed as one stream through 64
+slots; the warm-start network is trained beforehand (untimed) on cold solves that the same
+engine generates. Alongside: the same instances in batches of 64 from the learned and the cold
+start; u(0) of cold, learned and streamed solves against the exact optimum (oracle run to
+eps = 1e-8, stored values); per-instance latency statistics over 100 x0 (single-instance FP32,
+plain FP64 cold, batched, streamed); the 10-node chain (FP64, iteration floor) and the 16x16 box
+grid (FP64 vs FP32); the reduced-operator tier; a group of three networks; the roofline of the
+dominant kernel (HIP events around each launch); and the CPU oracle timed on a bounded sample on
+one core and on all cores. `--cpu-full` times the full oracle instead (every column block, one
+whole iteration), a run of its own.
 
 Prints one JSON line: value = ADMM iterations per second over the timed steps (instance
 iterations, whole job); time_to_eps_ms = device-and-host wall time per MPC solve.
@@ -58,17 +65,44 @@ def batch_algorithmic_bytes(info: dict, n_sub: int, rs: int, B: int, basis_bytes
     return {"bphi_kernel": bphi, "bpsi_kernel": bpsi, "bdecide_kernel": 0, "iteration": bphi + bpsi}
 
 
-def cpu_baseline(wl, iters_gpu_mean: float, sample_blocks: int = 16) -> dict:
+def lat_stats(ms) -> dict:
+    """Median, mean, std and p95 of per-instance times (ms)."""
+    import numpy as np
+    a = np.asarray(list(ms), dtype=float)
+    return {"n": int(a.size), "median": round(float(np.median(a)), 4), "mean": round(float(a.mean()), 4),
+            "std": round(float(a.std()), 4), "p95": round(float(np.percentile(a, 95)), 4)}
+
+
+def _oracle_iteration(O, pb, x0, rho):
+    """One ADMM iteration of the oracle from the cold start; seconds of (Phi-comp, Psi-comp,
+    Lambda-comp + Conv)."""
+    import numpy as np
+    Psi = np.zeros(pb.mask.shape)
+    Lam = np.zeros_like(Psi)
+    t2 = time.perf_counter()
+    Phi, _ = O.phi_comp(pb, Psi, Lam, x0, rho)
+    t3 = time.perf_counter()
+    Psi_new = O.psi_comp(pb, Phi, Lam)
+    t4 = time.perf_counter()
+    O.lambda_comp(Lam, Phi, Psi_new)
+    O.conv_residuals(Phi, Psi_new, Psi)
+    t5 = time.perf_counter()
+    return t3 - t2, t4 - t3, t5 - t4
+
+
+def cpu_baseline(wl, oracle_iters: float, sample_blocks: int = 16) -> dict:
     """The FP64 oracle as it stands, timed on a bounded sample: Phi-comp, Lambda-comp and the
     convergence norms on the full problem, Psi-comp on `sample_blocks` seeded column blocks
-    scaled to all N, one thread."""
+    scaled to all N; once with one thread and once with every host core (NumPy's BLAS threads).
+    Time-to-eps estimate: one iteration times the oracle's iteration count on these x0."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import dlmpc_oracle as O
 
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
         pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost, blocks=False)
         Z = O.build_zab(pb.A, pb.B, pb.lay.T)
         rng = np.random.default_rng(0)
@@ -76,26 +110,63 @@ def cpu_baseline(wl, iters_gpu_mean: float, sample_blocks: int = 16) -> dict:
         t1 = time.perf_counter()
         pb.blocks = [O.column_block(Z, pb.mask, pb.lay, j) for j in js]
         t_fac = time.perf_counter() - t1
-        x0 = wl.x0(1000)
-        Psi = np.zeros(pb.mask.shape)
-        Lam = np.zeros_like(Psi)
-        t2 = time.perf_counter()
-        Phi, _ = O.phi_comp(pb, Psi, Lam, x0, wl.rho)
-        t3 = time.perf_counter()
-        Psi_new = O.psi_comp(pb, Phi, Lam)
-        t4 = time.perf_counter()
-        Lam = O.lambda_comp(Lam, Phi, Psi_new)
-        O.conv_residuals(Phi, Psi_new, Psi)
-        t5 = time.perf_counter()
+    x0 = wl.x0(1000)
     n = wl.net.n_sub
-    s_iter = (t3 - t2) + (t4 - t3) * n / sample_blocks + (t5 - t4)
-    return {"value": 1.0 / s_iter, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one ADMM iteration of the FP64 oracle: Phi-comp, Lambda-comp and "
-                       f"Conv on all {n} subsystems, Psi-comp on {sample_blocks} seeded column "
-                       f"blocks scaled x{n / sample_blocks:.0f}; setup factorisation of those "
-                       f"blocks {t_fac:.1f} s (~{t_fac * n / sample_blocks:.0f} s for all)"),
-            "time_to_eps_ms_est": 1e3 * s_iter * iters_gpu_mean,
-            "wall_s": time.perf_counter() - t0}
+    per = {}
+    for label, lim in (("1", 1), ("all", cores)):
+        with threadpool_limits(limits=lim):
+            ph, ps, rest = _oracle_iteration(O, pb, x0, wl.rho)
+        per[label] = ph + ps * n / sample_blocks + rest
+    s1 = per["1"]
+    return {"value": round(1.0 / s1, 4), "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one ADMM iteration of the FP64 oracle: Phi-comp, Lambda-comp and Conv on all {n} "
+                       f"subsystems, Psi-comp on {sample_blocks} seeded column blocks scaled x{n / sample_blocks:.0f}; "
+                       f"setup factorisation of those blocks {t_fac:.1f} s (~{t_fac * n / sample_blocks:.0f} s "
+                       f"for all, one core)"),
+            "all_cores": {"value": round(1.0 / per["all"], 4), "unit": "iter/s", "cores": cores},
+            "time_to_eps_ms_est": round(1e3 * s1 * oracle_iters, 1),
+            "time_to_eps_ms_est_all_cores": round(1e3 * per["all"] * oracle_iters, 1),
+            "oracle_iters": oracle_iters, "nproc": cores,
+            "wall_s": round(time.perf_counter() - t0, 2)}
+
+
+def _block(j):
+    from oracle import dlmpc_oracle as O
+    Z, mask, lay = _FULL["args"]
+    return O.column_block(Z, mask, lay, j)
+
+
+_FULL = {}
+
+
+def cpu_full(wl) -> dict:
+    """The full oracle on this workload: every column block factored (the oracle's own
+    column_block, in a process per core), then one whole iteration on one thread and on every
+    core. Minutes; a run of its own (--cpu-full)."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dlmpc_oracle as O
+
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost, blocks=False)
+    _FULL["args"] = (O.build_zab(pb.A, pb.B, wl.T).tocsc(), pb.mask, pb.lay)
+    with threadpool_limits(limits=1):
+        with mp.get_context("fork").Pool(cores) as pool:
+            pb.blocks = pool.map(_block, range(pb.lay.n_sub), chunksize=4)
+    t_setup = time.perf_counter() - t0
+    log(f"oracle setup (all {pb.lay.n_sub} blocks, {cores} processes): {t_setup:.0f} s")
+    x0 = wl.x0(1000)
+    rec = {"workload": wl.name, "nproc": cores, "setup_s_all_cores": round(t_setup, 1)}
+    for label, lim in (("1_core", 1), ("all_cores", cores)):
+        with threadpool_limits(limits=lim):
+            ph, ps, rest = _oracle_iteration(O, pb, x0, wl.rho)
+        rec[label] = {"iteration_s": round(ph + ps + rest, 3), "phi_s": round(ph, 3), "psi_s": round(ps, 3),
+                      "lambda_conv_s": round(rest, 3), "iter_per_s": round(1.0 / (ph + ps + rest), 4)}
+        log(f"oracle iteration, {label}: {rec[label]}")
+    return rec
 
 
 def traffic_record(workload: str, kernel: str, launches_bytes: float):
@@ -138,9 +209,16 @@ def main() -> int:
     ap.add_argument("--train-solves", type=int, default=8192)
     ap.add_argument("--train-steps", type=int, default=10000)
     ap.add_argument("--hidden", type=int, default=64)
-    ap.add_argument("--single-steps", type=int, default=8, help="single-instance FP32 solves")
-    ap.add_argument("--ref-steps", type=int, default=4, help="plain FP64 single-instance solves")
+    ap.add_argument("--x3-share", type=float, default=0.0,
+                    help="share of training x0 drawn at 3x the workload's scale (only where the draw keeps the "
+                         "uncontrollable first step inside the box; 0 on box workloads of this size)")
+    ap.add_argument("--latency-seeds", type=int, default=100,
+                    help="x0 seeds 1000.. for the per-instance latency statistics of each mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", dest="configs", action="store_false",
+                    help="skip the 10-node chain and 16x16 box grid lines")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only the full oracle (every column block, one whole iteration, 1 and all cores)")
     ap.add_argument("--no-bf16-tier", dest="bf16_tier", action="store_false",
                     help="skip the reduced-operator tier (basis rounded once to bf16) comparison")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
@@ -148,7 +226,9 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-launch timing of the batched kernels (for profiler runs)")
-    ap.add_argument("--kernels-precision", default="fp32", choices=["fp32", "fp32_bf16"],
+    ap.add_argument("--kernels-engine", default="batched", choices=["batched", "single"],
+                    help="--kernels-only: the batched kernels, or the single-instance kernels (one x0)")
+    ap.add_argument("--kernels-precision", default="fp32", choices=["fp32", "fp32_bf16", "fp64"],
                     help="--kernels-only: split-operand kernels (fp32) or the reduced-operator tier")
     ap.add_argument("--setup-only", action="store_true",
                     help="only problem creation (device factorisation of the column blocks, engine layouts), "
@@ -161,6 +241,10 @@ def main() -> int:
         return 2
     if args.calibrate_copy:
         calibrate_copy()
+        return 0
+    if args.cpu_full:
+        from paper_2103_14990_amd import workloads as W
+        print(json.dumps(cpu_full(W.workload(args.workload))), flush=True)
         return 0
 
     import numpy as np
@@ -197,6 +281,24 @@ def main() -> int:
             p.close()
         print(json.dumps({"workload": args.workload, "setup": rec}), flush=True)
         return 0
+    if args.kernels_only and args.kernels_engine == "single":
+        ps_ = make(args.kernels_precision if args.kernels_precision != "fp32_bf16" else "fp32", 0)
+        xk = torch.tensor(wl.x0(1000), dtype=torch.float64, device=dev)
+        ku = ps_.time_kernels(xk.data_ptr(), 20)
+        nnz, dk = ps_.info["nnz"], ps_.info["sum_dcol_k"]
+        sz = 8 if args.kernels_precision == "fp64" else 4
+        # algorithmic bytes per launch (every array once): Phi-comp reads Psi, Lambda (nnz each) and
+        # the row data, writes Phi; pass 1 reads the bases and Phi + Lambda; pass 2 reads the bases,
+        # Phi, Lambda, Psi and writes Psi, Lambda
+        algo = {"phi_kernel": sz * (3 * nnz + 4 * R), "psi_pass1_kernel": sz * (dk + 2 * nnz),
+                "psi_pass2_kernel": sz * (dk + 6 * nnz), "conv_kernel": 0}
+        print(json.dumps({"kernels_us": ku, "engine": "single", "precision": args.kernels_precision,
+                          "timed_iterations": 20,
+                          "GB/s": {k: round(algo[k] / (v * 1e-6) / 1e9, 1) if algo[k] else None
+                                   for k, v in ku.items()},
+                          "algorithmic_bytes": algo}), flush=True)
+        ps_.close()
+        return 0
     pr = make(args.kernels_precision if args.kernels_only else "fp32", B)
     if args.kernels_only:
         xk = torch.tensor(np.stack([wl.x0(1000 + i) for i in range(B)]), dtype=torch.float64, device=dev)
@@ -216,7 +318,14 @@ def main() -> int:
     if args.start == "learned":
         t0 = time.perf_counter()
         nts = args.train_solves
-        xt = torch.tensor(np.stack([wl.x0(10**6 + i) for i in range(nts)]), dtype=torch.float64, device=dev)
+        xs_train, n3 = [], 0
+        for i in range(nts):
+            x = wl.x0(10**6 + i)
+            if args.x3_share > 0 and (i % 1000) < 1000 * args.x3_share:
+                if not W.first_step_outside_box(net, wl.cost, 3.0 * x):
+                    x, n3 = 3.0 * x, n3 + 1
+            xs_train.append(x)
+        xt = torch.tensor(np.stack(xs_train), dtype=torch.float64, device=dev)
         yt = torch.zeros((nts, R), dtype=torch.float64, device=dev)
         ut = torch.zeros((nts, n_u), dtype=torch.float64, device=dev)
         conv = []
@@ -240,7 +349,7 @@ def main() -> int:
         torch.cuda.synchronize()
         train = {"solves": nts, "converged_used": int(keep.numel()), "data_s": round(t_data, 2),
                  "train_steps": args.train_steps, "train_s": round(time.perf_counter() - t1, 2),
-                 "hidden": args.hidden, "loss_first": losses[0],
+                 "hidden": args.hidden, "x3_share": args.x3_share, "x3_drawn": n3, "loss_first": losses[0],
                  "loss_last50": float(np.mean(losses[-50:])),
                  "params": pr.ws_shape()["n_params"]}
         log(f"warm-start network: {train}")
@@ -334,55 +443,120 @@ def main() -> int:
     batched_learned = compare("learned", "batched_learned") if S else {}
     cold = compare("cold", "cold") if args.start != "cold" else {}
 
-    # ---- single-instance solves on the first x0 of the first timed batch
-    xs = x0[args.warmup]
-    us = torch.zeros((B, n_u), dtype=torch.float64, device=dev)
-    ks = min(args.single_steps, B)
-    pr.solve_device(xs[0].data_ptr(), us[0].data_ptr())
+    # ---- per-instance latency over the latency seeds (1000..): single-instance FP32 and the plain
+    # FP64 cold-start GPU solve (one solve per call), batched learned and cold (every instance of a
+    # batch returns with the batch), and the streamed instances of the timed region (join to stop)
+    nl = args.latency_seeds
+    xl = torch.tensor(np.stack([wl.x0(1000 + i) for i in range(nl)]), dtype=torch.float64, device=dev)
+    xs = x0[args.warmup]  # first timed step's instances (tier comparison below)
+    ul = torch.zeros((nl, n_u), dtype=torch.float64, device=dev)
+    pr.solve_device(xl[0].data_ptr(), ul[0].data_ptr())
     torch.cuda.synchronize()
-    ss = []
-    for i in range(ks):
-        _, s = pr.solve_device(xs[i].data_ptr(), us[i].data_ptr())
-        ss.append(s)
-    single = {"time_to_eps_ms_median": round(statistics.median(s["t_solve_ms"] for s in ss), 3),
-              "iters": [s["iters"] for s in ss],
+    ss = [pr.solve_device(xl[i].data_ptr(), ul[i].data_ptr())[1] for i in range(nl)]
+    single = {"latency_ms": lat_stats(q["t_solve_ms"] for q in ss),
+              "iters_mean": float(np.mean([q["iters"] for q in ss])),
+              "check_ms_mean": round(float(np.mean([q["t_check_ms"] for q in ss])), 4),
               "schedule": ["graph", "persistent"][pr.info["schedule"]]}
     ref = {}
-    if args.ref_steps > 0:
-        prf = make("fp64", 0)
-        kr = min(args.ref_steps, B)
-        uf = torch.zeros((kr, n_u), dtype=torch.float64, device=dev)
-        prf.solve_device(xs[0].data_ptr(), uf[0].data_ptr())
-        torch.cuda.synchronize()
-        sf = []
-        for i in range(kr):
-            _, s = prf.solve_device(xs[i].data_ptr(), uf[i].data_ptr())
-            sf.append(s)
-        torch.cuda.synchronize()
-        w = u0[args.warmup, :kr]
-        rel = ((w - uf).abs().amax(dim=1) / uf.abs().amax(dim=1)).tolist()
-        ref = {"time_to_eps_ms_median": round(statistics.median(s["t_solve_ms"] for s in sf), 3),
-               "iters": [s["iters"] for s in sf],
-               "schedule": ["graph", "persistent"][prf.info["schedule"]],
-               "u0_rel_diff_headline_vs_fp64_max": max(rel)}
-        prf.close()
-    log(f"single fp32: {single}; plain fp64: {ref}")
+    uf = torch.zeros((nl, n_u), dtype=torch.float64, device=dev)
+    prf = make("fp64", 0)
+    prf.solve_device(xl[0].data_ptr(), uf[0].data_ptr())
+    torch.cuda.synchronize()
+    sf = [prf.solve_device(xl[i].data_ptr(), uf[i].data_ptr())[1] for i in range(nl)]
+    torch.cuda.synchronize()
+    ref = {"latency_ms": lat_stats(q["t_solve_ms"] for q in sf),
+           "iters_mean": float(np.mean([q["iters"] for q in sf])),
+           "time_to_eps_ms_median": lat_stats(q["t_solve_ms"] for q in sf)["median"],
+           "schedule": ["graph", "persistent"][prf.info["schedule"]],
+           "u0_rel_diff_single_fp32_vs_fp64_max": float(((ul - uf).abs().amax(dim=1) / uf.abs().amax(dim=1)).max())}
+    prf.close()
+    bl = {}
+    for start in ("learned", "cold") if args.start == "learned" else ("cold",):
+        ub_ = torch.zeros((nl, n_u), dtype=torch.float64, device=dev)
+        sb_ = []
+        for b0 in range(0, nl, B):
+            sb_ += batch_solve(xl[b0:b0 + B], ub_[b0:b0 + B], start)[1]
+        bl[start] = lat_stats(q["t_solve_ms"] for q in sb_)
+        if start == "learned":
+            ul_learned = ub_
+        else:
+            ul_cold = ub_
+    ref["u0_rel_diff_batched_cold_vs_fp64_max"] = float(
+        ((ul_cold - uf).abs().amax(dim=1) / uf.abs().amax(dim=1)).max())
+    latency = {"seeds": [1000, 999 + nl], "single_fp32_cold": single["latency_ms"],
+               "plain_fp64_cold": ref["latency_ms"],
+               **{f"batched_{k}": v for k, v in bl.items()},
+               "streamed_learned": lat_stats(q["t_solve_ms"] for q in stats) if S else None}
+    log(f"latency: {latency}")
 
-    # ---- reduced-operator tier (basis rounded once to bf16): the first timed step's instances
-    # in batches of B from the cold start at eps = 1e-3 (above the tier's dual-residual floor on
-    # this mesh), against the split-operand tier at the same eps and at the headline eps, and
-    # the plain FP64 solves above; per-launch kernel times
+    # ---- u(0) against the exact optimum (FP64 oracle to eps = 1e-8, stored values)
+    optimum = {}
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_tight.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath))["records"]
+        gidx = [r["seed"] - 1000 for r in gold if 0 <= r["seed"] - 1000 < nl]
+        dist = {}
+        ustream = torch.zeros((len(gidx), n_u), dtype=torch.float64, device=dev)
+        if args.start == "learned":
+            xg = xl[torch.tensor(gidx, device=dev)].contiguous()
+            pr.solve_stream(len(gidx), xg.data_ptr(), ustream.data_ptr())
+        for label, uu in (("plain_fp64_cold", uf), ("batched_cold", ul_cold),
+                          *((("batched_learned", ul_learned), ("streamed_learned", ustream))
+                            if args.start == "learned" else ())):
+            d = []
+            for k, r in enumerate(g for g in gold if 0 <= g["seed"] - 1000 < nl):
+                ref_u = np.array(r["u0"])
+                row = uu[k] if label == "streamed_learned" else uu[r["seed"] - 1000]
+                d.append(float(np.abs(row.cpu().numpy() - ref_u).max() / np.abs(ref_u).max()))
+            dist[label] = {"max": max(d), "mean": float(np.mean(d))}
+        optimum = {"seeds": [r["seed"] for r in gold], "oracle_eps": gold[0]["eps"], "u0_rel_dist": dist}
+        log(f"u(0) vs the exact optimum: {optimum}")
+
+    # ---- the other configurations: 10-node chain (FP64, one solve per call: the launch and
+    # check floor per iteration) and the 16x16 box grid (FP64 vs FP32), over the latency seeds
+    configs = {}
+    if args.configs:
+        for name, precs in (("chain10", ("fp64",)), ("grid16_box", ("fp64", "fp32"))):
+            w_ = W.workload(name)
+            xc = torch.tensor(np.stack([w_.x0(1000 + i) for i in range(nl)]), dtype=torch.float64, device=dev)
+            rec, us_ = {}, {}
+            for prec in precs:
+                p_ = dlmpc.Problem.from_network(w_.net, w_.d, w_.T, w_.cost, rho=w_.rho, eps=w_.eps,
+                                                max_iter=w_.max_iter, precision=prec, device=0,
+                                                stream=stream.cuda_stream)
+                uc_ = torch.zeros((nl, w_.net.n_sub * w_.net.nu), dtype=torch.float64, device=dev)
+                p_.solve_device(xc[0].data_ptr(), uc_[0].data_ptr())
+                torch.cuda.synchronize()
+                sc_ = [p_.solve_device(xc[i].data_ptr(), uc_[i].data_ptr())[1] for i in range(nl)]
+                rec[prec] = {"time_to_eps_ms": lat_stats(q["t_solve_ms"] for q in sc_),
+                             "iters_mean": float(np.mean([q["iters"] for q in sc_])),
+                             "us_per_iteration_median": round(float(np.median(
+                                 [1e3 * q["t_iter_ms"] / max(q["iters"], 1) for q in sc_])), 2),
+                             "converged": f"{sum(q['converged'] for q in sc_)}/{nl}",
+                             "schedule": ["graph", "persistent"][p_.info["schedule"]]}
+                us_[prec] = uc_
+                p_.close()
+            if "fp32" in us_:
+                rec["u0_rel_diff_fp32_vs_fp64_max"] = float(
+                    ((us_["fp32"] - us_["fp64"]).abs().amax(dim=1) / us_["fp64"].abs().amax(dim=1)).max())
+            configs[name] = rec
+        log(f"configs: {configs}")
+
+    # ---- reduced-operator tier (basis rounded once to bf16): the latency seeds' instances in
+    # batches of B from the cold start at eps = 1e-3 (above the tier's dual-residual floor on this
+    # mesh), against the split-operand tier at the same eps and at the headline eps, and the plain
+    # FP64 solves above; per-launch kernel times
     tier = {}
     if args.bf16_tier:
         eps_t = 1e-3
 
         def timed_batches(p_, uu):
-            p_.solve_batch_ex(min(B, per), xs.data_ptr(), uu.data_ptr(), "cold")  # untimed first use
+            p_.solve_batch_ex(min(B, nl), xl.data_ptr(), uu.data_ptr(), "cold")  # untimed first use
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             sq = []
-            for b0 in range(0, per, B):
-                sq += p_.solve_batch_ex(min(B, per - b0), xs[b0:].data_ptr(), uu[b0:].data_ptr(), "cold")[1]
+            for b0 in range(0, nl, B):
+                sq += p_.solve_batch_ex(min(B, nl - b0), xl[b0:].data_ptr(), uu[b0:].data_ptr(), "cold")[1]
             torch.cuda.synchronize()
             return sq, time.perf_counter() - t1
 
@@ -395,26 +569,23 @@ def main() -> int:
             return ((a_ - b_).abs().amax(dim=1) / b_.abs().amax(dim=1)).max().item()
 
         p16, p32 = tier_problem("fp32_bf16"), tier_problem("fp32")
-        u16, u32, u4 = (torch.zeros((per, n_u), dtype=torch.float64, device=dev) for _ in range(3))
+        u16, u32 = (torch.zeros((nl, n_u), dtype=torch.float64, device=dev) for _ in range(2))
         s16, e16 = timed_batches(p16, u16)
         s32, e32 = timed_batches(p32, u32)
-        s4, _ = timed_batches(pr, u4)
-        k16 = p16.time_batch_kernels(B, xs.data_ptr(), 20)
+        k16 = p16.time_batch_kernels(B, xl.data_ptr(), 20)
         ab16 = batch_algorithmic_bytes(pr.info, N, rs, B, basis_bytes=2)
-        tier = {"eps": eps_t, "instances": per, "start": "cold",
-                "time_to_eps_ms": round(1e3 * e16 / per, 4),
+        tier = {"eps": eps_t, "instances": nl, "start": "cold",
+                "time_to_eps_ms": round(1e3 * e16 / nl, 4),
                 "iters_mean": float(np.mean([q["iters"] for q in s16])),
-                "converged": f"{sum(q['converged'] for q in s16)}/{per}",
-                "split_operands_same_eps": {"time_to_eps_ms": round(1e3 * e32 / per, 4),
+                "converged": f"{sum(q['converged'] for q in s16)}/{nl}",
+                "split_operands_same_eps": {"time_to_eps_ms": round(1e3 * e32 / nl, 4),
                                             "iters_mean": float(np.mean([q["iters"] for q in s32]))},
                 "u0_rel_diff_vs_split_operands_same_eps_max": urel(u16, u32),
-                "u0_rel_diff_vs_split_operands_headline_eps_max": urel(u16, u4),
+                "u0_rel_diff_vs_split_operands_headline_eps_max": urel(u16, ul_cold),
+                "u0_rel_diff_vs_fp64_max": urel(u16, uf),
                 "per_kernel": {k: {"us": round(v, 2),
                                    "GB/s": round(ab16[k] / (v * 1e-6) / 1e9, 1) if ab16[k] else None}
                                for k, v in k16.items()}}
-        if ref:
-            kr = len(ref["iters"])
-            tier["u0_rel_diff_vs_fp64_max"] = urel(u16[:kr], uf)
         p16.close()
         p32.close()
         log(f"bf16 operator tier: {tier}")
@@ -465,6 +636,10 @@ def main() -> int:
                 "instances_per_launch": B, "per_kernel": per_kernel,
                 "iteration_us": round(sum(ku.values()), 2),
                 "traffic": traffic_record(args.workload, kname, ab[kname])}
+    # matrix-core use of the dominant kernel: three bf16 products of 2 sum_j D_col k_j B flops
+    mfma_tf = 3 * 2.0 * pr.info["sum_dcol_k"] * B / (ku[kname] * 1e-6) / 1e12
+    roofline["mfma"] = {"achieved_tflops": round(mfma_tf, 1), "peak_tflops_bf16": 2500.0,
+                        "frac": round(mfma_tf / 2500.0, 4)}
 
     ms_step = 1e3 * elapsed / args.steps
     out = {
@@ -474,13 +649,21 @@ def main() -> int:
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32 state, split-bf16 products (~16-bit operands), f32 accumulation", "data": "synthetic",
         "config": {"workload": args.workload, "n_sub": N, "d": wl.d, "T": wl.T, "rho": wl.rho,
                    "eps": wl.eps, "max_iter": wl.max_iter, "x0_sigma": wl.sigma,
                    "instances_per_step": per, "slots": B, "mode": "stream" if S else "batch",
                    "x0_seeds": [seeds[args.warmup * per], seeds[-1]],
-                   "precision": "fp32 (split-bf16 matrix-core products)", "start": args.start},
+                   "precision": "fp32 state, split-bf16 matrix-core products", "start": args.start,
+                   "warm_eps_scale": 0.5},
         "time_to_eps_ms": round(ms_step / per, 4),
+        "time_to_eps_kind": "throughput: stream time over its instances (per-instance latency under latency_ms)",
+        "latency_ms": latency,
+        "u0_vs_exact_optimum": optimum,
+        "fp64_check": {"t_check_ms_per_instance_mean": round(float(np.mean([q["t_check_ms"] for q in stats])), 4),
+                       "eq_resid_max": float(max(q["eq_resid"] for q in stats)),
+                       "u0_check_max": float(max(q["u0_check"] for q in stats)),
+                       "kkt_max": float(max(q["kkt"] for q in stats))},
         "iters_mean": float(np.mean(iters)), "iters_max": int(max(iters)),
         "converged": f"{conv}/{n_solves}", "fell_back": int(fell),
         "stream": stream_rec,
@@ -490,7 +673,11 @@ def main() -> int:
         "single_fp32_cold": single,
         "plain_fp64_cold": ref,
         "bf16_operator_tier": tier,
-        "speedup_vs_plain_fp64": round(ref["time_to_eps_ms_median"] / (ms_step / per), 2) if ref else None,
+        "configs": configs,
+        "speedup_throughput_vs_plain_fp64": round(ref["latency_ms"]["median"] / (ms_step / per), 2),
+        "speedup_latency_streamed_vs_plain_fp64": (round(ref["latency_ms"]["median"] /
+                                                         latency["streamed_learned"]["median"], 2)
+                                                   if latency["streamed_learned"] else None),
         "warm_start_training": train,
         "setup_ms": round(pr.info["setup_ms"], 1),
         "factor_ms": round(pr.info["factor_ms"], 1),
@@ -498,7 +685,10 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, float(np.mean(iters)))
+        gp = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+        o_it = (float(np.mean([r["iters"] for r in json.load(open(gp))["records"]])) if os.path.exists(gp)
+                else float(np.mean(iters)))
+        out["cpu_baseline"] = cpu_baseline(wl, o_it)
     pr.close()
     print(json.dumps(out), flush=True)
     return 0

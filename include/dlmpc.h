@@ -49,7 +49,14 @@ typedef enum {
   DLMPC_FP64 = 0,     /* state, operators and reductions in double */
   DLMPC_FP32 = 1,     /* state and operators in float; setup and outputs stay double. Batched
                          solves: matrix-core products with both operands split into bf16 hi + lo
-                         and float accumulation (float-level products) */
+                         (three products hi*hi + hi*lo + lo*hi, float accumulation): each operand
+                         carries about 16 significant bits (relative error up to ~2^-17 per
+                         operand, against 2^-24 for float), so the products are accurate to a few
+                         1e-6 relative, not to float rounding. This sets a floor on the dual
+                         residual that grows with the size of x0 (measured 3e-5..1e-4 with
+                         x0 ~ N(0, I) on the 8x8 grid, far below 1e-4 with x0 ~ 0.15 N(0, I) on the
+                         1024-subsystem mesh): eps (times warm_eps_scale for warm starts) must
+                         stay above it. */
   DLMPC_FP32_BF16 = 2 /* reduced-operator tier: as DLMPC_FP32, except that the batched solves'
                          basis operands are rounded once to bf16 (two matrix-core products per
                          tile instead of three, half the basis bytes). The rounded basis is not
@@ -117,11 +124,12 @@ typedef struct {
                              subsystem to the Householder QR (0: 1e-10; 1 or more: always) */
   double warm_eps_scale; /* batched and streamed solves from a warm start (trajectory, learned,
                             alpha) stop on the eps rule with eps * warm_eps_scale, in (0, 1]
-                            (0: 1/3). The eps rule bounds the residuals, not the distance to the
-                            optimum: from a warm start the stopping iterate was measured up to
-                            3x farther from the optimum than the cold start's at the same eps,
-                            and within the cold start's distance at eps/3. Cold runs, including
-                            the cold fallback of a warm-started instance, use eps. */
+                            (0: 1/2). The eps rule bounds the residuals, not the distance to the
+                            optimum: from the learned start the stopping iterate was measured up
+                            to 1.7x farther from the exact optimum (u(0)) than the cold start's at
+                            the same eps, and no farther at eps/2 (16x16 box grid and 1024-
+                            subsystem mesh). Cold runs, including the cold fallback of a
+                            warm-started instance, use eps. */
 } dlmpc_options;
 
 /* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
@@ -138,7 +146,9 @@ typedef struct {
   double r_primal;      /* max over columns of ||Phi[:,c] - Psi[:,c]||_2 at the stopping iterate */
   double r_dual;        /* max over columns of ||Psi^{k+1}[:,c] - Psi^k[:,c]||_2 */
   double objective;     /* sum_r w_r (Phi x0)_r^2 at the stopping iterate, FP64 */
-  double t_solve_ms;    /* host wall time of the solve call */
+  double t_solve_ms;    /* host wall time of the solve call; streamed solves: of the instance,
+                           from its join to the host check that saw it stop (plus its cold
+                           fallback, if any) */
   double t_iter_ms;     /* device time of the iteration phase (HIP events) */
   int32_t graph_launches; /* kernel-graph launches (graph schedule) or 1 (persistent) */
   int32_t schedule;       /* 0 = graph, 1 = persistent, 2 = batched */

@@ -773,21 +773,45 @@ __global__ __launch_bounds__(kBlock) void cert_kernel(KArgs<Tf> a, CertArgs c) {
   const int D = int(t1 - t0) * rs, ld = (D + 3) & ~3, k = a.kdim[j];
   const Tf *Nj = a.nb + a.nb_off[j];
   const double rho = double(a.rho);
-  for (int i = tid; i < k; i += kBlock)
+  // one wave per basis vector i: lanes over the rows (coalesced column reads), wave reduction
+  for (int i = wave; i < k; i += kBlock / 64) {
+    double acc[NX];
+#pragma unroll
+    for (int col = 0; col < NX; ++col) acc[col] = 0.0;
+    for (int r = lane; r < D; r += 64) {
+      const double n = double(Nj[int64_t(i) * ld + r]);
+#pragma unroll
+      for (int col = 0; col < NX; ++col) acc[col] += n * rho * double(a.lam[t0 * ts + int64_t(r) * NX + col]);
+    }
 #pragma unroll
     for (int col = 0; col < NX; ++col) {
-      double acc = 0.0;
-      for (int r = 0; r < D; ++r) acc += double(Nj[int64_t(i) * ld + r]) * rho * double(a.lam[t0 * ts + int64_t(r) * NX + col]);
-      tk[col * k + i] = acc;
+      double v = acc[col];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) tk[col * k + i] = v;
     }
+  }
   __syncthreads();
-  for (int r = tid; r < D; r += kBlock)
+  // rows over the threads (consecutive rows, consecutive addresses), four basis vectors in flight
+  for (int r = tid; r < D; r += kBlock) {
+    double acc[NX];
 #pragma unroll
-    for (int col = 0; col < NX; ++col) {
-      double acc = 0.0;
-      for (int i = 0; i < k; ++i) acc += double(Nj[int64_t(i) * ld + r]) * tk[col * k + i];
-      m_stat = fmax(m_stat, fabs(acc));
+    for (int col = 0; col < NX; ++col) acc[col] = 0.0;
+    int i = 0;
+    for (; i + 4 <= k; i += 4) {
+      double n[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) n[u] = double(Nj[int64_t(i + u) * ld + r]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int col = 0; col < NX; ++col) acc[col] += n[u] * tk[col * k + i + u];
     }
+    for (; i < k; ++i)
+#pragma unroll
+      for (int col = 0; col < NX; ++col) acc[col] += double(Nj[int64_t(i) * ld + r]) * tk[col * k + i];
+#pragma unroll
+    for (int col = 0; col < NX; ++col) m_stat = fmax(m_stat, fabs(acc[col]));
+  }
   // bounds of row subsystem m = j: y = Phi x0 recomputed from the tiles of m's row
   const int m = j;
   for (int l = tid; l < rs; l += kBlock) {

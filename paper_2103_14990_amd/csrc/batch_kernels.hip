@@ -60,7 +60,9 @@ __device__ __forceinline__ void split8(const float *x, bf16x8 &hi, bf16x8 &lo) {
   }
 }
 
-// A*B with A = ah + al, B = bh + bl, dropping al*bl (below FP32 rounding of the sum).
+// A*B with A = ah + al, B = bh + bl, dropping al*bl. hi + lo carries about 16 significant
+// bits of each FP32 operand (lo is itself rounded to bf16: up to ~2^-17 relative error), so a
+// product is accurate to a few 1e-6 relative; al*bl (~2^-16 of the product) is below that.
 __device__ __forceinline__ f32x4 mfma3(const bf16x8 &ah, const bf16x8 &al, const bf16x8 &bh,
                                        const bf16x8 &bl, f32x4 c) {
   c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);

@@ -465,7 +465,7 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
     return fail(DLMPC_EINVAL, "unknown precision");
   if (o.max_batch < 0 || o.max_batch > 64) return fail(DLMPC_EINVAL, "max_batch must be in 0..64");
   if (!(o.factor_chol_tol >= 0.0)) return fail(DLMPC_EINVAL, "factor_chol_tol must be >= 0");
-  if (o.warm_eps_scale == 0.0) o.warm_eps_scale = 1.0 / 3.0;
+  if (o.warm_eps_scale == 0.0) o.warm_eps_scale = 0.5;
   if (!(o.warm_eps_scale > 0.0 && o.warm_eps_scale <= 1.0))
     return fail(DLMPC_EINVAL, "warm_eps_scale must be in (0, 1]");
   auto p = std::make_unique<dlmpc_problem>();
@@ -956,6 +956,7 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
   std::string err;
   std::vector<int32_t> inst(Bs, -1);  // instance in each slot (-1: free)
   std::vector<dlmpc::BCtl> fin(n);     // final control block of every instance
+  std::vector<double> t_lat(n, 0.0);   // host time of the join, then latency join -> stop seen
   // stopped instances whose FP64 check has not run yet (their slots not yet refilled)
   std::vector<int32_t> pend_s, pend_i;
   auto run_pending_checks = [&]() -> int {
@@ -988,7 +989,11 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
     const int r = p->beng->stream_start(x0_dev, slots.data(), xsrc.data(), S, sy, p->cg_iters, first,
                                         p->opt.max_iter, p->warm_eps, err);
     if (r) return fail(r, err);
-    for (int i = 0; i < S; ++i) inst[slots[i]] = next + i;
+    const double tj = now_ms();
+    for (int i = 0; i < S; ++i) {
+      inst[slots[i]] = next + i;
+      t_lat[next + i] = tj;
+    }
     next += S;
     active += S;
     ++joins;
@@ -1028,6 +1033,7 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
       API_HIP(hipStreamSynchronize(p->stream));
       for (size_t q = 0; q < done_s.size(); ++q) {
         fin[done_i[q]] = p->h_bctl[done_s[q]];
+        t_lat[done_i[q]] = now_ms() - t_lat[done_i[q]];
         inst[done_s[q]] = -1;
         if (check) {
           pend_s.push_back(done_s[q]);
@@ -1055,7 +1061,10 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
   for (int i = 0; i < n; ++i)
-    if (stats) fill_stats(stats[i], fin[i], ms, checks, DLMPC_START_LEARNED, t0);
+    if (stats) {
+      fill_stats(stats[i], fin[i], ms, checks, DLMPC_START_LEARNED, t0);
+      stats[i].t_solve_ms = t_lat[i];
+    }
   // Instances the warm start left unconverged (or with a NaN/Inf): cold batched solves.
   std::vector<int> redo;
   for (int i = 0; i < n; ++i)
@@ -1067,8 +1076,10 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
                              hipMemcpyDeviceToDevice, p->stream));
     RunTimes tm2;
     int checks2 = 0;
+    const double tf = now_ms();
     rc = run_batch_once(p, F, p->d_fx0, DLMPC_START_COLD, nullptr, p->d_fu0, nullptr, nullptr, &tm2, &checks2);
     if (rc) return rc;
+    const double t_redo = now_ms() - tf;
     const float ms2 = tm2.iter;
     t_check += tm2.check;
     t_pre += tm2.pre;
@@ -1082,6 +1093,7 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
       if (stats) {
         fill_stats(stats[i], ic, ms + ms2, checks + checks2, DLMPC_START_LEARNED, t0);
         stats[i].fell_back = 1;
+        stats[i].t_solve_ms = t_lat[i] + t_redo;
       }
     }
   }

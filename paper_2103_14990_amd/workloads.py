@@ -288,20 +288,35 @@ def first_step_outside_box(net: Network, cost: Cost, x: np.ndarray) -> bool:
     is infeasible. (On the swing plant this is theta_i(1) = theta_i(0) + dt omega_i(0).)"""
     if cost.x_lo is None and cost.x_hi is None:
         return False
-    nx = net.nx
-    for i in range(net.n_sub):
-        free = ~np.any(net.b_blocks[i] != 0, axis=1)  # states of i with no input
-        if not free.any():
-            continue
-        ax = np.zeros(nx)
-        for p in range(net.a_rowptr[i], net.a_rowptr[i + 1]):
-            j = int(net.a_colidx[p])
-            ax += net.a_blocks[p] @ x[j * nx:(j + 1) * nx]
-        lo = -np.inf if cost.x_lo is None else cost.x_lo[i * nx:(i + 1) * nx]
-        hi = np.inf if cost.x_hi is None else cost.x_hi[i * nx:(i + 1) * nx]
-        if np.any(free & ((ax < lo) | (ax > hi))):
-            return True
-    return False
+    free, A = _free_rows(net)
+    if not free.any():
+        return False
+    ax = A[free] @ x
+    lo = -np.inf if cost.x_lo is None else np.asarray(cost.x_lo)[free]
+    hi = np.inf if cost.x_hi is None else np.asarray(cost.x_hi)[free]
+    return bool(np.any((ax < lo) | (ax > hi)))
+
+
+def _free_rows(net: Network):
+    """(mask of the state rows with a zero row of B, A as a sparse matrix), cached per network."""
+    cached = net.meta.get("_free_rows")
+    if cached is None:
+        from scipy.sparse import csr_matrix
+        n, nx = net.n_sub, net.nx
+        rows, cols, vals = [], [], []
+        for i in range(n):
+            for p in range(net.a_rowptr[i], net.a_rowptr[i + 1]):
+                j = int(net.a_colidx[p])
+                for r in range(nx):
+                    for c in range(nx):
+                        rows.append(i * nx + r)
+                        cols.append(j * nx + c)
+                        vals.append(net.a_blocks[p][r, c])
+        A = csr_matrix((vals, (rows, cols)), shape=(n * nx, n * nx))
+        free = ~np.any(net.b_blocks != 0, axis=2).reshape(-1)
+        cached = (free, A)
+        net.meta["_free_rows"] = cached
+    return cached
 
 
 # Scale of x0 for the box-constrained workloads. With |theta| <= 0.8 and x0 ~ N(0, 1) the
