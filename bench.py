@@ -215,6 +215,8 @@ def main() -> int:
     ap.add_argument("--latency-seeds", type=int, default=100,
                     help="x0 seeds 1000.. for the per-instance latency statistics of each mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closed-loop", dest="closed_loop", action="store_false",
+                    help="skip the closed-loop line (Algorithm 1, 20 steps)")
     ap.add_argument("--no-configs", dest="configs", action="store_false",
                     help="skip the 10-node chain and 16x16 box grid lines")
     ap.add_argument("--cpu-full", action="store_true",
@@ -512,6 +514,33 @@ def main() -> int:
         optimum = {"seeds": [r["seed"] for r in gold], "oracle_eps": gold[0]["eps"], "u0_rel_dist": dist}
         log(f"u(0) vs the exact optimum: {optimum}")
 
+    # ---- closed loop (Algorithm 1): B loops of 20 steps on the device (solve from x(t), apply
+    # u(t), FP64 plant step), every step cold or from the previous input trajectory shifted one
+    # step ahead; whole-simulation time per MPC step (the paper's metric), per loop
+    loop = {}
+    if args.closed_loop:
+        T_sim = 20
+        xc0 = xl[:B].contiguous()
+        xs_ = torch.zeros((B, T_sim + 1, n_x), dtype=torch.float64, device=dev)
+        us_ = torch.zeros((B, T_sim, n_u), dtype=torch.float64, device=dev)
+        for warm in (False, True):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st_, lst = pr.closed_loop(B, T_sim, xc0.data_ptr(), xs_.data_ptr(), us_.data_ptr(), warm=warm)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            it_step = [float(np.mean([q["iters"] for q in row])) for row in lst]
+            loop["shifted" if warm else "cold"] = {
+                "ms_per_mpc_step": round(1e3 * el / T_sim, 3),
+                "ms_per_mpc_step_per_loop": round(1e3 * el / (T_sim * B), 4),
+                "iters_mean_per_step": [round(v, 1) for v in it_step],
+                "iters_total": int(sum(q["iters"] for row in lst for q in row)),
+                "converged": f"{sum(q['converged'] for row in lst for q in row)}/{T_sim * B}",
+                "fell_back": int(sum(q["fell_back"] for row in lst for q in row)),
+                "state_norm_end_max": float(xs_[:, -1].abs().max())}
+        loop.update({"loops": B, "T_sim": T_sim, "x0_seeds": [1000, 999 + B]})
+        log(f"closed loop: {loop}")
+
     # ---- the other configurations: 10-node chain (FP64, one solve per call: the launch and
     # check floor per iteration) and the 16x16 box grid (FP64 vs FP32), over the latency seeds
     configs = {}
@@ -674,6 +703,7 @@ def main() -> int:
         "plain_fp64_cold": ref,
         "bf16_operator_tier": tier,
         "configs": configs,
+        "closed_loop": loop,
         "speedup_throughput_vs_plain_fp64": round(ref["latency_ms"]["median"] / (ms_step / per), 2),
         "speedup_latency_streamed_vs_plain_fp64": (round(ref["latency_ms"]["median"] /
                                                          latency["streamed_learned"]["median"], 2)

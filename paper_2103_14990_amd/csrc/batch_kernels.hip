@@ -906,6 +906,61 @@ __global__ __launch_bounds__(256) void bcheck_red_kernel(BArgs a, const double *
   }
 }
 
+// ------------------------------------------------------------------ closed loop (Algorithm 1)
+
+// Plant step of every instance (FP64): x(t+1) = A x(t) + B u(t) with u(t) the u_0 rows just
+// written to u [B][N*nu]; x(t) and u(t) are also stored in the loop's trajectories
+// xs [B][T_sim+1][N*nx] (x(0) at t = 0) and us [B][T_sim][N*nu]. One block per instance.
+template <int NX>
+__global__ __launch_bounds__(256) void bplant_kernel(BArgs a, double *x, const double *u, double *xs, double *us,
+                                                     int t, int T_sim) {
+  const int b = blockIdx.x, tid = threadIdx.x, N = a.N, nu = a.nu;
+  double *xb = x + int64_t(b) * N * NX;
+  const double *ub = u + int64_t(b) * N * nu;
+  double *xsb = xs + int64_t(b) * (T_sim + 1) * N * NX;
+  double *usb = us + int64_t(b) * T_sim * N * nu;
+  if (t == 0)
+    for (int i = tid; i < N * NX; i += 256) xsb[i] = xb[i];
+  for (int i = tid; i < N * nu; i += 256) usb[int64_t(t) * N * nu + i] = ub[i];
+  // x(t+1) into the trajectory first (x itself is read by other threads of this block)
+  double *xnext = xsb + int64_t(t + 1) * N * NX;
+  for (int m = tid; m < N; m += 256) {
+    double v[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) v[c] = 0.0;
+    for (int64_t q = a.a_rowptr[m]; q < a.a_rowptr[m + 1]; ++q) {
+      const double *blk = a.a64 + q * NX * NX;
+      const double *xj = xb + int64_t(a.a_colidx[q]) * NX;
+#pragma unroll
+      for (int c = 0; c < NX; ++c)
+#pragma unroll
+        for (int c2 = 0; c2 < NX; ++c2) v[c] += blk[c * NX + c2] * xj[c2];
+    }
+    const double *bb = a.b64 + int64_t(m) * NX * nu;
+    for (int k = 0; k < nu; ++k)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) v[c] += bb[c * nu + k] * ub[int64_t(m) * nu + k];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) xnext[m * NX + c] = v[c];
+  }
+  __syncthreads();
+  for (int i = tid; i < N * NX; i += 256) xb[i] = xnext[i];
+}
+
+// Input rows of the trajectories y [B][N*rs] (library row order) moved one step ahead into ys:
+// u_k <- u_{k+1} for k < T-2, u_{T-2} held (the start of the next step of the loop).
+__global__ __launch_bounds__(256) void bshift_kernel(BArgs a, const double *y, double *ys, int B) {
+  const int ux = a.nx * a.T, nur = a.rs - ux, nu = a.nu;
+  const int64_t n = int64_t(B) * a.N * nur;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int64_t row = i / nur;  // b * N + g
+    const int l = int(i - row * nur);
+    const int k = l / nu;
+    const int src = (k + 1 < a.T - 1) ? l + nu : l;
+    ys[row * a.rs + ux + l] = y[row * a.rs + ux + src];
+  }
+}
+
 // ------------------------------------------------------------------ trajectory warm start
 
 // Input rows of y0 (FP64, [B][N*rs]) into yhat.
@@ -1481,6 +1536,20 @@ class BatchEngineT final : public BatchEngine {
 
   int output(double *u0_dev, std::string &err) override {
     hipLaunchKernelGGL((boutput_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, u0_dev, nullptr, nullptr);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int plant_step(double *x_dev, const double *u_dev, double *xs_dev, double *us_dev, int t, int T_sim, int B,
+                 std::string &err) override {
+    hipLaunchKernelGGL((bplant_kernel<NX>), dim3(B), dim3(256), 0, stream_, args_, x_dev, u_dev, xs_dev, us_dev, t,
+                       T_sim);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int shift_inputs(const double *y_dev, double *ys_dev, int B, std::string &err) override {
+    hipLaunchKernelGGL(bshift_kernel, dim3(256), dim3(256), 0, stream_, args_, y_dev, ys_dev, B);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }

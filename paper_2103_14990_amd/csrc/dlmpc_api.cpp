@@ -47,6 +47,8 @@ struct dlmpc_problem {
   int cg_iters = 12;
   hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
   float *d_sy = nullptr;
+  // closed loop: current states and inputs, stopping trajectories, shifted starts
+  double *d_clx = nullptr, *d_clu = nullptr, *d_cly = nullptr, *d_clys = nullptr;
   // per-solve precompute and FP64 check timing; device finiteness flag of x0 (device entries)
   hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr, ev_c0 = nullptr, ev_c1 = nullptr;
   int32_t *d_flag = nullptr, *h_flag = nullptr;
@@ -87,9 +89,11 @@ void release_device(dlmpc_problem *p) {
     p->bgraph[g] = nullptr;
   }
   if (p->h_bctl) (void)hipHostFree(p->h_bctl);
-  for (double *d : {p->d_bx0, p->d_bu0, p->d_fx0, p->d_fu0, p->d_falpha, p->d_fy})
+  for (double *d : {p->d_bx0, p->d_bu0, p->d_fx0, p->d_fu0, p->d_falpha, p->d_fy, p->d_clx, p->d_clu, p->d_cly,
+                    p->d_clys})
     if (d) (void)hipFree(d);
   p->d_fx0 = p->d_fu0 = p->d_falpha = p->d_fy = nullptr;
+  p->d_clx = p->d_clu = p->d_cly = p->d_clys = nullptr;
   if (p->d_sy) (void)hipFree(p->d_sy);
   p->d_sy = nullptr;
   for (hipEvent_t e : {p->ev_w0, p->ev_w1})
@@ -190,6 +194,10 @@ int setup_batch(dlmpc_problem *p) {
   p->cg_iters = p->opt.warm_cg_iters > 0 ? p->opt.warm_cg_iters : 12;
   API_HIP(hipMalloc(&p->d_fx0, sizeof(double) * size_t(B) * hs.N * hs.nx));
   API_HIP(hipMalloc(&p->d_fu0, sizeof(double) * size_t(B) * hs.N * hs.nu));
+  API_HIP(hipMalloc(&p->d_clx, sizeof(double) * size_t(B) * hs.N * hs.nx));
+  API_HIP(hipMalloc(&p->d_clu, sizeof(double) * size_t(B) * hs.N * hs.nu));
+  API_HIP(hipMalloc(&p->d_cly, sizeof(double) * size_t(B) * R));
+  API_HIP(hipMalloc(&p->d_clys, sizeof(double) * size_t(B) * R));
   API_HIP(hipEventCreate(&p->ev_w0));
   API_HIP(hipEventCreate(&p->ev_w1));
   for (int joins = 0; joins < 2; ++joins)
@@ -1123,6 +1131,32 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
 }
 
 }  // namespace
+
+int dlmpc_closed_loop(dlmpc_problem *p, int32_t B, int32_t T_sim, const double *x0_dev, double *xs_dev,
+                      double *us_dev, int32_t warm, dlmpc_stats *stats) {
+  int rc = check_batch(p, B);
+  if (rc) return rc;
+  if (!x0_dev || !xs_dev || !us_dev) return fail(DLMPC_EINVAL, "NULL argument");
+  if (T_sim < 1 || (warm != 0 && warm != 1)) return fail(DLMPC_EINVAL, "need T_sim >= 1 and warm in {0, 1}");
+  API_HIP(hipSetDevice(p->opt.device));
+  if ((rc = check_x0_device(p, x0_dev, B))) return rc;
+  const HostSetup &h = p->hs;
+  const size_t nxs = size_t(h.N) * h.nx;
+  API_HIP(hipMemcpyAsync(p->d_clx, x0_dev, sizeof(double) * B * nxs, hipMemcpyDeviceToDevice, p->stream));
+  std::string err;
+  bool all = true;
+  for (int t = 0; t < T_sim; ++t) {
+    const int start = (warm && t > 0) ? DLMPC_START_TRAJECTORY : DLMPC_START_COLD;
+    rc = run_batch(p, B, p->d_clx, p->d_clu, start, p->d_clys, warm ? p->d_cly : nullptr, nullptr,
+                   stats ? stats + size_t(t) * B : nullptr, now_ms());
+    if (rc < 0) return rc;
+    all = all && rc == DLMPC_OK;
+    if ((rc = p->beng->plant_step(p->d_clx, p->d_clu, xs_dev, us_dev, t, T_sim, B, err))) return fail(rc, err);
+    if (warm && (rc = p->beng->shift_inputs(p->d_cly, p->d_clys, B, err))) return fail(rc, err);
+  }
+  API_HIP(hipStreamSynchronize(p->stream));
+  return all ? DLMPC_OK : DLMPC_ENOCONV;
+}
 
 int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,
                        int32_t check_iters, dlmpc_stats *stats, dlmpc_stream_info *info) {

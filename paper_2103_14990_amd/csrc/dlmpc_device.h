@@ -217,6 +217,13 @@ class BatchEngine {
   // One kernel of an iteration: 0 bphi_kernel, 1 bpsi_kernel, 2 bdecide_kernel.
   virtual int launch_one(int k, std::string &err) = 0;
   virtual int output(double *u0_dev, std::string &err) = 0;
+  // Closed loop (Algorithm 1), FP64: x(t+1) = A x(t) + B u(t) for B instances in place in x_dev
+  // [B][N*nx] (u_dev [B][N*nu]), with x(t) (at t = 0), x(t+1) and u(t) stored in the loop's
+  // trajectories xs_dev [B][T_sim+1][N*nx] and us_dev [B][T_sim][N*nu].
+  virtual int plant_step(double *x_dev, const double *u_dev, double *xs_dev, double *us_dev, int t, int T_sim,
+                         int B, std::string &err) = 0;
+  // Input rows of y_dev [B][N*rs] moved one step ahead (last held) into ys_dev.
+  virtual int shift_inputs(const double *y_dev, double *ys_dev, int B, std::string &err) = 0;
   // FP64 check of the stopping iterate of every instance of the batch (x0_dev [B][N*nx], the
   // solve's FP64 initial states): results in the per-instance control blocks (BCtl eq_resid,
   // box, u0dev, objective64).

@@ -118,6 +118,8 @@ EXPORTS = {
     "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_solve_stream": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p]),
+    "dlmpc_closed_loop": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_int32, C.c_void_p]),
     "dlmpc_solve_stream_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                              C.c_void_p, C.c_void_p]),
     "dlmpc_solve_batch_ex": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
@@ -332,6 +334,17 @@ class Problem:
         s = self._check(self._lib.dlmpc_solve_stream(self._h, n, C.c_void_p(x0_dev), C.c_void_p(u0_dev),
                                                       refill_min, check_iters, st, C.byref(info)))
         return s, [x.as_dict() for x in st], info.as_dict()
+
+    def closed_loop(self, B: int, T_sim: int, x0_dev: int, xs_dev: int, us_dev: int,
+                    warm: bool = False) -> tuple[int, list[list[dict]]]:
+        """B closed loops of T_sim steps (Algorithm 1) from x0_dev [B][N*nx]; xs_dev
+        [B][T_sim+1][N*nx] and us_dev [B][T_sim][N*nu] receive the state and input trajectories
+        (device pointers of float64 buffers). Returns (status, stats[t][b])."""
+        st = (Stats * (B * T_sim))()
+        s = self._check(self._lib.dlmpc_closed_loop(self._h, B, T_sim, C.c_void_p(x0_dev), C.c_void_p(xs_dev),
+                                                     C.c_void_p(us_dev), 1 if warm else 0, st))
+        flat = [x.as_dict() for x in st]
+        return s, [flat[t * B:(t + 1) * B] for t in range(T_sim)]
 
     def solve_stream_noalloc(self, n: int, x0_dev: int, u0_dev: int, refill_min: int = 0,
                              check_iters: int = 0) -> tuple[int, list[dict], dict]:

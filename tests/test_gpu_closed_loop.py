@@ -1,0 +1,109 @@
+"""Closed-loop MPC (Algorithm 1) on the device against the closed-loop oracle (needs a GPU).
+
+The library runs B loops at once: each step a batched solve from the measured state, u(t) read
+from Phi, and the FP64 plant step on the device. The oracle (oracle/closed_loop.py, pinned by the
+receding-horizon LQR loop) runs the same loop in FP64 with the same start at every step (cold,
+or the previous input trajectory shifted one step ahead, with the library's default eps scale of
+warm starts and CG steps). Bar (reduced precision, as for single solves): per step u(t) within
+1e-4 relative of the oracle's, the states within 1e-4 relative over the whole loop, iteration
+counts within a few (the shifted start is built with FP32 CG steps on the device and FP64 CG in
+the oracle: nearby, not equal, starts). The shifted start saves iterations over the loop.
+"""
+import numpy as np
+import pytest
+
+from oracle import closed_loop as CL
+from oracle import dlmpc_oracle as O
+from paper_2103_14990_amd import dlmpc
+from paper_2103_14990_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+T_SIM = 10
+WARM_EPS_SCALE = 0.5  # the library default
+CG = 12               # the library default
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def grid8():
+    wl = W.workload("grid8")
+    return wl, O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_closed_loop_matches_oracle(torch, grid8, warm):
+    wl, pb = grid8
+    seeds = [9, 4]
+    B, G, nx, nu = len(seeds), wl.net.n_sub, wl.net.nx, wl.net.nu
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps, max_iter=1000,
+                                    precision="fp32", max_batch=4)
+    x0 = np.stack([wl.x0(s) for s in seeds])
+    xd = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    xs = torch.zeros((B, T_SIM + 1, G * nx), dtype=torch.float64, device="cuda")
+    us = torch.zeros((B, T_SIM, G * nu), dtype=torch.float64, device="cuda")
+    st, stats = pr.closed_loop(B, T_SIM, xd.data_ptr(), xs.data_ptr(), us.data_ptr(), warm=warm)
+    assert st == dlmpc.OK
+    xs, us = xs.cpu().numpy(), us.cpu().numpy()
+    for b, sd in enumerate(seeds):
+        ref = CL.closed_loop(pb, x0[b], T_SIM, wl.rho, wl.eps, 1000, warm=warm, eps_warm=WARM_EPS_SCALE * wl.eps,
+                             cg_iters=CG)
+        it_g = [stats[t][b]["iters"] for t in range(T_SIM)]
+        eu = max(_rel(us[b, t], ref.u[t]) for t in range(T_SIM))
+        ex = _rel(xs[b], ref.x)
+        print(f"  seed {sd} warm {warm}: iters gpu {it_g}\n      oracle {ref.iters}; u rel {eu:.2e}, x rel {ex:.2e}",
+              flush=True)
+        assert np.array_equal(xs[b, 0], x0[b])
+        assert all(ref.converged) and all(stats[t][b]["converged"] for t in range(T_SIM))
+        for t in range(T_SIM):
+            slack = 3 if (not warm or t == 0) else max(3, 0.1 * ref.iters[t])
+            assert abs(it_g[t] - ref.iters[t]) <= slack, t
+        assert eu < 1e-4 and ex < 1e-4
+        # every returned state is the plant step of the previous one (FP64 on the device)
+        A, Bm = wl.net.dense_A(), wl.net.dense_B()
+        for t in range(T_SIM):
+            assert np.abs(xs[b, t + 1] - (A @ xs[b, t] + Bm @ us[b, t])).max() <= 1e-12 * np.abs(xs[b]).max()
+
+
+def test_shifted_start_saves_iterations_on_device(torch, grid8):
+    wl, _ = grid8
+    B = 8
+    G, nx, nu = wl.net.n_sub, wl.net.nx, wl.net.nu
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps, max_iter=1000,
+                                    precision="fp32", max_batch=B)
+    xd = torch.tensor(np.stack([wl.x0(3000 + i) for i in range(B)]), dtype=torch.float64, device="cuda")
+    its = {}
+    for warm in (False, True):
+        xs = torch.zeros((B, 21, G * nx), dtype=torch.float64, device="cuda")
+        us = torch.zeros((B, 20, G * nu), dtype=torch.float64, device="cuda")
+        st, stats = pr.closed_loop(B, 20, xd.data_ptr(), xs.data_ptr(), us.data_ptr(), warm=warm)
+        assert st == dlmpc.OK
+        its[warm] = sum(q["iters"] for row in stats[1:] for q in row)
+        print(f"  warm {warm}: mean iterations per step {[round(np.mean([q['iters'] for q in r]), 1) for r in stats]}; "
+              f"fell back {sum(q['fell_back'] for r in stats for q in r)}", flush=True)
+    print(f"  iterations over steps 1..19 of 8 loops: cold {its[False]}, shifted {its[True]}", flush=True)
+    assert its[True] < its[False]
+
+
+def test_closed_loop_argument_errors(torch, grid8):
+    wl, _ = grid8
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, precision="fp32", max_batch=2)
+    x = torch.zeros((2, wl.net.n_sub * 2), dtype=torch.float64, device="cuda")
+    xs = torch.zeros((2, 3, wl.net.n_sub * 2), dtype=torch.float64, device="cuda")
+    us = torch.zeros((2, 2, wl.net.n_sub), dtype=torch.float64, device="cuda")
+    with pytest.raises(dlmpc.DlmpcError):
+        pr.closed_loop(3, 2, x.data_ptr(), xs.data_ptr(), us.data_ptr())  # above max_batch
+    with pytest.raises(dlmpc.DlmpcError):
+        pr.closed_loop(2, 0, x.data_ptr(), xs.data_ptr(), us.data_ptr())
+    x[1, 3] = float("nan")
+    with pytest.raises(dlmpc.DlmpcError):
+        pr.closed_loop(2, 2, x.data_ptr(), xs.data_ptr(), us.data_ptr())
