@@ -45,9 +45,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_hash(kernel: str) -> str:
+    """sha256 (first 16 hex) of the kernel's own source text: from the template line before its
+    definition to the next section marker of batch_kernels.hip."""
+    src = open(KERNEL_SRC).read()
+    at = src.index(f" void {kernel}(")
+    start = src.rfind("\ntemplate", 0, at) + 1
+    end = src.find("\n// ------", at)
+    return hashlib.sha256(src[start:end if end > 0 else len(src)].encode()).hexdigest()[:16]
 
 
 def batch_algorithmic_bytes(info: dict, n_sub: int, rs: int, B: int, basis_bytes: int = 4) -> dict:
@@ -176,7 +181,7 @@ def traffic_record(workload: str, kernel: str, launches_bytes: float):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha") != kernel_source_hash():
+    if rec.get("kernel_source_sha") != kernel_source_hash(kernel):
         return None
     return rec.get("traffic_bytes_per_launch")
 
