@@ -17,9 +17,9 @@ start; u(0) of cold, learned and streamed solves against the exact optimum (orac
 eps = 1e-8, stored values); per-instance latency statistics over 100 x0 (single-instance FP32,
 plain FP64 cold, batched, streamed); the 10-node chain (FP64, iteration floor) and the 16x16 box
 grid (FP64 vs FP32); the reduced-operator tier; a group of three networks; the roofline of the
-dominant kernel (HIP events around each launch); and the CPU oracle timed on a bounded sample on
-one core and on all cores. `--cpu-full` times the full oracle instead (every column block, one
-whole iteration), a run of its own.
+dominant kernel (HIP events around each launch); and the CPU oracle timed on the full workload (one
+whole iteration, every column block factored first) on one core and on all cores, in a child
+process (`--cpu-full`).
 
 Prints one JSON line: value = ADMM iterations per second over the timed steps (instance
 iterations, whole job); time_to_eps_ms = device-and-host wall time per MPC solve.
@@ -95,43 +95,29 @@ def _oracle_iteration(O, pb, x0, rho):
     return t3 - t2, t4 - t3, t5 - t4
 
 
-def cpu_baseline(wl, oracle_iters: float, sample_blocks: int = 16) -> dict:
-    """The FP64 oracle as it stands, timed on a bounded sample: Phi-comp, Lambda-comp and the
-    convergence norms on the full problem, Psi-comp on `sample_blocks` seeded column blocks
-    scaled to all N; once with one thread and once with every host core (NumPy's BLAS threads).
-    Time-to-eps estimate: one iteration times the oracle's iteration count on these x0."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
-    from oracle import dlmpc_oracle as O
-
-    cores = os.cpu_count() or 1
+def cpu_baseline(wl, oracle_iters: float) -> dict:
+    """The FP64 oracle as it stands, on the full workload: a child process (it touches no GPU)
+    factors every column block (one process per host core) and times one whole ADMM iteration
+    from the cold start on one thread and on every core; time-to-eps = that iteration times the
+    oracle's iteration count on these x0 (its own stored runs)."""
+    import subprocess
     t0 = time.perf_counter()
-    with threadpool_limits(limits=1):
-        pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost, blocks=False)
-        Z = O.build_zab(pb.A, pb.B, pb.lay.T)
-        rng = np.random.default_rng(0)
-        js = sorted(rng.choice(wl.net.n_sub, sample_blocks, replace=False).tolist())
-        t1 = time.perf_counter()
-        pb.blocks = [O.column_block(Z, pb.mask, pb.lay, j) for j in js]
-        t_fac = time.perf_counter() - t1
-    x0 = wl.x0(1000)
-    n = wl.net.n_sub
-    per = {}
-    for label, lim in (("1", 1), ("all", cores)):
-        with threadpool_limits(limits=lim):
-            ph, ps, rest = _oracle_iteration(O, pb, x0, wl.rho)
-        per[label] = ph + ps * n / sample_blocks + rest
-    s1 = per["1"]
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-full", "--workload", wl.name],
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle timing failed: {r.stderr[-2000:]}")
+    full = json.loads(r.stdout.strip().splitlines()[-1])
+    s1, sa = full["1_core"]["iteration_s"], full["all_cores"]["iteration_s"]
     return {"value": round(1.0 / s1, 4), "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one ADMM iteration of the FP64 oracle: Phi-comp, Lambda-comp and Conv on all {n} "
-                       f"subsystems, Psi-comp on {sample_blocks} seeded column blocks scaled x{n / sample_blocks:.0f}; "
-                       f"setup factorisation of those blocks {t_fac:.1f} s (~{t_fac * n / sample_blocks:.0f} s "
-                       f"for all, one core)"),
-            "all_cores": {"value": round(1.0 / per["all"], 4), "unit": "iter/s", "cores": cores},
+            "sample": (f"one whole ADMM iteration of the FP64 oracle on the full workload ({wl.net.n_sub} "
+                       f"subsystems, every column block), cold start at x0 seed 1000; column blocks factored "
+                       f"beforehand in {full['nproc']} processes ({full['setup_s_all_cores']} s)"),
+            "all_cores": {"value": round(1.0 / sa, 4), "unit": "iter/s", "cores": full["nproc"]},
+            "iteration_s": {"1_core": full["1_core"], "all_cores": full["all_cores"]},
             "time_to_eps_ms_est": round(1e3 * s1 * oracle_iters, 1),
-            "time_to_eps_ms_est_all_cores": round(1e3 * per["all"] * oracle_iters, 1),
-            "oracle_iters": oracle_iters, "nproc": cores,
+            "time_to_eps_ms_est_all_cores": round(1e3 * sa * oracle_iters, 1),
+            "oracle_iters": oracle_iters, "nproc": full["nproc"],
+            "setup_s_all_cores": full["setup_s_all_cores"],
             "wall_s": round(time.perf_counter() - t0, 2)}
 
 
@@ -147,7 +133,7 @@ _FULL = {}
 def cpu_full(wl) -> dict:
     """The full oracle on this workload: every column block factored (the oracle's own
     column_block, in a process per core), then one whole iteration on one thread and on every
-    core. Minutes; a run of its own (--cpu-full)."""
+    core (--cpu-full; run in a child process by cpu_baseline)."""
     import multiprocessing as mp
 
     from threadpoolctl import threadpool_limits
@@ -211,7 +197,7 @@ def main() -> int:
     ap.add_argument("--refill-min", type=int, default=0, help="free slots before new instances join (0: an eighth)")
     ap.add_argument("--check-iters", type=int, default=0, help="iterations between host checks (0: 16)")
     ap.add_argument("--cg-iters", type=int, default=0, help="CG steps of the trajectory start (0: library default 12)")
-    ap.add_argument("--train-solves", type=int, default=8192)
+    ap.add_argument("--train-solves", type=int, default=20000)
     ap.add_argument("--train-steps", type=int, default=10000)
     ap.add_argument("--hidden", type=int, default=64)
     ap.add_argument("--x3-share", type=float, default=0.0,
