@@ -80,6 +80,10 @@ typedef enum {
                                             the solve with DLMPC_EDEVICE */
 #define DLMPC_FLAG_HOST_FACTOR 0x8u /* factor the column blocks with host threads instead of the
                                        device kernels (host-only problems always do) */
+#define DLMPC_FLAG_NO_TUNE 0x20u   /* no autotuning at setup: graph schedule (unless the persistent
+                                      one is asked for), batched-engine kernel variants at their
+                                      defaults (1 instance tile per Phi-comp wave, Psi-comp split at
+                                      8x the mean basis cost); the tuning cache is not used */
 #define DLMPC_FLAG_NO_CHECK 0x10u  /* skip the FP64 check of the stopping iterate that every solve
                                       otherwise runs (stats kkt, eq_resid, u0_check are then 0) */
 
@@ -129,7 +133,9 @@ typedef struct {
                             to 1.7x farther from the exact optimum (u(0)) than the cold start's at
                             the same eps, and no farther at eps/2 (16x16 box grid and 1024-
                             subsystem mesh). Cold runs, including the cold fallback of a
-                            warm-started instance, use eps. */
+                            warm-started instance, use eps. A warm-started instance that reaches
+                            max_iter without meeting eps * warm_eps_scale but whose last iterate
+                            meets eps is kept (converged) instead of being solved again. */
 } dlmpc_options;
 
 /* Optional warm start (Algorithm 2 initial iterate): Psi^0 and Lambda^0 as values on the
@@ -194,6 +200,20 @@ typedef struct {
   int32_t factor_device; /* 1 if the column blocks were factored on the device, 0 on the host */
   int32_t factor_fallbacks; /* device factorisation: subsystems whose null basis came from the
                                Householder QR because Cholesky QR of S K met a tiny pivot */
+  /* Autotuner (dlmpc_setup). The single-instance schedule (graph or persistent, both timed over 32
+   * iterations) and the batched engine's kernel variants are chosen by timing at setup, or taken
+   * from the cache file named by the environment variable DLMPC_TUNE_CACHE (one line per problem
+   * signature: sizes, precision, max_batch and the device's architecture; appended after a timed
+   * setup). Batched variants: instance tiles per Phi-comp wave (1: each basis fragment feeds one
+   * 16-instance tile; 2: two, with half the waves loading it), and the split of heavy column blocks
+   * over several Psi-comp work units (the waves serving one patch): a block whose basis cost
+   * exceeds batch_psi_capx times the mean is split. */
+  int32_t batch_phi_ntw;    /* 1 or 2 (0 without a batched engine) */
+  int32_t batch_psi_capx;   /* 2, 4, 8, 16 or 1048576 (no split) */
+  int32_t batch_psi_units;  /* Psi-comp work units (blocks per launch) */
+  int32_t tune_cached;      /* 1 if the choices came from the cache */
+  double tune_phi_us[2];    /* per-launch us of the Phi-comp variants 1, 2 (0 if not timed) */
+  double tune_psi_us[5];    /* per-launch us of the Psi-comp splits 2, 4, 8, 16, none */
 } dlmpc_info;
 
 /* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the

@@ -194,16 +194,21 @@ __global__ __launch_bounds__(256) void bexport_alpha_kernel(BArgs a, double *out
 // order) are the left operand. The (tile, k-step) sequence of a wave is one flat loop whose
 // next step's operands are in flight while the current step's products run.
 // SPLIT: basis fragments as bf16 hi + lo (three products per tile); otherwise hi only (two).
-template <int NX, int NRT, bool SPLIT>
+// NTW: instance tiles per wave. 1: wave w serves instance tile w % 4 and half w / 4 of the tile
+// list; 2: instance tiles 2 (w % 2), 2 (w % 2) + 1 and quarter w / 2 of the tile list (each basis
+// fragment loaded by half as many waves, twice the accumulators). The parts are summed in a
+// fixed order.
+template <int NX, int NRT, bool SPLIT, int NTW>
 __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   constexpr int kFB = frag_block<SPLIT>();
+  constexpr int NPART = 2 * NTW;  // parts of m's tile list
   if (a.ctl->stop) return;
-  __shared__ float Ct[2][64][kBMax + 1];
+  __shared__ float Ct[NPART][64][kBMax + 1];
   __shared__ double red[kPhiThreads / 64][kBMax];
   __shared__ int64_t s_fb[kMaxPatch], s_w8[kMaxPatch];
   __shared__ int s_nkt[kMaxPatch];
   const int m = a.phi_order[blockIdx.x], tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nt = wave & 3, half = wave >> 2;
+  const int ntg = wave & (4 / NTW - 1), half = wave / (4 / NTW);  // instance-tile group, part
   const int rs = a.rs, B = a.ctl->batch;
   const bool warm = a.ctl->warm != 0;
   const bool cgm = a.phi_mode != 0;  // set-up pass: q = sum_j ||x0_j||^2 N_j eta_j
@@ -219,17 +224,28 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   }
   __syncthreads();
   constexpr int nrt = NRT;
-  f32x4 acc[NRT];
+  f32x4 acc[NRT][NTW];
 #pragma unroll
-  for (int rt = 0; rt < NRT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[rt][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // instance tiles of this wave that hold instances (wave-uniform); tiles past B are not loaded
+  int ntv = 0;
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) ntv += (ntg * NTW + u) * 16 < B;
   // from a cold start tau = eta = 0 before the third iteration
-  if ((cgm || warm || it >= 3) && nt * 16 < B && half < pm) {
-    const int b = nt * 16 + (lane & 15);
-    bf16x8 wh, wl, ah[NRT], al[NRT];
-    auto load_step = [&](int t, int kt, bf16x8 &ph, bf16x8 &pl, bf16x8 *qh, bf16x8 *ql) {
-      const int64_t wi = ((s_w8[t] + 4 * kt + (lane >> 4)) * a.Bw + b) * 8;
-      ph = load8(a.w_hi + wi);
-      pl = load8(a.w_lo + wi);
+  if ((cgm || warm || it >= 3) && ntv > 0 && half < pm) {
+    const int b0 = ntg * NTW * 16 + (lane & 15);
+    bf16x8 wh[NTW], wl[NTW], ah[NRT], al[NRT];
+    auto load_step = [&](int t, int kt, bf16x8 *ph, bf16x8 *pl, bf16x8 *qh, bf16x8 *ql) {
+      const int64_t wrow = (s_w8[t] + 4 * kt + (lane >> 4)) * a.Bw;
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        if (u >= ntv) break;
+        const int64_t wi = (wrow + b0 + 16 * u) * 8;
+        ph[u] = load8(a.w_hi + wi);
+        pl[u] = load8(a.w_lo + wi);
+      }
       const int64_t fb = s_fb[t] + lane * 8 + int64_t(kt) * kFB, stride = int64_t(s_nkt[t]) * kFB;
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt) {  // rows past rs are zero in the fragments
@@ -241,12 +257,12 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
     // the other run (no register copies between steps)
     // (the loads of the step after the last one repeat the last step: always issued, so that
     // the number of loads in flight is the same on every path)
-    bf16x8 wh2, wl2, ah2[NRT], al2[NRT];
+    bf16x8 wh2[NTW], wl2[NTW], ah2[NRT], al2[NRT];
     int t = half, kt = 0;
     auto advance = [&]() {
       int tn = t, kn = kt + 1;
       if (kn >= s_nkt[t]) {
-        tn = t + 2;
+        tn = t + NPART;
         kn = 0;
       }
       const bool more = tn < pm;
@@ -256,34 +272,46 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
       }
       return more;
     };
+    auto products = [&](const bf16x8 *qh, const bf16x8 *ql, const bf16x8 *ph, const bf16x8 *pl) {
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int u = 0; u < NTW; ++u) {
+          if (u >= ntv) break;
+          acc[rt][u] = SPLIT ? mfma3(qh[rt], ql[rt], ph[u], pl[u], acc[rt][u]) : mfma2(qh[rt], ph[u], pl[u], acc[rt][u]);
+        }
+    };
     load_step(t, kt, wh, wl, ah, al);
     while (true) {
       bool more = advance();
       load_step(t, kt, wh2, wl2, ah2, al2);
       __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the products
-#pragma unroll
-      for (int rt = 0; rt < NRT; ++rt)
-        acc[rt] = SPLIT ? mfma3(ah[rt], al[rt], wh, wl, acc[rt]) : mfma2(ah[rt], wh, wl, acc[rt]);
+      products(ah, al, wh, wl);
       if (!more) break;
       more = advance();
       load_step(t, kt, wh, wl, ah, al);
       __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int rt = 0; rt < NRT; ++rt)
-        acc[rt] = SPLIT ? mfma3(ah2[rt], al2[rt], wh2, wl2, acc[rt]) : mfma2(ah2[rt], wh2, wl2, acc[rt]);
+      products(ah2, al2, wh2, wl2);
       if (!more) break;
     }
   }
-  // C tile: lane holds rows 16 rt + 4 (lane / 16) + e of instance column 16 nt + lane % 16
+  // C tile: lane holds rows 16 rt + 4 (lane / 16) + e of instance column 16 (ntg NTW + u) + lane % 16
 #pragma unroll
   for (int rt = 0; rt < nrt; ++rt)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) Ct[half][rt * 16 + 4 * (lane >> 4) + e][nt * 16 + (lane & 15)] = acc[rt][e];
+    for (int u = 0; u < NTW; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        Ct[half][rt * 16 + 4 * (lane >> 4) + e][(ntg * NTW + u) * 16 + (lane & 15)] = acc[rt][u][e];
   __syncthreads();
+  auto csum = [&](int l, int b) {
+    if constexpr (NPART == 2) return Ct[0][l][b] + Ct[1][l][b];
+    else return (Ct[0][l][b] + Ct[1][l][b]) + (Ct[2][l][b] + Ct[3][l][b]);
+  };
   if (cgm) {
     for (int idx = tid; idx < rs * B; idx += blockDim.x) {
       const int l = idx / B, b = idx - l * B;
-      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = Ct[0][l][b] + Ct[1][l][b];
+      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = csum(l, b);
     }
     return;
   }
@@ -292,7 +320,7 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
     const int l = idx / B, b = idx - l * B;
     const int ph = a.phase[b];
     if (ph >= 1 && ph <= a.ctl->cg_k && !a.ictl[b].stop)
-      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = Ct[0][l][b] + Ct[1][l][b];
+      a.cg_q[int64_t(b) * a.N * rs + int64_t(m) * rs + l] = csum(l, b);
   }
   // Row update: thread (instance b, row group lg) handles rows lg, lg + 8, ... of m, and the
   // sum of (alpha - alpha_prev)^2 over m's rows (the residual term Psi-comp needs) per instance.
@@ -307,7 +335,7 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
       const int64_t o = int64_t(m) * rs + l;
       const int64_t rb = o * a.Bmax + b;  // consecutive instances: consecutive addresses
       const float ap = a.alpha[prev * plane + rb];
-      const float av = coef * a.bvec[rb] + (Ct[0][l][b] + Ct[1][l][b]) - n * ap;
+      const float av = coef * a.bvec[rb] + csum(l, b) - n * ap;
       float sv, al;
       if (n > 0.f) {
         sv = a.rho * av / (a.rho + 2.f * a.w[o] * n);
@@ -1143,6 +1171,63 @@ __global__ void bfrag_kernel(const double *__restrict__ nb, const int64_t *__res
   }
 }
 
+// Psi-comp work units: column blocks whose basis is more than capx times the mean are split into
+// np row ranges of whole kKC-row chunks, so that a heavy patch is served by np blocks (more waves
+// per patch) whose partial sums the last one adds; units are dispatched heaviest first.
+// Candidates of the autotuner; the default 8 was the fastest on the 1024 mesh when fixed by hand
+// (splitting blocks of two to four times the mean cost more in partial sums than it gained).
+constexpr int kPsiCaps[] = {2, 4, 8, 16, 1 << 20};
+constexpr int kPsiCapDefault = 8;
+
+struct PsiSplit {
+  std::vector<int32_t> pu_j, pu_r0, pu_r1, pu_p, pj_n, pj_first;
+  std::vector<int64_t> pj_off;
+  int64_t poff = 0;
+  int32_t pfirst = 0;
+};
+
+PsiSplit psi_split(const HostSetup &hs, int capx) {
+  const int N = hs.N;
+  std::vector<int64_t> cost(N);
+  int64_t csum = 0;
+  for (int j = 0; j < N; ++j) {
+    const int64_t D = int64_t(hs.patch[j].size()) * hs.rs;
+    cost[j] = ((D + kKC - 1) / kKC * kKC) * ((hs.kdim[j] + 15) & ~15);
+    csum += cost[j];
+  }
+  const int64_t cap = std::max<int64_t>(1, int64_t(capx) * csum / N);
+  struct Unit { int32_t j, r0, r1, p; int64_t c; };
+  std::vector<Unit> units;
+  PsiSplit sp;
+  sp.pj_n.assign(N, 1);
+  sp.pj_first.assign(N, 0);
+  sp.pj_off.assign(N, 0);
+  for (int j = 0; j < N; ++j) {
+    const int D = int(hs.patch[j].size()) * hs.rs, chunks = (D + kKC - 1) / kKC;
+    const int np = int(std::min<int64_t>(chunks, (cost[j] + cap - 1) / cap));
+    const int per = (chunks + np - 1) / np;
+    int p = 0;
+    for (int c0 = 0; c0 < chunks; c0 += per, ++p)
+      units.push_back({j, kKC * c0, kKC * std::min(chunks, c0 + per), p,
+                       cost[j] * (std::min(chunks, c0 + per) - c0) / chunks});
+    sp.pj_n[j] = p;
+    if (p > 1) {
+      sp.pj_off[j] = sp.poff;
+      sp.pj_first[j] = sp.pfirst;
+      sp.poff += int64_t(p) * ((hs.kdim[j] + 15) & ~15) * kBMax;
+      sp.pfirst += p;
+    }
+  }
+  std::stable_sort(units.begin(), units.end(), [](const Unit &x, const Unit &y) { return x.c > y.c; });
+  for (const Unit &u : units) {
+    sp.pu_j.push_back(u.j);
+    sp.pu_r0.push_back(u.r0);
+    sp.pu_r1.push_back(u.r1);
+    sp.pu_p.push_back(u.p);
+  }
+  return sp;
+}
+
 template <int NX>
 class BatchEngineT final : public BatchEngine {
  public:
@@ -1192,48 +1277,17 @@ class BatchEngineT final : public BatchEngine {
       }
     }
     a.ktot = koff[N];
-    // Psi-comp work units: column blocks whose basis is more than eight times the mean are
-    // split into np row ranges of whole kKC-row chunks (measured: splitting blocks of two to
-    // four times the mean costs more in partial sums than it gains in balance); units are
-    // dispatched heaviest first.
-    std::vector<int64_t> cost(N);
-    int64_t csum = 0;
-    for (int j = 0; j < N; ++j) {
-      const int64_t D = int64_t(hs.patch[j].size()) * hs.rs;
-      cost[j] = ((D + kKC - 1) / kKC * kKC) * ((hs.kdim[j] + 15) & ~15);
-      csum += cost[j];
-    }
-    const int64_t cap = std::max<int64_t>(1, 8 * csum / N);
-    struct Unit { int32_t j, r0, r1, p; int64_t c; };
-    std::vector<Unit> units;
-    std::vector<int32_t> pj_n(N, 1), pj_first(N, 0);
-    std::vector<int64_t> pj_off(N, 0);
-    int64_t poff = 0;
-    int32_t pfirst = 0;
-    for (int j = 0; j < N; ++j) {
-      const int D = int(hs.patch[j].size()) * hs.rs, chunks = (D + kKC - 1) / kKC;
-      const int np = int(std::min<int64_t>(chunks, (cost[j] + cap - 1) / cap));
-      const int per = (chunks + np - 1) / np;
-      int p = 0;
-      for (int c0 = 0; c0 < chunks; c0 += per, ++p)
-        units.push_back({j, kKC * c0, kKC * std::min(chunks, c0 + per), p,
-                         cost[j] * (std::min(chunks, c0 + per) - c0) / chunks});
-      pj_n[j] = p;
-      if (p > 1) {
-        pj_off[j] = poff;
-        pj_first[j] = pfirst;
-        poff += int64_t(p) * ((hs.kdim[j] + 15) & ~15) * kBMax;
-        pfirst += p;
-      }
-    }
-    std::stable_sort(units.begin(), units.end(), [](const Unit &x, const Unit &y) { return x.c > y.c; });
-    n_units_ = int(units.size());
-    std::vector<int32_t> pu_j(n_units_), pu_r0(n_units_), pu_r1(n_units_), pu_p(n_units_);
-    for (int q = 0; q < n_units_; ++q) {
-      pu_j[q] = units[q].j;
-      pu_r0[q] = units[q].r0;
-      pu_r1[q] = units[q].r1;
-      pu_p[q] = units[q].p;
+    // Psi-comp work units (waves per patch): the default split and the largest any candidate of
+    // the autotuner needs (buffers sized for it)
+    PsiSplit sp = psi_split(hs, kPsiCapDefault);
+    size_t max_units = 0;
+    int64_t max_poff = 1;
+    int32_t max_pfirst = 1;
+    for (int capx : kPsiCaps) {
+      const PsiSplit c = psi_split(hs, capx);
+      max_units = std::max(max_units, c.pu_j.size());
+      max_poff = std::max(max_poff, c.poff);
+      max_pfirst = std::max(max_pfirst, c.pfirst);
     }
     // Phi-comp dispatch order: row subsystems with the most tiles first
     std::vector<int32_t> fo(N);
@@ -1301,14 +1355,27 @@ class BatchEngineT final : public BatchEngine {
         (rc = up(hs.kdim, &a.kdim, err)) || (rc = up(hs.tile_rsub, &a.tile_rsub, err)) ||
         (rc = up(koff, &a.koff, err)) || (rc = up(ntf_off, &a.ntf_off, err)) || (rc = up(nf_off, &a.nf_off, err)) ||
         (rc = up(hs.off_ptr, &a.off_ptr, err)) || (rc = up(on2, &a.onorm2, err)) ||
-        (rc = up(hs.w, &a.w64, err)) || (rc = up(fo, &a.phi_order, err)) || (rc = up(pu_j, &a.pu_j, err)) ||
-        (rc = up(pu_r0, &a.pu_r0, err)) || (rc = up(pu_r1, &a.pu_r1, err)) || (rc = up(pu_p, &a.pu_p, err)) ||
-        (rc = up(pj_n, &a.pj_n, err)) || (rc = up(pj_first, &a.pj_first, err)) || (rc = up(pj_off, &a.pj_off, err)))
+        (rc = up(hs.w, &a.w64, err)) || (rc = up(fo, &a.phi_order, err)))
       return rc;
-    if ((rc = al(&a.ppart, size_t(std::max<int64_t>(poff, 1)), err)) ||
-        (rc = al(&a.ppod, size_t(std::max<int32_t>(pfirst, 1)) * kBMax * 8 * NX, err)) ||
-        (rc = al(&a.pcnt, size_t(N), err)))
+    int32_t *d_pu_j = nullptr, *d_pu_r0 = nullptr, *d_pu_r1 = nullptr, *d_pu_p = nullptr;
+    int32_t *d_pj_n = nullptr, *d_pj_first = nullptr;
+    int64_t *d_pj_off = nullptr;
+    if ((rc = al(&d_pu_j, max_units, err)) || (rc = al(&d_pu_r0, max_units, err)) ||
+        (rc = al(&d_pu_r1, max_units, err)) || (rc = al(&d_pu_p, max_units, err)) ||
+        (rc = al(&d_pj_n, size_t(N), err)) || (rc = al(&d_pj_first, size_t(N), err)) ||
+        (rc = al(&d_pj_off, size_t(N), err)))
       return rc;
+    a.pu_j = d_pu_j;
+    a.pu_r0 = d_pu_r0;
+    a.pu_r1 = d_pu_r1;
+    a.pu_p = d_pu_p;
+    a.pj_n = d_pj_n;
+    a.pj_first = d_pj_first;
+    a.pj_off = d_pj_off;
+    if ((rc = al(&a.ppart, size_t(max_poff), err)) ||
+        (rc = al(&a.ppod, size_t(max_pfirst) * kBMax * 8 * NX, err)) || (rc = al(&a.pcnt, size_t(N), err)))
+      return rc;
+    if ((rc = load_split(sp, kPsiCapDefault, err))) return rc;
     BENG_CHECK(hipMemset(a.pcnt, 0, sizeof(int32_t) * N));
     std::vector<float> offf(hs.off.begin(), hs.off.end()), wf(hs.w.begin(), hs.w.end()),
         lbf(hs.lb.begin(), hs.lb.end()), ubf(hs.ub.begin(), hs.ub.end());
@@ -1554,6 +1621,27 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
+  int set_variant(int phi_ntw, int psi_capx, std::string &err) override {
+    if (phi_ntw != 1 && phi_ntw != 2) {
+      err = "Phi-comp instance tiles per wave must be 1 or 2";
+      return DLMPC_EINVAL;
+    }
+    bool known = false;
+    for (int c : kPsiCaps) known = known || c == psi_capx;
+    if (!known) {
+      err = "unknown Psi-comp split";
+      return DLMPC_EINVAL;
+    }
+    phi_ntw_ = phi_ntw;
+    if (psi_capx != psi_capx_) return load_split(psi_split(*hs_, psi_capx), psi_capx, err);
+    return DLMPC_OK;
+  }
+  void variant(int *phi_ntw, int *psi_capx, int *n_units) const override {
+    *phi_ntw = phi_ntw_;
+    *psi_capx = psi_capx_;
+    *n_units = n_units_;
+  }
+
   int check(const double *x0_dev, std::string &err) override {
     hipLaunchKernelGGL((bcheck_w_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
                        B_);
@@ -1625,6 +1713,23 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
+  // Psi-comp work units of one split into the engine's (preallocated) device arrays.
+  int load_split(const PsiSplit &sp, int capx, std::string &err) {
+    const size_t nu = sp.pu_j.size(), N = size_t(hs_->N);
+    BENG_CHECK(hipStreamSynchronize(stream_));
+    BENG_CHECK(hipMemcpy(const_cast<int32_t *>(args_.pu_j), sp.pu_j.data(), nu * 4, hipMemcpyHostToDevice));
+    BENG_CHECK(hipMemcpy(const_cast<int32_t *>(args_.pu_r0), sp.pu_r0.data(), nu * 4, hipMemcpyHostToDevice));
+    BENG_CHECK(hipMemcpy(const_cast<int32_t *>(args_.pu_r1), sp.pu_r1.data(), nu * 4, hipMemcpyHostToDevice));
+    BENG_CHECK(hipMemcpy(const_cast<int32_t *>(args_.pu_p), sp.pu_p.data(), nu * 4, hipMemcpyHostToDevice));
+    BENG_CHECK(hipMemcpy(const_cast<int32_t *>(args_.pj_n), sp.pj_n.data(), N * 4, hipMemcpyHostToDevice));
+    BENG_CHECK(hipMemcpy(const_cast<int32_t *>(args_.pj_first), sp.pj_first.data(), N * 4, hipMemcpyHostToDevice));
+    BENG_CHECK(hipMemcpy(const_cast<int64_t *>(args_.pj_off), sp.pj_off.data(), N * 8, hipMemcpyHostToDevice));
+    BENG_CHECK(hipMemset(args_.pcnt, 0, sizeof(int32_t) * N));
+    n_units_ = int(nu);
+    psi_capx_ = capx;
+    return DLMPC_OK;
+  }
+
   const HostSetup *hs_ = nullptr;
   hipStream_t stream_ = nullptr;
   BArgs args_{};
@@ -1643,11 +1748,18 @@ class BatchEngineT final : public BatchEngine {
   }
   template <bool SPLIT>
   void launch_phi_t(const BArgs &x) {
+    if (phi_ntw_ == 2)
+      launch_phi_n<SPLIT, 2>(x);
+    else
+      launch_phi_n<SPLIT, 1>(x);
+  }
+  template <bool SPLIT, int NTW>
+  void launch_phi_n(const BArgs &x) {
     switch (nrt_) {
-      case 1: hipLaunchKernelGGL((bphi_kernel<NX, 1, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
-      case 2: hipLaunchKernelGGL((bphi_kernel<NX, 2, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
-      case 3: hipLaunchKernelGGL((bphi_kernel<NX, 3, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
-      default: hipLaunchKernelGGL((bphi_kernel<NX, 4, SPLIT>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      case 1: hipLaunchKernelGGL((bphi_kernel<NX, 1, SPLIT, NTW>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      case 2: hipLaunchKernelGGL((bphi_kernel<NX, 2, SPLIT, NTW>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      case 3: hipLaunchKernelGGL((bphi_kernel<NX, 3, SPLIT, NTW>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
+      default: hipLaunchKernelGGL((bphi_kernel<NX, 4, SPLIT, NTW>), dim3(hs_->N), dim3(kPhiThreads), 0, stream_, x); break;
     }
   }
   template <bool SPLIT>
@@ -1660,6 +1772,8 @@ class BatchEngineT final : public BatchEngine {
     }
   }
   int nrt_ = 1, mtw_ = 1;
+  int phi_ntw_ = 1;  // instance tiles per Phi-comp wave (autotuned)
+  int psi_capx_ = kPsiCapDefault;  // Psi-comp split (autotuned)
   bool split_ = true;  // basis operands as bf16 hi + lo
   int B_ = 0;
   int64_t ny_ = 0;  // N * rs

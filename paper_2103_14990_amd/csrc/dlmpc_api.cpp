@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -29,6 +31,10 @@ struct dlmpc_problem {
   int K = 32;  // fixed chunk when check_every > 0; otherwise the first chunk
   int sched = 0;  // 0 = graph, 1 = persistent
   double tune_graph_us = 0.0, tune_persistent_us = 0.0;
+  // batched-engine autotuning: per-launch us of the Phi-comp variants (1, 2 instance tiles per
+  // wave) and of the Psi-comp splits (kPsiCaps order); 1 if the choice came from the cache
+  double tune_phi_us[2] = {0, 0}, tune_psi_us[5] = {0, 0, 0, 0, 0};
+  int32_t tune_cached = 0;
   Ctl *h_ctl = nullptr;  // pinned, 2 slots
   hipEvent_t ev_ctl[2] = {nullptr, nullptr};
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
@@ -175,6 +181,110 @@ int setup_device(dlmpc_problem *p) {
   return choose_schedule(p);
 }
 
+// Autotuner cache (file named by DLMPC_TUNE_CACHE): one line per problem signature,
+// "<signature>|phi_ntw=<1|2> psi_capx=<n> sched=<0|1>".
+std::string tune_signature(const dlmpc_problem *p) {
+  const HostSetup &h = p->hs;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, p->opt.device) == hipSuccess) arch = prop.gcnArchName;
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "N=%d nx=%d nu=%d T=%d nnz=%lld sumk=%lld sumdk=%lld dmax=%d bmax=%d prec=%d arch=%s",
+                h.N, h.nx, h.nu, h.T, static_cast<long long>(h.nnz), static_cast<long long>(h.sum_k),
+                static_cast<long long>(h.sum_dcol_k), h.d_col_max, p->opt.max_batch, p->opt.precision, arch.c_str());
+  return buf;
+}
+
+bool tune_cache_read(const std::string &sig, int *phi_ntw, int *psi_capx, int *sched) {
+  const char *path = std::getenv("DLMPC_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    std::string l(line);
+    const size_t bar = l.find('|');
+    if (bar == std::string::npos || l.substr(0, bar) != sig) continue;
+    int a = 0, b = 0, c = 0;
+    if (std::sscanf(l.c_str() + bar + 1, "phi_ntw=%d psi_capx=%d sched=%d", &a, &b, &c) == 3) {
+      *phi_ntw = a;
+      *psi_capx = b;
+      *sched = c;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_write(const std::string &sig, int phi_ntw, int psi_capx, int sched) {
+  const char *path = std::getenv("DLMPC_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s|phi_ntw=%d psi_capx=%d sched=%d\n", sig.c_str(), phi_ntw, psi_capx, sched);
+  std::fclose(f);
+}
+
+// Times the batched-engine variants with max_batch instances from a zero-multiplier start (every
+// launch does the full work; x0 = 1 everywhere) and keeps the fastest Phi-comp and Psi-comp.
+int tune_batch(dlmpc_problem *p) {
+  const HostSetup &hs = p->hs;
+  const int B = p->beng->bmax();
+  const size_t nx = size_t(B) * hs.N * hs.nx, nr = size_t(B) * hs.N * hs.rs;
+  std::vector<double> ones(nx, 1.0);
+  double *x = nullptr, *z = nullptr;
+  API_HIP(hipMalloc(&x, sizeof(double) * nx));
+  API_HIP(hipMalloc(&z, sizeof(double) * nr));
+  std::string err;
+  auto run = [&]() -> int {
+    API_HIP(hipMemcpy(x, ones.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
+    API_HIP(hipMemset(z, 0, sizeof(double) * nr));
+    int rc = p->beng->precompute(x, B, 1 << 20, -1.0, 1, err);
+    if (!rc) rc = p->beng->start_alpha(z, err);
+    if (rc) return fail(rc, err);
+    auto time_k = [&](int k, double *us) -> int {
+      float best = 1e30f;
+      for (int rep = 0; rep < 6; ++rep) {  // the first launch warms code and caches
+        API_HIP(hipEventRecord(p->ev_t0, p->stream));
+        int r = p->beng->launch_one(k, err);
+        if (r) return fail(r, err);
+        API_HIP(hipEventRecord(p->ev_t1, p->stream));
+        API_HIP(hipEventSynchronize(p->ev_t1));
+        float ms = 0.f;
+        API_HIP(hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1));
+        if (rep > 0) best = std::min(best, ms);
+      }
+      *us = 1e3 * best;
+      return DLMPC_OK;
+    };
+    int cur_ntw = 1, cur_cap = 8, nu = 0;
+    p->beng->variant(&cur_ntw, &cur_cap, &nu);
+    for (int v = 0; v < 2; ++v) {
+      if ((rc = p->beng->set_variant(v + 1, cur_cap, err))) return fail(rc, err);
+      if ((rc = time_k(0, &p->tune_phi_us[v]))) return rc;
+    }
+    // a candidate replaces the default only when it is faster by more than timing noise (1 %)
+    const int ntw = p->tune_phi_us[1] < 0.99 * p->tune_phi_us[0] ? 2 : 1;
+    static const int caps[5] = {2, 4, 8, 16, 1 << 20};
+    for (int c = 0; c < 5; ++c) {
+      if ((rc = p->beng->set_variant(ntw, caps[c], err))) return fail(rc, err);
+      if ((rc = time_k(1, &p->tune_psi_us[c]))) return rc;
+    }
+    int best_c = 2;  // the default split
+    for (int c = 0; c < 5; ++c)
+      if (p->tune_psi_us[c] < 0.99 * p->tune_psi_us[best_c]) best_c = c;
+    if ((rc = p->beng->set_variant(ntw, caps[best_c], err))) return fail(rc, err);
+    return DLMPC_OK;
+  };
+  const int rc = run();
+  (void)hipStreamSynchronize(p->stream);
+  (void)hipFree(x);
+  (void)hipFree(z);
+  return rc;
+}
+
 int setup_batch(dlmpc_problem *p) {
   const HostSetup &hs = p->hs;
   std::string err;
@@ -200,6 +310,18 @@ int setup_batch(dlmpc_problem *p) {
   API_HIP(hipMalloc(&p->d_clys, sizeof(double) * size_t(B) * R));
   API_HIP(hipEventCreate(&p->ev_w0));
   API_HIP(hipEventCreate(&p->ev_w1));
+  // kernel variants: from the tuning cache, else timed here (before the graphs are captured:
+  // they record the variant and the work-unit count), unless the caller fixed the defaults
+  if (!(p->opt.flags & DLMPC_FLAG_NO_TUNE)) {
+    int ntw = 0, capx = 0, sched = 0;
+    std::string err2;
+    if (tune_cache_read(tune_signature(p), &ntw, &capx, &sched) && !p->beng->set_variant(ntw, capx, err2)) {
+      p->tune_cached = 1;
+    } else {
+      rc = tune_batch(p);
+      if (rc) return rc;
+    }
+  }
   for (int joins = 0; joins < 2; ++joins)
     for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
       API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
@@ -310,6 +432,17 @@ int choose_schedule(dlmpc_problem *p) {
     p->sched = 1;
     return DLMPC_OK;
   }
+  if (f & DLMPC_FLAG_NO_TUNE) {
+    p->sched = 0;
+    return DLMPC_OK;
+  }
+  const std::string sig = tune_signature(p);
+  int ntw = 0, capx = 0, sched = 0;
+  if (!(f & DLMPC_FLAG_NO_TUNE) && tune_cache_read(sig, &ntw, &capx, &sched) && (sched == 0 || can_persist)) {
+    p->sched = sched;
+    p->tune_cached = 1;
+    return DLMPC_OK;
+  }
   const int n = 32;
   int rc = time_schedule(p, 0, n, &p->tune_graph_us);
   if (rc) return rc;
@@ -318,6 +451,13 @@ int choose_schedule(dlmpc_problem *p) {
     if (rc) return rc;
   }
   p->sched = (can_persist && p->tune_persistent_us < p->tune_graph_us) ? 1 : 0;
+  if (!(f & DLMPC_FLAG_NO_TUNE)) {
+    int nu = 0;
+    ntw = 1;
+    capx = 8;
+    if (p->beng) p->beng->variant(&ntw, &capx, &nu);
+    tune_cache_write(sig, ntw, capx, p->sched);
+  }
   return DLMPC_OK;
 }
 
@@ -529,6 +669,13 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   info->persistent_grid = (p->eng ? p->eng->persistent_grid() : 0);
   info->tune_graph_us = p->tune_graph_us;
   info->tune_persistent_us = p->tune_persistent_us;
+  info->batch_phi_ntw = 0;
+  info->batch_psi_capx = 0;
+  info->batch_psi_units = 0;
+  if (p->beng) p->beng->variant(&info->batch_phi_ntw, &info->batch_psi_capx, &info->batch_psi_units);
+  for (int v = 0; v < 2; ++v) info->tune_phi_us[v] = p->tune_phi_us[v];
+  for (int c = 0; c < 5; ++c) info->tune_psi_us[c] = p->tune_psi_us[c];
+  info->tune_cached = p->tune_cached;
   return DLMPC_OK;
 }
 
@@ -793,6 +940,19 @@ int run_batch_once(dlmpc_problem *p, int B, const double *x0_dev, int start, con
   return DLMPC_OK;
 }
 
+// A warm-started instance is kept when it met eps * warm_eps_scale, or when it ran out of
+// iterations but its last iterate meets the unscaled eps (the cold start's own rule; it is then
+// marked converged); otherwise it is solved again from the cold start.
+bool warm_accept(const dlmpc_problem *p, dlmpc::BCtl &ic) {
+  if (ic.numeric) return false;
+  if (ic.converged) return true;
+  if (ic.last_rp <= p->opt.eps && ic.last_rd <= p->opt.eps) {
+    ic.converged = 1;
+    return true;
+  }
+  return false;
+}
+
 void fill_stats(dlmpc_stats &st, const dlmpc::BCtl &ic, float ms, int checks, int start, double t0) {
   st.eq_resid = ic.eq_resid;
   st.u0_check = ic.u0dev;
@@ -824,11 +984,11 @@ int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, int
   const float ms = tm.iter, mw = tm.warm;
   std::vector<dlmpc::BCtl> first(p->h_bctl, p->h_bctl + B);
   std::vector<int> redo;
-  for (int b = 0; b < B; ++b)
-    if (stats) fill_stats(stats[b], first[b], ms, checks, start, t0);
   if (start != DLMPC_START_COLD)
     for (int b = 0; b < B; ++b)
-      if (!first[b].converged || first[b].numeric) redo.push_back(b);
+      if (!warm_accept(p, first[b])) redo.push_back(b);
+  for (int b = 0; b < B; ++b)
+    if (stats) fill_stats(stats[b], first[b], ms, checks, start, t0);
   if (!redo.empty()) {
     const int F = int(redo.size());
     for (int f = 0; f < F; ++f)
@@ -1068,15 +1228,15 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
   API_HIP(hipStreamSynchronize(p->stream));
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, p->ev_t0, p->ev_t1);
+  // Instances the warm start left unconverged (or with a NaN/Inf): cold batched solves.
+  std::vector<int> redo;
+  for (int i = 0; i < n; ++i)
+    if (!warm_accept(p, fin[i])) redo.push_back(i);
   for (int i = 0; i < n; ++i)
     if (stats) {
       fill_stats(stats[i], fin[i], ms, checks, DLMPC_START_LEARNED, t0);
       stats[i].t_solve_ms = t_lat[i];
     }
-  // Instances the warm start left unconverged (or with a NaN/Inf): cold batched solves.
-  std::vector<int> redo;
-  for (int i = 0; i < n; ++i)
-    if (!fin[i].converged || fin[i].numeric) redo.push_back(i);
   for (size_t r0 = 0; r0 < redo.size(); r0 += size_t(Bm)) {
     const int F = int(std::min(redo.size() - r0, size_t(Bm)));
     for (int f = 0; f < F; ++f)

@@ -214,6 +214,11 @@ class BatchEngine {
   virtual int export_y(double *y_dev, std::string &err) = 0;
   // One iteration (capturable); with `joins`, also the CG step of streamed joins.
   virtual int iteration(std::string &err, bool joins = false) = 0;
+  // Kernel variants (autotuned at setup): instance tiles per Phi-comp wave (1 or 2) and the
+  // Psi-comp split of heavy patches into several work units (basis cost above psi_capx times the
+  // mean; one of 2, 4, 8, 16, 1 << 20). Synchronises the engine's stream.
+  virtual int set_variant(int phi_ntw, int psi_capx, std::string &err) = 0;
+  virtual void variant(int *phi_ntw, int *psi_capx, int *n_units) const = 0;
   // One kernel of an iteration: 0 bphi_kernel, 1 bpsi_kernel, 2 bdecide_kernel.
   virtual int launch_one(int k, std::string &err) = 0;
   virtual int output(double *u0_dev, std::string &err) = 0;

@@ -25,6 +25,7 @@ FLAG_SCHED_GRAPH = 0x2
 FLAG_SCHED_PERSISTENT = 0x4
 FLAG_HOST_FACTOR = 0x8
 FLAG_NO_CHECK = 0x10
+FLAG_NO_TUNE = 0x20
 FACTORS = {"device": 0, "host": FLAG_HOST_FACTOR}
 SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16": FP32_BF16}
@@ -97,10 +98,16 @@ class Info(C.Structure):
                 ("setup_ms", C.c_double), ("factor_ms", C.c_double), ("schedule", C.c_int32),
                 ("persistent_grid", C.c_int32), ("tune_graph_us", C.c_double),
                 ("tune_persistent_us", C.c_double), ("sum_k", C.c_int64),
-                ("factor_device", C.c_int32), ("factor_fallbacks", C.c_int32)]
+                ("factor_device", C.c_int32), ("factor_fallbacks", C.c_int32),
+                ("batch_phi_ntw", C.c_int32), ("batch_psi_capx", C.c_int32), ("batch_psi_units", C.c_int32),
+                ("tune_cached", C.c_int32), ("tune_phi_us", C.c_double * 2), ("tune_psi_us", C.c_double * 5)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        out = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            out[f] = list(v) if isinstance(v, C.Array) else v
+        return out
 
 
 EXPORTS = {
@@ -217,7 +224,7 @@ class Problem:
                  device: int = 0, stream: int | None = None, check_every: int = 0,
                  host_only: bool = False, schedule: str = "auto", max_batch: int = 0,
                  warm_cg_iters: int = 0, factor: str = "device", factor_chol_tol: float = 0.0,
-                 warm_eps_scale: float = 0.0, check: bool = True):
+                 warm_eps_scale: float = 0.0, check: bool = True, tune: bool = True):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -232,7 +239,7 @@ class Problem:
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
                        (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule] | FACTORS[factor]
-                       | (0 if check else FLAG_NO_CHECK), max_batch,
+                       | (0 if check else FLAG_NO_CHECK) | (0 if tune else FLAG_NO_TUNE), max_batch,
                        warm_cg_iters, factor_chol_tol, warm_eps_scale)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:

@@ -25,7 +25,7 @@ def batch_problem(wl, max_batch=64, max_iter=MAXIT):
                                       precision="fp32", max_batch=max_batch)
 
 
-def check_instances(pb, x0s, u0, stats, n_check=None, iter_slack=3):
+def check_instances(pb, x0s, u0, stats, n_check=None, iter_slack=5):
     idx = range(len(x0s)) if n_check is None else np.linspace(0, len(x0s) - 1, n_check).astype(int)
     for i in idx:
         ref = O.solve(pb, x0s[i], RHO, EPS, MAXIT)
