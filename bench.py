@@ -507,21 +507,23 @@ def main() -> int:
 
     # ---- closed loop (Algorithm 1): B loops of 20 steps on the device (solve from x(t), apply
     # u(t), FP64 plant step), every step cold or from the previous input trajectory shifted one
-    # step ahead; whole-simulation time per MPC step (the paper's metric), per loop
+    # step ahead, with the fixed penalty rho or rho ||x(t)||^2 / ||x(0)||^2; whole-simulation
+    # time per MPC step (the paper's metric), per loop
     loop = {}
     if args.closed_loop:
         T_sim = 20
         xc0 = xl[:B].contiguous()
         xs_ = torch.zeros((B, T_sim + 1, n_x), dtype=torch.float64, device=dev)
         us_ = torch.zeros((B, T_sim, n_u), dtype=torch.float64, device=dev)
-        for warm in (False, True):
+        for warm, scale in ((False, False), (True, False), (False, True), (True, True)):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            st_, lst = pr.closed_loop(B, T_sim, xc0.data_ptr(), xs_.data_ptr(), us_.data_ptr(), warm=warm)
+            st_, lst = pr.closed_loop(B, T_sim, xc0.data_ptr(), xs_.data_ptr(), us_.data_ptr(), warm=warm,
+                                      scale_rho=scale)
             torch.cuda.synchronize()
             el = time.perf_counter() - t1
             it_step = [float(np.mean([q["iters"] for q in row])) for row in lst]
-            loop["shifted" if warm else "cold"] = {
+            loop[("shifted" if warm else "cold") + ("_scaled_rho" if scale else "_fixed_rho")] = {
                 "ms_per_mpc_step": round(1e3 * el / T_sim, 3),
                 "ms_per_mpc_step_per_loop": round(1e3 * el / (T_sim * B), 4),
                 "iters_mean_per_step": [round(v, 1) for v in it_step],

@@ -342,19 +342,32 @@ int dlmpc_solve_batch_ex(struct dlmpc_problem *p, int32_t B, const double *x0_de
                          int32_t start, const double *start_dev, double *y_out_dev,
                          double *alpha_out_dev, dlmpc_stats *stats);
 
+/* Modes of dlmpc_closed_loop (bit flags). */
+#define DLMPC_CL_SHIFT 1     /* steps t >= 1 start from the previous step's inputs, shifted */
+#define DLMPC_CL_SCALE_RHO 2 /* step t runs with rho * ||x(t)||^2 / ||x(0)||^2 */
+
 /* Closed-loop MPC (Algorithm 1) for B in 1..max_batch independent loops on this network: at
  * every step t = 0..T_sim-1 each loop measures its state x(t), solves the MPC subproblem from it
  * (a batched solve, as dlmpc_solve_batch_ex), applies u(t) = the u_0 block of Phi x(t) and moves
- * to x(t+1) = A x(t) + B u(t), all on the device (FP64 plant step). warm = 0: every step starts
- * cold; warm = 1: steps t >= 1 start from the previous step's input trajectory moved one step
- * ahead (u_1..u_{T-2} become u_0..u_{T-3}, the last input held), as DLMPC_START_TRAJECTORY, with
- * the cold fallback of a warm-started instance. Device buffers: x0_dev [B][N*nx] (x(0));
- * xs_dev [B][T_sim+1][N*nx] receives x(0)..x(T_sim) of each loop, us_dev [B][T_sim][N*nu]
- * u(0)..u(T_sim-1). stats (or NULL): [T_sim][B], step-major, each the step's batched-solve stats.
- * Returns DLMPC_OK when every step of every loop converged, DLMPC_ENOCONV otherwise (the loop
- * continues with the last iterate's u(t)), a negative status on error. */
+ * to x(t+1) = A x(t) + B u(t), all on the device (FP64 plant step). mode is 0 or a combination
+ * of:
+ *  - DLMPC_CL_SHIFT: steps t >= 1 start from the previous step's input trajectory moved one
+ *    step ahead (u_1..u_{T-2} become u_0..u_{T-3}, the last input held), as
+ *    DLMPC_START_TRAJECTORY, with the cold fallback of a warm-started instance; otherwise every
+ *    step starts cold.
+ *  - DLMPC_CL_SCALE_RHO: the ADMM penalty of step t is rho * max(||x(t)||^2 / ||x(0)||^2, 1e-20)
+ *    (rho when x(0) = 0). Scaling x(t) by s scales the Phi-step's cost by s^2, so ADMM from x(t)
+ *    with penalty rho s^2 runs the same Phi iterates as ADMM from x(t)/s with rho and bounds
+ *    divided by s: the iteration count no longer grows as the loop drives x(t) to 0 (with a
+ *    fixed rho the cost's weight relative to the penalty shrinks as ||x(t)||^2). The eps test
+ *    is on Phi, whose scale does not depend on x(t).
+ * Device buffers: x0_dev [B][N*nx] (x(0)); xs_dev [B][T_sim+1][N*nx] receives x(0)..x(T_sim) of
+ * each loop, us_dev [B][T_sim][N*nu] u(0)..u(T_sim-1). stats (or NULL): [T_sim][B], step-major,
+ * each the step's batched-solve stats. Returns DLMPC_OK when every step of every loop
+ * converged, DLMPC_ENOCONV otherwise (the loop continues with the last iterate's u(t)), a
+ * negative status on error (DLMPC_EINVAL for an unknown mode bit or a NaN/Inf in x0). */
 int dlmpc_closed_loop(struct dlmpc_problem *p, int32_t B, int32_t T_sim, const double *x0_dev, double *xs_dev,
-                      double *us_dev, int32_t warm, dlmpc_stats *stats);
+                      double *us_dev, int32_t mode, dlmpc_stats *stats);
 
 /* Counters of a streamed solve (dlmpc_solve_stream). */
 typedef struct {

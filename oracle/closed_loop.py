@@ -16,6 +16,12 @@ Two initial iterates per step:
   ``warm_start.trajectory_start`` (state rows simulated from x(t), CG on M beta = y - b, the
   multiplier guess), then Algorithm 2 with eps_warm; an unconverged warm-started step is solved
   again from the cold start with eps.
+
+Penalty per step: rho (the paper's fixed penalty), or, with scale_rho, rho times
+||x(t)||^2 / ||x(0)||^2 (at least 1e-20). The Phi-step minimises w (phi . x_r)^2 +
+(rho/2) ||phi - v||^2; with x(t) = s z this is s^2 [w (phi . z_r)^2 + (rho/(2 s^2)) ||phi - v||^2],
+so a penalty of rho s^2 at x(t) runs the Phi iterates of rho at z with the bounds divided by s:
+the iteration no longer slows down as the loop drives the state to zero.
 """
 from __future__ import annotations
 
@@ -47,14 +53,22 @@ class ClosedLoop:
     J: list  # objective of every step's solve
 
 
-def closed_loop(pb: O.Problem, x0: np.ndarray, T_sim: int, rho: float, eps: float, max_iter: int,
-                warm: bool = False, eps_warm: float | None = None, cg_iters: int = 12) -> ClosedLoop:
-    """Algorithm 1 over T_sim steps from x(0) = x0."""
+def step_rho(rho: float, x: np.ndarray, x0: np.ndarray) -> float:
+    """rho ||x||^2 / ||x0||^2, at least rho * 1e-20 (rho when x0 = 0)."""
+    n0 = float(np.dot(x0, x0))
+    return rho if n0 == 0.0 else rho * max(float(np.dot(x, x)) / n0, 1e-20)
+
+
+def closed_loop(pb: O.Problem, x0: np.ndarray, T_sim: int, rho0: float, eps: float, max_iter: int,
+                warm: bool = False, eps_warm: float | None = None, cg_iters: int = 12,
+                scale_rho: bool = False) -> ClosedLoop:
+    """Algorithm 1 over T_sim steps from x(0) = x0 (penalty rho0, or step_rho with scale_rho)."""
     eps_warm = eps if eps_warm is None else eps_warm
     x = np.asarray(x0, dtype=np.float64)
     xs, us, iters, conv, fb, Js = [x], [], [], [], [], []
     prev_y = None
     for _ in range(T_sim):
+        rho = step_rho(rho0, x, xs[0]) if scale_rho else rho0
         fell = False
         if warm and prev_y is not None:
             psi0, lam0, _, _ = WS.trajectory_start(pb, x, shift_inputs(pb.lay, prev_y), rho, cg_iters)

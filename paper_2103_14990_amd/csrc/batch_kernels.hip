@@ -96,9 +96,11 @@ __device__ __forceinline__ T wsum(T v) {
 template <int NX>
 __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double *x0, int B, int warm,
                                                           int max_iter, double eps, const int32_t *slots,
-                                                          const int32_t *xsrc, int reset, int join, int cg_k) {
+                                                          const int32_t *xsrc, int reset, int join, int cg_k,
+                                                          const double *rscale) {
   // instance blockIdx.y: slot slots[y] (or y), initial state row xsrc[y] (or y) of x0; reset:
-  // the solve starts here (global control block reset); otherwise the slot joins a running one
+  // the solve starts here (global control block reset); otherwise the slot joins a running one;
+  // rscale[y] (or 1): factor of the instance's penalty
   const int m = blockIdx.x, y = blockIdx.y, tid = threadIdx.x;
   const int b = slots ? slots[y] : y;
   const int rs = a.rs;
@@ -147,6 +149,7 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
     ic.numeric = 0;
     ic.it0 = reset ? 0 : a.ctl->iters;
     a.phase[b] = join ? 0 : -1;
+    a.rho_b[b] = rscale ? static_cast<float>(double(a.rho) * rscale[y]) : a.rho;
     if (y == 0) a.ctl->cg_k = cg_k;
     ic.last_rp = ic.last_rd = INFINITY;
     ic.objective = 0.0;
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
   const int b = tid & 63, lg = tid >> 6;
   double dl = 0.0;
   if (b < B && !a.ictl[b].stop && a.phase[b] < 0) {
-    const float n = a.nrm[int64_t(b) * a.N + m];
+    const float n = a.nrm[int64_t(b) * a.N + m], rho = a.rho_b[b];
     for (int l = lg; l < rs; l += kLG) {
       const int64_t o = int64_t(m) * rs + l;
       const int64_t rb = o * a.Bmax + b;  // consecutive instances: consecutive addresses
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
       const float av = coef * a.bvec[rb] + csum(l, b) - n * ap;
       float sv, al;
       if (n > 0.f) {
-        sv = a.rho * av / (a.rho + 2.f * a.w[o] * n);
+        sv = rho * av / (rho + 2.f * a.w[o] * n);
         sv = sv < a.lb[o] ? a.lb[o] : (sv > a.ub[o] ? a.ub[o] : sv);
         al = (sv - av) / n;
       } else {
@@ -941,7 +944,7 @@ __global__ __launch_bounds__(256) void bcheck_red_kernel(BArgs a, const double *
 // xs [B][T_sim+1][N*nx] (x(0) at t = 0) and us [B][T_sim][N*nu]. One block per instance.
 template <int NX>
 __global__ __launch_bounds__(256) void bplant_kernel(BArgs a, double *x, const double *u, double *xs, double *us,
-                                                     int t, int T_sim) {
+                                                     int t, int T_sim, double *rscale) {
   const int b = blockIdx.x, tid = threadIdx.x, N = a.N, nu = a.nu;
   double *xb = x + int64_t(b) * N * NX;
   const double *ub = u + int64_t(b) * N * nu;
@@ -972,7 +975,28 @@ __global__ __launch_bounds__(256) void bplant_kernel(BArgs a, double *x, const d
     for (int c = 0; c < NX; ++c) xnext[m * NX + c] = v[c];
   }
   __syncthreads();
-  for (int i = tid; i < N * NX; i += 256) xb[i] = xnext[i];
+  double n1 = 0.0, n0 = 0.0;
+  for (int i = tid; i < N * NX; i += 256) {
+    xb[i] = xnext[i];
+    n1 += xnext[i] * xnext[i];
+    n0 += xsb[i] * xsb[i];
+  }
+  if (rscale) {
+    // ||x(t+1)||^2 / ||x(0)||^2: the penalty factor of the next step's solve
+    __shared__ double red[2][4];
+    n1 = wsum(n1);
+    n0 = wsum(n0);
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = n1;
+      red[1][tid >> 6] = n0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double s1 = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+      const double s0 = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+      rscale[b] = s0 > 0.0 ? fmax(s1 / s0, 1e-20) : 1.0;
+    }
+  }
 }
 
 // Input rows of the trajectories y [B][N*rs] (library row order) moved one step ahead into ys:
@@ -1050,7 +1074,7 @@ __device__ __forceinline__ double block_sum1024(double v, double *red) {
   return s;
 }
 
-// r = yhat - b, p = r, x = 0, rr = r'r; alpha^0 = -2 w yhat / rho into plane `pl` (the one the
+// r = yhat - b, p = r, x = 0, rr = r'r; alpha^0 = -2 w yhat / rho_b into plane `pl` (the one the
 // next iteration reads as its previous iterate).
 __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *slots, int pl) {
   __shared__ double red[16];
@@ -1059,13 +1083,14 @@ __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *
   float *alpha = a.alpha + int64_t(pl < 0 ? 0 : pl) * plane;
   const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
   double acc = 0.0;
+  const float rho = a.rho_b[b];
   for (int64_t i = threadIdx.x; i < ny; i += 1024) {
     const float y = a.yhat[o + i];
     const float r = y - a.bvec[i * a.Bmax + b];
     a.cg_r[o + i] = r;
     a.cg_p[o + i] = r;
     a.cg_x[o + i] = 0.f;
-    const float a0 = -2.f * a.w[i] * y / a.rho;
+    const float a0 = -2.f * a.w[i] * y / rho;
     alpha[i * a.Bmax + b] = a0;
     if (pl < 0) alpha[plane + i * a.Bmax + b] = a0;  // both planes: read by whichever iteration starts
     acc += double(r) * double(r);
@@ -1392,11 +1417,13 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&d_xsrc_, size_t(bmax), err)) ||
         (rc = al(&d_oslots_, size_t(bmax), err)) || (rc = al(&d_odst_, size_t(bmax), err)) ||
         (rc = al(&d_cslots_, size_t(bmax), err)) || (rc = al(&d_cdst_, size_t(bmax), err)) ||
-        (rc = al(&a.phase, size_t(bmax), err)))
+        (rc = al(&a.phase, size_t(bmax), err)) || (rc = al(&a.rho_b, size_t(bmax), err)))
       return rc;
     {
       const std::vector<int32_t> adm(bmax, -1);  // every slot in the ADMM iteration
       BENG_CHECK(hipMemcpy(a.phase, adm.data(), sizeof(int32_t) * bmax, hipMemcpyHostToDevice));
+      const std::vector<float> rb(bmax, a.rho);
+      BENG_CHECK(hipMemcpy(a.rho_b, rb.data(), sizeof(float) * bmax, hipMemcpyHostToDevice));
     }
 
     // trajectory warm start: vectors and the plant in FP32
@@ -1448,14 +1475,15 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
-  int precompute(const double *x0_dev, int B, int max_iter, double eps, int warm, std::string &err) override {
+  int precompute(const double *x0_dev, int B, int max_iter, double eps, int warm, const double *rho_scale_dev,
+                 std::string &err) override {
     if (B < 1 || B > args_.Bmax) {
       err = "batch size out of range";
       return DLMPC_EINVAL;
     }
     B_ = B;
     hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, B), dim3(256), 0, stream_, args_, x0_dev, B,
-                       warm ? 1 : 0, max_iter, eps, nullptr, nullptr, 1, 0, 0);
+                       warm ? 1 : 0, max_iter, eps, nullptr, nullptr, 1, 0, 0, rho_scale_dev);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -1533,7 +1561,7 @@ class BatchEngineT final : public BatchEngine {
     BENG_CHECK(hipMemcpyAsync(d_xsrc_, st_xsrc_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
     if (first) B_ = S;
     hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, S), dim3(256), 0, stream_, args_, x0_dev, S, 1,
-                       max_iter, eps, d_slots_, d_xsrc_, first ? 1 : 0, 1, cg_iters);
+                       max_iter, eps, d_slots_, d_xsrc_, first ? 1 : 0, 1, cg_iters, nullptr);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL(bscatter_rows_kernel, dim3(S, 16), dim3(256), 0, stream_, ypred, d_slots_, ny_, args_.yhat);
     BENG_CHECK(hipGetLastError());
@@ -1608,9 +1636,9 @@ class BatchEngineT final : public BatchEngine {
   }
 
   int plant_step(double *x_dev, const double *u_dev, double *xs_dev, double *us_dev, int t, int T_sim, int B,
-                 std::string &err) override {
+                 double *rho_scale_dev, std::string &err) override {
     hipLaunchKernelGGL((bplant_kernel<NX>), dim3(B), dim3(256), 0, stream_, args_, x_dev, u_dev, xs_dev, us_dev, t,
-                       T_sim);
+                       T_sim, rho_scale_dev);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }

@@ -55,6 +55,7 @@ struct dlmpc_problem {
   float *d_sy = nullptr;
   // closed loop: current states and inputs, stopping trajectories, shifted starts
   double *d_clx = nullptr, *d_clu = nullptr, *d_cly = nullptr, *d_clys = nullptr;
+  double *d_clrs = nullptr, *d_frs = nullptr;  // penalty factors of the closed loop's instances
   // per-solve precompute and FP64 check timing; device finiteness flag of x0 (device entries)
   hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr, ev_c0 = nullptr, ev_c1 = nullptr;
   int32_t *d_flag = nullptr, *h_flag = nullptr;
@@ -96,10 +97,10 @@ void release_device(dlmpc_problem *p) {
   }
   if (p->h_bctl) (void)hipHostFree(p->h_bctl);
   for (double *d : {p->d_bx0, p->d_bu0, p->d_fx0, p->d_fu0, p->d_falpha, p->d_fy, p->d_clx, p->d_clu, p->d_cly,
-                    p->d_clys})
+                    p->d_clys, p->d_clrs, p->d_frs})
     if (d) (void)hipFree(d);
   p->d_fx0 = p->d_fu0 = p->d_falpha = p->d_fy = nullptr;
-  p->d_clx = p->d_clu = p->d_cly = p->d_clys = nullptr;
+  p->d_clx = p->d_clu = p->d_cly = p->d_clys = p->d_clrs = p->d_frs = nullptr;
   if (p->d_sy) (void)hipFree(p->d_sy);
   p->d_sy = nullptr;
   for (hipEvent_t e : {p->ev_w0, p->ev_w1})
@@ -241,7 +242,7 @@ int tune_batch(dlmpc_problem *p) {
   auto run = [&]() -> int {
     API_HIP(hipMemcpy(x, ones.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
     API_HIP(hipMemset(z, 0, sizeof(double) * nr));
-    int rc = p->beng->precompute(x, B, 1 << 20, -1.0, 1, err);
+    int rc = p->beng->precompute(x, B, 1 << 20, -1.0, 1, nullptr, err);
     if (!rc) rc = p->beng->start_alpha(z, err);
     if (rc) return fail(rc, err);
     auto time_k = [&](int k, double *us) -> int {
@@ -308,6 +309,8 @@ int setup_batch(dlmpc_problem *p) {
   API_HIP(hipMalloc(&p->d_clu, sizeof(double) * size_t(B) * hs.N * hs.nu));
   API_HIP(hipMalloc(&p->d_cly, sizeof(double) * size_t(B) * R));
   API_HIP(hipMalloc(&p->d_clys, sizeof(double) * size_t(B) * R));
+  API_HIP(hipMalloc(&p->d_clrs, sizeof(double) * size_t(B)));
+  API_HIP(hipMalloc(&p->d_frs, sizeof(double) * size_t(B)));
   API_HIP(hipEventCreate(&p->ev_w0));
   API_HIP(hipEventCreate(&p->ev_w1));
   // kernel variants: from the tuning cache, else timed here (before the graphs are captured:
@@ -828,7 +831,7 @@ int dlmpc_time_batch_kernels(dlmpc_problem *p, int32_t B, const double *x0_dev, 
   double *zero = nullptr;
   API_HIP(hipMalloc(&zero, sizeof(double) * nrow));
   int rc = hipMemsetAsync(zero, 0, sizeof(double) * nrow, p->stream) == hipSuccess ? DLMPC_OK : DLMPC_EDEVICE;
-  if (!rc) rc = p->beng->precompute(x0_dev, B, iters, -1.0, 1, err);
+  if (!rc) rc = p->beng->precompute(x0_dev, B, iters, -1.0, 1, nullptr, err);
   if (!rc) rc = p->beng->start_alpha(zero, err);
   const bool dev_ok = hipStreamSynchronize(p->stream) == hipSuccess;
   (void)hipFree(zero);
@@ -869,13 +872,14 @@ struct RunTimes {
 };
 
 int run_batch_once(dlmpc_problem *p, int B, const double *x0_dev, int start, const double *start_dev,
-                   double *u0_dev, double *y_out_dev, double *alpha_out_dev, RunTimes *times, int *checks_out) {
+                   double *u0_dev, double *y_out_dev, double *alpha_out_dev, RunTimes *times, int *checks_out,
+                   const double *rscale_dev = nullptr) {
   std::string err;
   const int max_iter = p->opt.max_iter;
   const HostSetup &h = p->hs;
   const double eps = start != DLMPC_START_COLD ? p->warm_eps : p->opt.eps;
   API_HIP(hipEventRecord(p->ev_p0, p->stream));
-  int rc = p->beng->precompute(x0_dev, B, max_iter, eps, start != DLMPC_START_COLD ? 1 : 0, err);
+  int rc = p->beng->precompute(x0_dev, B, max_iter, eps, start != DLMPC_START_COLD ? 1 : 0, rscale_dev, err);
   if (rc) return fail(rc, err);
   API_HIP(hipEventRecord(p->ev_p1, p->stream));
   API_HIP(hipEventRecord(p->ev_w0, p->stream));
@@ -972,14 +976,17 @@ void fill_stats(dlmpc_stats &st, const dlmpc::BCtl &ic, float ms, int checks, in
 }
 
 // Batched solve with the given start; warm-started instances that end unconverged (or with a
-// NaN/Inf) are solved again from the cold start in one more batched run.
+// NaN/Inf) are solved again from the cold start in one more batched run. rscale_dev [B] (or
+// NULL): per-instance factors of the penalty rho.
 int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, int start, const double *start_dev,
-              double *y_out_dev, double *alpha_out_dev, dlmpc_stats *stats, double t0) {
+              double *y_out_dev, double *alpha_out_dev, dlmpc_stats *stats, double t0,
+              const double *rscale_dev = nullptr) {
   const HostSetup &h = p->hs;
   const size_t nxs = size_t(h.N) * h.nx, nus = size_t(h.N) * h.nu, R = size_t(h.N) * h.rs;
   RunTimes tm;
   int checks = 0;
-  int rc = run_batch_once(p, B, x0_dev, start, start_dev, u0_dev, y_out_dev, alpha_out_dev, &tm, &checks);
+  int rc = run_batch_once(p, B, x0_dev, start, start_dev, u0_dev, y_out_dev, alpha_out_dev, &tm, &checks,
+                          rscale_dev);
   if (rc) return rc;
   const float ms = tm.iter, mw = tm.warm;
   std::vector<dlmpc::BCtl> first(p->h_bctl, p->h_bctl + B);
@@ -991,13 +998,17 @@ int run_batch(dlmpc_problem *p, int B, const double *x0_dev, double *u0_dev, int
     if (stats) fill_stats(stats[b], first[b], ms, checks, start, t0);
   if (!redo.empty()) {
     const int F = int(redo.size());
-    for (int f = 0; f < F; ++f)
+    for (int f = 0; f < F; ++f) {
       API_HIP(hipMemcpyAsync(p->d_fx0 + f * nxs, x0_dev + redo[f] * nxs, nxs * sizeof(double),
                              hipMemcpyDeviceToDevice, p->stream));
+      if (rscale_dev)
+        API_HIP(hipMemcpyAsync(p->d_frs + f, rscale_dev + redo[f], sizeof(double), hipMemcpyDeviceToDevice,
+                               p->stream));
+    }
     RunTimes tm2;
     int checks2 = 0;
     rc = run_batch_once(p, F, p->d_fx0, DLMPC_START_COLD, nullptr, p->d_fu0, y_out_dev ? p->d_fy : nullptr,
-                        alpha_out_dev ? p->d_falpha : nullptr, &tm2, &checks2);
+                        alpha_out_dev ? p->d_falpha : nullptr, &tm2, &checks2, rscale_dev ? p->d_frs : nullptr);
     if (rc) return rc;
     const float ms2 = tm2.iter;
     tm.pre += tm2.pre;
@@ -1293,26 +1304,35 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
 }  // namespace
 
 int dlmpc_closed_loop(dlmpc_problem *p, int32_t B, int32_t T_sim, const double *x0_dev, double *xs_dev,
-                      double *us_dev, int32_t warm, dlmpc_stats *stats) {
+                      double *us_dev, int32_t mode, dlmpc_stats *stats) {
   int rc = check_batch(p, B);
   if (rc) return rc;
   if (!x0_dev || !xs_dev || !us_dev) return fail(DLMPC_EINVAL, "NULL argument");
-  if (T_sim < 1 || (warm != 0 && warm != 1)) return fail(DLMPC_EINVAL, "need T_sim >= 1 and warm in {0, 1}");
+  if (T_sim < 1 || (mode & ~(DLMPC_CL_SHIFT | DLMPC_CL_SCALE_RHO)))
+    return fail(DLMPC_EINVAL, "need T_sim >= 1 and mode a combination of DLMPC_CL_SHIFT, DLMPC_CL_SCALE_RHO");
   API_HIP(hipSetDevice(p->opt.device));
   if ((rc = check_x0_device(p, x0_dev, B))) return rc;
   const HostSetup &h = p->hs;
   const size_t nxs = size_t(h.N) * h.nx;
+  const bool shift = mode & DLMPC_CL_SHIFT, scale = mode & DLMPC_CL_SCALE_RHO;
   API_HIP(hipMemcpyAsync(p->d_clx, x0_dev, sizeof(double) * B * nxs, hipMemcpyDeviceToDevice, p->stream));
+  if (scale) {
+    const std::vector<double> ones(B, 1.0);  // step 0 runs with rho itself
+    API_HIP(hipMemcpyAsync(p->d_clrs, ones.data(), sizeof(double) * B, hipMemcpyHostToDevice, p->stream));
+    API_HIP(hipStreamSynchronize(p->stream));
+  }
   std::string err;
   bool all = true;
   for (int t = 0; t < T_sim; ++t) {
-    const int start = (warm && t > 0) ? DLMPC_START_TRAJECTORY : DLMPC_START_COLD;
-    rc = run_batch(p, B, p->d_clx, p->d_clu, start, p->d_clys, warm ? p->d_cly : nullptr, nullptr,
-                   stats ? stats + size_t(t) * B : nullptr, now_ms());
+    const int start = (shift && t > 0) ? DLMPC_START_TRAJECTORY : DLMPC_START_COLD;
+    rc = run_batch(p, B, p->d_clx, p->d_clu, start, p->d_clys, shift ? p->d_cly : nullptr, nullptr,
+                   stats ? stats + size_t(t) * B : nullptr, now_ms(), scale ? p->d_clrs : nullptr);
     if (rc < 0) return rc;
     all = all && rc == DLMPC_OK;
-    if ((rc = p->beng->plant_step(p->d_clx, p->d_clu, xs_dev, us_dev, t, T_sim, B, err))) return fail(rc, err);
-    if (warm && (rc = p->beng->shift_inputs(p->d_cly, p->d_clys, B, err))) return fail(rc, err);
+    if ((rc = p->beng->plant_step(p->d_clx, p->d_clu, xs_dev, us_dev, t, T_sim, B, scale ? p->d_clrs : nullptr,
+                                  err)))
+      return fail(rc, err);
+    if (shift && (rc = p->beng->shift_inputs(p->d_cly, p->d_clys, B, err))) return fail(rc, err);
   }
   API_HIP(hipStreamSynchronize(p->stream));
   return all ? DLMPC_OK : DLMPC_ENOCONV;
@@ -1587,7 +1607,7 @@ int dlmpc_group_solve_batch(dlmpc_group *g, const int32_t *B, const double *cons
   double eps = 0.0;
   for (int i = 0; i < n; ++i) {
     dlmpc_problem *q = g->p[i];
-    int rc = q->beng->precompute(x0_dev[i], B[i], q->opt.max_iter, q->opt.eps, 0, err);
+    int rc = q->beng->precompute(x0_dev[i], B[i], q->opt.max_iter, q->opt.eps, 0, nullptr, err);
     if (rc) return fail(rc, err);
     API_HIP(hipEventRecord(g->ev_join[i], q->stream));
     API_HIP(hipStreamWaitEvent(g->stream, g->ev_join[i], 0));

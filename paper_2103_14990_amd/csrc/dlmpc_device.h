@@ -124,6 +124,7 @@ struct BCtl {  // per-instance control block
 struct BArgs {
   int32_t N, nx, nu, T, rs, Bmax;
   float rho;
+  float *rho_b;  // [Bmax] penalty of each instance: rho, or rho times a per-instance factor
   const int64_t *tile_off, *rt_ptr, *rt_tile;
   const int32_t *rt_col, *kdim, *tile_rsub;
   const int64_t *koff;      // [N+1] offsets of the k-space vectors (multiples of 32)
@@ -197,9 +198,10 @@ class BatchEngine {
   // split: basis operands as bf16 hi + lo (FP32-level products); otherwise rounded once to bf16
   virtual int init(const HostSetup &hs, double rho, int bmax, bool split, hipStream_t s, std::string &err) = 0;
   // Per-solve set-up of B instances; warm != 0 selects the iteration of a warm start (one of
-  // the start_* calls below must follow before the first iteration).
+  // the start_* calls below must follow before the first iteration). rho_scale_dev [B] (or
+  // NULL: all 1): instance b runs with the penalty rho * rho_scale_dev[b].
   virtual int precompute(const double *x0_dev, int B, int max_iter, double eps, int warm,
-                         std::string &err) = 0;
+                         const double *rho_scale_dev, std::string &err) = 0;
   // Compact start from row multipliers alpha0 [B][N*rs]: Psi^0[:,c] = o_c,
   // Lambda^0[:,c] = x0_c (I - N_j N_j') alpha0 on supp j.
   virtual int start_alpha(const double *alpha0_dev, std::string &err) = 0;
@@ -224,9 +226,10 @@ class BatchEngine {
   virtual int output(double *u0_dev, std::string &err) = 0;
   // Closed loop (Algorithm 1), FP64: x(t+1) = A x(t) + B u(t) for B instances in place in x_dev
   // [B][N*nx] (u_dev [B][N*nu]), with x(t) (at t = 0), x(t+1) and u(t) stored in the loop's
-  // trajectories xs_dev [B][T_sim+1][N*nx] and us_dev [B][T_sim][N*nu].
+  // trajectories xs_dev [B][T_sim+1][N*nx] and us_dev [B][T_sim][N*nu]. rho_scale_dev [B] (or
+  // NULL): receives ||x(t+1)||^2 / ||x(0)||^2 (at least 1e-20; 1 when x(0) = 0).
   virtual int plant_step(double *x_dev, const double *u_dev, double *xs_dev, double *us_dev, int t, int T_sim,
-                         int B, std::string &err) = 0;
+                         int B, double *rho_scale_dev, std::string &err) = 0;
   // Input rows of y_dev [B][N*rs] moved one step ahead (last held) into ys_dev.
   virtual int shift_inputs(const double *y_dev, double *ys_dev, int B, std::string &err) = 0;
   // FP64 check of the stopping iterate of every instance of the batch (x0_dev [B][N*nx], the

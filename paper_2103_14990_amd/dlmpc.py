@@ -26,6 +26,8 @@ FLAG_SCHED_PERSISTENT = 0x4
 FLAG_HOST_FACTOR = 0x8
 FLAG_NO_CHECK = 0x10
 FLAG_NO_TUNE = 0x20
+CL_SHIFT = 1
+CL_SCALE_RHO = 2
 FACTORS = {"device": 0, "host": FLAG_HOST_FACTOR}
 SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16": FP32_BF16}
@@ -343,13 +345,15 @@ class Problem:
         return s, [x.as_dict() for x in st], info.as_dict()
 
     def closed_loop(self, B: int, T_sim: int, x0_dev: int, xs_dev: int, us_dev: int,
-                    warm: bool = False) -> tuple[int, list[list[dict]]]:
+                    warm: bool = False, scale_rho: bool = False) -> tuple[int, list[list[dict]]]:
         """B closed loops of T_sim steps (Algorithm 1) from x0_dev [B][N*nx]; xs_dev
         [B][T_sim+1][N*nx] and us_dev [B][T_sim][N*nu] receive the state and input trajectories
-        (device pointers of float64 buffers). Returns (status, stats[t][b])."""
+        (device pointers of float64 buffers). warm: shifted start (CL_SHIFT); scale_rho: penalty
+        rho ||x(t)||^2 / ||x(0)||^2 (CL_SCALE_RHO). Returns (status, stats[t][b])."""
         st = (Stats * (B * T_sim))()
+        mode = (CL_SHIFT if warm else 0) | (CL_SCALE_RHO if scale_rho else 0)
         s = self._check(self._lib.dlmpc_closed_loop(self._h, B, T_sim, C.c_void_p(x0_dev), C.c_void_p(xs_dev),
-                                                     C.c_void_p(us_dev), 1 if warm else 0, st))
+                                                     C.c_void_p(us_dev), mode, st))
         flat = [x.as_dict() for x in st]
         return s, [flat[t * B:(t + 1) * B] for t in range(T_sim)]
 
@@ -425,8 +429,8 @@ class Problem:
             self._lib.dlmpc_destroy(self._h)
             self._h = C.c_void_p()
 
-    def __del__(self):
-        if sys.is_finalizing():  # the exit hook has closed every live handle
+    def __del__(self, _finalizing=sys.is_finalizing):  # bound here: module globals may be gone at exit
+        if _finalizing():  # the exit hook has closed every live handle
             return
         try:
             self.close()
@@ -470,8 +474,8 @@ class Group:
             self._lib.dlmpc_group_destroy(self._h)
             self._h = C.c_void_p()
 
-    def __del__(self):
-        if sys.is_finalizing():  # the exit hook has closed every live handle
+    def __del__(self, _finalizing=sys.is_finalizing):  # bound here: module globals may be gone at exit
+        if _finalizing():  # the exit hook has closed every live handle
             return
         try:
             self.close()

@@ -7,7 +7,11 @@ or the previous input trajectory shifted one step ahead, with the library's defa
 warm starts and CG steps). Bar (reduced precision, as for single solves): per step u(t) within
 1e-4 relative of the oracle's, the states within 1e-4 relative over the whole loop, iteration
 counts within a few (the shifted start is built with FP32 CG steps on the device and FP64 CG in
-the oracle: nearby, not equal, starts). The shifted start saves iterations over the loop.
+the oracle: nearby, not equal, starts). The shifted start saves iterations over the loop. The
+penalty scaled with the state (rho ||x(t)||^2 / ||x(0)||^2) is checked against the oracle's loop
+with the same rule; it keeps the iteration count of later steps near that of step 0, where the
+fixed penalty's count first drops (the effective penalty passes through a better value for this
+plant) and then grows without bound as the state decays.
 """
 import numpy as np
 import pytest
@@ -40,10 +44,10 @@ def _rel(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
 
 
-@pytest.mark.parametrize("warm", [False, True])
-def test_closed_loop_matches_oracle(torch, grid8, warm):
+@pytest.mark.parametrize("warm,scale", [(False, False), (True, False), (False, True), (True, True)])
+def test_closed_loop_matches_oracle(torch, grid8, warm, scale):
     wl, pb = grid8
-    seeds = [9, 4]
+    seeds = [9] if scale else [9, 4]
     B, G, nx, nu = len(seeds), wl.net.n_sub, wl.net.nx, wl.net.nu
     pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps, max_iter=1000,
                                     precision="fp32", max_batch=4)
@@ -51,16 +55,17 @@ def test_closed_loop_matches_oracle(torch, grid8, warm):
     xd = torch.tensor(x0, dtype=torch.float64, device="cuda")
     xs = torch.zeros((B, T_SIM + 1, G * nx), dtype=torch.float64, device="cuda")
     us = torch.zeros((B, T_SIM, G * nu), dtype=torch.float64, device="cuda")
-    st, stats = pr.closed_loop(B, T_SIM, xd.data_ptr(), xs.data_ptr(), us.data_ptr(), warm=warm)
+    st, stats = pr.closed_loop(B, T_SIM, xd.data_ptr(), xs.data_ptr(), us.data_ptr(), warm=warm, scale_rho=scale)
     assert st == dlmpc.OK
     xs, us = xs.cpu().numpy(), us.cpu().numpy()
     for b, sd in enumerate(seeds):
         ref = CL.closed_loop(pb, x0[b], T_SIM, wl.rho, wl.eps, 1000, warm=warm, eps_warm=WARM_EPS_SCALE * wl.eps,
-                             cg_iters=CG)
+                             cg_iters=CG, scale_rho=scale)
         it_g = [stats[t][b]["iters"] for t in range(T_SIM)]
         eu = max(_rel(us[b, t], ref.u[t]) for t in range(T_SIM))
         ex = _rel(xs[b], ref.x)
-        print(f"  seed {sd} warm {warm}: iters gpu {it_g}\n      oracle {ref.iters}; u rel {eu:.2e}, x rel {ex:.2e}",
+        print(f"  seed {sd} warm {warm} scale {scale}: iters gpu {it_g}\n      oracle {ref.iters}; "
+              f"u rel {eu:.2e}, x rel {ex:.2e}",
               flush=True)
         assert np.array_equal(xs[b, 0], x0[b])
         assert all(ref.converged) and all(stats[t][b]["converged"] for t in range(T_SIM))
@@ -94,6 +99,35 @@ def test_shifted_start_saves_iterations_on_device(torch, grid8):
     assert its[True] < its[False]
 
 
+def test_scaled_penalty_bounds_iterations_on_device(torch, grid8):
+    wl, _ = grid8
+    B = 8
+    G, nx, nu = wl.net.n_sub, wl.net.nx, wl.net.nu
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps, max_iter=1000,
+                                    precision="fp32", max_batch=B)
+    xd = torch.tensor(np.stack([wl.x0(1000 + i) for i in range(B)]), dtype=torch.float64, device="cuda")
+    its, xe = {}, {}
+    for scale in (False, True):
+        xs = torch.zeros((B, 21, G * nx), dtype=torch.float64, device="cuda")
+        us = torch.zeros((B, 20, G * nu), dtype=torch.float64, device="cuda")
+        st, stats = pr.closed_loop(B, 20, xd.data_ptr(), xs.data_ptr(), us.data_ptr(), scale_rho=scale)
+        assert st == dlmpc.OK
+        its[scale] = [sum(q["iters"] for q in row) for row in stats]
+        xe[scale] = xs.cpu().numpy()
+        print(f"  scale {scale}: mean iterations per step {[round(v / B, 1) for v in its[scale]]}", flush=True)
+    assert its[True][0] == its[False][0]  # step 0 runs with rho itself
+    assert max(its[True]) <= 1.6 * its[True][0]
+    assert max(its[True]) < max(its[False])
+    # both loops eps-converged at every step: the trajectories stay close
+    assert np.abs(xe[True] - xe[False]).max() <= 1e-2 * np.abs(xe[False]).max()
+    # a plain solve after the scaled loop runs with rho again (the per-instance penalty is reset)
+    st, u0, s1 = pr.solve_batch(np.stack([wl.x0(1000 + i) for i in range(2)]))
+    pr2 = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps, max_iter=1000,
+                                     precision="fp32", max_batch=B)
+    _, u0b, s2 = pr2.solve_batch(np.stack([wl.x0(1000 + i) for i in range(2)]))
+    assert np.array_equal(u0, u0b) and [q["iters"] for q in s1] == [q["iters"] for q in s2]
+
+
 def test_closed_loop_argument_errors(torch, grid8):
     wl, _ = grid8
     pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, precision="fp32", max_batch=2)
@@ -104,6 +138,8 @@ def test_closed_loop_argument_errors(torch, grid8):
         pr.closed_loop(3, 2, x.data_ptr(), xs.data_ptr(), us.data_ptr())  # above max_batch
     with pytest.raises(dlmpc.DlmpcError):
         pr.closed_loop(2, 0, x.data_ptr(), xs.data_ptr(), us.data_ptr())
+    st = pr._lib.dlmpc_closed_loop(pr._h, 2, 2, x.data_ptr(), xs.data_ptr(), us.data_ptr(), 4, None)
+    assert st == dlmpc.EINVAL  # unknown mode bit
     x[1, 3] = float("nan")
     with pytest.raises(dlmpc.DlmpcError):
         pr.closed_loop(2, 2, x.data_ptr(), xs.data_ptr(), us.data_ptr())
