@@ -183,6 +183,80 @@ def calibrate_copy(nbytes: int = 1 << 30) -> None:
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
+PAPER_SWEEP = ([(10, 2, 10), (25, 2, 10), (100, 2, 10)]  # N
+               + [(25, 2, 5), (25, 2, 15)]  # T (the batched engine takes nx T + nu (T - 1) <= 64 rows)
+               + [(25, 1, 10), (25, 3, 10), (25, 4, 10)])  # d
+PAPER_SCHEDULES = ("graph", "persistent", "stepwise", "host_exchange", "naive")
+
+
+def paper_plant_sweep(args, dev, stream) -> dict:
+    """The paper's chain plant (Section IV-A) over its N, T and d sweep: for each (N, d, T), x0
+    seeds 1000.. (sigma = 1): closed loops of T_sim = 20 steps on the device (FP32 batched
+    engine, penalty scaled with the state; whole-simulation time per MPC step per loop), then
+    every single-instance FP64 schedule (this library's graph and persistent schedules and the
+    per-iteration designs of Section III: stepwise, host exchange, naive) solving the same 20
+    states of each loop one by one with the same penalty rho ||x(t)||^2 / ||x(0)||^2: runtime
+    per MPC step (sum of the 20 solve times over 20), mean and standard deviation over the
+    initial conditions, as the paper reports."""
+    import numpy as np
+    import torch
+    from paper_2103_14990_amd import dlmpc
+    from paper_2103_14990_amd import workloads as W
+    T_sim, ns, out = 20, max(1, min(args.paper_seeds, 64)), {}
+    for (n, d, T) in PAPER_SWEEP:
+        wl = W.paper_workload(n, d=d, T=T)
+        key = f"N{n}_d{d}_T{T}"
+        rec = {}
+        G, nx, nu = wl.net.n_sub, wl.net.nx, wl.net.nu
+        xb = torch.tensor(np.stack([wl.x0(1000 + i) for i in range(ns)]), dtype=torch.float64, device=dev)
+        pb = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps, max_iter=2000,
+                                        precision="fp32", device=0, stream=stream.cuda_stream, max_batch=ns)
+        xs = torch.zeros((ns, T_sim + 1, G * nx), dtype=torch.float64, device=dev)
+        us = torch.zeros((ns, T_sim, G * nu), dtype=torch.float64, device=dev)
+        pb.closed_loop(ns, T_sim, xb.data_ptr(), xs.data_ptr(), us.data_ptr(), scale_rho=True)  # untimed
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, lst = pb.closed_loop(ns, T_sim, xb.data_ptr(), xs.data_ptr(), us.data_ptr(), scale_rho=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        pb.close()
+        rec["batched_closed_loop"] = {
+            "ms_per_mpc_step_per_loop": round(1e3 * el / (T_sim * ns), 4), "loops": ns,
+            "iters_mean": round(float(np.mean([q["iters"] for r in lst for q in r])), 1),
+            "converged": f"{sum(q['converged'] for r in lst for q in r)}/{T_sim * ns}"}
+        xs_flat = xs[:, :T_sim].reshape(ns * T_sim, G * nx).contiguous()
+        xh = xs.cpu().numpy()
+        n0 = (xh[:, 0] ** 2).sum(axis=1)
+        rho_t = wl.rho * np.maximum((xh[:, :T_sim] ** 2).sum(axis=2) / np.where(n0 > 0, n0, 1.0)[:, None], 1e-20)
+        uo = torch.zeros((G * nu,), dtype=torch.float64, device=dev)
+        u_graph = None
+        for sched in PAPER_SCHEDULES:
+            ps = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps, max_iter=2000,
+                                            precision="fp64", device=0, stream=stream.cuda_stream,
+                                            schedule=sched)
+            ps.solve_device(xs_flat[0].data_ptr(), uo.data_ptr())  # untimed first use (rho itself)
+            per_loop, its, us_ = [], [], []
+            for b in range(ns):
+                tot = 0.0
+                for t in range(T_sim):
+                    ps.set_rho(float(rho_t[b, t]))
+                    _, st = ps.solve_device(xs_flat[b * T_sim + t].data_ptr(), uo.data_ptr())
+                    tot += st["t_solve_ms"]
+                    its.append(st["iters"])
+                    us_.append(uo.clone())
+                per_loop.append(tot / T_sim)
+            ps.close()
+            u_all = torch.stack(us_)
+            if u_graph is None:
+                u_graph = u_all
+            rec[sched] = {"ms_per_mpc_step_mean": round(float(np.mean(per_loop)), 4),
+                          "ms_per_mpc_step_std": round(float(np.std(per_loop)), 4),
+                          "iters_mean": round(float(np.mean(its)), 1),
+                          "u_equal_to_graph": bool(torch.equal(u_all, u_graph))}
+        out[key] = rec
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +290,10 @@ def main() -> int:
                     help="skip the reduced-operator tier (basis rounded once to bf16) comparison")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the 192-instance mixed-network group solve")
+    ap.add_argument("--no-paper-sweep", dest="paper_sweep", action="store_false",
+                    help="skip the paper's chain plant: N, T and d sweep and the schedule comparison")
+    ap.add_argument("--paper-seeds", type=int, default=8,
+                    help="initial conditions per configuration of the paper-plant sweep (x0 seeds 1000..)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-launch timing of the batched kernels (for profiler runs)")
@@ -449,7 +527,7 @@ def main() -> int:
     single = {"latency_ms": lat_stats(q["t_solve_ms"] for q in ss),
               "iters_mean": float(np.mean([q["iters"] for q in ss])),
               "check_ms_mean": round(float(np.mean([q["t_check_ms"] for q in ss])), 4),
-              "schedule": ["graph", "persistent"][pr.info["schedule"]]}
+              "schedule": dlmpc.SCHEDULE_NAMES[pr.info["schedule"]]}
     ref = {}
     uf = torch.zeros((nl, n_u), dtype=torch.float64, device=dev)
     prf = make("fp64", 0)
@@ -460,7 +538,7 @@ def main() -> int:
     ref = {"latency_ms": lat_stats(q["t_solve_ms"] for q in sf),
            "iters_mean": float(np.mean([q["iters"] for q in sf])),
            "time_to_eps_ms_median": lat_stats(q["t_solve_ms"] for q in sf)["median"],
-           "schedule": ["graph", "persistent"][prf.info["schedule"]],
+           "schedule": dlmpc.SCHEDULE_NAMES[prf.info["schedule"]],
            "u0_rel_diff_single_fp32_vs_fp64_max": float(((ul - uf).abs().amax(dim=1) / uf.abs().amax(dim=1)).max())}
     prf.close()
     bl = {}
@@ -555,7 +633,7 @@ def main() -> int:
                              "us_per_iteration_median": round(float(np.median(
                                  [1e3 * q["t_iter_ms"] / max(q["iters"], 1) for q in sc_])), 2),
                              "converged": f"{sum(q['converged'] for q in sc_)}/{nl}",
-                             "schedule": ["graph", "persistent"][p_.info["schedule"]]}
+                             "schedule": dlmpc.SCHEDULE_NAMES[p_.info["schedule"]]}
                 us_[prec] = uc_
                 p_.close()
             if "fp32" in us_:
@@ -563,6 +641,11 @@ def main() -> int:
                     ((us_["fp32"] - us_["fp64"]).abs().amax(dim=1) / us_["fp64"].abs().amax(dim=1)).max())
             configs[name] = rec
         log(f"configs: {configs}")
+
+    # ---- the paper's own plant (Section IV-A) and sweep
+    paper = paper_plant_sweep(args, dev, stream) if args.paper_sweep else {}
+    if paper:
+        log(f"paper plant: {json.dumps(paper)}")
 
     # ---- reduced-operator tier (basis rounded once to bf16): the latency seeds' instances in
     # batches of B from the cold start at eps = 1e-3 (above the tier's dual-residual floor on this
@@ -697,6 +780,7 @@ def main() -> int:
         "bf16_operator_tier": tier,
         "configs": configs,
         "closed_loop": loop,
+        "paper_plant": paper,
         "speedup_throughput_vs_plain_fp64": round(ref["latency_ms"]["median"] / (ms_step / per), 2),
         "speedup_latency_streamed_vs_plain_fp64": (round(ref["latency_ms"]["median"] /
                                                          latency["streamed_learned"]["median"], 2)

@@ -86,6 +86,19 @@ typedef enum {
                                       8x the mean basis cost); the tuning cache is not used */
 #define DLMPC_FLAG_NO_CHECK 0x10u  /* skip the FP64 check of the stopping iterate that every solve
                                       otherwise runs (stats kkt, eq_resid, u0_check are then 0) */
+/* Per-iteration schedules of single-instance solves, the designs of Section III that this
+ * library's graph and persistent schedules improve on (for comparison; same kernels, same
+ * iterates, so results equal the graph schedule's). At most one DLMPC_FLAG_SCHED_* flag. */
+#define DLMPC_FLAG_SCHED_STEPWISE 0x40u  /* the kernels of an iteration launched one by one, the
+                                            row-to-column exchange on the device, the host reads the
+                                            stop flag after every iteration (column patches: no CPU
+                                            exchange inside the iteration, Section III-D) */
+#define DLMPC_FLAG_SCHED_HOST_EXCHANGE 0x80u /* as STEPWISE, and Phi is copied to host memory and back
+                                            between Phi-comp and Psi-comp (combined kernels: one
+                                            CPU exchange per iteration, Section III-C) */
+#define DLMPC_FLAG_SCHED_NAIVE 0x100u    /* as STEPWISE, and every kernel's results are copied to
+                                            host memory and back before the next kernel runs (the
+                                            naive parallelization of Section III-A) */
 
 /* Networked plant. G_(A,B) is read off the block sparsity of A: subsystems i != j are
  * adjacent iff block A_ij or A_ji is present in the block-CSR with a nonzero entry. Every
@@ -156,8 +169,10 @@ typedef struct {
                            from its join to the host check that saw it stop (plus its cold
                            fallback, if any) */
   double t_iter_ms;     /* device time of the iteration phase (HIP events) */
-  int32_t graph_launches; /* kernel-graph launches (graph schedule) or 1 (persistent) */
-  int32_t schedule;       /* 0 = graph, 1 = persistent, 2 = batched */
+  int32_t graph_launches; /* kernel-graph launches (graph schedule), iterations (per-iteration
+                             schedules) or 1 (persistent) */
+  int32_t schedule;       /* 0 = graph, 1 = persistent, 2 = batched, 3 = stepwise, 4 = host
+                             exchange, 5 = naive */
   int32_t start;          /* initial iterate: one of DLMPC_START_* */
   int32_t fell_back;      /* 1 if the warm-started run did not converge and the instance was
                              solved again from the cold start (iters then counts both runs) */
@@ -192,7 +207,7 @@ typedef struct {
   double setup_ms;      /* wall time of dlmpc_setup up to the factorisation's end */
   double factor_ms;     /* of which the FP64 factorisation of the column blocks (device
                            factorisation: list building, transfers and both kernels) */
-  int32_t schedule;     /* 0 = graph, 1 = persistent */
+  int32_t schedule;     /* 0 = graph, 1 = persistent, 3..5 as dlmpc_stats.schedule */
   int32_t persistent_grid; /* co-resident blocks of the persistent schedule (0 = unavailable) */
   double tune_graph_us;      /* per-iteration time measured at setup (0 if not measured) */
   double tune_persistent_us;
@@ -368,6 +383,14 @@ int dlmpc_solve_batch_ex(struct dlmpc_problem *p, int32_t B, const double *x0_de
  * negative status on error (DLMPC_EINVAL for an unknown mode bit or a NaN/Inf in x0). */
 int dlmpc_closed_loop(struct dlmpc_problem *p, int32_t B, int32_t T_sim, const double *x0_dev, double *xs_dev,
                       double *us_dev, int32_t mode, dlmpc_stats *stats);
+
+/* Penalty rho of the ADMM of Algorithm 2 (the (rho/2) ||Phi - Psi + Lambda||^2 term) for every
+ * solve started after this call, in every entry point (options.rho until the first call; the
+ * closed loop's DLMPC_CL_SCALE_RHO factors multiply it). The paper does not fix rho; a caller
+ * that runs its own receding-horizon loop can pass rho * ||x(t)||^2 / ||x(0)||^2 here, which
+ * gives the iterates of dlmpc_closed_loop with DLMPC_CL_SCALE_RHO. Returns DLMPC_EINVAL unless
+ * rho is finite and > 0. */
+int dlmpc_set_rho(struct dlmpc_problem *p, double rho);
 
 /* Counters of a streamed solve (dlmpc_solve_stream). */
 typedef struct {

@@ -63,7 +63,8 @@ __device__ __forceinline__ unsigned long long as_bits(double v) {
 // control block reset (Algorithm 1, per-step precomputation with x(t)).
 template <typename Tf, int NX>
 __global__ __launch_bounds__(kBlock) void precompute_kernel(KArgs<Tf> a, const double *x0,
-                                                            int cold, int max_iter, double eps) {
+                                                            int cold, int max_iter, double eps,
+                                                            double rho) {
   const int m = blockIdx.x;
   const int tid = threadIdx.x;
   if (tid < NX) a.x0f[m * NX + tid] = static_cast<Tf>(x0[m * NX + tid]);
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(kBlock) void precompute_kernel(KArgs<Tf> a, const d
     c->last_rp = INFINITY;
     c->last_rd = INFINITY;
     c->eps = eps;
+    c->rho = rho;
     c->objective = 0.0;
     c->bar_count = 0u;
     c->bar_gen = 0u;
@@ -138,7 +140,7 @@ __device__ __forceinline__ void phi_body(const KArgs<Tf> &a, int m, unsigned cha
   Tf *alpha_s = part + kWaves * 64;           // [64]
   for (int i = tid; i < np * NX; i += kBlock) xs[i] = a.x0f[a.rt_col[t0 + i / NX] * NX + i % NX];
   __syncthreads();
-  const Tf n = a.nrm[m];
+  const Tf n = a.nrm[m], rho = static_cast<Tf>(a.ctl->rho);
   for (int l0 = 0; l0 < rs; l0 += 64) {
     const int l = l0 + lane;
     const bool act = l < rs;
@@ -171,7 +173,7 @@ __device__ __forceinline__ void phi_body(const KArgs<Tf> &a, int m, unsigned cha
       const int64_t o = int64_t(m) * rs + l;
       Tf sv, al;
       if (n > Tf(0)) {
-        sv = clip(a.rho * s / (a.rho + Tf(2) * a.w[o] * n), a.lb[o], a.ub[o]);
+        sv = clip(rho * s / (rho + Tf(2) * a.w[o] * n), a.lb[o], a.ub[o]);
         al = (sv - s) / n;
       } else {
         sv = s;
@@ -772,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void cert_kernel(KArgs<Tf> a, CertArgs c) {
   // N_j N_j' (rho Lambda_c): coordinates first, then the rows
   const int D = int(t1 - t0) * rs, ld = (D + 3) & ~3, k = a.kdim[j];
   const Tf *Nj = a.nb + a.nb_off[j];
-  const double rho = double(a.rho);
+  const double rho = a.ctl->rho;
   // one wave per basis vector i: lanes over the rows (coalesced column reads), wave reduction
   for (int i = wave; i < k; i += kBlock / 64) {
     double acc[NX];
@@ -887,7 +889,6 @@ class EngineT final : public Engine {
     a.T = hs.T;
     a.rs = hs.rs;
     a.ts = hs.ts;
-    a.rho = static_cast<Tf>(rho);
     int rc;
     if ((rc = upload(hs.tile_off, &a.tile_off, err))) return rc;
     if ((rc = upload(hs.rt_ptr, &a.rt_ptr, err))) return rc;
@@ -980,6 +981,7 @@ class EngineT final : public Engine {
     if ((rc = upload(count, &pu_.p2_count, err))) return rc;
     if ((rc = upload(toff, &pu_.t_off, err))) return rc;
     if ((rc = alloc(&pu_.t, size_t(toff[hs.N]), err))) return rc;
+    t_len_ = size_t(toff[hs.N]);
     int max_units = 1;
     for (int j = 0; j < hs.N; ++j) max_units = std::max(max_units, count[j]);
     pu_.max_units = max_units;
@@ -1060,10 +1062,10 @@ class EngineT final : public Engine {
   int persistent_grid() const override { return grid_; }
 
   int precompute(const double *x0_dev, const double *wpsi, const double *wlam, int max_iter,
-                 double eps, std::string &err) override {
+                 double eps, double rho, std::string &err) override {
     const int cold = (wpsi == nullptr);
     hipLaunchKernelGGL((precompute_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), 0, stream_, args_,
-                       x0_dev, cold, max_iter, eps);
+                       x0_dev, cold, max_iter, eps, rho);
     ENG_CHECK(hipGetLastError());
     if (!cold) {
       const int64_t n = int64_t(hs_->n_tiles) * hs_->ts;
@@ -1099,6 +1101,42 @@ class EngineT final : public Engine {
         break;
     }
     ENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  size_t exchange_bytes() const override {
+    return std::max(std::max(2 * size_t(hs_->n_tiles) * hs_->ts, t_len_) * sizeof(Tf), sizeof(Ctl));
+  }
+
+  int host_exchange(int which, void *host, std::string &err) override {
+    const size_t nst = size_t(hs_->n_tiles) * hs_->ts;
+    struct Part {
+      void *dev;
+      size_t bytes;
+    } parts[2] = {{nullptr, 0}, {nullptr, 0}};
+    switch (which) {
+      case 0: parts[0] = {args_.phi, nst * sizeof(Tf)}; break;
+      case 1: parts[0] = {pu_.t, t_len_ * sizeof(Tf)}; break;
+      case 2:
+        parts[0] = {args_.psi, nst * sizeof(Tf)};
+        parts[1] = {args_.lam, nst * sizeof(Tf)};
+        break;
+      default: parts[0] = {args_.ctl, sizeof(Ctl)}; break;
+    }
+    char *h = static_cast<char *>(host);
+    size_t o = 0;
+    for (const Part &q : parts)
+      if (q.bytes) {
+        ENG_CHECK(hipMemcpyAsync(h + o, q.dev, q.bytes, hipMemcpyDeviceToHost, stream_));
+        o += q.bytes;
+      }
+    ENG_CHECK(hipStreamSynchronize(stream_));
+    o = 0;
+    for (const Part &q : parts)
+      if (q.bytes) {
+        ENG_CHECK(hipMemcpyAsync(q.dev, h + o, q.bytes, hipMemcpyHostToDevice, stream_));
+        o += q.bytes;
+      }
     return DLMPC_OK;
   }
 
@@ -1217,6 +1255,7 @@ class EngineT final : public Engine {
 
   const HostSetup *hs_ = nullptr;
   hipStream_t stream_ = nullptr;
+  size_t t_len_ = 0;  // entries of the Psi pass-1 products t_j
   KArgs<Tf> args_{};
   const int64_t *map_ = nullptr;
   const double *w64_ = nullptr;

@@ -1635,6 +1635,8 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
+  void set_rho(double rho) override { args_.rho = float(rho); }
+
   int plant_step(double *x_dev, const double *u_dev, double *xs_dev, double *us_dev, int t, int T_sim, int B,
                  double *rho_scale_dev, std::string &err) override {
     hipLaunchKernelGGL((bplant_kernel<NX>), dim3(B), dim3(256), 0, stream_, args_, x_dev, u_dev, xs_dev, us_dev, t,

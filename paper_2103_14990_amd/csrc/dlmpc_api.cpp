@@ -36,6 +36,7 @@ struct dlmpc_problem {
   double tune_phi_us[2] = {0, 0}, tune_psi_us[5] = {0, 0, 0, 0, 0};
   int32_t tune_cached = 0;
   Ctl *h_ctl = nullptr;  // pinned, 2 slots
+  void *h_xchg = nullptr;  // pinned staging of the host-exchange schedules
   hipEvent_t ev_ctl[2] = {nullptr, nullptr};
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
   double *d_x0 = nullptr, *d_u0 = nullptr, *d_phi = nullptr, *d_warm = nullptr;
@@ -52,14 +53,15 @@ struct dlmpc_problem {
   double *d_fx0 = nullptr, *d_fu0 = nullptr, *d_falpha = nullptr, *d_fy = nullptr;
   int cg_iters = 12;
   hipEvent_t ev_w0 = nullptr, ev_w1 = nullptr;
-  float *d_sy = nullptr;
+  float *d_sy = nullptr;  // streamed solves: predicted trajectories of the joining instances [Bmax][R]
   // closed loop: current states and inputs, stopping trajectories, shifted starts
   double *d_clx = nullptr, *d_clu = nullptr, *d_cly = nullptr, *d_clys = nullptr;
   double *d_clrs = nullptr, *d_frs = nullptr;  // penalty factors of the closed loop's instances
   // per-solve precompute and FP64 check timing; device finiteness flag of x0 (device entries)
   hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr, ev_c0 = nullptr, ev_c1 = nullptr;
   int32_t *d_flag = nullptr, *h_flag = nullptr;
-  double warm_eps = 1e-4;  // eps of warm-started batched and streamed runs  // streamed solves: predicted trajectories of the joining instances [Bmax][R]
+  double warm_eps = 1e-4;  // eps of warm-started batched and streamed runs
+  double rho = 5.0;        // penalty of the solves (options.rho until dlmpc_set_rho)
 };
 
 namespace {
@@ -117,6 +119,8 @@ void release_device(dlmpc_problem *p) {
   if (p->h_flag) (void)hipHostFree(p->h_flag);
   p->d_flag = p->h_flag = nullptr;
   if (p->h_ctl) (void)hipHostFree(p->h_ctl);
+  if (p->h_xchg) (void)hipHostFree(p->h_xchg);
+  p->h_xchg = nullptr;
   for (double *d : {p->d_x0, p->d_u0, p->d_phi, p->d_warm})
     if (d) (void)hipFree(d);
   p->eng.reset();
@@ -401,7 +405,7 @@ int time_schedule(dlmpc_problem *p, int sched, int n, double *us_per_iter) {
   API_HIP(hipMemcpy(p->d_x0, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
   float best = 1e30f;
   for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms code and caches
-    int rc = p->eng->precompute(p->d_x0, nullptr, nullptr, n, -1.0, err);
+    int rc = p->eng->precompute(p->d_x0, nullptr, nullptr, n, -1.0, p->opt.rho, err);
     if (rc) return fail(rc, err);
     API_HIP(hipEventRecord(p->ev_t0, p->stream));
     if (sched == 1) {
@@ -426,6 +430,16 @@ int time_schedule(dlmpc_problem *p, int sched, int n, double *us_per_iter) {
 int choose_schedule(dlmpc_problem *p) {
   const uint32_t f = p->opt.flags;
   const bool can_persist = p->eng->persistent_grid() > 0;
+  // the per-iteration schedules of the exchange ablation (no tuning)
+  const int per_iter = (f & DLMPC_FLAG_SCHED_STEPWISE) ? 3
+                       : (f & DLMPC_FLAG_SCHED_HOST_EXCHANGE) ? 4
+                       : (f & DLMPC_FLAG_SCHED_NAIVE) ? 5 : 0;
+  if (per_iter) {
+    p->sched = per_iter;
+    if (per_iter >= 4)
+      API_HIP(hipHostMalloc(&p->h_xchg, p->eng->exchange_bytes(), hipHostMallocDefault));
+    return DLMPC_OK;
+  }
   if (f & DLMPC_FLAG_SCHED_GRAPH) {
     p->sched = 0;
     return DLMPC_OK;
@@ -482,7 +496,7 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
   std::string err;
   const int max_iter = p->opt.max_iter;
   API_HIP(hipEventRecord(p->ev_p0, p->stream));
-  int rc = p->eng->precompute(x0_dev, wpsi, wlam, max_iter, p->opt.eps, err);
+  int rc = p->eng->precompute(x0_dev, wpsi, wlam, max_iter, p->opt.eps, p->rho, err);
   if (rc) return fail(rc, err);
   API_HIP(hipEventRecord(p->ev_p1, p->stream));
   API_HIP(hipEventRecord(p->ev_t0, p->stream));
@@ -495,12 +509,28 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     launches = 1;
     stopped = true;
   }
+  // Per-iteration schedules: the kernels of one iteration launched one by one and the stop flag
+  // read after every iteration; 4 also copies Phi through host memory between Phi-comp and
+  // Psi-comp (the row-to-column exchange on the host, the other steps combined on the device),
+  // 5 copies each kernel's results through host memory before the next kernel runs.
+  for (int it = 0; p->sched >= 3 && !stopped && it < max_iter; ++it) {
+    for (int kk = 0; kk < 4; ++kk) {
+      if ((rc = p->eng->launch_one(kk, err))) return fail(rc, err);
+      if ((p->sched == 5 || (p->sched == 4 && kk == 0)) && (rc = p->eng->host_exchange(kk, p->h_xchg, err)))
+        return fail(rc, err);
+    }
+    ++launches;
+    API_HIP(hipMemcpyAsync(&p->h_ctl[1], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipEventRecord(p->ev_ctl[1], p->stream));
+    API_HIP(hipEventSynchronize(p->ev_ctl[1]));
+    stopped = p->h_ctl[1].stop != 0;
+  }
   // Graph schedule: launch a chunk of iterations, read the control block, and size the next
   // chunk from the residual decay (ChunkPredictor), so that few launches land after the
   // device-side stop and few host checks are needed. With check_every > 0 the chunk is fixed.
   ChunkPredictor pred;
   int n = p->K;
-  while (!stopped) {
+  while (!stopped && p->sched == 0) {
     n = std::max(1, std::min(n, max_iter - launched));
     rc = launch_iterations(p, n);
     if (rc) return rc;
@@ -518,7 +548,7 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     if (p->opt.check_every > 0) continue;
     n = pred.next(c.iters, c.last_rp, c.last_rd, p->opt.eps);
   }
-  if (!stopped) return fail(DLMPC_EDEVICE, "iteration graph did not reach its stop condition");
+  if (!stopped) return fail(DLMPC_EDEVICE, "the iteration did not reach its stop condition");
   API_HIP(hipEventRecord(p->ev_t1, p->stream));
   rc = p->eng->output(u0_dev, err);
   if (rc) return fail(rc, err);
@@ -555,7 +585,7 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     stats->r_dual = c.last_rd;
     stats->objective = c.objective;
     stats->t_iter_ms = ms;
-    stats->graph_launches = launches;  // host checks (graph schedule) or 1 (persistent)
+    stats->graph_launches = launches;  // host checks (graph and per-iteration schedules) or 1 (persistent)
     stats->schedule = p->sched;
     stats->start = wpsi ? DLMPC_START_STATE : DLMPC_START_COLD;
     stats->fell_back = 0;
@@ -615,6 +645,11 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
   if (o.precision != DLMPC_FP64 && o.precision != DLMPC_FP32 && o.precision != DLMPC_FP32_BF16)
     return fail(DLMPC_EINVAL, "unknown precision");
   if (o.max_batch < 0 || o.max_batch > 64) return fail(DLMPC_EINVAL, "max_batch must be in 0..64");
+  {
+    const uint32_t sf = o.flags & (DLMPC_FLAG_SCHED_GRAPH | DLMPC_FLAG_SCHED_PERSISTENT | DLMPC_FLAG_SCHED_STEPWISE |
+                                   DLMPC_FLAG_SCHED_HOST_EXCHANGE | DLMPC_FLAG_SCHED_NAIVE);
+    if (sf & (sf - 1)) return fail(DLMPC_EINVAL, "at most one DLMPC_FLAG_SCHED_* flag");
+  }
   if (!(o.factor_chol_tol >= 0.0)) return fail(DLMPC_EINVAL, "factor_chol_tol must be >= 0");
   if (o.warm_eps_scale == 0.0) o.warm_eps_scale = 0.5;
   if (!(o.warm_eps_scale > 0.0 && o.warm_eps_scale <= 1.0))
@@ -622,6 +657,7 @@ int dlmpc_setup(const dlmpc_system *sys, int32_t d, int32_t T, const dlmpc_cost 
   auto p = std::make_unique<dlmpc_problem>();
   p->opt = o;
   p->warm_eps = o.eps * o.warm_eps_scale;
+  p->rho = o.rho;
   p->host_only = (o.flags & DLMPC_FLAG_HOST_ONLY) != 0;
   std::string err;
   const auto t_setup = std::chrono::steady_clock::now();
@@ -792,7 +828,7 @@ int dlmpc_time_kernels(dlmpc_problem *p, const double *x0_dev, int32_t iters, do
   if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
   API_HIP(hipSetDevice(p->opt.device));
   std::string err;
-  int rc = p->eng->precompute(x0_dev, nullptr, nullptr, iters, -1.0, err);
+  int rc = p->eng->precompute(x0_dev, nullptr, nullptr, iters, -1.0, p->rho, err);
   if (rc) return fail(rc, err);
   constexpr int nk = DLMPC_TIMED_KERNELS;
   std::vector<hipEvent_t> ev(size_t(nk) * iters + 1);
@@ -1336,6 +1372,14 @@ int dlmpc_closed_loop(dlmpc_problem *p, int32_t B, int32_t T_sim, const double *
   }
   API_HIP(hipStreamSynchronize(p->stream));
   return all ? DLMPC_OK : DLMPC_ENOCONV;
+}
+
+int dlmpc_set_rho(dlmpc_problem *p, double rho) {
+  if (!p) return fail(DLMPC_EINVAL, "NULL problem");
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(DLMPC_EINVAL, "need a finite rho > 0");
+  p->rho = rho;
+  if (p->beng) p->beng->set_rho(rho);
+  return DLMPC_OK;
 }
 
 int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,

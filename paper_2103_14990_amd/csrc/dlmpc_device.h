@@ -34,6 +34,7 @@ struct Ctl {
   // read these here, not from their launch arguments)
   int32_t batch, warm;
   int32_t cg_k, pad3;  // CG steps of the streamed joins' trajectory start
+  double rho;          // single-instance engine: the penalty of the current solve
 };
 
 // Static work lists of the persistent schedule: block b runs Phi-comp for
@@ -58,7 +59,6 @@ struct PsiUnits {
 template <typename Tf>
 struct KArgs {
   int32_t N, nx, nu, T, rs, ts;
-  Tf rho;
   const int64_t *tile_off;  // [N+1]
   const int64_t *rt_ptr;    // [N+1]
   const int64_t *rt_tile;   // [n_tiles]
@@ -82,9 +82,10 @@ class Engine {
  public:
   virtual ~Engine() = default;
   virtual int init(const HostSetup &hs, double rho, hipStream_t s, std::string &err) = 0;
-  // Enqueue the per-solve precompute (cold start when wpsi == nullptr) on the stream.
+  // Enqueue the per-solve precompute (cold start when wpsi == nullptr) on the stream; rho is
+  // the penalty of this solve (kernels read it from the control block).
   virtual int precompute(const double *x0_dev, const double *wpsi, const double *wlam,
-                         int max_iter, double eps, std::string &err) = 0;
+                         int max_iter, double eps, double rho, std::string &err) = 0;
   // Enqueue one ADMM iteration of the graph schedule (capturable), or one of its kernels
   // (0 Phi-comp, 1 Psi pass 1, 2 Psi pass 2, 3 Conv).
   virtual int iteration(std::string &err) = 0;
@@ -94,6 +95,12 @@ class Engine {
   virtual int persistent_grid() const = 0;  // 0 when the device cannot co-schedule the grid
   virtual int output(double *u0_dev, std::string &err) = 0;
   virtual int export_phi(double *phi_dev, std::string &err) = 0;
+  // Exchange through host memory (the schedules that hand the results of one step to the next
+  // through the host): the arrays kernel `which` of an iteration wrote (0 Phi, 1 the pass-1
+  // products, 2 Psi and Lambda, 3 the control block) are copied into the pinned buffer `host`
+  // (exchange_bytes() bytes), the stream is synchronised, and they are copied back.
+  virtual size_t exchange_bytes() const = 0;
+  virtual int host_exchange(int which, void *host, std::string &err) = 0;
   // FP64 certificate of the current iterate for x0_dev: out[0] = max |Z_AB Psi - I| over the
   // support and the (d+1)-hop ring of every column, out[1] = max |Phi - Psi|, out[2] = max over
   // columns of ||Phi[:,c] - Psi[:,c]||_2, out[3] = largest bound violation of Phi x0, out[4] =
@@ -224,6 +231,8 @@ class BatchEngine {
   // One kernel of an iteration: 0 bphi_kernel, 1 bpsi_kernel, 2 bdecide_kernel.
   virtual int launch_one(int k, std::string &err) = 0;
   virtual int output(double *u0_dev, std::string &err) = 0;
+  // Base penalty of the solves started after this call (per-instance factors multiply it).
+  virtual void set_rho(double rho) = 0;
   // Closed loop (Algorithm 1), FP64: x(t+1) = A x(t) + B u(t) for B instances in place in x_dev
   // [B][N*nx] (u_dev [B][N*nu]), with x(t) (at t = 0), x(t+1) and u(t) stored in the loop's
   // trajectories xs_dev [B][T_sim+1][N*nx] and us_dev [B][T_sim][N*nu]. rho_scale_dev [B] (or

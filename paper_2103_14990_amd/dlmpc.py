@@ -26,10 +26,15 @@ FLAG_SCHED_PERSISTENT = 0x4
 FLAG_HOST_FACTOR = 0x8
 FLAG_NO_CHECK = 0x10
 FLAG_NO_TUNE = 0x20
+FLAG_SCHED_STEPWISE = 0x40
+FLAG_SCHED_HOST_EXCHANGE = 0x80
+FLAG_SCHED_NAIVE = 0x100
 CL_SHIFT = 1
 CL_SCALE_RHO = 2
 FACTORS = {"device": 0, "host": FLAG_HOST_FACTOR}
-SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT}
+SCHEDULES = {"auto": 0, "graph": FLAG_SCHED_GRAPH, "persistent": FLAG_SCHED_PERSISTENT,
+             "stepwise": FLAG_SCHED_STEPWISE, "host_exchange": FLAG_SCHED_HOST_EXCHANGE, "naive": FLAG_SCHED_NAIVE}
+SCHEDULE_NAMES = {0: "graph", 1: "persistent", 2: "batched", 3: "stepwise", 4: "host_exchange", 5: "naive"}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16": FP32_BF16}
 TIMED_KERNELS = 4
 KERNEL_NAMES = ("phi_kernel", "psi_pass1_kernel", "psi_pass2_kernel", "conv_kernel")
@@ -127,6 +132,7 @@ EXPORTS = {
     "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_solve_stream": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p]),
+    "dlmpc_set_rho": (C.c_int, [C.c_void_p, C.c_double]),
     "dlmpc_closed_loop": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_int32, C.c_void_p]),
     "dlmpc_solve_stream_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
@@ -226,7 +232,7 @@ class Problem:
                  device: int = 0, stream: int | None = None, check_every: int = 0,
                  host_only: bool = False, schedule: str = "auto", max_batch: int = 0,
                  warm_cg_iters: int = 0, factor: str = "device", factor_chol_tol: float = 0.0,
-                 warm_eps_scale: float = 0.0, check: bool = True, tune: bool = True):
+                 warm_eps_scale: float = 0.0, check: bool = True, tune: bool = True, flags: int = 0):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -241,7 +247,7 @@ class Problem:
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
                        (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule] | FACTORS[factor]
-                       | (0 if check else FLAG_NO_CHECK) | (0 if tune else FLAG_NO_TUNE), max_batch,
+                       | (0 if check else FLAG_NO_CHECK) | (0 if tune else FLAG_NO_TUNE) | flags, max_batch,
                        warm_cg_iters, factor_chol_tol, warm_eps_scale)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
@@ -356,6 +362,10 @@ class Problem:
                                                      C.c_void_p(us_dev), mode, st))
         flat = [x.as_dict() for x in st]
         return s, [flat[t * B:(t + 1) * B] for t in range(T_sim)]
+
+    def set_rho(self, rho: float) -> None:
+        """Penalty of every solve started after this call (dlmpc_set_rho)."""
+        self._check(self._lib.dlmpc_set_rho(self._h, float(rho)))
 
     def solve_stream_noalloc(self, n: int, x0_dev: int, u0_dev: int, refill_min: int = 0,
                              check_iters: int = 0) -> tuple[int, list[dict], dict]:

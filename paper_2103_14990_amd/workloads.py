@@ -16,6 +16,12 @@ evaluation uses synthetic chain networks of 2-state nodes (Section IV-A); the gr
 irregular-mesh topologies and the swing parameters follow the workload definitions this
 project is measured on.
 
+The paper's own evaluation plant (Section IV-A) is ``paper_chain``: a chain of 2-state nodes
+with A_ii = [[1, 0.1], [-0.3, 0.7]], A_ij = [[0, 0], [0.1, 0.1]] for the chain neighbours,
+B_ii = I (two inputs per node, as the printed matrix says; the text's count of one input per
+node would need a 2x1 block the paper does not give), Q = I, R = I and
+-0.2 <= x_{i,1} <= 1.2 on the first state of every node for t >= 1.
+
 Every random draw goes through ``numpy.random.default_rng(seed)`` in a fixed order, so a
 (topology, seed) pair always yields the same plant.
 """
@@ -185,6 +191,33 @@ def swing_network(name: str, n: int, edges: np.ndarray, seed: int, dt: float = D
                    meta={"seed": seed, "dt": dt})
 
 
+def paper_chain(n: int) -> Network:
+    """The paper's chain plant (Section IV-A; see the module docstring): no random draw."""
+    edges = chain_edges(n)
+    a_ii = np.array([[1.0, 0.1], [-0.3, 0.7]])
+    a_ij = np.array([[0.0, 0.0], [0.1, 0.1]])
+    rowptr, colidx, blocks = [0], [], []
+    for i in range(n):
+        for j in sorted({i, i - 1, i + 1} & set(range(n))):
+            colidx.append(j)
+            blocks.append(a_ii if j == i else a_ij)
+        rowptr.append(len(colidx))
+    b = np.broadcast_to(np.eye(2), (n, 2, 2)).copy()
+    return Network(name=f"paper_chain{n}", n_sub=n, nx=2, nu=2, edges=np.asarray(edges, dtype=np.int64),
+                   a_rowptr=np.array(rowptr, dtype=np.int64), a_colidx=np.array(colidx, dtype=np.int32),
+                   a_blocks=np.array(blocks, dtype=np.float64).reshape(-1, 2, 2), b_blocks=b, meta={})
+
+
+def paper_cost(net: Network, lo: float = -0.2, hi: float = 1.2) -> Cost:
+    """Q = I, R = I, lo <= x_{i,1} <= hi (the first state of every node), inputs unbounded."""
+    c = unit_cost(net)
+    nxs = net.n_sub * net.nx
+    x_lo, x_hi = np.full(nxs, -np.inf), np.full(nxs, np.inf)
+    x_lo[0::net.nx], x_hi[0::net.nx] = lo, hi
+    c.x_lo, c.x_hi = x_lo, x_hi
+    return c
+
+
 def chain(n: int, seed: int = 0) -> Network:
     return swing_network(f"chain{n}", n, chain_edges(n), seed)
 
@@ -326,6 +359,13 @@ def _free_rows(net: Network):
 CONSTRAINED_SIGMA = {"grid16": 0.2, "irregular32": 0.15}
 
 
+def paper_workload(n: int, d: int = 1, T: int = 5, sigma: float = 1.0) -> Workload:
+    """The paper's chain plant and cost (Section IV-A) with N = n, locality d and horizon T;
+    x0 = sigma * N(0, I) (the paper does not state its initial conditions)."""
+    net = paper_chain(n)
+    return Workload(f"paper_chain{n}_d{d}_T{T}", net, d=d, T=T, cost=paper_cost(net), sigma=sigma)
+
+
 def workload(name: str) -> Workload:
     """Named workloads (parameter seed 0 for every network)."""
     if name == "chain10":
@@ -344,6 +384,10 @@ def workload(name: str) -> Workload:
     if name == "irregular1024":
         net = irregular_mesh(32, 32, 0)
         return Workload(name, net, d=3, T=15, cost=unit_cost(net), sigma=1.0)
+    if name.startswith("paper_chain"):  # paper_chain<N>[_d<d>_T<T>]
+        parts = name[len("paper_chain"):].split("_")
+        kw = {p[0]: int(p[1:]) for p in parts[1:]}
+        return paper_workload(int(parts[0]), d=kw.get("d", 1), T=kw.get("T", 5))
     if name in ("grid8", "grid32"):
         side = int(name[4:])
         net = grid(side)

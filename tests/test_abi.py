@@ -192,3 +192,14 @@ def test_full_size_irregular_mesh_sampled_blocks():
         assert np.array_equal(blk.rows[idx], rows)
         assert np.abs(P - blk.P[np.ix_(idx, idx)]).max() < 1e-8
         assert np.abs(Ob - blk.O[idx]).max() < 1e-7 * max(1.0, np.abs(blk.O).max())
+
+
+def test_set_rho_argument_checks():
+    wl = W.workload("chain10")
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, host_only=True)
+    pr.set_rho(2.5)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(dlmpc.DlmpcError) as e:
+            pr.set_rho(bad)
+        assert e.value.status == dlmpc.EINVAL
+    pr.close()
