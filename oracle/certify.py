@@ -127,6 +127,62 @@ class QPSolution:
     active_upper: np.ndarray
     kkt: dict
     feasible_resid: float
+    active_pairs: np.ndarray | None = None  # indices into 2 * n_pairs rows: e (upper), n_pairs + e (lower)
+
+
+def separable_qp(c, m, lb, ub, ra, rb, lo, hi, max_active_iter=500, tol=1e-10):
+    """min sum_r c_r (y_r - m_r)^2 s.t. lb <= y <= ub, lo_e <= y[ra_e] - y[rb_e] <= hi_e, by the
+    same dual active-set loop on the dense KKT system (a direct solve of the Phi-step problem that
+    the nested ADMM iterates on). Returns (y, kkt residuals)."""
+    c, m = np.asarray(c, float), np.asarray(m, float)
+    n = len(c)
+    rows, rhs = [], []
+    for r in range(n):
+        if np.isfinite(ub[r]):
+            e = np.zeros(n)
+            e[r] = 1.0
+            rows.append(e)
+            rhs.append(ub[r])
+        if np.isfinite(lb[r]):
+            e = np.zeros(n)
+            e[r] = -1.0
+            rows.append(e)
+            rhs.append(-lb[r])
+    for a_, b_, l_, h_ in zip(ra, rb, lo, hi):
+        e = np.zeros(n)
+        e[a_], e[b_] = 1.0, -1.0
+        rows += [e, -e]
+        rhs += [h_, -l_]
+    Ain, bin_ = np.array(rows).reshape(-1, n), np.array(rhs)
+    H, g = np.diag(2.0 * c), -2.0 * c * m
+    active: list[int] = []
+    for _ in range(max_active_iter):
+        k = len(active)
+        Aa = Ain[active]
+        KKT = np.block([[H, Aa.T], [Aa, np.zeros((k, k))]])
+        sol = np.linalg.lstsq(KKT, np.concatenate([-g, bin_[active]]), rcond=None)[0]
+        y, lam = sol[:n], sol[n:]
+        if k and lam.min() < -tol:
+            active.pop(int(np.argmin(lam)))
+            continue
+        viol = Ain @ y - bin_
+        if len(viol) and viol.max() > tol:
+            cand = int(np.argmax(viol))
+            if cand in active:
+                raise RuntimeError("active-set loop stalled")
+            active.append(cand)
+            continue
+        break
+    else:
+        raise RuntimeError("active-set loop did not converge")
+    mult = np.zeros(len(bin_))
+    mult[active] = lam
+    viol = Ain @ y - bin_
+    kkt = {"stationarity": float(np.abs(H @ y + g + Ain.T @ mult).max()),
+           "primal": float(max(viol.max(initial=0.0), 0.0)),
+           "dual_sign": float(max(-mult.min(initial=0.0), 0.0)),
+           "complementarity": float(np.abs(mult * viol).max(initial=0.0))}
+    return y, kkt
 
 
 def _affine_trajectory_set(sls: DenseSLS, tol: float = 1e-10):
@@ -141,8 +197,9 @@ def _affine_trajectory_set(sls: DenseSLS, tol: float = 1e-10):
 
 
 def localized_qp(A, B, n_sub, nx, nu, d, T, w, x0, lb=None, ub=None, max_active_iter=500,
-                 tol=1e-10) -> QPSolution:
-    """Optimum of min sum_r w_r y_r^2 over y in the localised achievable set, lb <= y <= ub.
+                 tol=1e-10, pairs=None) -> QPSolution:
+    """Optimum of min sum_r w_r y_r^2 over y in the localised achievable set, lb <= y <= ub,
+    and, with pairs = (ra, rb, lo, hi), lo_e <= y[ra_e] - y[rb_e] <= hi_e.
 
     Dual active-set loop on the strictly convex QP in coordinates s (y = y_p + U s): start
     from the unconstrained minimiser, add the most violated bound, solve the equality-
@@ -161,6 +218,12 @@ def localized_qp(A, B, n_sub, nx, nu, d, T, w, x0, lb=None, ub=None, max_active_
     los = np.flatnonzero(np.isfinite(lb))
     Ain = np.vstack([U[ups], -U[los]]) if (len(ups) + len(los)) else np.zeros((0, U.shape[1]))
     bin_ = np.concatenate([ub[ups] - y_p[ups], y_p[los] - lb[los]])
+    n_box = len(bin_)
+    if pairs is not None:
+        ra, rb, plo, phi_ = (np.asarray(v) for v in pairs)
+        Dm, dp = U[ra] - U[rb], y_p[ra] - y_p[rb]
+        Ain = np.vstack([Ain, Dm, -Dm])
+        bin_ = np.concatenate([bin_, phi_ - dp, dp - plo])
     active: list[int] = []
     s = lam = None
     for _ in range(max_active_iter):
@@ -196,9 +259,10 @@ def localized_qp(A, B, n_sub, nx, nu, d, T, w, x0, lb=None, ub=None, max_active_
     act = set(active)
     nu_ = len(ups)
     return QPSolution(y=y, J=float(np.sum(w * y * y)),
-                      active_lower=np.array([los[i - nu_] for i in sorted(act) if i >= nu_], dtype=int),
+                      active_lower=np.array([los[i - nu_] for i in sorted(act) if nu_ <= i < n_box], dtype=int),
                       active_upper=np.array([ups[i] for i in sorted(act) if i < nu_], dtype=int),
-                      kkt=kkt, feasible_resid=eq_resid)
+                      kkt=kkt, feasible_resid=eq_resid,
+                      active_pairs=np.array(sorted(i - n_box for i in act if i >= n_box), dtype=int))
 
 
 def projection_by_kkt(H: np.ndarray, v: np.ndarray, e: np.ndarray) -> np.ndarray:

@@ -218,6 +218,23 @@ def paper_cost(net: Network, lo: float = -0.2, hi: float = 1.2) -> Cost:
     return c
 
 
+def line_limits(net: Network, T: int, limit: float, t0: int = 2) -> tuple:
+    """Couplings lo <= x_{i,1}(t) - x_{j,1}(t) <= hi with lo = -limit, hi = limit for every edge
+    (i < j) and t = t0..T-1 (first state of each node; on the swing network the angle difference
+    of a line, whose flow it sets). Returns (ra, rb, lo, hi) in the canonical row order (state
+    rows x_t subsystem-major). On the swing plant the angles at t = 1 follow from x0 alone, so
+    the default starts at t = 2."""
+    Nx = net.n_sub * net.nx
+    ra, rb = [], []
+    for t in range(t0, T):
+        for i, j in net.edges:
+            ra.append(t * Nx + int(i) * net.nx)
+            rb.append(t * Nx + int(j) * net.nx)
+    n = len(ra)
+    return (np.array(ra, dtype=np.int64), np.array(rb, dtype=np.int64), np.full(n, -float(limit)),
+            np.full(n, float(limit)))
+
+
 def chain(n: int, seed: int = 0) -> Network:
     return swing_network(f"chain{n}", n, chain_edges(n), seed)
 
