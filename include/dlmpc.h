@@ -191,6 +191,9 @@ typedef struct {
   double u0_check;
   double t_precompute_ms; /* device time of the per-solve precompute (Algorithm 1, with x0) */
   double t_check_ms;      /* device time of the FP64 check (per instance share for streams) */
+  int32_t inner_iters;    /* nested-ADMM iterations over the solve (couplings, dlmpc_set_coupling) */
+  int32_t pad;
+  double coupling_viol;   /* largest violation of a coupling by Phi x0 at the stopping iterate */
 } dlmpc_stats;
 
 typedef struct {
@@ -391,6 +394,26 @@ int dlmpc_closed_loop(struct dlmpc_problem *p, int32_t B, int32_t T_sim, const d
  * gives the iterates of dlmpc_closed_loop with DLMPC_CL_SCALE_RHO. Returns DLMPC_EINVAL unless
  * rho is finite and > 0. */
 int dlmpc_set_rho(struct dlmpc_problem *p, double rho);
+
+/* Neighbour-coupled constraints for the single-instance solves (dlmpc_solve, dlmpc_solve_device):
+ * lo_e <= y[row_a_e] - y[row_b_e] <= hi_e for e < n, y = Phi x0 in the canonical row order (x_t
+ * blocks t = 0..T-1, then u_t blocks; rows of x_0 are fixed by x(0) and not allowed). Such
+ * constraints (e.g. the angle difference of a line between neighbouring nodes of the swing
+ * network) couple the rows of different subsystems, so Phi-comp (Algorithm 2) is no longer one
+ * clip per row: its problem in y is min sum_r c_r (y_r - m_r)^2 over the row boxes and the pairs
+ * (c_r = w_r + rho / (2 ||x_r||^2), m_r the uncoupled row value), solved inside every outer
+ * iteration by a nested ADMM with penalty sigma between the coupled rows (per row a clipped 1-D
+ * solve over its own pairs' copies; per pair a projection onto its slab; scaled duals), at most
+ * inner_max iterations, stopping when the copies agree with y and stopped moving to inner_eps,
+ * warm-started from the previous outer iteration (zero at the start of a solve). The rows of
+ * Phi then follow y as in the uncoupled Phi-comp. n = 0 removes the couplings. The persistent
+ * schedule does not take couplings: a problem on it moves to the graph schedule; batched,
+ * streamed, group and closed-loop entries return DLMPC_EINVAL while couplings are set. The
+ * iteration graphs are captured again (synchronises). Stats report inner_iters and the largest
+ * coupling violation of the returned trajectory. Returns DLMPC_EINVAL for a row out of range or
+ * in x_0, row_a == row_b, lo > hi or NaN bounds, sigma <= 0, inner_max < 1 or inner_eps < 0. */
+int dlmpc_set_coupling(struct dlmpc_problem *p, int32_t n, const int64_t *row_a, const int64_t *row_b,
+                       const double *lo, const double *hi, double sigma, int32_t inner_max, double inner_eps);
 
 /* Counters of a streamed solve (dlmpc_solve_stream). */
 typedef struct {

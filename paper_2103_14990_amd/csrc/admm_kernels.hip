@@ -101,6 +101,7 @@ __global__ __launch_bounds__(kBlock) void precompute_kernel(KArgs<Tf> a, const d
     c->last_rd = INFINITY;
     c->eps = eps;
     c->rho = rho;
+    c->inner_iters = 0;
     c->objective = 0.0;
     c->bar_count = 0u;
     c->bar_gen = 0u;
@@ -181,6 +182,13 @@ __device__ __forceinline__ void phi_body(const KArgs<Tf> &a, int m, unsigned cha
       }
       alpha_s[lane] = al;
       a.y[o] = sv;
+      if (a.cp_slot) {  // coupled row: the nested ADMM replaces sv (coupled_fix_kernel)
+        const int k = a.cp_slot[o];
+        if (k >= 0) {
+          a.cp_a[k] = s;
+          a.cp_s0[k] = sv;
+        }
+      }
     }
     __syncthreads();
     if (act) {
@@ -209,6 +217,99 @@ __global__ __launch_bounds__(kBlock) void phi_kernel(KArgs<Tf> a) {
   if (a.ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   phi_body<Tf, NX>(a, a.phi_order[blockIdx.x], smem_raw);
+}
+
+// ------------------------------------------------------------------ coupled Phi-step
+
+__device__ __forceinline__ double block_max1024(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();  // red may still be read by the previous call
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
+  return m;
+}
+
+// Nested ADMM of the coupled Phi-step, one workgroup: the Phi-step in y = Phi x0 is
+// min sum_r c_r (y_r - m_r)^2 over the row boxes and the pairs lo_e <= y_a - y_b <= hi_e, with
+// c_r = w_r + rho / (2 n), m_r = rho a_r / (rho + 2 w_r n). Per inner iteration: every coupled
+// row's y from its own pairs' copies and duals (a 1-D quadratic clipped to its box), then every
+// pair's copies projected onto its slab and its duals updated; stop when the copies agree with
+// y and stopped moving to inner_eps (max norms), or after inner_max iterations. Copies and
+// duals carry over to the next outer iteration.
+template <typename Tf, int NX>
+__global__ __launch_bounds__(1024) void coupled_inner_kernel(KArgs<Tf> a, CoupleArgs<Tf> c) {
+  if (a.ctl->stop) return;
+  __shared__ double red[16];
+  const int tid = threadIdx.x;
+  const double rho = a.ctl->rho, sig = c.sigma;
+  int it = 0;
+  for (it = 1; it <= c.inner_max; ++it) {
+    for (int k = tid; k < c.K; k += 1024) {
+      const int64_t o = c.row[k];
+      const double n = double(a.nrm[c.sub[k]]), ak = double(a.cp_a[k]);
+      double y = ak;
+      if (n > 0.0) {
+        const double w = double(a.w[o]);
+        const double cc = w + rho / (2.0 * n), mm = rho * ak / (rho + 2.0 * w * n);
+        double acc_a = 0.0, acc_b = 0.0;  // first-row pairs, then second-row pairs
+        const int p0 = c.kp_ptr[k], p1 = c.kp_ptr[k + 1];
+        for (int p = p0; p < p1; ++p) {
+          const int e = c.kp_ent[p] >> 1;
+          if (c.kp_ent[p] & 1)
+            acc_b += double(c.zb[e]) - double(c.lb[e]);
+          else
+            acc_a += double(c.za[e]) - double(c.la[e]);
+        }
+        y = (2.0 * cc * mm + sig * (acc_a + acc_b)) / (2.0 * cc + sig * double(p1 - p0));
+        y = fmin(fmax(y, double(a.lb[o])), double(a.ub[o]));
+      }
+      c.y[k] = static_cast<Tf>(y);
+    }
+    __syncthreads();
+    double rp = 0.0, dz = 0.0;
+    for (int e = tid; e < c.E; e += 1024) {
+      const double ya = double(c.y[c.ka[e]]), yb = double(c.y[c.kb[e]]);
+      const double pa = ya + double(c.la[e]), pb = yb + double(c.lb[e]);
+      const double d = pa - pb, sh = 0.5 * (fmin(fmax(d, c.lo[e]), c.hi[e]) - d);
+      const double za = pa + sh, zb = pb - sh;
+      dz = fmax(dz, fmax(fabs(za - double(c.za[e])), fabs(zb - double(c.zb[e]))));
+      rp = fmax(rp, fmax(fabs(ya - za), fabs(yb - zb)));
+      c.la[e] = static_cast<Tf>(double(c.la[e]) + ya - za);
+      c.lb[e] = static_cast<Tf>(double(c.lb[e]) + yb - zb);
+      c.za[e] = static_cast<Tf>(za);
+      c.zb[e] = static_cast<Tf>(zb);
+    }
+    rp = block_max1024(rp, red);
+    dz = block_max1024(dz, red);
+    if (rp <= c.inner_eps && sig * dz <= c.inner_eps) break;
+  }
+  if (tid == 0) a.ctl->inner_iters += it > c.inner_max ? c.inner_max : it;
+}
+
+// The coupled rows' Phi-comp result with the nested ADMM's y: phi = v + ((y - a)/n) x_r, i.e.
+// the uncoupled result plus ((y - s0)/n) x_r on every tile of the row's subsystem.
+template <typename Tf, int NX>
+__global__ __launch_bounds__(256) void coupled_fix_kernel(KArgs<Tf> a, CoupleArgs<Tf> c) {
+  if (a.ctl->stop) return;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= c.K) return;
+  const int64_t o = c.row[k];
+  const int m = c.sub[k], l = int(o - int64_t(m) * a.rs);
+  const Tf n = a.nrm[m];
+  const Tf y = c.y[k];
+  if (!(n > Tf(0))) return;
+  const Tf dl = (y - a.cp_s0[k]) / n;
+  for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
+    const int64_t base = a.rt_tile[q] * a.ts + int64_t(l) * NX;
+    const Tf *xj = a.x0f + int64_t(a.rt_col[q]) * NX;
+#pragma unroll
+    for (int cc = 0; cc < NX; ++cc) a.phi[base + cc] += dl * xj[cc];
+  }
+  a.y[o] = y;
 }
 
 // ------------------------------------------------------------------ Psi/Lambda/Conv
@@ -1067,6 +1168,10 @@ class EngineT final : public Engine {
     hipLaunchKernelGGL((precompute_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), 0, stream_, args_,
                        x0_dev, cold, max_iter, eps, rho);
     ENG_CHECK(hipGetLastError());
+    if (cp_.E > 0) {  // nested ADMM copies and duals start at zero in every solve
+      for (Tf *v : {cp_.za, cp_.zb, cp_.la, cp_.lb})
+        ENG_CHECK(hipMemsetAsync(v, 0, sizeof(Tf) * size_t(cp_.E), stream_));
+    }
     if (!cold) {
       const int64_t n = int64_t(hs_->n_tiles) * hs_->ts;
       const int g = int(std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
@@ -1089,6 +1194,13 @@ class EngineT final : public Engine {
     switch (which) {
       case 0:
         hipLaunchKernelGGL((phi_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_phi_, stream_, args_);
+        if (cp_.K > 0) {
+          ENG_CHECK(hipGetLastError());
+          hipLaunchKernelGGL((coupled_inner_kernel<Tf, NX>), dim3(1), dim3(1024), 0, stream_, args_, cp_);
+          ENG_CHECK(hipGetLastError());
+          hipLaunchKernelGGL((coupled_fix_kernel<Tf, NX>), dim3((cp_.K + 255) / 256), dim3(256), 0, stream_, args_,
+                             cp_);
+        }
         break;
       case 1:
         hipLaunchKernelGGL((psi_pass1_kernel<Tf, NX>), dim3(n1_), dim3(kBlock), lds_p1_, stream_, args_, pu_);
@@ -1101,6 +1213,85 @@ class EngineT final : public Engine {
         break;
     }
     ENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  int set_coupling(int n, const int64_t *row_a, const int64_t *row_b, const double *lo, const double *hi,
+                   double sigma, int inner_max, double inner_eps, std::string &err) override {
+    ENG_CHECK(hipStreamSynchronize(stream_));
+    cp_ = CoupleArgs<Tf>{};
+    args_.cp_slot = nullptr;
+    args_.cp_a = args_.cp_s0 = nullptr;
+    if (n == 0) return DLMPC_OK;
+    const int64_t R = int64_t(hs_->N) * hs_->rs;
+    // coupled rows in order of first appearance; pairs of every coupled row (CSR)
+    std::vector<int32_t> slot(size_t(R), -1), ka(n), kb(n);
+    std::vector<int64_t> rows;
+    auto idx = [&](int64_t o) {
+      if (slot[o] < 0) {
+        slot[o] = int32_t(rows.size());
+        rows.push_back(o);
+      }
+      return slot[o];
+    };
+    for (int e = 0; e < n; ++e) {
+      ka[e] = idx(row_a[e]);
+      kb[e] = idx(row_b[e]);
+    }
+    const int K = int(rows.size());
+    std::vector<int32_t> sub(K), ptr(K + 1, 0), ent(2 * size_t(n));
+    for (int k = 0; k < K; ++k) sub[k] = int32_t(rows[k] / hs_->rs);
+    for (int e = 0; e < n; ++e) {
+      ++ptr[ka[e] + 1];
+      ++ptr[kb[e] + 1];
+    }
+    for (int k = 0; k < K; ++k) ptr[k + 1] += ptr[k];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    // at every row: its first-row pairs in ascending order, then its second-row pairs
+    for (int e = 0; e < n; ++e) ent[fill[ka[e]]++] = 2 * e;
+    for (int e = 0; e < n; ++e) ent[fill[kb[e]]++] = 2 * e + 1;
+    const std::vector<double> vlo(lo, lo + n), vhi(hi, hi + n);
+    CoupleArgs<Tf> c{};
+    c.K = K;
+    c.E = n;
+    c.inner_max = inner_max;
+    c.sigma = sigma;
+    c.inner_eps = inner_eps;
+    int rc;
+    int64_t *d_row = nullptr;
+    int32_t *d_sub = nullptr, *d_ka = nullptr, *d_kb = nullptr, *d_ptr = nullptr, *d_ent = nullptr;
+    double *d_lo = nullptr, *d_hi = nullptr;
+    if ((rc = upload(rows, &d_row, err)) || (rc = upload(sub, &d_sub, err)) || (rc = upload(ka, &d_ka, err)) ||
+        (rc = upload(kb, &d_kb, err)) || (rc = upload(ptr, &d_ptr, err)) || (rc = upload(ent, &d_ent, err)) ||
+        (rc = upload(vlo, &d_lo, err)) || (rc = upload(vhi, &d_hi, err)) || (rc = alloc(&c.za, size_t(n), err)) ||
+        (rc = alloc(&c.zb, size_t(n), err)) || (rc = alloc(&c.la, size_t(n), err)) ||
+        (rc = alloc(&c.lb, size_t(n), err)) || (rc = alloc(&c.y, size_t(K), err)))
+      return rc;
+    c.row = d_row;
+    c.sub = d_sub;
+    c.ka = d_ka;
+    c.kb = d_kb;
+    c.kp_ptr = d_ptr;
+    c.kp_ent = d_ent;
+    c.lo = d_lo;
+    c.hi = d_hi;
+    int32_t *d_slot = nullptr;
+    Tf *d_a = nullptr, *d_s0 = nullptr;
+    if ((rc = upload(slot, &d_slot, err)) || (rc = alloc(&d_a, size_t(K), err)) || (rc = alloc(&d_s0, size_t(K), err)))
+      return rc;
+    args_.cp_slot = d_slot;
+    args_.cp_a = d_a;
+    args_.cp_s0 = d_s0;
+    cp_ = c;
+    return DLMPC_OK;
+  }
+
+  int copy_y(std::vector<double> &out, std::string &err) override {
+    const size_t R = size_t(hs_->N) * hs_->rs;
+    std::vector<Tf> tmp(R);
+    ENG_CHECK(hipMemcpyAsync(tmp.data(), args_.y, R * sizeof(Tf), hipMemcpyDeviceToHost, stream_));
+    ENG_CHECK(hipStreamSynchronize(stream_));
+    out.assign(tmp.begin(), tmp.end());
     return DLMPC_OK;
   }
 
@@ -1257,6 +1448,7 @@ class EngineT final : public Engine {
   hipStream_t stream_ = nullptr;
   size_t t_len_ = 0;  // entries of the Psi pass-1 products t_j
   KArgs<Tf> args_{};
+  CoupleArgs<Tf> cp_{};  // K = 0: no couplings
   const int64_t *map_ = nullptr;
   const double *w64_ = nullptr;
   CertArgs cert_{};

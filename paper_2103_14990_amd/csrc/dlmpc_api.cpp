@@ -62,6 +62,9 @@ struct dlmpc_problem {
   int32_t *d_flag = nullptr, *h_flag = nullptr;
   double warm_eps = 1e-4;  // eps of warm-started batched and streamed runs
   double rho = 5.0;        // penalty of the solves (options.rho until dlmpc_set_rho)
+  // neighbour-coupled constraints of the single-instance solves (library row indices)
+  std::vector<int64_t> cp_a, cp_b;
+  std::vector<double> cp_lo, cp_hi;
 };
 
 namespace {
@@ -131,6 +134,32 @@ void release_device(dlmpc_problem *p) {
 }
 
 int choose_schedule(dlmpc_problem *p);
+
+// (Re)captures the single-instance iteration graphs of 2^g iterations (synchronises).
+int capture_single(dlmpc_problem *p) {
+  std::string err;
+  API_HIP(hipStreamSynchronize(p->stream));
+  for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
+    if (p->gexec[g]) (void)hipGraphExecDestroy(p->gexec[g]);
+    if (p->graph[g]) (void)hipGraphDestroy(p->graph[g]);
+    p->gexec[g] = nullptr;
+    p->graph[g] = nullptr;
+    API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < (1 << g); ++i) {
+      const int rc = p->eng->iteration(err);
+      if (rc) {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(p->stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(rc, err);
+      }
+    }
+    API_HIP(hipStreamEndCapture(p->stream, &p->graph[g]));
+    API_HIP(hipGraphInstantiate(&p->gexec[g], p->graph[g], nullptr, nullptr, 0));
+  }
+  API_HIP(hipStreamSynchronize(p->stream));
+  return DLMPC_OK;
+}
 int setup_batch(dlmpc_problem *p);
 
 int setup_device(dlmpc_problem *p) {
@@ -164,21 +193,7 @@ int setup_device(dlmpc_problem *p) {
   API_HIP(hipHostMalloc(reinterpret_cast<void **>(&p->h_flag), sizeof(int32_t), hipHostMallocDefault));
   // Iteration graphs of 2^g iterations; every launch after the device-side stop is a no-op.
   p->K = p->opt.check_every > 0 ? std::min(p->opt.check_every, p->opt.max_iter) : 32;
-  for (int g = 0; g < dlmpc_problem::kGraphs; ++g) {
-    API_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < (1 << g); ++i) {
-      rc = p->eng->iteration(err);
-      if (rc) {
-        hipGraph_t gr = nullptr;
-        (void)hipStreamEndCapture(p->stream, &gr);
-        if (gr) (void)hipGraphDestroy(gr);
-        return fail(rc, err);
-      }
-    }
-    API_HIP(hipStreamEndCapture(p->stream, &p->graph[g]));
-    API_HIP(hipGraphInstantiate(&p->gexec[g], p->graph[g], nullptr, nullptr, 0));
-  }
-  API_HIP(hipStreamSynchronize(p->stream));
+  if ((rc = capture_single(p))) return rc;
   if (p->opt.max_batch > 0) {
     rc = setup_batch(p);
     if (rc) return rc;
@@ -579,6 +594,16 @@ int run_solve(dlmpc_problem *p, const double *x0_dev, const double *wpsi, const 
     stats->u0_check = 0.0;
     stats->t_precompute_ms = mp;
     stats->t_check_ms = mc;
+    stats->inner_iters = c.inner_iters;
+    stats->coupling_viol = 0.0;
+    if (!p->cp_a.empty()) {
+      std::vector<double> y;
+      if ((rc = p->eng->copy_y(y, err))) return fail(rc, err);
+      for (size_t e = 0; e < p->cp_a.size(); ++e) {
+        const double d = y[p->cp_a[e]] - y[p->cp_b[e]];
+        stats->coupling_viol = std::max(stats->coupling_viol, std::max(p->cp_lo[e] - d, d - p->cp_hi[e]));
+      }
+    }
     stats->iters = c.iters;
     stats->converged = c.converged;
     stats->r_primal = c.last_rp;
@@ -1088,6 +1113,7 @@ int check_batch(dlmpc_problem *p, int32_t B) {
   if (!p) return fail(DLMPC_EINVAL, "NULL problem");
   if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
   if (!p->beng) return fail(DLMPC_EINVAL, "problem was set up without max_batch");
+  if (!p->cp_a.empty()) return fail(DLMPC_EINVAL, "couplings are set: only single-instance solves take them");
   if (B < 1 || B > p->beng->bmax()) return fail(DLMPC_EINVAL, "batch size out of range");
   return DLMPC_OK;
 }
@@ -1382,6 +1408,45 @@ int dlmpc_set_rho(dlmpc_problem *p, double rho) {
   return DLMPC_OK;
 }
 
+int dlmpc_set_coupling(dlmpc_problem *p, int32_t n, const int64_t *row_a, const int64_t *row_b, const double *lo,
+                       const double *hi, double sigma, int32_t inner_max, double inner_eps) {
+  if (!p) return fail(DLMPC_EINVAL, "NULL problem");
+  if (n < 0 || (n > 0 && (!row_a || !row_b || !lo || !hi))) return fail(DLMPC_EINVAL, "NULL coupling array");
+  if (!(sigma > 0.0) || !std::isfinite(sigma) || inner_max < 1 || !(inner_eps >= 0.0))
+    return fail(DLMPC_EINVAL, "need sigma > 0, inner_max >= 1, inner_eps >= 0");
+  const HostSetup &h = p->hs;
+  const int64_t Nx = int64_t(h.N) * h.nx, Nu = int64_t(h.N) * h.nu, R = Nx * h.T + Nu * (h.T - 1);
+  // canonical row -> library row m * rs + l (local order x_0..x_{T-1}, then u_0..u_{T-2})
+  auto lib_row = [&](int64_t r) -> int64_t {
+    if (r < Nx * h.T) {
+      const int64_t t = r / Nx, q = r % Nx;
+      return (q / h.nx) * h.rs + t * h.nx + q % h.nx;
+    }
+    const int64_t r2 = r - Nx * h.T, t = r2 / Nu, q = r2 % Nu;
+    return (q / h.nu) * h.rs + int64_t(h.nx) * h.T + t * h.nu + q % h.nu;
+  };
+  std::vector<int64_t> a(n), b(n);
+  for (int32_t e = 0; e < n; ++e) {
+    if (row_a[e] < Nx || row_a[e] >= R || row_b[e] < Nx || row_b[e] >= R || row_a[e] == row_b[e])
+      return fail(DLMPC_EINVAL, "coupling " + std::to_string(e) + ": rows must be distinct, in range and not in x_0");
+    if (std::isnan(lo[e]) || std::isnan(hi[e]) || lo[e] > hi[e])
+      return fail(DLMPC_EINVAL, "coupling " + std::to_string(e) + ": need lo <= hi");
+    a[e] = lib_row(row_a[e]);
+    b[e] = lib_row(row_b[e]);
+  }
+  if (p->host_only) return fail(DLMPC_EDEVICE, "problem was set up host-only");
+  API_HIP(hipSetDevice(p->opt.device));
+  std::string err;
+  int rc = p->eng->set_coupling(n, a.data(), b.data(), lo, hi, sigma, inner_max, inner_eps, err);
+  if (rc) return fail(rc, err);
+  p->cp_a = a;
+  p->cp_b = b;
+  p->cp_lo.assign(lo, lo + n);
+  p->cp_hi.assign(hi, hi + n);
+  if (p->sched == 1) p->sched = 0;  // the persistent kernel has no nested step
+  return capture_single(p);
+}
+
 int dlmpc_solve_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev, int32_t refill_min,
                        int32_t check_iters, dlmpc_stats *stats, dlmpc_stream_info *info) {
   const double t0 = now_ms();
@@ -1575,6 +1640,7 @@ int dlmpc_group_create(dlmpc_problem *const *probs, int32_t n, dlmpc_group **out
   for (int i = 0; i < n; ++i) {
     if (!probs[i]) return fail(DLMPC_EINVAL, "NULL problem in group");
     if (probs[i]->host_only || !probs[i]->beng) return fail(DLMPC_EINVAL, "group members need the batched engine (max_batch > 0)");
+    if (!probs[i]->cp_a.empty()) return fail(DLMPC_EINVAL, "couplings are set: only single-instance solves take them");
     if (probs[i]->opt.device != probs[0]->opt.device) return fail(DLMPC_EINVAL, "group members must share one device");
     for (int k = 0; k < i; ++k)
       if (probs[k] == probs[i]) return fail(DLMPC_EINVAL, "a problem appears twice in the group");

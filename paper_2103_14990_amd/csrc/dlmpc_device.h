@@ -35,6 +35,8 @@ struct Ctl {
   int32_t batch, warm;
   int32_t cg_k, pad3;  // CG steps of the streamed joins' trajectory start
   double rho;          // single-instance engine: the penalty of the current solve
+  int32_t inner_iters;  // single-instance engine: nested-ADMM iterations of the solve (couplings)
+  int32_t pad4;
 };
 
 // Static work lists of the persistent schedule: block b runs Phi-comp for
@@ -76,6 +78,23 @@ struct KArgs {
   Tf *nrm;                  // [N] ||x_r||^2 per row subsystem
   Tf *y;                    // [N*rs] (Phi x0)_r of the latest Phi-comp
   Ctl *ctl;
+  // Neighbour-coupled constraints (NULL cp_slot: none): coupled-row index of each row (-1 if
+  // uncoupled), and per coupled row the Phi-comp's a = v . x_r and its uncoupled row value
+  int32_t *cp_slot;
+  Tf *cp_a, *cp_s0;
+};
+
+// Nested ADMM of the coupled Phi-step (single-instance engine): K coupled rows (library row
+// index and subsystem), E pairs lo_e <= y[ka_e] - y[kb_e] <= hi_e, the pairs of every coupled
+// row (CSR, entries 2 e + side), the pair copies and scaled duals, and the inner y.
+template <typename Tf>
+struct CoupleArgs {
+  int32_t K, E, inner_max;
+  double sigma, inner_eps;
+  const int64_t *row;
+  const int32_t *sub, *ka, *kb, *kp_ptr, *kp_ent;
+  const double *lo, *hi;
+  Tf *za, *zb, *la, *lb, *y;
 };
 
 class Engine {
@@ -100,6 +119,14 @@ class Engine {
   // products, 2 Psi and Lambda, 3 the control block) are copied into the pinned buffer `host`
   // (exchange_bytes() bytes), the stream is synchronised, and they are copied back.
   virtual size_t exchange_bytes() const = 0;
+  // Phi x0 of the latest Phi-comp (library row order), on the host. Synchronises.
+  virtual int copy_y(std::vector<double> &out, std::string &err) = 0;
+  // Neighbour-coupled constraints on the rows of Phi x0 (library row indices o = m * rs + l):
+  // lo_e <= y[row_a_e] - y[row_b_e] <= hi_e, solved inside Phi-comp by a nested ADMM (penalty
+  // sigma, at most inner_max iterations, stop at inner_eps); n = 0 removes them.
+  virtual int set_coupling(int n, const int64_t *row_a, const int64_t *row_b, const double *lo,
+                           const double *hi, double sigma, int inner_max, double inner_eps,
+                           std::string &err) = 0;
   virtual int host_exchange(int which, void *host, std::string &err) = 0;
   // FP64 certificate of the current iterate for x0_dev: out[0] = max |Z_AB Psi - I| over the
   // support and the (d+1)-hop ring of every column, out[1] = max |Phi - Psi|, out[2] = max over

@@ -75,7 +75,8 @@ class Stats(C.Structure):
                 ("t_iter_ms", C.c_double), ("graph_launches", C.c_int32), ("schedule", C.c_int32),
                 ("start", C.c_int32), ("fell_back", C.c_int32), ("t_warm_ms", C.c_double),
                 ("kkt", C.c_double), ("eq_resid", C.c_double), ("u0_check", C.c_double),
-                ("t_precompute_ms", C.c_double), ("t_check_ms", C.c_double)]
+                ("t_precompute_ms", C.c_double), ("t_check_ms", C.c_double), ("inner_iters", C.c_int32),
+                ("pad", C.c_int32), ("coupling_viol", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -132,6 +133,9 @@ EXPORTS = {
     "dlmpc_solve_batch_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
     "dlmpc_solve_stream": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p]),
+    "dlmpc_set_coupling": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_int32,
+                                     C.c_double]),
     "dlmpc_set_rho": (C.c_int, [C.c_void_p, C.c_double]),
     "dlmpc_closed_loop": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_int32, C.c_void_p]),
@@ -362,6 +366,20 @@ class Problem:
                                                      C.c_void_p(us_dev), mode, st))
         flat = [x.as_dict() for x in st]
         return s, [flat[t * B:(t + 1) * B] for t in range(T_sim)]
+
+    def set_coupling(self, row_a, row_b, lo, hi, sigma: float = 1.0, inner_max: int = 50,
+                     inner_eps: float = 1e-9) -> None:
+        """Neighbour-coupled constraints lo <= y[row_a] - y[row_b] <= hi on canonical rows of
+        Phi x0 for the single-instance solves (dlmpc_set_coupling); empty arrays remove them."""
+        ra = np.ascontiguousarray(row_a, dtype=np.int64)
+        rb = np.ascontiguousarray(row_b, dtype=np.int64)
+        lo_, hi_ = _f64(lo), _f64(hi)
+        n = len(ra)
+        if not (len(rb) == n and len(lo_) == n and len(hi_) == n):
+            raise ValueError("row_a, row_b, lo, hi must have one entry per coupling")
+        self._check(self._lib.dlmpc_set_coupling(self._h, n, _ptr(ra, C.c_int64), _ptr(rb, C.c_int64), _ptr(lo_),
+                                                 _ptr(hi_), float(sigma), int(inner_max), float(inner_eps)))
+        self._coupling = (ra, rb, lo_, hi_)
 
     def set_rho(self, rho: float) -> None:
         """Penalty of every solve started after this call (dlmpc_set_rho)."""

@@ -203,3 +203,22 @@ def test_set_rho_argument_checks():
             pr.set_rho(bad)
         assert e.value.status == dlmpc.EINVAL
     pr.close()
+
+
+def test_set_coupling_argument_checks_host_only():
+    wl = W.workload("paper_chain10")
+    pr = dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, host_only=True)
+    ra, rb, lo, hi = W.line_limits(wl.net, wl.T, 0.3, t0=1)
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        pr.set_coupling(ra, rb, hi, lo)  # lo > hi
+    assert e.value.status == dlmpc.EINVAL
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        pr.set_coupling(ra * 0 + 1, rb, lo, hi)  # rows of x_0
+    assert e.value.status == dlmpc.EINVAL
+    with pytest.raises(dlmpc.DlmpcError) as e:
+        pr.set_coupling(ra, rb, lo, hi, inner_max=0)
+    assert e.value.status == dlmpc.EINVAL
+    with pytest.raises(dlmpc.DlmpcError) as e:  # valid couplings, but no device
+        pr.set_coupling(ra, rb, lo, hi)
+    assert e.value.status == dlmpc.EDEVICE
+    pr.close()
