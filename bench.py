@@ -333,11 +333,12 @@ def main() -> int:
     R = N * rs
     stream = torch.cuda.current_stream(dev)
 
-    def make(precision, max_batch):
+    def make(precision, max_batch, **kw):
         t = time.perf_counter()
         p = dlmpc.Problem.from_network(net, wl.d, wl.T, wl.cost, rho=wl.rho, eps=wl.eps,
                                        max_iter=wl.max_iter, precision=precision, device=0,
-                                       stream=stream.cuda_stream, max_batch=max_batch, warm_cg_iters=args.cg_iters)
+                                       stream=stream.cuda_stream, max_batch=max_batch, warm_cg_iters=args.cg_iters,
+                                       **kw)
         log(f"setup {precision} (max_batch {max_batch}): {time.perf_counter() - t:.1f} s")
         return p
 
@@ -527,10 +528,14 @@ def main() -> int:
     single = {"latency_ms": lat_stats(q["t_solve_ms"] for q in ss),
               "iters_mean": float(np.mean([q["iters"] for q in ss])),
               "check_ms_mean": round(float(np.mean([q["t_check_ms"] for q in ss])), 4),
-              "schedule": dlmpc.SCHEDULE_NAMES[pr.info["schedule"]]}
+              "schedule": dlmpc.SCHEDULE_NAMES[pr.info["schedule"]],
+              "psi_structured": bool(pr.info["psi_structured"])}
+    # the plain FP64 cold-start solve: the paper's iteration on the graph schedule with the dense
+    # Psi-comp; then the library's own FP64 single solve (the setup's choice of schedule and
+    # Psi-comp) beside it
     ref = {}
     uf = torch.zeros((nl, n_u), dtype=torch.float64, device=dev)
-    prf = make("fp64", 0)
+    prf = make("fp64", 0, schedule="graph")
     prf.solve_device(xl[0].data_ptr(), uf[0].data_ptr())
     torch.cuda.synchronize()
     sf = [prf.solve_device(xl[i].data_ptr(), uf[i].data_ptr())[1] for i in range(nl)]
@@ -538,9 +543,23 @@ def main() -> int:
     ref = {"latency_ms": lat_stats(q["t_solve_ms"] for q in sf),
            "iters_mean": float(np.mean([q["iters"] for q in sf])),
            "time_to_eps_ms_median": lat_stats(q["t_solve_ms"] for q in sf)["median"],
-           "schedule": dlmpc.SCHEDULE_NAMES[prf.info["schedule"]],
+           "schedule": dlmpc.SCHEDULE_NAMES[prf.info["schedule"]], "psi_structured": False,
            "u0_rel_diff_single_fp32_vs_fp64_max": float(((ul - uf).abs().amax(dim=1) / uf.abs().amax(dim=1)).max())}
     prf.close()
+    pra = make("fp64", 0)
+    ua = torch.zeros((nl, n_u), dtype=torch.float64, device=dev)
+    pra.solve_device(xl[0].data_ptr(), ua[0].data_ptr())
+    torch.cuda.synchronize()
+    sa_ = [pra.solve_device(xl[i].data_ptr(), ua[i].data_ptr())[1] for i in range(nl)]
+    single64 = {"latency_ms": lat_stats(q["t_solve_ms"] for q in sa_),
+                "iters_mean": float(np.mean([q["iters"] for q in sa_])),
+                "schedule": dlmpc.SCHEDULE_NAMES[pra.info["schedule"]],
+                "psi_structured": bool(pra.info["psi_structured"]),
+                "tune_us_per_iteration": {"graph_dense": round(pra.info["tune_graph_us"], 1),
+                                          "persistent": round(pra.info["tune_persistent_us"], 1),
+                                          "graph_structured": round(pra.info["tune_structured_us"], 1)},
+                "u0_rel_diff_vs_plain_fp64_max": float(((ua - uf).abs().amax(dim=1) / uf.abs().amax(dim=1)).max())}
+    pra.close()
     bl = {}
     for start in ("learned", "cold") if args.start == "learned" else ("cold",):
         ub_ = torch.zeros((nl, n_u), dtype=torch.float64, device=dev)
@@ -555,7 +574,7 @@ def main() -> int:
     ref["u0_rel_diff_batched_cold_vs_fp64_max"] = float(
         ((ul_cold - uf).abs().amax(dim=1) / uf.abs().amax(dim=1)).max())
     latency = {"seeds": [1000, 999 + nl], "single_fp32_cold": single["latency_ms"],
-               "plain_fp64_cold": ref["latency_ms"],
+               "single_fp64_cold": single64["latency_ms"], "plain_fp64_cold": ref["latency_ms"],
                **{f"batched_{k}": v for k, v in bl.items()},
                "streamed_learned": lat_stats(q["t_solve_ms"] for q in stats) if S else None}
     log(f"latency: {latency}")
@@ -776,6 +795,7 @@ def main() -> int:
         "batched_cold": cold,
         "mixed_networks": mixed,
         "single_fp32_cold": single,
+        "single_fp64_cold": single64,
         "plain_fp64_cold": ref,
         "bf16_operator_tier": tier,
         "configs": configs,

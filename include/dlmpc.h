@@ -96,6 +96,14 @@ typedef enum {
 #define DLMPC_FLAG_SCHED_HOST_EXCHANGE 0x80u /* as STEPWISE, and Phi is copied to host memory and back
                                             between Phi-comp and Psi-comp (combined kernels: one
                                             CPU exchange per iteration, Section III-C) */
+#define DLMPC_FLAG_STRUCTURED_PSI 0x200u /* single-instance solves: Psi-comp through the input rows of
+                                            the null bases and the patch simulation (a null-space
+                                            trajectory is fixed by its inputs: N_j = S_j N_u), reading
+                                            p nu (T-1) instead of p (nx T + nu (T-1)) basis rows per
+                                            column subsystem; same iterates up to rounding; graph or
+                                            per-iteration schedules only. Without any schedule flag
+                                            (and without DLMPC_FLAG_NO_TUNE) setup times it against
+                                            the dense Psi-comp and keeps the faster one */
 #define DLMPC_FLAG_SCHED_NAIVE 0x100u    /* as STEPWISE, and every kernel's results are copied to
                                             host memory and back before the next kernel runs (the
                                             naive parallelization of Section III-A) */
@@ -232,6 +240,12 @@ typedef struct {
   int32_t tune_cached;      /* 1 if the choices came from the cache */
   double tune_phi_us[2];    /* per-launch us of the Phi-comp variants 1, 2 (0 if not timed) */
   double tune_psi_us[5];    /* per-launch us of the Psi-comp splits 2, 4, 8, 16, none */
+  /* Single-instance Psi-comp: 1 if the structured one (DLMPC_FLAG_STRUCTURED_PSI) runs, chosen
+   * by the flag, or by timing at setup when no schedule flag is given (tune_structured_us: its
+   * per-iteration time on the graph schedule, 0 if not timed). */
+  int32_t psi_structured;
+  int32_t pad_info;
+  double tune_structured_us;
 } dlmpc_info;
 
 /* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the

@@ -629,6 +629,242 @@ __global__ __launch_bounds__(kBlock) void psi_pass2_kernel(KArgs<Tf> a, PsiUnits
   }
 }
 
+// ------------------------------------------------------------------ structured Psi-comp
+//
+// Pass 1a (one block per column subsystem j): g = v_u + S_x' v_x for v = (Phi + Lambda) on
+// supp(j) by the adjoint recursion mu_t = v_{x,t} + A_PP' mu_{t+1} (mu_T = 0),
+// g_{t-1} = v_{u,t-1} + B_P' mu_t. Pass 1b (the dense pass 1's units of basis vectors):
+// t_j = N_u' g. Pass 2 (one block per j): w = N_u t_j, the trajectory x_0 = 0,
+// x_t = A_PP x_{t-1} + B_P w_{t-1} on the patch, Psi = [x; w] + o_c, then Lambda and the
+// residual partial sums as in the dense pass 2 (one unit per column subsystem).
+
+// Pass 1a: the adjoint recursion of column subsystem j (one block per j) into sa.g.
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void sadj_kernel(KArgs<Tf> a, SimArgs<Tf> sa) {
+  if (a.ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  const int j = a.psi_order[blockIdx.x];
+  const int64_t tb = a.tile_off[j];
+  const int p = int(a.tile_off[j + 1] - tb), rs = a.rs, nu = a.nu, T = a.T;
+  const int D = p * rs, ld = (D + 3) & ~3, nxT = NX * T, nuT = nu * (T - 1);
+  const int mu = p * nuT, mul = (mu + 3) & ~3, ns = p * NX;
+  const int64_t base = tb * a.ts;
+  Tf *v = reinterpret_cast<Tf *>(smem_raw);  // [NX][ld]
+  Tf *m0 = v + NX * ld;                       // [NX][ns] adjoint state, two buffers
+  Tf *m1 = m0 + NX * ns;
+  Tf *g = sa.g + sa.goff[j];                  // [NX][mul]
+  for (int e = tid; e < D * NX; e += kBlock) {
+    const int r = e / NX, c = e - r * NX;
+    v[c * ld + r] = a.phi[base + e] + a.lam[base + e];
+  }
+  for (int e = tid; e < NX * (mul - mu); e += kBlock) {  // zero padding rows
+    const int c = e / (mul - mu);
+    g[c * mul + mu + e - c * (mul - mu)] = Tf(0);
+  }
+  for (int e = tid; e < NX * ns; e += kBlock) m1[e] = Tf(0);
+  __syncthreads();
+  const int32_t *rpt = sa.rpt + sa.rp0[j];
+  const int32_t *colt = sa.colt + sa.e0[j];
+  const Tf *valt = sa.valt + sa.e0[j];
+  Tf *mcur = m0, *mnext = m1;  // mnext holds mu_{t+1}
+  for (int t = T - 1; t >= 1; --t) {
+    for (int e = tid; e < ns * NX; e += kBlock) {
+      const int c = e / ns, r = e - c * ns;
+      const int ti = r / NX, st = r - ti * NX;
+      Tf acc = v[c * ld + ti * rs + t * NX + st];
+      for (int q = rpt[r]; q < rpt[r + 1]; ++q) acc += valt[q] * mnext[c * ns + colt[q]];
+      mcur[c * ns + r] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < p * nu * NX; e += kBlock) {
+      const int c = e / (p * nu), rr = e - c * p * nu;
+      const int ti = rr / nu, kk = rr - ti * nu;
+      const Tf *bb = sa.bblk + int64_t(sa.tile_sub[tb + ti]) * NX * nu;
+      Tf acc = v[c * ld + ti * rs + nxT + (t - 1) * nu + kk];
+#pragma unroll
+      for (int st = 0; st < NX; ++st) acc += bb[st * nu + kk] * mcur[c * ns + ti * NX + st];
+      g[c * mul + ti * nuT + (t - 1) * nu + kk] = acc;
+    }
+    __syncthreads();
+    Tf *tmp = mcur;
+    mcur = mnext;
+    mnext = tmp;
+  }
+}
+
+// Pass 1b: t_j = N_u' g for kP1Cols basis vectors per unit (the dense pass 1's units).
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void spass1_kernel(KArgs<Tf> a, PsiUnits<Tf> pu, SimArgs<Tf> sa) {
+  if (a.ctl->stop) return;
+  using V = typename VecT<Tf>::type;
+  constexpr int VN = VecT<Tf>::N;
+  constexpr int kUC = 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = pu.p1[2 * blockIdx.x], ibase = pu.p1[2 * blockIdx.x + 1];
+  const int p = int(a.tile_off[j + 1] - a.tile_off[j]);
+  const int mul = (p * a.nu * (a.T - 1) + 3) & ~3, nvec = mul / VN, k = a.kdim[j];
+  Tf *g = reinterpret_cast<Tf *>(smem_raw);  // [NX][mul]
+  const Tf *gg = sa.g + sa.goff[j];
+  for (int e = tid; e < NX * mul; e += kBlock) g[e] = gg[e];
+  __syncthreads();
+  const int i0 = ibase + wave * kUC;
+  if (i0 >= k) return;
+  const Tf *__restrict__ Nu = sa.nbu + sa.nbu_off[j];
+  Tf acc[kUC][NX];
+#pragma unroll
+  for (int u = 0; u < kUC; ++u)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) acc[u][c] = Tf(0);
+  for (int q = lane; q < nvec; q += 64) {
+    V nv[kUC];
+#pragma unroll
+    for (int u = 0; u < kUC; ++u)
+      nv[u] = (i0 + u < k) ? *reinterpret_cast<const V *>(Nu + int64_t(i0 + u) * mul + q * VN) : V(0);
+    V gv[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) gv[c] = *reinterpret_cast<const V *>(g + c * mul + q * VN);
+#pragma unroll
+    for (int u = 0; u < kUC; ++u)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) acc[u][c] += hsum(nv[u] * gv[c]);
+  }
+  Tf *tj = pu.t + pu.t_off[j];
+#pragma unroll
+  for (int u = 0; u < kUC; ++u)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const Tf sm = wave_sum(acc[u][c]);
+      if (lane == 0 && i0 + u < k) tj[c * k + i0 + u] = sm;
+    }
+}
+
+template <typename Tf, int NX>
+__global__ __launch_bounds__(kBlock) void spsi2_kernel(KArgs<Tf> a, PsiUnits<Tf> pu, SimArgs<Tf> sa) {
+  if (a.ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[kWaves][2 * NX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = a.psi_order[a.N - 1 - blockIdx.x];  // the bases pass 1 read last come first
+  const int64_t tb = a.tile_off[j];
+  const int p = int(a.tile_off[j + 1] - tb), rs = a.rs, nu = a.nu, T = a.T;
+  const int D = p * rs, ld = (D + 3) & ~3, nxT = NX * T, nuT = nu * (T - 1);
+  const int mu = p * nuT, mul = (mu + 3) & ~3, ns = p * NX, k = a.kdim[j];
+  const int64_t base = tb * a.ts;
+  using V = typename VecT<Tf>::type;
+  constexpr int VN = VecT<Tf>::N;
+  Tf *y = reinterpret_cast<Tf *>(smem_raw);  // [NX][ld] the new Psi columns on supp(j)
+  Tf *tl = y + NX * ld;                       // [NX][k]
+  Tf *x0b = tl + NX * k;                      // [NX][ns] trajectory state, two buffers
+  Tf *x1b = x0b + NX * ns;
+  const Tf *tj = pu.t + pu.t_off[j];
+  for (int e = tid; e < NX * k; e += kBlock) tl[e] = tj[e];
+  for (int e = tid; e < NX * ns; e += kBlock) x0b[e] = Tf(0);
+  for (int e = tid; e < NX * ld; e += kBlock) y[e] = Tf(0);  // x_0 rows stay 0
+  __syncthreads();
+  // w = N_u t_j into the input rows of y
+  const Tf *__restrict__ Nu = sa.nbu + sa.nbu_off[j];
+  for (int q = tid; q < mul / VN; q += kBlock) {
+    V acc[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) acc[c] = V(0);
+#pragma unroll 4
+    for (int i = 0; i < k; ++i) {
+      const V nv = *reinterpret_cast<const V *>(Nu + int64_t(i) * mul + q * VN);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) acc[c] += nv * tl[c * k + i];
+    }
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+      const int u = q * VN + e;
+      if (u >= mu) break;
+      const int ti = u / nuT, w = u - ti * nuT;
+#pragma unroll
+      for (int c = 0; c < NX; ++c) y[c * ld + ti * rs + nxT + w] = acc[c][e];
+    }
+  }
+  __syncthreads();
+  const int32_t *rpp = sa.rp + sa.rp0[j];
+  const int32_t *col = sa.col + sa.e0[j];
+  const Tf *val = sa.val + sa.e0[j];
+  Tf *xprev = x0b, *xcur = x1b;
+  for (int t = 1; t < T; ++t) {
+    for (int e = tid; e < ns * NX; e += kBlock) {
+      const int c = e / ns, r = e - c * ns;
+      const int ti = r / NX, st = r - ti * NX;
+      Tf acc = Tf(0);
+      for (int q = rpp[r]; q < rpp[r + 1]; ++q) acc += val[q] * xprev[c * ns + col[q]];
+      const Tf *bb = sa.bblk + int64_t(sa.tile_sub[tb + ti]) * NX * nu;
+      for (int kk = 0; kk < nu; ++kk) acc += bb[st * nu + kk] * y[c * ld + ti * rs + nxT + (t - 1) * nu + kk];
+      xcur[c * ns + r] = acc;
+      y[c * ld + ti * rs + t * NX + st] = acc;
+    }
+    __syncthreads();
+    Tf *tmp = xprev;
+    xprev = xcur;
+    xcur = tmp;
+  }
+  // Psi = y + o_c, Lambda, residual partial sums (as the dense pass 2, all rows of j)
+  const Tf *__restrict__ Oj = a.off + a.off_ptr[j];
+  double rp[NX], rd[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) rp[c] = rd[c] = 0.0;
+  for (int e = tid; e < D * NX; e += kBlock) {
+    const int r = e / NX, c = e - r * NX;
+    const Tf psn = y[c * ld + r] + Oj[c * ld + r];
+    const int64_t idx = base + e;
+    const Tf ph = a.phi[idx], la = a.lam[idx], pso = a.psi[idx];
+    a.lam[idx] = (la + ph) - psn;
+    a.psi[idx] = psn;
+    const double dp = double(ph - psn), dd = double(psn - pso);
+#pragma unroll
+    for (int cc = 0; cc < NX; ++cc)
+      if (cc == c) {
+        rp[cc] += dp * dp;
+        rd[cc] += dd * dd;
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < NX; ++c) {
+    rp[c] = wave_sum(rp[c]);
+    rd[c] = wave_sum(rd[c]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      red[wave][c] = rp[c];
+      red[wave][NX + c] = rd[c];
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * NX) {
+    double sm = 0.0;
+    for (int w = 0; w < kWaves; ++w) sm += red[w][tid];
+    pu.part[int64_t(j) * pu.max_units * 2 * NX + tid] = sm;
+  }
+}
+
+// Input rows of every null basis, gathered into the structured Psi-comp's layout.
+template <typename Tf>
+__global__ __launch_bounds__(kBlock) void gather_nu_kernel(KArgs<Tf> a, SimArgs<Tf> sa) {
+  const int j = blockIdx.x;
+  const int p = int(a.tile_off[j + 1] - a.tile_off[j]), rs = a.rs;
+  const int D = p * rs, ld = (D + 3) & ~3, nxT = a.nx * a.T, nuT = a.nu * (a.T - 1);
+  const int mu = p * nuT, mul = (mu + 3) & ~3, k = a.kdim[j];
+  const Tf *Nj = a.nb + a.nb_off[j];
+  Tf *Nu = const_cast<Tf *>(sa.nbu) + sa.nbu_off[j];
+  for (int64_t e = threadIdx.x; e < int64_t(k) * mul; e += kBlock) {
+    const int i = int(e / mul), u = int(e - int64_t(i) * mul);
+    Tf vv = Tf(0);
+    if (u < mu) {
+      const int ti = u / nuT, w = u - ti * nuT;
+      vv = Nj[int64_t(i) * ld + ti * rs + nxT + w];
+    }
+    Nu[e] = vv;
+  }
+}
+
 constexpr int kConvBlock = 1024;
 
 template <typename Tf, int NX>
@@ -1203,16 +1439,115 @@ class EngineT final : public Engine {
         }
         break;
       case 1:
-        hipLaunchKernelGGL((psi_pass1_kernel<Tf, NX>), dim3(n1_), dim3(kBlock), lds_p1_, stream_, args_, pu_);
+        if (structured_) {
+          hipLaunchKernelGGL((sadj_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_s1_, stream_, args_, sa_);
+          ENG_CHECK(hipGetLastError());
+          hipLaunchKernelGGL((spass1_kernel<Tf, NX>), dim3(n1_), dim3(kBlock), lds_s1b_, stream_, args_, spu_, sa_);
+        } else
+          hipLaunchKernelGGL((psi_pass1_kernel<Tf, NX>), dim3(n1_), dim3(kBlock), lds_p1_, stream_, args_, pu_);
         break;
       case 2:
-        hipLaunchKernelGGL((psi_pass2_kernel<Tf, NX>), dim3(n2_), dim3(kBlock), lds_p2_, stream_, args_, pu_);
+        if (structured_)
+          hipLaunchKernelGGL((spsi2_kernel<Tf, NX>), dim3(hs_->N), dim3(kBlock), lds_s2_, stream_, args_, spu_, sa_);
+        else
+          hipLaunchKernelGGL((psi_pass2_kernel<Tf, NX>), dim3(n2_), dim3(kBlock), lds_p2_, stream_, args_, pu_);
         break;
       default:
-        hipLaunchKernelGGL((conv_kernel<Tf, NX>), dim3(1), dim3(kConvBlock), 0, stream_, args_, pu_);
+        hipLaunchKernelGGL((conv_kernel<Tf, NX>), dim3(1), dim3(kConvBlock), 0, stream_, args_, structured_ ? spu_ : pu_);
         break;
     }
     ENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  void set_structured(bool on) override { structured_ = on && struct_ready_; }
+
+  int enable_structured(std::string &err) override {
+    if (struct_ready_) {
+      structured_ = true;
+      return DLMPC_OK;
+    }
+    const HostSetup &hs = *hs_;
+    const int N = hs.N, nx = hs.nx, nu = hs.nu, T = hs.T;
+    const int nuT = nu * (T - 1);
+    std::vector<int64_t> nbu_off(N + 1, 0), rp0(N), e0(N), goff(N + 1, 0);
+    std::vector<int32_t> rp, rpt, col, colt;
+    std::vector<Tf> val, valt;
+    size_t lds1 = 0, lds1b = 0, lds2 = 0;
+    for (int j = 0; j < N; ++j) {
+      const std::vector<int32_t> &P = hs.patch[j];
+      const int p = int(P.size()), ns = p * nx, mu = p * nuT, mul = (mu + 3) & ~3;
+      const int ld = padded_ld(p * hs.rs);
+      nbu_off[j + 1] = nbu_off[j] + int64_t(mul) * hs.kdim[j];
+      goff[j + 1] = goff[j] + int64_t(nx) * mul;
+      lds1 = std::max(lds1, size_t(nx) * (ld + 2 * ns) * sizeof(Tf));
+      lds1b = std::max(lds1b, size_t(nx) * mul * sizeof(Tf));
+      lds2 = std::max(lds2, size_t(nx) * (ld + hs.kdim[j] + 2 * ns) * sizeof(Tf));
+      // A_PP: rows and columns are the patch states (member position * nx + state)
+      std::vector<std::vector<std::pair<int32_t, double>>> rows(ns), cols(ns);
+      for (int ti = 0; ti < p; ++ti) {
+        const int m = P[ti];
+        for (int64_t q = hs.a_rowptr[m]; q < hs.a_rowptr[m + 1]; ++q) {
+          const auto it = std::lower_bound(P.begin(), P.end(), hs.a_colidx[q]);
+          if (it == P.end() || *it != hs.a_colidx[q]) continue;  // outside the patch: state is 0
+          const int tn = int(it - P.begin());
+          for (int st = 0; st < nx; ++st)
+            for (int s2 = 0; s2 < nx; ++s2) {
+              const double v = hs.a_blocks[size_t(q) * nx * nx + st * nx + s2];
+              if (v == 0.0) continue;
+              rows[ti * nx + st].push_back({tn * nx + s2, v});
+              cols[tn * nx + s2].push_back({ti * nx + st, v});
+            }
+        }
+      }
+      rp0[j] = int64_t(rp.size());
+      e0[j] = int64_t(col.size());
+      int32_t c0 = 0, c1 = 0;
+      rp.push_back(0);
+      rpt.push_back(0);
+      for (int r = 0; r < ns; ++r) {
+        for (const auto &e : rows[r]) {
+          col.push_back(e.first);
+          val.push_back(static_cast<Tf>(e.second));
+        }
+        for (const auto &e : cols[r]) {
+          colt.push_back(e.first);
+          valt.push_back(static_cast<Tf>(e.second));
+        }
+        c0 += int32_t(rows[r].size());
+        c1 += int32_t(cols[r].size());
+        rp.push_back(c0);
+        rpt.push_back(c1);
+      }
+    }
+    if (lds1 > kMaxLds || lds2 > kMaxLds) {
+      err = "patch too large for the on-chip staging of the structured Psi-comp";
+      return DLMPC_EINVAL;
+    }
+    std::vector<Tf> bb(hs.b_blocks.begin(), hs.b_blocks.end());
+    SimArgs<Tf> x{};
+    int rc;
+    Tf *nbu = nullptr;
+    if ((rc = upload(nbu_off, &x.nbu_off, err)) || (rc = alloc(&nbu, size_t(nbu_off[N]), err)) ||
+        (rc = upload(rp0, &x.rp0, err)) || (rc = upload(rp, &x.rp, err)) || (rc = upload(rpt, &x.rpt, err)) ||
+        (rc = upload(e0, &x.e0, err)) || (rc = upload(col, &x.col, err)) || (rc = upload(colt, &x.colt, err)) ||
+        (rc = upload(val, &x.val, err)) || (rc = upload(valt, &x.valt, err)) || (rc = upload(bb, &x.bblk, err)) ||
+        (rc = upload(hs.tile_rsub, &x.tile_sub, err)) || (rc = upload(goff, &x.goff, err)) ||
+        (rc = alloc(&x.g, size_t(goff[N]), err)))
+      return rc;
+    x.nbu = nbu;
+    hipLaunchKernelGGL(gather_nu_kernel<Tf>, dim3(N), dim3(kBlock), 0, stream_, args_, x);
+    ENG_CHECK(hipGetLastError());
+    ENG_CHECK(hipStreamSynchronize(stream_));
+    spu_ = pu_;
+    spu_.max_units = 1;
+    if ((rc = alloc(&spu_.part, size_t(N) * 2 * NX, err))) return rc;
+    ENG_CHECK(hipMemset(spu_.part, 0, sizeof(double) * size_t(N) * 2 * NX));
+    sa_ = x;
+    lds_s1_ = lds1;
+    lds_s1b_ = lds1b;
+    lds_s2_ = lds2;
+    struct_ready_ = structured_ = true;
     return DLMPC_OK;
   }
 
@@ -1449,6 +1784,12 @@ class EngineT final : public Engine {
   size_t t_len_ = 0;  // entries of the Psi pass-1 products t_j
   KArgs<Tf> args_{};
   CoupleArgs<Tf> cp_{};  // K = 0: no couplings
+  // structured Psi-comp (enable_structured): its arguments, one residual slot per column
+  // subsystem, and the on-chip staging of its two kernels
+  bool structured_ = false, struct_ready_ = false;
+  SimArgs<Tf> sa_{};
+  PsiUnits<Tf> spu_{};
+  size_t lds_s1_ = 0, lds_s1b_ = 0, lds_s2_ = 0;
   const int64_t *map_ = nullptr;
   const double *w64_ = nullptr;
   CertArgs cert_{};

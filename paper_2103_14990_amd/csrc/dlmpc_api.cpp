@@ -62,6 +62,9 @@ struct dlmpc_problem {
   int32_t *d_flag = nullptr, *h_flag = nullptr;
   double warm_eps = 1e-4;  // eps of warm-started batched and streamed runs
   double rho = 5.0;        // penalty of the solves (options.rho until dlmpc_set_rho)
+  bool struct_ok = false;  // the structured Psi-comp is a candidate of the setup timing
+  bool psi_structured = false;
+  double tune_structured_us = 0.0;
   // neighbour-coupled constraints of the single-instance solves (library row indices)
   std::vector<int64_t> cp_a, cp_b;
   std::vector<double> cp_lo, cp_hi;
@@ -179,6 +182,19 @@ int setup_device(dlmpc_problem *p) {
   std::string err;
   int rc = p->eng->init(hs, p->opt.rho, p->stream, err);
   if (rc) return fail(rc, err);
+  {
+    // structured Psi-comp: forced by its flag, or a candidate of the setup timing when no
+    // schedule is given (a patch too large for its staging leaves only the dense one)
+    const uint32_t f = p->opt.flags;
+    const uint32_t fixed = DLMPC_FLAG_SCHED_GRAPH | DLMPC_FLAG_SCHED_PERSISTENT | DLMPC_FLAG_SCHED_STEPWISE |
+                           DLMPC_FLAG_SCHED_HOST_EXCHANGE | DLMPC_FLAG_SCHED_NAIVE | DLMPC_FLAG_NO_TUNE;
+    if (f & DLMPC_FLAG_STRUCTURED_PSI) {
+      if ((rc = p->eng->enable_structured(err))) return fail(rc, err);
+    } else if (!(f & fixed)) {
+      p->struct_ok = p->eng->enable_structured(err) == DLMPC_OK;
+      p->eng->set_structured(false);
+    }
+  }
   API_HIP(hipMalloc(&p->d_x0, sizeof(double) * size_t(hs.N) * hs.nx));
   API_HIP(hipMalloc(&p->d_u0, sizeof(double) * size_t(hs.N) * hs.nu));
   API_HIP(hipMalloc(&p->d_phi, sizeof(double) * size_t(std::max<int64_t>(hs.nnz, 1))));
@@ -445,6 +461,7 @@ int time_schedule(dlmpc_problem *p, int sched, int n, double *us_per_iter) {
 int choose_schedule(dlmpc_problem *p) {
   const uint32_t f = p->opt.flags;
   const bool can_persist = p->eng->persistent_grid() > 0;
+  p->psi_structured = (f & DLMPC_FLAG_STRUCTURED_PSI) != 0;
   // the per-iteration schedules of the exchange ablation (no tuning)
   const int per_iter = (f & DLMPC_FLAG_SCHED_STEPWISE) ? 3
                        : (f & DLMPC_FLAG_SCHED_HOST_EXCHANGE) ? 4
@@ -459,6 +476,11 @@ int choose_schedule(dlmpc_problem *p) {
     p->sched = 0;
     return DLMPC_OK;
   }
+  if (f & DLMPC_FLAG_STRUCTURED_PSI) {  // the persistent kernel runs the dense Psi-comp only
+    if (f & DLMPC_FLAG_SCHED_PERSISTENT) return fail(DLMPC_EINVAL, "the structured Psi-comp runs on the graph schedule");
+    p->sched = 0;
+    return DLMPC_OK;
+  }
   if (f & DLMPC_FLAG_SCHED_PERSISTENT) {
     if (!can_persist) return fail(DLMPC_EDEVICE, "persistent schedule unavailable on this device");
     p->sched = 1;
@@ -470,10 +492,18 @@ int choose_schedule(dlmpc_problem *p) {
   }
   const std::string sig = tune_signature(p);
   int ntw = 0, capx = 0, sched = 0;
-  if (!(f & DLMPC_FLAG_NO_TUNE) && tune_cache_read(sig, &ntw, &capx, &sched) && (sched == 0 || can_persist)) {
-    p->sched = sched;
+  // candidates: 0 graph schedule with the dense Psi-comp, 1 persistent, 2 graph schedule with the
+  // structured Psi-comp (cached as such; p->sched is 0 for it)
+  auto apply = [&](int s) -> int {
+    p->sched = s == 1 ? 1 : 0;
+    p->psi_structured = s == 2;
+    p->eng->set_structured(s == 2);
+    return capture_single(p);
+  };
+  if (tune_cache_read(sig, &ntw, &capx, &sched) && (sched == 0 || (sched == 1 && can_persist) ||
+                                                    (sched == 2 && p->struct_ok))) {
     p->tune_cached = 1;
-    return DLMPC_OK;
+    return apply(sched);
   }
   const int n = 32;
   int rc = time_schedule(p, 0, n, &p->tune_graph_us);
@@ -482,14 +512,24 @@ int choose_schedule(dlmpc_problem *p) {
     rc = time_schedule(p, 1, n, &p->tune_persistent_us);
     if (rc) return rc;
   }
-  p->sched = (can_persist && p->tune_persistent_us < p->tune_graph_us) ? 1 : 0;
-  if (!(f & DLMPC_FLAG_NO_TUNE)) {
-    int nu = 0;
-    ntw = 1;
-    capx = 8;
-    if (p->beng) p->beng->variant(&ntw, &capx, &nu);
-    tune_cache_write(sig, ntw, capx, p->sched);
+  if (p->struct_ok) {
+    if ((rc = apply(2))) return rc;
+    rc = time_schedule(p, 0, n, &p->tune_structured_us);
+    if (rc) return rc;
   }
+  int best = 0;
+  double best_us = p->tune_graph_us;
+  if (can_persist && p->tune_persistent_us < best_us) {
+    best = 1;
+    best_us = p->tune_persistent_us;
+  }
+  if (p->struct_ok && p->tune_structured_us < best_us) best = 2;
+  if ((rc = apply(best))) return rc;
+  int nu = 0;
+  ntw = 1;
+  capx = 8;
+  if (p->beng) p->beng->variant(&ntw, &capx, &nu);
+  tune_cache_write(sig, ntw, capx, best);
   return DLMPC_OK;
 }
 
@@ -740,6 +780,8 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   for (int v = 0; v < 2; ++v) info->tune_phi_us[v] = p->tune_phi_us[v];
   for (int c = 0; c < 5; ++c) info->tune_psi_us[c] = p->tune_psi_us[c];
   info->tune_cached = p->tune_cached;
+  info->psi_structured = p->psi_structured ? 1 : 0;
+  info->tune_structured_us = p->tune_structured_us;
   return DLMPC_OK;
 }
 

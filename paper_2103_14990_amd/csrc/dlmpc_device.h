@@ -84,6 +84,26 @@ struct KArgs {
   Tf *cp_a, *cp_s0;
 };
 
+// Structured Psi-comp (single-instance engine). A null-space trajectory of column subsystem j is
+// fixed by its input rows: x_0 = 0 and x_t = A_PP x_{t-1} + B_P u_{t-1} inside the patch, so
+// N_j = S_j N_u with N_u the input rows of N_j and S_j the patch simulation. N_j' v = N_u' (v_u +
+// S_x' v_x) by an adjoint recursion, N_j t = [simulate(N_u t); N_u t]: the products read N_u
+// (p nu (T-1) rows) instead of N_j (p (nx T + nu (T-1)) rows).
+template <typename Tf>
+struct SimArgs {
+  const int64_t *nbu_off;  // [N+1] N_u of j at nbu + nbu_off[j], column-major, leading dim round4(mu_j)
+  const Tf *nbu;
+  const int64_t *rp0;      // [N] first row pointer of j's patch dynamics (p nx + 1 entries each)
+  const int32_t *rp, *rpt; // row pointers of A_PP and of its transpose (local to j's entries)
+  const int64_t *e0;       // [N] first entry of j's A_PP (and of its transpose)
+  const int32_t *col, *colt;  // patch-state columns (local: member position * nx + state)
+  const Tf *val, *valt;
+  const Tf *bblk;          // [N][nx][nu] input blocks
+  const int32_t *tile_sub; // [n_tiles] row subsystem of each tile
+  const int64_t *goff;     // [N] the adjoint result g of j at g + goff[j], [nx][round4(mu_j)]
+  Tf *g;
+};
+
 // Nested ADMM of the coupled Phi-step (single-instance engine): K coupled rows (library row
 // index and subsystem), E pairs lo_e <= y[ka_e] - y[kb_e] <= hi_e, the pairs of every coupled
 // row (CSR, entries 2 e + side), the pair copies and scaled duals, and the inner y.
@@ -121,6 +141,10 @@ class Engine {
   virtual size_t exchange_bytes() const = 0;
   // Phi x0 of the latest Phi-comp (library row order), on the host. Synchronises.
   virtual int copy_y(std::vector<double> &out, std::string &err) = 0;
+  // Structured Psi-comp (SimArgs) for the following iterations; graphs must be captured after.
+  virtual int enable_structured(std::string &err) = 0;
+  // Switches between the structured (after enable_structured) and the dense Psi-comp.
+  virtual void set_structured(bool on) = 0;
   // Neighbour-coupled constraints on the rows of Phi x0 (library row indices o = m * rs + l):
   // lo_e <= y[row_a_e] - y[row_b_e] <= hi_e, solved inside Phi-comp by a nested ADMM (penalty
   // sigma, at most inner_max iterations, stop at inner_eps); n = 0 removes them.

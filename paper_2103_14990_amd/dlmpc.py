@@ -29,6 +29,7 @@ FLAG_NO_TUNE = 0x20
 FLAG_SCHED_STEPWISE = 0x40
 FLAG_SCHED_HOST_EXCHANGE = 0x80
 FLAG_SCHED_NAIVE = 0x100
+FLAG_STRUCTURED_PSI = 0x200
 CL_SHIFT = 1
 CL_SCALE_RHO = 2
 FACTORS = {"device": 0, "host": FLAG_HOST_FACTOR}
@@ -108,7 +109,8 @@ class Info(C.Structure):
                 ("tune_persistent_us", C.c_double), ("sum_k", C.c_int64),
                 ("factor_device", C.c_int32), ("factor_fallbacks", C.c_int32),
                 ("batch_phi_ntw", C.c_int32), ("batch_psi_capx", C.c_int32), ("batch_psi_units", C.c_int32),
-                ("tune_cached", C.c_int32), ("tune_phi_us", C.c_double * 2), ("tune_psi_us", C.c_double * 5)]
+                ("tune_cached", C.c_int32), ("tune_phi_us", C.c_double * 2), ("tune_psi_us", C.c_double * 5),
+                ("psi_structured", C.c_int32), ("pad_info", C.c_int32), ("tune_structured_us", C.c_double)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -236,7 +238,8 @@ class Problem:
                  device: int = 0, stream: int | None = None, check_every: int = 0,
                  host_only: bool = False, schedule: str = "auto", max_batch: int = 0,
                  warm_cg_iters: int = 0, factor: str = "device", factor_chol_tol: float = 0.0,
-                 warm_eps_scale: float = 0.0, check: bool = True, tune: bool = True, flags: int = 0):
+                 warm_eps_scale: float = 0.0, check: bool = True, tune: bool = True, flags: int = 0,
+                 structured_psi: bool = False):
         self._lib = load()
         self._h = C.c_void_p()
         keep = dict(rowptr=np.ascontiguousarray(a_rowptr, dtype=np.int64),
@@ -251,7 +254,8 @@ class Problem:
         opts = Options(rho, eps, max_iter, check_every, PRECISIONS[precision], device,
                        C.c_void_p(stream) if stream else None,
                        (FLAG_HOST_ONLY if host_only else 0) | SCHEDULES[schedule] | FACTORS[factor]
-                       | (0 if check else FLAG_NO_CHECK) | (0 if tune else FLAG_NO_TUNE) | flags, max_batch,
+                       | (0 if check else FLAG_NO_CHECK) | (0 if tune else FLAG_NO_TUNE) | flags
+                       | (FLAG_STRUCTURED_PSI if structured_psi else 0), max_batch,
                        warm_cg_iters, factor_chol_tol, warm_eps_scale)
         st = self._lib.dlmpc_setup(C.byref(sysd), d, T, C.byref(cost), C.byref(opts), C.byref(self._h))
         if st != OK:
