@@ -235,11 +235,14 @@ typedef struct {
    * over several Psi-comp work units (the waves serving one patch): a block whose basis cost
    * exceeds batch_psi_capx times the mean is split. */
   int32_t batch_phi_ntw;    /* 1 or 2 (0 without a batched engine) */
-  int32_t batch_psi_capx;   /* 2, 4, 8, 16 or 1048576 (no split) */
+  int32_t batch_psi_capx;   /* 2, 4, 8, 16 or 1048576 (no split); 0: the structured Psi-comp (input
+                               rows of the null bases and the patch's adjoint recursion per
+                               instance, one unit per column subsystem; split operands only) */
   int32_t batch_psi_units;  /* Psi-comp work units (blocks per launch) */
   int32_t tune_cached;      /* 1 if the choices came from the cache */
   double tune_phi_us[2];    /* per-launch us of the Phi-comp variants 1, 2 (0 if not timed) */
-  double tune_psi_us[5];    /* per-launch us of the Psi-comp splits 2, 4, 8, 16, none */
+  double tune_psi_us[6];    /* per-launch us of the Psi-comp splits 2, 4, 8, 16, none, and of the
+                               structured Psi-comp (batch_psi_capx = 0; 0 us when not available) */
   /* Single-instance Psi-comp: 1 if the structured one (DLMPC_FLAG_STRUCTURED_PSI) runs, chosen
    * by the flag, or by timing at setup when no schedule flag is given (tune_structured_us: its
    * per-iteration time on the graph schedule, 0 if not timed). */

@@ -46,6 +46,8 @@ constexpr int kKC = 64;           // support rows staged per chunk in bpsi_kerne
 constexpr int kRPT = kKC / 8;     // staged rows per thread (8 row groups of 64 threads)
 constexpr int kPhiThreads = 512;  // bphi_kernel: 4 instance tiles x 2 halves of the tile list
 constexpr int kMaxPatch = 64;     // subsystems per d-hop patch (batched engine)
+constexpr int kSNs = 88;          // structured Psi-comp: patch states (p nx) at most
+constexpr int kSPnu = 64;         // structured Psi-comp: patch inputs per time step (p nu) at most
 
 __device__ __forceinline__ unsigned long long ord_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(v));
@@ -370,12 +372,19 @@ __global__ __launch_bounds__(kPhiThreads) void bphi_kernel(BArgs a) {
 // Two 8-wave blocks per CU (four waves per SIMD, 128 registers per lane, a few of them spilled)
 // while a wave has at most 3 tiles, one block otherwise. SPLIT: basis fragments as bf16 hi + lo
 // (three products per tile); otherwise hi only (two).
-template <int NX, int MTW, bool SPLIT>
-__global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW <= 3 ? 4 : 2))) void bpsi_kernel(BArgs a) {
+// STRUCT: the structured Psi-comp (one unit per column subsystem): eta_j = N_u' g with
+// g = alpha_u + S_x' alpha_x from the adjoint recursion mu_t = alpha_{x,t} + A_PP' mu_{t+1},
+// g_{t-1} = alpha_{u,t-1} + B_P' mu_t run per instance; the rows of g go through the staging
+// buffer as they are produced and every full kKC-row chunk feeds the products.
+// (two blocks per CU need MTW <= 3; the structured variant's staging also needs NX <= 2)
+template <int NX, int MTW, bool SPLIT, bool STRUCT = false>
+__global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu((MTW <= 3 && (!STRUCT || NX <= 2)) ? 4 : 2))) void bpsi_kernel(BArgs a) {
   constexpr int kFB = frag_block<SPLIT>();
+  constexpr int kSH = STRUCT ? kKC + kSPnu + 8 : kKC + 8;
   if (a.ctl->stop) return;
-  __shared__ __align__(16) __bf16 sh_hi[kBMax][kKC + 8];
-  __shared__ __align__(16) __bf16 sh_lo[kBMax][kKC + 8];
+  __shared__ __align__(16) __bf16 sh_hi[kBMax][kSH];
+  __shared__ __align__(16) __bf16 sh_lo[kBMax][kSH];
+  __shared__ float smu[STRUCT ? kBMax : 1][STRUCT ? kSNs + 1 : 1];
   __shared__ int s_rsub[kMaxPatch];
   __shared__ double red_e[kPsiWaves][kBMax], red_d[kPsiWaves][kBMax];
   __shared__ double red_od[kBMax][8][NX];
@@ -448,6 +457,109 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
       v[e] = ok ? x : 0.f;
     }
   };
+  if constexpr (STRUCT) {
+    const int p = D / rs, ns = p * NX, nu = a.nu, T = a.T, pnu = p * nu, nxT = NX * a.T;
+    const int nku = ((T - 1) * pnu + kKC - 1) / kKC * kKC / 32;  // K-steps of N_u (whole chunks)
+    const int32_t *rpt = a.srpt + a.srp0[j];
+    const int32_t *colt = a.scolt + a.se0[j];
+    const float *valt = a.svalt + a.se0[j];
+    // value of instance sb's row `row` of the staged vectors (library row index)
+    auto src_at = [&](int64_t row) -> float {
+      if (!sact) return 0.f;
+      return jstage ? jsrc[int64_t(sb) * a.N * rs + row] : stage_src[int64_t(sb) * a.src_bs + row * a.src_rs];
+    };
+    for (int s0 = sub; s0 < kSNs + 1; s0 += 8) smu[sb][s0] = 0.f;  // mu_T = 0
+    int fill = 0, chunk = 0;
+    auto products = [&](int nrows) {  // chunk `chunk` of the K rows: sh rows [0, nrows)
+      for (int ks = 0; ks < nrows / 32; ++ks) {
+        bf16x8 ah[MTW], al[MTW];
+#pragma unroll
+        for (int t = 0; t < MTW; ++t) {
+          const int mt = min(wave + kPsiWaves * t, nmt - 1);
+          const int64_t ai = a.ntu_off[j] + (int64_t(mt) * nku + 2 * chunk + ks) * kFB + lane * 8;
+          ah[t] = load8(a.ntu + ai);
+          if constexpr (SPLIT) al[t] = load8(a.ntu + ai + 512);
+        }
+        const int kr = ks * 32 + 8 * (lane >> 4);
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+          if (nt * 16 >= B) break;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sh_hi[nt * 16 + (lane & 15)][kr]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sh_lo[nt * 16 + (lane & 15)][kr]);
+#pragma unroll
+          for (int t = 0; t < MTW; ++t) {
+            if (wave + kPsiWaves * t >= nmt) break;
+            acc[t][nt] = SPLIT ? mfma3(ah[t], al[t], bh, bl, acc[t][nt]) : mfma2(ah[t], bh, bl, acc[t][nt]);
+          }
+        }
+      }
+    };
+    __syncthreads();
+    for (int q = 0; q < T - 1; ++q) {
+      const int t = T - 1 - q;
+      // mu_t for this thread's states sub, sub + 8, ... (instance sb)
+      float mreg[(kSNs + 7) / 8];
+#pragma unroll
+      for (int i = 0; i < (kSNs + 7) / 8; ++i) {
+        const int st = sub + 8 * i;
+        float v = 0.f;
+        if (st < ns) {
+          const int ti = st / NX, sx = st - ti * NX;
+          v = src_at(int64_t(s_rsub[ti]) * rs + t * NX + sx);
+          for (int e = rpt[st]; e < rpt[st + 1]; ++e) v += valt[e] * smu[sb][colt[e]];
+        }
+        mreg[i] = v;
+      }
+      __syncthreads();  // every read of mu_{t+1} is done
+#pragma unroll
+      for (int i = 0; i < (kSNs + 7) / 8; ++i)
+        if (sub + 8 * i < ns) smu[sb][sub + 8 * i] = mreg[i];
+      __syncthreads();
+      // g_{t-1}: rows fill + w, w = member * nu + input
+      for (int w = sub; w < pnu; w += 8) {
+        const int ti = w / nu, kk = w - ti * nu;
+        const int m = s_rsub[ti];
+        float gv = src_at(int64_t(m) * rs + nxT + (t - 1) * nu + kk);
+        const float *bb = a.b_blk + int64_t(m) * NX * nu;
+#pragma unroll
+        for (int sx = 0; sx < NX; ++sx) gv += bb[sx * nu + kk] * smu[sb][ti * NX + sx];
+        const __bf16 gh = static_cast<__bf16>(gv);
+        sh_hi[sb][fill + w] = gh;
+        sh_lo[sb][fill + w] = static_cast<__bf16>(gv - static_cast<float>(gh));
+      }
+      fill += pnu;
+      const bool last = q == T - 2;
+      if (last) {  // zero rows up to the next multiple of 32 (the basis rows there are zero too)
+        const int pad = (fill + 31) & ~31;
+        for (int w = fill + sub; w < pad; w += 8) {
+          sh_hi[sb][w] = static_cast<__bf16>(0.f);
+          sh_lo[sb][w] = static_cast<__bf16>(0.f);
+        }
+      }
+      __syncthreads();
+      while (fill >= kKC || (last && fill > 0)) {
+        products(fill >= kKC ? kKC : ((fill + 31) & ~31));
+        __syncthreads();  // the products read the staged rows
+        if (fill > kKC) {
+          for (int w = sub; w < fill - kKC; w += 8) {
+            sh_hi[sb][w] = sh_hi[sb][kKC + w];
+            sh_lo[sb][w] = sh_lo[sb][kKC + w];
+          }
+          __syncthreads();
+        }
+        fill = fill > kKC ? fill - kKC : 0;
+        ++chunk;
+        if (last && fill > 0) {
+          const int pad = (fill + 31) & ~31;
+          for (int w = fill + sub; w < pad; w += 8) {
+            sh_hi[sb][w] = static_cast<__bf16>(0.f);
+            sh_lo[sb][w] = static_cast<__bf16>(0.f);
+          }
+          __syncthreads();
+        }
+      }
+    }
+  } else {
   float v[kRPT];
   fetch(r_begin, v);
   for (int r0 = r_begin; r0 < r_end; r0 += kKC) {
@@ -493,8 +605,10 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu(MTW
     }
     __syncthreads();
   }
+  }
   if (cold2) {  // offset terms of the second cold iteration: sum_rows alpha o_c over the unit
     for (int r0 = r_begin; r0 < r_end; r0 += kKC) {
+      float v[kRPT];
       fetch(r0, v);
 #pragma unroll
       for (int e = 0; e < kRPT; ++e) {
@@ -1196,6 +1310,32 @@ __global__ void bfrag_kernel(const double *__restrict__ nb, const int64_t *__res
   }
 }
 
+// Fragments of N_u' for the structured Psi-comp: M = basis i, K = input row ku in the order of
+// the adjoint recursion (step q = ku / (p nu) holds u_{T-2-q}, member-major within the step).
+__global__ void bfragu_kernel(const double *__restrict__ nb, const int64_t *__restrict__ nb_off,
+                              const int32_t *__restrict__ kdim, const int64_t *__restrict__ tile_off,
+                              const int64_t *__restrict__ ntu_off, int rs, int nx, int nu, int T,
+                              __bf16 *__restrict__ ntu) {
+  const int j = blockIdx.x;
+  const int p = int(tile_off[j + 1] - tile_off[j]);
+  const int D = p * rs, k = kdim[j], ld = (D + 3) & ~3, pnu = p * nu, mu = (T - 1) * pnu;
+  const int nku = (mu + kKC - 1) / kKC * kKC / 32;
+  const double *Nj = nb + nb_off[j];
+  for (int64_t e = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; e < int64_t(k) * mu;
+       e += int64_t(gridDim.y) * blockDim.x) {
+    const int i = int(e / mu), ku = int(e % mu);
+    const int q = ku / pnu, w = ku - q * pnu, ti = w / nu, kk = w - ti * nu;
+    const int r = ti * rs + nx * T + (T - 2 - q) * nu + kk;
+    const float x = float(Nj[int64_t(i) * ld + r]);
+    const __bf16 h = static_cast<__bf16>(x);
+    const int mt = i / 16, kt = ku / 32, kq = ku % 32;
+    const int l = (i % 16) + 16 * (kq / 8), el = kq % 8;
+    const int64_t at = ntu_off[j] + (int64_t(mt) * nku + kt) * 1024 + l * 8 + el;
+    ntu[at] = h;
+    ntu[at + 512] = static_cast<__bf16>(x - static_cast<float>(h));
+  }
+}
+
 // Psi-comp work units: column blocks whose basis is more than capx times the mean are split into
 // np row ranges of whole kKC-row chunks, so that a heavy patch is served by np blocks (more waves
 // per patch) whose partial sums the last one adds; units are dispatched heaviest first.
@@ -1402,6 +1542,69 @@ class BatchEngineT final : public BatchEngine {
       return rc;
     if ((rc = load_split(sp, kPsiCapDefault, err))) return rc;
     BENG_CHECK(hipMemset(a.pcnt, 0, sizeof(int32_t) * N));
+    // structured Psi-comp (split operands, bases on the device, patches within its staging):
+    // N_u fragments and the transposed patch dynamics
+    struct_ok_ = false;
+    {
+      int ns_max = 0, pnu_max = 0;
+      for (int j = 0; j < N; ++j) {
+        ns_max = std::max(ns_max, int(hs.patch[j].size()) * NX);
+        pnu_max = std::max(pnu_max, int(hs.patch[j].size()) * hs.nu);
+      }
+      if (split && hs.d_nb && ns_max <= kSNs && pnu_max <= kSPnu && hs.T >= 2) {
+        std::vector<int64_t> ntu_off(N + 1, 0), srp0(N), se0(N);
+        std::vector<int32_t> srpt, scolt;
+        std::vector<float> svalt;
+        for (int j = 0; j < N; ++j) {
+          const std::vector<int32_t> &P = hs.patch[j];
+          const int p = int(P.size()), mu = (hs.T - 1) * p * hs.nu, ns = p * NX;
+          const int64_t nku = (mu + kKC - 1) / kKC * kKC / 32, nmt = ((hs.kdim[j] + 15) & ~15) / 16;
+          ntu_off[j + 1] = ntu_off[j] + nmt * nku * 1024;
+          std::vector<std::vector<std::pair<int32_t, float>>> cols(ns);
+          for (int ti = 0; ti < p; ++ti) {
+            const int m = P[ti];
+            for (int64_t q = hs.a_rowptr[m]; q < hs.a_rowptr[m + 1]; ++q) {
+              const auto it = std::lower_bound(P.begin(), P.end(), hs.a_colidx[q]);
+              if (it == P.end() || *it != hs.a_colidx[q]) continue;
+              const int tn = int(it - P.begin());
+              for (int st = 0; st < NX; ++st)
+                for (int s2 = 0; s2 < NX; ++s2) {
+                  const double v = hs.a_blocks[size_t(q) * NX * NX + st * NX + s2];
+                  if (v != 0.0) cols[tn * NX + s2].push_back({ti * NX + st, float(v)});
+                }
+            }
+          }
+          srp0[j] = int64_t(srpt.size());
+          se0[j] = int64_t(scolt.size());
+          int32_t c = 0;
+          srpt.push_back(0);
+          for (int r = 0; r < ns; ++r) {
+            for (const auto &e : cols[r]) {
+              scolt.push_back(e.first);
+              svalt.push_back(e.second);
+            }
+            c += int32_t(cols[r].size());
+            srpt.push_back(c);
+          }
+        }
+        __bf16 *d_ntu = nullptr;
+        const int64_t *d_nboff = nullptr, *d_ntuoff = nullptr, *d_toff = nullptr;
+        const int32_t *d_k = nullptr;
+        if ((rc = al(&d_ntu, size_t(std::max<int64_t>(ntu_off[N], 1)), err)) || (rc = up(hs.nb_off, &d_nboff, err)) ||
+            (rc = up(ntu_off, &d_ntuoff, err)) || (rc = up(hs.tile_off, &d_toff, err)) || (rc = up(hs.kdim, &d_k, err)) ||
+            (rc = up(srp0, &a.srp0, err)) || (rc = up(se0, &a.se0, err)) || (rc = up(srpt, &a.srpt, err)) ||
+            (rc = up(scolt, &a.scolt, err)) || (rc = up(svalt, &a.svalt, err)))
+          return rc;
+        BENG_CHECK(hipMemset(d_ntu, 0, sizeof(__bf16) * std::max<int64_t>(ntu_off[N], 1)));
+        hipLaunchKernelGGL(bfragu_kernel, dim3(N, 16), dim3(256), 0, nullptr, hs.d_nb, d_nboff, d_k, d_toff, d_ntuoff,
+                           hs.rs, hs.nx, hs.nu, hs.T, d_ntu);
+        BENG_CHECK(hipGetLastError());
+        BENG_CHECK(hipDeviceSynchronize());
+        a.ntu = d_ntu;
+        a.ntu_off = d_ntuoff;
+        struct_ok_ = true;
+      }
+    }
     std::vector<float> offf(hs.off.begin(), hs.off.end()), wf(hs.w.begin(), hs.w.end()),
         lbf(hs.lb.begin(), hs.lb.end()), ubf(hs.ub.begin(), hs.ub.end());
     if ((rc = up(offf, &a.off, err)) || (rc = up(wf, &a.w, err)) || (rc = up(lbf, &a.lb, err)) ||
@@ -1656,14 +1859,19 @@ class BatchEngineT final : public BatchEngine {
       err = "Phi-comp instance tiles per wave must be 1 or 2";
       return DLMPC_EINVAL;
     }
-    bool known = false;
+    bool known = psi_capx == 0 && struct_ok_;  // 0: the structured Psi-comp
     for (int c : kPsiCaps) known = known || c == psi_capx;
     if (!known) {
-      err = "unknown Psi-comp split";
+      err = psi_capx == 0 ? "the structured Psi-comp is not available for this problem" : "unknown Psi-comp split";
       return DLMPC_EINVAL;
     }
     phi_ntw_ = phi_ntw;
-    if (psi_capx != psi_capx_) return load_split(psi_split(*hs_, psi_capx), psi_capx, err);
+    if (psi_capx != psi_capx_) {
+      // the structured variant runs one unit per column subsystem
+      const int rc = load_split(psi_split(*hs_, psi_capx == 0 ? (1 << 20) : psi_capx), psi_capx, err);
+      bstruct_ = psi_capx == 0;
+      return rc;
+    }
     return DLMPC_OK;
   }
   void variant(int *phi_ntw, int *psi_capx, int *n_units) const override {
@@ -1794,6 +2002,17 @@ class BatchEngineT final : public BatchEngine {
   }
   template <bool SPLIT>
   void launch_psi_t(const BArgs &x) {
+    if constexpr (SPLIT) {
+      if (bstruct_) {
+        switch (mtw_) {
+          case 1: hipLaunchKernelGGL((bpsi_kernel<NX, 1, true, true>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+          case 2: hipLaunchKernelGGL((bpsi_kernel<NX, 2, true, true>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+          case 3: hipLaunchKernelGGL((bpsi_kernel<NX, 3, true, true>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+          default: hipLaunchKernelGGL((bpsi_kernel<NX, 4, true, true>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
+        }
+        return;
+      }
+    }
     switch (mtw_) {
       case 1: hipLaunchKernelGGL((bpsi_kernel<NX, 1, SPLIT>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
       case 2: hipLaunchKernelGGL((bpsi_kernel<NX, 2, SPLIT>), dim3(n_units_), dim3(kPsiThreads), 0, stream_, x); break;
@@ -1805,6 +2024,7 @@ class BatchEngineT final : public BatchEngine {
   int phi_ntw_ = 1;  // instance tiles per Phi-comp wave (autotuned)
   int psi_capx_ = kPsiCapDefault;  // Psi-comp split (autotuned)
   bool split_ = true;  // basis operands as bf16 hi + lo
+  bool struct_ok_ = false, bstruct_ = false;  // structured Psi-comp available / running
   int B_ = 0;
   int64_t ny_ = 0;  // N * rs
   // streamed solves: slot lists on the device and their host staging

@@ -33,7 +33,7 @@ struct dlmpc_problem {
   double tune_graph_us = 0.0, tune_persistent_us = 0.0;
   // batched-engine autotuning: per-launch us of the Phi-comp variants (1, 2 instance tiles per
   // wave) and of the Psi-comp splits (kPsiCaps order); 1 if the choice came from the cache
-  double tune_phi_us[2] = {0, 0}, tune_psi_us[5] = {0, 0, 0, 0, 0};
+  double tune_phi_us[2] = {0, 0}, tune_psi_us[6] = {0, 0, 0, 0, 0, 0};
   int32_t tune_cached = 0;
   Ctl *h_ctl = nullptr;  // pinned, 2 slots
   void *h_xchg = nullptr;  // pinned staging of the host-exchange schedules
@@ -303,14 +303,16 @@ int tune_batch(dlmpc_problem *p) {
     }
     // a candidate replaces the default only when it is faster by more than timing noise (1 %)
     const int ntw = p->tune_phi_us[1] < 0.99 * p->tune_phi_us[0] ? 2 : 1;
-    static const int caps[5] = {2, 4, 8, 16, 1 << 20};
-    for (int c = 0; c < 5; ++c) {
-      if ((rc = p->beng->set_variant(ntw, caps[c], err))) return fail(rc, err);
+    // splits of heavy column blocks, and the structured Psi-comp (0) where the problem allows it
+    static const int caps[6] = {2, 4, 8, 16, 1 << 20, 0};
+    for (int c = 0; c < 6; ++c) {
+      p->tune_psi_us[c] = 0.0;
+      if (p->beng->set_variant(ntw, caps[c], err)) continue;  // not available
       if ((rc = time_k(1, &p->tune_psi_us[c]))) return rc;
     }
     int best_c = 2;  // the default split
-    for (int c = 0; c < 5; ++c)
-      if (p->tune_psi_us[c] < 0.99 * p->tune_psi_us[best_c]) best_c = c;
+    for (int c = 0; c < 6; ++c)
+      if (p->tune_psi_us[c] > 0.0 && p->tune_psi_us[c] < 0.99 * p->tune_psi_us[best_c]) best_c = c;
     if ((rc = p->beng->set_variant(ntw, caps[best_c], err))) return fail(rc, err);
     return DLMPC_OK;
   };
@@ -778,7 +780,7 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   info->batch_psi_units = 0;
   if (p->beng) p->beng->variant(&info->batch_phi_ntw, &info->batch_psi_capx, &info->batch_psi_units);
   for (int v = 0; v < 2; ++v) info->tune_phi_us[v] = p->tune_phi_us[v];
-  for (int c = 0; c < 5; ++c) info->tune_psi_us[c] = p->tune_psi_us[c];
+  for (int c = 0; c < 6; ++c) info->tune_psi_us[c] = p->tune_psi_us[c];
   info->tune_cached = p->tune_cached;
   info->psi_structured = p->psi_structured ? 1 : 0;
   info->tune_structured_us = p->tune_structured_us;

@@ -200,6 +200,14 @@ struct BArgs {
   const int64_t *ntf_off;   // [N+1] fragments of N_j' (Psi-comp left operand)
   const int64_t *nf_off;    // [n_tiles+1] fragments of the rows of tile (j, m) (Phi-comp)
   const __bf16 *ntf, *nf;
+  // Structured Psi-comp (left operand N_u' of the input rows only, K = input rows in the order
+  // the adjoint recursion produces them: step q = 0..T-2 gives u_{T-2-q} of every member) and
+  // the transposed patch dynamics A_PP' per column subsystem (CSR over the patch states).
+  const int64_t *ntu_off;   // [N+1]
+  const __bf16 *ntu;
+  const int64_t *srp0, *se0;
+  const int32_t *srpt, *scolt;
+  const float *svalt;
   const float *off;         // o_c, column-major per subsystem (leading dim ld4)
   const int64_t *off_ptr;
   const float *w, *lb, *ub; // [N*rs]

@@ -138,3 +138,32 @@ def test_setup_times_structured_against_dense(tmp_path, monkeypatch):
     x0 = wl.x0(1000)
     ra, rb = a.solve(x0), b.solve(x0)
     assert np.array_equal(ra.u0, rb.u0) and ra.stats["iters"] == rb.stats["iters"]
+
+
+@pytest.mark.parametrize("name", ["grid8", "paper_chain25_d2_T10"])
+def test_batched_structured_psi_matches_oracle(tmp_path, monkeypatch, name):
+    """The batched engine's structured Psi-comp (batch_psi_capx 0, forced through the tuning
+    cache): FP32-tier bar against the FP64 oracle, instance by instance."""
+    wl = W.workload(name)
+    pb = O.setup_from_network(wl.net, wl.d, wl.T, wl.cost)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("DLMPC_TUNE_CACHE", str(cache))
+    mk = lambda: dlmpc.Problem.from_network(wl.net, wl.d, wl.T, wl.cost, rho=RHO, eps=EPS, max_iter=MAXIT,
+                                            precision="fp32", max_batch=8)
+    probe = mk()
+    sig = cache.read_text().split("|")[0]
+    probe.close()
+    cache.write_text(f"{sig}|phi_ntw=1 psi_capx=0 sched=0\n")
+    pr = mk()
+    assert pr.info["batch_psi_capx"] == 0 and pr.info["tune_cached"] == 1
+    seeds = [1000 + i for i in range(8)]
+    x0 = np.stack([wl.x0(s) for s in seeds])
+    st, u0, stats = pr.solve_batch(x0)
+    for i, s in enumerate(seeds):
+        ref = O.solve(pb, x0[i], RHO, EPS, MAXIT)
+        print(f"  {name} seed {s}: iters {stats[i]['iters']} oracle {ref.iters} u0 rel {rel(u0[i], ref.u0):.2e}",
+              flush=True)
+        assert stats[i]["converged"] and ref.converged
+        assert rel(u0[i], ref.u0) < 1e-4
+        assert abs(stats[i]["objective"] - ref.J) <= 1e-5 * ref.J
+        assert abs(stats[i]["iters"] - ref.iters) <= 5

@@ -31,9 +31,10 @@ def test_tuner_picks_fastest_and_caches(tmp_path, monkeypatch):
     print(f"  timed: phi {ia['tune_phi_us']} psi {ia['tune_psi_us']} -> ntw {ia['batch_phi_ntw']} "
           f"capx {ia['batch_psi_capx']} units {ia['batch_psi_units']}; graph {ia['tune_graph_us']:.1f} us, "
           f"persistent {ia['tune_persistent_us']:.1f} us -> schedule {ia['schedule']}", flush=True)
+    # five splits and the structured Psi-comp (available here: split operands, small patches)
     assert ia["tune_cached"] == 0 and all(v > 0 for v in ia["tune_phi_us"]) and all(v > 0 for v in ia["tune_psi_us"])
     # the chosen variants are the fastest, up to the 1 % margin that keeps the defaults on ties
-    caps = [2, 4, 8, 16, 1 << 20]
+    caps = [2, 4, 8, 16, 1 << 20, 0]
     assert ia["tune_phi_us"][ia["batch_phi_ntw"] - 1] <= min(ia["tune_phi_us"]) / 0.99 + 1e-9
     assert ia["tune_psi_us"][caps.index(ia["batch_psi_capx"])] <= min(ia["tune_psi_us"]) / 0.99 + 1e-9
     line = cache.read_text().strip().splitlines()
@@ -48,7 +49,7 @@ def test_tuner_picks_fastest_and_caches(tmp_path, monkeypatch):
     b.close()
 
 
-@pytest.mark.parametrize("ntw,capx", [(1, 8), (2, 8), (1, 2), (2, 1 << 20)])
+@pytest.mark.parametrize("ntw,capx", [(1, 8), (2, 8), (1, 2), (2, 1 << 20), (1, 0), (2, 0)])
 def test_every_variant_computes_the_same_iteration(tmp_path, monkeypatch, ntw, capx):
     """Variants forced through the cache against the defaults (no tuning): same iteration counts
     (up to a stopping iterate near eps), u(0) within FP32-tier rounding."""
