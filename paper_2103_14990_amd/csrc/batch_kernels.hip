@@ -95,55 +95,87 @@ __device__ __forceinline__ T wsum(T v) {
 
 // ------------------------------------------------------------------ per-solve precompute
 
+// Instances per bprecompute_kernel block, and the parts one instance's row sweeps are split
+// into (bcg_init_kernel, boutput_kernel; their partial sums are added in part order by
+// bpart_sum_kernel).
+constexpr int kPreY = 16;
+constexpr int kParts = 8;
+constexpr int kCgParts = 16;  // row ranges of one instance's CG step
+
 template <int NX>
 __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double *x0, int B, int warm,
                                                           int max_iter, double eps, const int32_t *slots,
                                                           const int32_t *xsrc, int reset, int join, int cg_k,
                                                           const double *rscale) {
-  // instance blockIdx.y: slot slots[y] (or y), initial state row xsrc[y] (or y) of x0; reset:
-  // the solve starts here (global control block reset); otherwise the slot joins a running one;
-  // rscale[y] (or 1): factor of the instance's penalty
-  const int m = blockIdx.x, y = blockIdx.y, tid = threadIdx.x;
-  const int b = slots ? slots[y] : y;
+  // row subsystem blockIdx.x, instances y = kPreY blockIdx.y + yy (y < B): slot slots[y] (or
+  // y), initial state row xsrc[y] (or y) of x0; reset: the solve starts here (global control
+  // block reset); otherwise the slots join a running one; rscale[y] (or 1): factor of the
+  // instance's penalty. The patch columns of m and their x0 values are staged once per block.
+  __shared__ int64_t s_base[kMaxPatch];
+  __shared__ int s_ld[kMaxPatch], s_j[kMaxPatch], s_b[kPreY];
+  __shared__ double s_x[kPreY][kMaxPatch][NX];
+  const int m = blockIdx.x, tid = threadIdx.x;
+  const int y0 = kPreY * blockIdx.y, ny = min(kPreY, B - y0);
   const int rs = a.rs;
   const int64_t nxs = int64_t(a.N) * NX;
-  const double *xb = x0 + int64_t(xsrc ? xsrc[y] : y) * nxs;
-  if (tid < NX) a.x0[int64_t(b) * nxs + m * NX + tid] = static_cast<float>(xb[m * NX + tid]);
-  if (tid == 0) {
+  const int64_t q0 = a.rt_ptr[m];
+  const int np = int(a.rt_ptr[m + 1] - q0);
+  if (tid < np) {
+    const int j = a.rt_col[q0 + tid];
+    const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
+    s_j[tid] = j;
+    s_ld[tid] = (D + 3) & ~3;
+    s_base[tid] = a.off_ptr[j] + int64_t(a.rt_tile[q0 + tid] - a.tile_off[j]) * rs;
+  }
+  if (tid < ny) s_b[tid] = slots ? slots[y0 + tid] : y0 + tid;
+  __syncthreads();
+  for (int e = tid; e < ny * np * NX; e += 256) {
+    const int yy = e / (np * NX), r = e - yy * np * NX, q = r / NX, c = r - q * NX;
+    const int y = y0 + yy;
+    s_x[yy][q][c] = x0[int64_t(xsrc ? xsrc[y] : y) * nxs + s_j[q] * NX + c];
+  }
+  __syncthreads();
+  if (tid < ny) {
+    const int y = y0 + tid, b = s_b[tid];
+    const double *xb = x0 + int64_t(xsrc ? xsrc[y] : y) * nxs;
     double sm = 0.0, sn = 0.0;
 #pragma unroll
-    for (int c = 0; c < NX; ++c) sm += xb[m * NX + c] * xb[m * NX + c];
-    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
-      const int j = a.rt_col[q];
-#pragma unroll
-      for (int c = 0; c < NX; ++c) sn += xb[j * NX + c] * xb[j * NX + c];
+    for (int c = 0; c < NX; ++c) {
+      a.x0[int64_t(b) * nxs + m * NX + c] = static_cast<float>(xb[m * NX + c]);
+      sm += xb[m * NX + c] * xb[m * NX + c];
     }
+    for (int q = 0; q < np; ++q)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) sn += s_x[tid][q][c] * s_x[tid][q][c];
     a.xn[int64_t(b) * a.N + m] = static_cast<float>(sm);
     a.nrm[int64_t(b) * a.N + m] = static_cast<float>(sn);
   }
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
-  for (int l = tid; l < rs; l += 256) {
-    const int64_t ri = (int64_t(m) * rs + l) * a.Bmax + b;  // row vectors: [R][Bmax]
+  // row l of m for instance yy (instances fastest: neighbouring slots share a row's cache line)
+  for (int e = tid; e < rs * ny; e += 256) {
+    const int l = e / ny, yy = e - l * ny;
+    const int64_t ri = (int64_t(m) * rs + l) * a.Bmax + s_b[yy];  // row vectors: [R][Bmax]
     double bv = 0.0;
-    for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
-      const int j = a.rt_col[q];
-      const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
-      const int ld = (D + 3) & ~3;
-      const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
+    for (int q = 0; q < np; ++q) {
+      const float *o = a.off + s_base[q] + l;
 #pragma unroll
-      for (int c = 0; c < NX; ++c) bv += xb[j * NX + c] * double(a.off[a.off_ptr[j] + int64_t(c) * ld + ro + l]);
+      for (int c = 0; c < NX; ++c) bv += s_x[yy][q][c] * double(o[int64_t(c) * s_ld[q]]);
     }
     a.bvec[ri] = static_cast<float>(bv);
     a.alpha[ri] = 0.f;
     a.alpha[plane + ri] = 0.f;
     a.s[ri] = 0.f;
   }
-  for (int64_t i = a.koff[m] + tid; i < a.koff[m + 1]; i += 256) {
+  const int64_t k0 = a.koff[m], nk = a.koff[m + 1] - k0;
+  for (int64_t e = tid; e < nk * ny; e += 256) {
+    const int64_t i = k0 + e / ny;
+    const int b = s_b[int(e % ny)];
     a.tau[i * a.Bmax + b] = 0.f;
     a.eta[i * a.Bmax + b] = 0.f;
     a.eta[(a.ktot + i) * a.Bmax + b] = 0.f;
   }
-  if (m == 0 && tid == 0) {
+  if (m == 0 && tid < ny) {
+    const int y = y0 + tid, b = s_b[tid];
     BCtl &ic = a.ictl[b];
     ic.iters = 0;
     ic.stop = 0;
@@ -170,6 +202,22 @@ __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double 
       c->batch = B;
       c->warm = warm;
     }
+  }
+}
+
+// Sums of the kParts partial sums of each listed instance, in part order: which 0 gives r'r of
+// the trajectory start (cg_rr), 1 the objective of the returned trajectory.
+__global__ __launch_bounds__(64) void bpart_sum_kernel(BArgs a, const int32_t *slots, int S, int which) {
+  for (int y = threadIdx.x; y < S; y += 64) {
+    const int b = slots ? slots[y] : y;
+    const double *p = a.bpart + (int64_t(b) * 2 + which) * kParts;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kParts; ++q) v += p[q];
+    if (which == 0)
+      a.cg_rr[b] = a.cg_rrn[b] = v;
+    else
+      a.ictl[b].objective = v;
   }
 }
 
@@ -826,19 +874,21 @@ __global__ __launch_bounds__(64) void bdecide_kernel(BArgs a) {
 template <int NX>
 __global__ __launch_bounds__(256) void boutput_kernel(BArgs a, double *u0, const int32_t *slots,
                                                       const int32_t *dst) {
-  // slot slots[x] (or x) into row dst[x] (or x) of u0
+  // slot slots[x] (or x) into row dst[x] (or x) of u0; part blockIdx.y of kParts writes its
+  // share of u(0) and the partial objective of its row range (summed by bpart_sum_kernel)
   __shared__ double red[4];
-  const int b = slots ? slots[blockIdx.x] : blockIdx.x, tid = threadIdx.x;
+  const int b = slots ? slots[blockIdx.x] : blockIdx.x, tid = threadIdx.x, part = blockIdx.y;
   const int64_t orow = dst ? dst[blockIdx.x] : blockIdx.x;
-  const int64_t ny = int64_t(a.N) * a.rs;
+  const int64_t ny = int64_t(a.N) * a.rs, chunk = (ny + kParts - 1) / kParts;
+  const int64_t r0 = part * chunk, r1 = min(ny, r0 + chunk);
   const float *sb = a.s + b;  // row i of instance b at sb[i * Bmax]
   double acc = 0.0;
-  for (int64_t i = tid; i < ny; i += 256) acc += a.w64[i] * double(sb[i * a.Bmax]) * double(sb[i * a.Bmax]);
+  for (int64_t i = r0 + tid; i < r1; i += 256) acc += a.w64[i] * double(sb[i * a.Bmax]) * double(sb[i * a.Bmax]);
   acc = wsum(acc);
   if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
-  if (tid == 0) a.ictl[b].objective = (red[0] + red[1]) + (red[2] + red[3]);
-  for (int i = tid; i < a.N * a.nu; i += 256) {
+  if (tid == 0) a.bpart[(int64_t(b) * 2 + 1) * kParts + part] = (red[0] + red[1]) + (red[2] + red[3]);
+  for (int i = part * 256 + tid; i < a.N * a.nu; i += kParts * 256) {
     const int m = i / a.nu, q = i - m * a.nu;
     u0[orow * a.N * a.nu + i] = double(sb[(int64_t(m) * a.rs + NX * a.T + q) * a.Bmax]);
   }
@@ -1113,6 +1163,37 @@ __global__ __launch_bounds__(256) void bplant_kernel(BArgs a, double *x, const d
   }
 }
 
+// Stopping state of slots from[0..S) copied into stash slots to[0..S): what the FP64 check
+// reads (both alpha and eta planes, tau, the row values s, the control block), so that streams
+// refill the slots at once and check the stopped instances later, many at a time. One thread
+// per row of the [rows][Bmax] arrays (alpha and s rows first, then the k-space rows).
+__global__ __launch_bounds__(256) void bstash_kernel(BArgs a, BArgs st, const int32_t *from, const int32_t *to,
+                                                     int S) {
+  // one thread per (row, listed slot), the slots fastest (a row's entries share cache lines)
+  __shared__ int s_f[kBMax], s_t[kBMax];
+  if (threadIdx.x < S) {
+    s_f[threadIdx.x] = from[threadIdx.x];
+    s_t[threadIdx.x] = to[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t R = int64_t(a.N) * a.rs, plane = R * a.Bmax, eplane = a.ktot * a.Bmax;
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x, r = e / S;
+  const int y = int(e - r * S);
+  if (e < S) st.ictl[s_t[e]] = a.ictl[s_f[e]];
+  const int f = s_f[y], t = s_t[y];
+  if (r < R) {
+    const int64_t o = r * a.Bmax;
+    st.alpha[o + t] = a.alpha[o + f];
+    st.alpha[plane + o + t] = a.alpha[plane + o + f];
+    st.s[o + t] = a.s[o + f];
+  } else if (r < R + a.ktot) {
+    const int64_t o = (r - R) * a.Bmax;
+    st.tau[o + t] = a.tau[o + f];
+    st.eta[o + t] = a.eta[o + f];
+    st.eta[eplane + o + t] = a.eta[eplane + o + f];
+  }
+}
+
 // Input rows of the trajectories y [B][N*rs] (library row order) moved one step ahead into ys:
 // u_k <- u_{k+1} for k < T-2, u_{T-2} held (the start of the next step of the loop).
 __global__ __launch_bounds__(256) void bshift_kernel(BArgs a, const double *y, double *ys, int B) {
@@ -1143,17 +1224,17 @@ __global__ __launch_bounds__(256) void btraj_load_kernel(BArgs a, const double *
 // State rows of yhat: x_0 = x0, x_{t+1} = sum_j A_ij x_j(t) + B_i u_i(t), one block per
 // instance, one time step per barrier interval.
 template <int NX>
-__global__ __launch_bounds__(256) void bsim_kernel(BArgs a, const int32_t *slots) {
+__global__ __launch_bounds__(1024) void bsim_kernel(BArgs a, const int32_t *slots) {
   const int b = slots ? slots[blockIdx.x] : blockIdx.x, tid = threadIdx.x;
   const int rs = a.rs, nu = a.nu, N = a.N;
   float *y = a.yhat + int64_t(b) * N * rs;
   const float *x0 = a.x0 + int64_t(b) * N * NX;
-  for (int i = tid; i < N; i += 256)
+  for (int i = tid; i < N; i += 1024)
 #pragma unroll
     for (int c = 0; c < NX; ++c) y[int64_t(i) * rs + c] = x0[i * NX + c];
   __syncthreads();
   for (int t = 0; t + 1 < a.T; ++t) {
-    for (int i = tid; i < N; i += 256) {
+    for (int i = tid; i < N; i += 1024) {
       float v[NX];
 #pragma unroll
       for (int c = 0; c < NX; ++c) v[c] = 0.f;
@@ -1189,16 +1270,18 @@ __device__ __forceinline__ double block_sum1024(double v, double *red) {
 }
 
 // r = yhat - b, p = r, x = 0, rr = r'r; alpha^0 = -2 w yhat / rho_b into plane `pl` (the one the
-// next iteration reads as its previous iterate).
+// next iteration reads as its previous iterate). Part blockIdx.y of kParts takes a contiguous
+// row range; its share of r'r goes to the partial sums (added by bpart_sum_kernel).
 __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *slots, int pl) {
   __shared__ double red[16];
-  const int b = slots ? slots[blockIdx.x] : blockIdx.x;
+  const int b = slots ? slots[blockIdx.x] : blockIdx.x, part = blockIdx.y;
   const int64_t plane = int64_t(a.Bmax) * a.N * a.rs;
   float *alpha = a.alpha + int64_t(pl < 0 ? 0 : pl) * plane;
-  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
+  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny, chunk = (ny + kParts - 1) / kParts;
+  const int64_t r0 = part * chunk, r1 = min(ny, r0 + chunk);
   double acc = 0.0;
   const float rho = a.rho_b[b];
-  for (int64_t i = threadIdx.x; i < ny; i += 1024) {
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 1024) {
     const float y = a.yhat[o + i];
     const float r = y - a.bvec[i * a.Bmax + b];
     a.cg_r[o + i] = r;
@@ -1210,37 +1293,83 @@ __global__ __launch_bounds__(1024) void bcg_init_kernel(BArgs a, const int32_t *
     acc += double(r) * double(r);
   }
   acc = block_sum1024(acc, red);
-  if (threadIdx.x == 0) a.cg_rr[b] = acc;
+  if (threadIdx.x == 0) a.bpart[int64_t(b) * 2 * kParts + part] = acc;
 }
 
-// One CG step per instance after cg_q = M cg_p.
-__global__ __launch_bounds__(1024) void bcg_step_kernel(BArgs a, const int32_t *slots, int gate) {
-  // gate: inside the iteration, only instances whose Phi-comp just wrote q = M p (phase 1..cg_k)
-  __shared__ double red[16];
-  const int b = slots ? slots[blockIdx.x] : blockIdx.x;
-  if (gate) {
-    if (a.ctl->stop || b >= a.ctl->batch || a.ictl[b].stop) return;
-    const int ph = a.phase[b];
-    if (ph < 1 || ph > a.ctl->cg_k) return;
-  }
-  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny;
-  const double rr = a.cg_rr[b];
+// One CG step per instance after cg_q = M cg_p, in three passes over kCgParts row ranges of
+// the instance (the scalars are sums of the parts' partial sums in part order, so every part
+// takes the same step): bcg_pq_kernel p'q; bcg_upd_kernel x += s p, r -= s q with s = r'r / p'q,
+// and r'r of the new r; bcg_dir_kernel p = r + g p with g = new r'r / r'r. r'r of the step's
+// start is cg_rr; the new one goes to cg_rrn and becomes cg_rr in the next step's first pass.
+// gate: inside the iteration, only instances whose Phi-comp just wrote q = M p (phase
+// 1..cg_k); otherwise instances 0..gridDim.x-1.
+__device__ __forceinline__ bool cg_gated(const BArgs &a, int b, int gate) {
+  if (!gate) return true;
+  if (a.ctl->stop || b >= a.ctl->batch || a.ictl[b].stop) return false;
+  const int ph = a.phase[b];
+  return ph >= 1 && ph <= a.ctl->cg_k;
+}
+
+__device__ __forceinline__ double block_sum256(double v, double *red) {
+  v = wsum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ __forceinline__ double cg_part_sum(const double *p) {
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < kCgParts; ++q) v += p[q];
+  return v;
+}
+
+__global__ __launch_bounds__(256) void bcg_pq_kernel(BArgs a, int gate) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, part = blockIdx.y;
+  if (!cg_gated(a, b, gate)) return;
+  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny, chunk = (ny + kCgParts - 1) / kCgParts;
+  const int64_t r0 = part * chunk, r1 = min(ny, r0 + chunk);
   double pq = 0.0;
-  for (int64_t i = threadIdx.x; i < ny; i += 1024) pq += double(a.cg_p[o + i]) * double(a.cg_q[o + i]);
-  pq = block_sum1024(pq, red);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) pq += double(a.cg_p[o + i]) * double(a.cg_q[o + i]);
+  pq = block_sum256(pq, red);
+  if (threadIdx.x == 0) {
+    a.cgpart[int64_t(b) * 2 * kCgParts + part] = pq;
+    if (part == 0) a.cg_rr[b] = a.cg_rrn[b];
+  }
+}
+
+__global__ __launch_bounds__(256) void bcg_upd_kernel(BArgs a, int gate) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, part = blockIdx.y;
+  if (!cg_gated(a, b, gate)) return;
+  const double rr = a.cg_rr[b], pq = cg_part_sum(a.cgpart + int64_t(b) * 2 * kCgParts);
   if (!(rr > 0.0) || !(pq > 0.0)) return;  // converged (or breakdown): keep x
   const float step = float(rr / pq);
+  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny, chunk = (ny + kCgParts - 1) / kCgParts;
+  const int64_t r0 = part * chunk, r1 = min(ny, r0 + chunk);
   double rn = 0.0;
-  for (int64_t i = threadIdx.x; i < ny; i += 1024) {
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
     a.cg_x[o + i] += step * a.cg_p[o + i];
     const float r = a.cg_r[o + i] - step * a.cg_q[o + i];
     a.cg_r[o + i] = r;
     rn += double(r) * double(r);
   }
-  rn = block_sum1024(rn, red);
+  rn = block_sum256(rn, red);
+  if (threadIdx.x == 0) a.cgpart[(int64_t(b) * 2 + 1) * kCgParts + part] = rn;
+}
+
+__global__ __launch_bounds__(256) void bcg_dir_kernel(BArgs a, int gate) {
+  const int b = blockIdx.x, part = blockIdx.y;
+  if (!cg_gated(a, b, gate)) return;
+  const double rr = a.cg_rr[b], pq = cg_part_sum(a.cgpart + int64_t(b) * 2 * kCgParts);
+  if (!(rr > 0.0) || !(pq > 0.0)) return;
+  const double rn = cg_part_sum(a.cgpart + (int64_t(b) * 2 + 1) * kCgParts);
   const float g = float(rn / rr);
-  for (int64_t i = threadIdx.x; i < ny; i += 1024) a.cg_p[o + i] = a.cg_r[o + i] + g * a.cg_p[o + i];
-  if (threadIdx.x == 0) a.cg_rr[b] = rn;
+  const int64_t ny = int64_t(a.N) * a.rs, o = int64_t(b) * ny, chunk = (ny + kCgParts - 1) / kCgParts;
+  const int64_t r0 = part * chunk, r1 = min(ny, r0 + chunk);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) a.cg_p[o + i] = a.cg_r[o + i] + g * a.cg_p[o + i];
+  if (part == 0 && threadIdx.x == 0) a.cg_rrn[b] = rn;
 }
 
 __global__ __launch_bounds__(256) void bexport_y_kernel(BArgs a, double *out, int B) {
@@ -1620,6 +1749,10 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&d_xsrc_, size_t(bmax), err)) ||
         (rc = al(&d_oslots_, size_t(bmax), err)) || (rc = al(&d_odst_, size_t(bmax), err)) ||
         (rc = al(&d_cslots_, size_t(bmax), err)) || (rc = al(&d_cdst_, size_t(bmax), err)) ||
+        (rc = al(&d_sfrom_, size_t(bmax), err)) || (rc = al(&d_sto_, size_t(bmax), err)) ||
+        (rc = al(&sk_alpha_, 2 * size_t(bmax) * ny, err)) || (rc = al(&sk_s_, size_t(bmax) * ny, err)) ||
+        (rc = al(&sk_tau_, size_t(bmax) * a.ktot, err)) || (rc = al(&sk_eta_, 2 * size_t(bmax) * a.ktot, err)) ||
+        (rc = al(&sk_ictl_, size_t(bmax), err)) ||
         (rc = al(&a.phase, size_t(bmax), err)) || (rc = al(&a.rho_b, size_t(bmax), err)))
       return rc;
     {
@@ -1640,7 +1773,9 @@ class BatchEngineT final : public BatchEngine {
     BENG_CHECK(hipMemset(a.w_lo, 0, sizeof(__bf16) * size_t(a.Bw) * a.ktot));
     if ((rc = al(&a.yhat, size_t(bmax) * ny, err)) || (rc = al(&a.cg_x, size_t(bmax) * ny, err)) ||
         (rc = al(&a.cg_r, size_t(bmax) * ny, err)) || (rc = al(&a.cg_p, size_t(bmax) * ny, err)) ||
-        (rc = al(&a.cg_q, size_t(bmax) * ny, err)) || (rc = al(&a.cg_rr, size_t(bmax), err)))
+        (rc = al(&a.cg_q, size_t(bmax) * ny, err)) || (rc = al(&a.cg_rr, size_t(bmax), err)) ||
+        (rc = al(&a.bpart, size_t(bmax) * 2 * kParts, err)) || (rc = al(&a.cg_rrn, size_t(bmax), err)) ||
+        (rc = al(&a.cgpart, size_t(bmax) * 2 * kCgParts, err)))
       return rc;
     std::vector<float> ablk(hs.a_blocks.begin(), hs.a_blocks.end()), bblk(hs.b_blocks.begin(), hs.b_blocks.end());
     if ((rc = up(hs.a_rowptr, &a.a_rowptr, err)) || (rc = up(hs.a_colidx, &a.a_colidx, err)) ||
@@ -1685,7 +1820,8 @@ class BatchEngineT final : public BatchEngine {
       return DLMPC_EINVAL;
     }
     B_ = B;
-    hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, B), dim3(256), 0, stream_, args_, x0_dev, B,
+    hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, (B + kPreY - 1) / kPreY), dim3(256), 0, stream_, args_,
+                       x0_dev, B,
                        warm ? 1 : 0, max_iter, eps, nullptr, nullptr, 1, 0, 0, rho_scale_dev);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
@@ -1717,9 +1853,11 @@ class BatchEngineT final : public BatchEngine {
       hipLaunchKernelGGL(btraj_load_kernel, dim3(1024), dim3(256), 0, stream_, args_, y0_dev, B_);
       BENG_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, nullptr);
+    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(B_), dim3(1024), 0, stream_, args_, nullptr);
     BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(bcg_init_kernel, dim3(B_), dim3(1024), 0, stream_, args_, nullptr, 0);
+    hipLaunchKernelGGL(bcg_init_kernel, dim3(B_, kParts), dim3(1024), 0, stream_, args_, nullptr, 0);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bpart_sum_kernel, dim3(1), dim3(64), 0, stream_, args_, nullptr, B_, 0);
     BENG_CHECK(hipGetLastError());
     BArgs qa = args_;
     qa.phi_mode = 1;
@@ -1728,7 +1866,7 @@ class BatchEngineT final : public BatchEngine {
       if ((rc = project_t(args_.cg_p, ny_, 1, args_.eta, 1, err))) return rc;  // eta = N' p, W = ||x0_j||^2 eta
       launch_phi(qa);  // q = M p
       BENG_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(bcg_step_kernel, dim3(B_), dim3(1024), 0, stream_, args_, nullptr, 0);
+      launch_cg_step(B_, 0);
       BENG_CHECK(hipGetLastError());
     }
     if ((rc = project_t(args_.cg_x, ny_, 1, args_.tau, 0, err))) return rc;  // tau = N' beta
@@ -1763,15 +1901,18 @@ class BatchEngineT final : public BatchEngine {
     BENG_CHECK(hipMemcpyAsync(d_slots_, st_slots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
     BENG_CHECK(hipMemcpyAsync(d_xsrc_, st_xsrc_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
     if (first) B_ = S;
-    hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, S), dim3(256), 0, stream_, args_, x0_dev, S, 1,
+    hipLaunchKernelGGL((bprecompute_kernel<NX>), dim3(hs_->N, (S + kPreY - 1) / kPreY), dim3(256), 0, stream_, args_,
+                       x0_dev, S, 1,
                        max_iter, eps, d_slots_, d_xsrc_, first ? 1 : 0, 1, cg_iters, nullptr);
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL(bscatter_rows_kernel, dim3(S, 16), dim3(256), 0, stream_, ypred, d_slots_, ny_, args_.yhat);
     BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, d_slots_);
+    hipLaunchKernelGGL((bsim_kernel<NX>), dim3(S), dim3(1024), 0, stream_, args_, d_slots_);
     BENG_CHECK(hipGetLastError());
     // the CG steps and the start projections run inside the following iterations (phases)
-    hipLaunchKernelGGL(bcg_init_kernel, dim3(S), dim3(1024), 0, stream_, args_, d_slots_, -1);
+    hipLaunchKernelGGL(bcg_init_kernel, dim3(S, kParts), dim3(1024), 0, stream_, args_, d_slots_, -1);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bpart_sum_kernel, dim3(1), dim3(64), 0, stream_, args_, d_slots_, S, 0);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -1790,7 +1931,10 @@ class BatchEngineT final : public BatchEngine {
     st_odst_.assign(dst, dst + S);
     BENG_CHECK(hipMemcpyAsync(d_oslots_, st_oslots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
     BENG_CHECK(hipMemcpyAsync(d_odst_, st_odst_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
-    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, u0_dev, d_oslots_, d_odst_);
+    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(S, kParts), dim3(256), 0, stream_, args_, u0_dev, d_oslots_,
+                       d_odst_);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bpart_sum_kernel, dim3(1), dim3(64), 0, stream_, args_, d_oslots_, S, 1);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -1822,7 +1966,7 @@ class BatchEngineT final : public BatchEngine {
     launch_phi(args_);
     BENG_CHECK(hipGetLastError());
     if (joins) {  // CG steps of streamed joins (a no-op for instances in the ADMM iteration)
-      hipLaunchKernelGGL(bcg_step_kernel, dim3(args_.Bmax), dim3(1024), 0, stream_, args_, nullptr, 1);
+      launch_cg_step(args_.Bmax, 1);
       BENG_CHECK(hipGetLastError());
     }
     launch_psi(args_);
@@ -1833,7 +1977,10 @@ class BatchEngineT final : public BatchEngine {
   }
 
   int output(double *u0_dev, std::string &err) override {
-    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, u0_dev, nullptr, nullptr);
+    hipLaunchKernelGGL((boutput_kernel<NX>), dim3(B_, kParts), dim3(256), 0, stream_, args_, u0_dev, nullptr,
+                       nullptr);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bpart_sum_kernel, dim3(1), dim3(64), 0, stream_, args_, nullptr, B_, 1);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -1893,31 +2040,49 @@ class BatchEngineT final : public BatchEngine {
     return DLMPC_OK;
   }
 
-  int check_slots(const double *x0_dev, const int32_t *slots, const int32_t *dst, int S, std::string &err) override {
-    if (S < 1 || S > args_.Bmax) {
-      err = "check_slots: slot count out of range";
+  int stash_slots(const int32_t *slots, const int32_t *to, int S, std::string &err) override {
+    const int Bm = args_.Bmax;
+    if (S < 1 || S > Bm) {
+      err = "stash_slots: slot count out of range";
       return DLMPC_EINVAL;
     }
     for (int i = 0; i < S; ++i)
-      if (slots[i] < 0 || slots[i] >= args_.Bmax) {
-        err = "check_slots: bad slot";
+      if (slots[i] < 0 || slots[i] >= Bm || to[i] < 0 || to[i] >= Bm) {
+        err = "stash_slots: bad slot";
         return DLMPC_EINVAL;
       }
-    st_cslots_.assign(slots, slots + S);
-    st_cdst_.assign(dst, dst + S);
-    BENG_CHECK(hipMemcpyAsync(d_cslots_, st_cslots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
-    BENG_CHECK(hipMemcpyAsync(d_cdst_, st_cdst_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
-    hipLaunchKernelGGL((bcheck_w_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, d_cslots_, d_cdst_,
-                       S);
-    BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, d_cslots_, d_cdst_,
-                       S);
-    BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(S), dim3(256), 0, stream_, args_, x0_dev, d_cslots_, d_cdst_,
-                       S);
+    st_sfrom_.assign(slots, slots + S);
+    st_sto_.assign(to, to + S);
+    BENG_CHECK(hipMemcpyAsync(d_sfrom_, st_sfrom_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    BENG_CHECK(hipMemcpyAsync(d_sto_, st_sto_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    const int64_t items = (int64_t(hs_->N) * hs_->rs + args_.ktot) * S;
+    hipLaunchKernelGGL(bstash_kernel, dim3(unsigned((items + 255) / 256)), dim3(256), 0, stream_, args_,
+                       stash_args(), d_sfrom_, d_sto_, S);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
+
+  int check_stash(const double *x0_dev, const int32_t *dst, int S, std::string &err) override {
+    if (S < 1 || S > args_.Bmax) {
+      err = "check_stash: slot count out of range";
+      return DLMPC_EINVAL;
+    }
+    st_cslots_.resize(S);
+    for (int i = 0; i < S; ++i) st_cslots_[i] = i;
+    st_cdst_.assign(dst, dst + S);
+    BENG_CHECK(hipMemcpyAsync(d_cslots_, st_cslots_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    BENG_CHECK(hipMemcpyAsync(d_cdst_, st_cdst_.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, stream_));
+    const BArgs sa = stash_args();
+    hipLaunchKernelGGL((bcheck_w_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, sa, x0_dev, d_cslots_, d_cdst_, S);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, sa, x0_dev, d_cslots_, d_cdst_, S);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(S), dim3(256), 0, stream_, sa, x0_dev, d_cslots_, d_cdst_, S);
+    BENG_CHECK(hipGetLastError());
+    return DLMPC_OK;
+  }
+
+  BCtl *stash_ictl() override { return sk_ictl_; }
 
   Ctl *ctl() override { return args_.ctl; }
   BCtl *ictl() override { return args_.ictl; }
@@ -2029,8 +2194,26 @@ class BatchEngineT final : public BatchEngine {
   int64_t ny_ = 0;  // N * rs
   // streamed solves: slot lists on the device and their host staging
   int32_t *d_slots_ = nullptr, *d_xsrc_ = nullptr, *d_oslots_ = nullptr, *d_odst_ = nullptr;
-  int32_t *d_cslots_ = nullptr, *d_cdst_ = nullptr;
-  std::vector<int32_t> st_slots_, st_xsrc_, st_mask_, st_oslots_, st_odst_, st_cslots_, st_cdst_;
+  int32_t *d_cslots_ = nullptr, *d_cdst_ = nullptr, *d_sfrom_ = nullptr, *d_sto_ = nullptr;
+  std::vector<int32_t> st_slots_, st_xsrc_, st_mask_, st_oslots_, st_odst_, st_cslots_, st_cdst_, st_sfrom_, st_sto_;
+  // stash of stopped streamed instances awaiting their FP64 check (same layouts as the slots)
+  float *sk_alpha_ = nullptr, *sk_s_ = nullptr, *sk_tau_ = nullptr, *sk_eta_ = nullptr;
+  BCtl *sk_ictl_ = nullptr;
+  void launch_cg_step(int nb, int gate) {
+    hipLaunchKernelGGL(bcg_pq_kernel, dim3(nb, kCgParts), dim3(256), 0, stream_, args_, gate);
+    hipLaunchKernelGGL(bcg_upd_kernel, dim3(nb, kCgParts), dim3(256), 0, stream_, args_, gate);
+    hipLaunchKernelGGL(bcg_dir_kernel, dim3(nb, kCgParts), dim3(256), 0, stream_, args_, gate);
+  }
+  // the arguments of the check kernels, reading the stash in place of the slots
+  BArgs stash_args() const {
+    BArgs sa = args_;
+    sa.alpha = sk_alpha_;
+    sa.s = sk_s_;
+    sa.tau = sk_tau_;
+    sa.eta = sk_eta_;
+    sa.ictl = sk_ictl_;
+    return sa;
+  }
   int n_units_ = 0;  // Psi-comp work units
   std::vector<void *> owned_;
 };

@@ -1242,20 +1242,33 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
   std::vector<int32_t> inst(Bs, -1);  // instance in each slot (-1: free)
   std::vector<dlmpc::BCtl> fin(n);     // final control block of every instance
   std::vector<double> t_lat(n, 0.0);   // host time of the join, then latency join -> stop seen
-  // stopped instances whose FP64 check has not run yet (their slots not yet refilled)
-  std::vector<int32_t> pend_s, pend_i;
+  // Stopped instances awaiting their FP64 check: their stopping state is copied into the
+  // engine's stash (stash slot c holds instance pend_i[c]) and their slots are refilled at once;
+  // the check runs once the stash is full and at the end, many instances per pass over the
+  // FP64 bases. stash_t: a stash copy whose device time has not been read yet.
+  std::vector<int32_t> pend_i;
+  bool stash_t = false;
+  auto read_stash_time = [&]() {
+    if (!stash_t) return;
+    float mc = 0.f;
+    (void)hipEventElapsedTime(&mc, p->ev_p0, p->ev_p1);
+    t_check += mc;
+    stash_t = false;
+  };
   auto run_pending_checks = [&]() -> int {
+    const int S = int(pend_i.size());
     API_HIP(hipEventRecord(p->ev_c0, p->stream));
-    const int r = p->beng->check_slots(x0_dev, pend_s.data(), pend_i.data(), int(pend_s.size()), err);
+    const int r = p->beng->check_stash(x0_dev, pend_i.data(), S, err);
     if (r) return fail(r, err);
     API_HIP(hipEventRecord(p->ev_c1, p->stream));
-    API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
+    API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->stash_ictl(), sizeof(dlmpc::BCtl) * S, hipMemcpyDeviceToHost,
+                           p->stream));
     API_HIP(hipStreamSynchronize(p->stream));
+    read_stash_time();
     float mc = 0.f;
     (void)hipEventElapsedTime(&mc, p->ev_c0, p->ev_c1);
     t_check += mc;
-    for (size_t q = 0; q < pend_s.size(); ++q) fin[pend_i[q]] = p->h_bctl[pend_s[q]];
-    pend_s.clear();
+    for (int c = 0; c < S; ++c) fin[pend_i[c]] = p->h_bctl[c];
     pend_i.clear();
     return DLMPC_OK;
   };
@@ -1304,6 +1317,7 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
     API_HIP(hipMemcpyAsync(&p->h_ctl[1], d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
     API_HIP(hipMemcpyAsync(p->h_bctl, p->beng->ictl(), sizeof(dlmpc::BCtl) * Bs, hipMemcpyDeviceToHost, p->stream));
     API_HIP(hipStreamSynchronize(p->stream));
+    read_stash_time();
     std::vector<int32_t> done_s, done_i, free_s;
     for (int b = 0; b < Bs; ++b) {
       if (inst[b] >= 0 && p->h_bctl[b].stop) {
@@ -1320,27 +1334,30 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
         fin[done_i[q]] = p->h_bctl[done_s[q]];
         t_lat[done_i[q]] = now_ms() - t_lat[done_i[q]];
         inst[done_s[q]] = -1;
-        if (check) {
-          pend_s.push_back(done_s[q]);
-          pend_i.push_back(done_i[q]);
-        }
       }
       active -= int(done_s.size());
+      if (check) {
+        if (pend_i.size() + done_s.size() > size_t(Bm) && (rc = run_pending_checks())) return rc;
+        std::vector<int32_t> to(done_s.size());
+        for (size_t q = 0; q < done_s.size(); ++q) to[q] = int32_t(pend_i.size() + q);
+        API_HIP(hipEventRecord(p->ev_p0, p->stream));
+        if ((rc = p->beng->stash_slots(done_s.data(), to.data(), int(done_s.size()), err))) return fail(rc, err);
+        API_HIP(hipEventRecord(p->ev_p1, p->stream));
+        stash_t = true;
+        pend_i.insert(pend_i.end(), done_i.begin(), done_i.end());
+      }
     }
     for (int b = 0; b < Bs; ++b)
       if (inst[b] < 0) free_s.push_back(b);
     const int want = std::min<int>(int(free_s.size()), n - next);
     const bool refill = want > 0 && (int(free_s.size()) >= refill_min || active == 0 || next + want == n);
-    if ((refill || active == 0) && !pend_s.empty()) {
-      // FP64 check of the stopped instances before their slots are reused (or at the end)
-      if ((rc = run_pending_checks())) return rc;
-    }
     if (refill) {
       free_s.resize(want);
       if ((rc = join(free_s, false))) return rc;
     }
     if (launched > guard) return fail(DLMPC_EDEVICE, "streamed solve did not drain");
   }
+  if (!pend_i.empty() && (rc = run_pending_checks())) return rc;
   API_HIP(hipEventRecord(p->ev_t1, p->stream));
   API_HIP(hipStreamSynchronize(p->stream));
   float ms = 0.f;

@@ -245,7 +245,9 @@ struct BArgs {
   double *dlm;
   // Trajectory warm start: predicted trajectory (state rows simulated), CG vectors, r'r.
   float *yhat, *cg_x, *cg_r, *cg_p, *cg_q;
-  double *cg_rr;
+  double *cg_rr, *cg_rrn;  // [Bmax] r'r at the start of the CG step, and after it
+  double *cgpart;          // [Bmax][2][row ranges] partial sums of p'q and of the new r'r
+  double *bpart;  // [Bmax][2][parts] partial sums of r'r (start) and of the objective (output)
   const int64_t *a_rowptr;
   const int32_t *a_colidx;
   const float *a_blk, *b_blk;  // plant blocks (row-major nx x nx, nx x nu)
@@ -304,10 +306,12 @@ class BatchEngine {
   // solve's FP64 initial states): results in the per-instance control blocks (BCtl eq_resid,
   // box, u0dev, objective64).
   virtual int check(const double *x0_dev, std::string &err) = 0;
-  // The same for slots[0..S) holding the stopped instances dst[0..S) of x0_dev (streams: before
-  // the slots are refilled).
-  virtual int check_slots(const double *x0_dev, const int32_t *slots, const int32_t *dst, int S,
-                          std::string &err) = 0;
+  // Streams: the stopping state of slots[0..S) copied into stash slots to[0..S) (the slots can
+  // then be refilled); the FP64 check of stash slots 0..S-1, holding the stopped instances
+  // dst[0..S) of x0_dev, with its results in the stash's control blocks (stash_ictl).
+  virtual int stash_slots(const int32_t *slots, const int32_t *to, int S, std::string &err) = 0;
+  virtual int check_stash(const double *x0_dev, const int32_t *dst, int S, std::string &err) = 0;
+  virtual BCtl *stash_ictl() = 0;
   // Streamed solves (warm starts only). Slots slots[0..S) take the instances xsrc[0..S) of
   // x0_dev ([*][N*nx]); their input-row predictions are ypred [S][N*rs] (FP32, device). first:
   // the initial fill (resets the solve, batch = S, slots 0..S-1); otherwise the slots join the
