@@ -268,8 +268,8 @@ def main() -> int:
     ap.add_argument("--stream", type=int, default=256,
                     help="learned start: instances per step streamed through the --batch slots "
                          "(0: one batch of --batch instances per step)")
-    ap.add_argument("--refill-min", type=int, default=0, help="free slots before new instances join (0: an eighth)")
-    ap.add_argument("--check-iters", type=int, default=0, help="iterations between host checks (0: 16)")
+    ap.add_argument("--refill-min", type=int, default=0, help="free slots before new instances join (0: a tenth)")
+    ap.add_argument("--check-iters", type=int, default=0, help="iterations between host checks (0: 12)")
     ap.add_argument("--cg-iters", type=int, default=0, help="CG steps of the trajectory start (0: library default 12)")
     ap.add_argument("--train-solves", type=int, default=20000)
     ap.add_argument("--train-steps", type=int, default=10000)
@@ -486,7 +486,7 @@ def main() -> int:
                   "joins": int(sum(q["joins"] for q in sinfo)),
                   "slot_use": round(sum(q["instance_iterations"] for q in sinfo) /
                                     sum(q["slot_iterations"] for q in sinfo), 4),
-                  "refill_min": args.refill_min or max(1, B // 8), "check_iters": args.check_iters or 16}
+                  "refill_min": args.refill_min or max(1, B // 10), "check_iters": args.check_iters or 12}
 
     def compare(start, label):
         """The timed instances again, in batches of B from `start`: time per solve, iterations,

@@ -445,10 +445,11 @@ typedef struct {
 
 /* n independent instances of this network (any n >= 1) streamed through the batched engine's
  * max_batch slots, each from the learned start (needs the warm-start network): every
- * check_iters iterations (0: 16) the host reads the per-instance stop flags, writes u(0) of the
- * instances that stopped to their rows of u0_dev, and once at least refill_min slots are free
- * (0: an eighth of the slots; or the last instances are waiting; or no slot is busy) starts the next
- * instances in them: network inference and simulation at once, then the CG steps and the start
+ * check_iters iterations (0: 12) the host reads the per-instance stop flags, writes u(0) of the
+ * instances that stopped to their rows of u0_dev, copies their stopping state aside for the FP64
+ * check (run once that copy holds max_batch instances, and at the end), and once at least
+ * refill_min slots are free (0: a tenth of the slots, at least one; or the last instances are
+ * waiting; or no slot is busy) starts the next instances in them: network inference and simulation at once, then the CG steps and the start
  * projections of their trajectory start inside the following iterations, in the joiners'
  * columns of the same basis products (no pass over the bases of their own), after which each
  * joiner iterates with its own iteration count. Per instance the arithmetic is that of

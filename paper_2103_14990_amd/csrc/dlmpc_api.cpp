@@ -1232,12 +1232,14 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
   const HostSetup &h = p->hs;
   const size_t nxs = size_t(h.N) * h.nx, nus = size_t(h.N) * h.nu, R = size_t(h.N) * h.rs;
   const int Bm = p->beng->bmax(), Bs = std::min<int>(Bm, n);
-  if (refill_min == 0) refill_min = std::max(1, Bs / 8);
+  if (refill_min == 0) refill_min = std::max(1, Bs / 10);
   refill_min = std::min(refill_min, Bs);
   // Every check leaves the device idle for one host round trip (stop flags read, u(0) of the
-  // stopped instances written, joiners started): 16 iterations between checks measured faster
-  // than 2..12 or 32 on the 1024 mesh with 64 slots (the iterates do not depend on it).
-  const int K = check_iters > 0 ? check_iters : 16;
+  // stopped instances written, their state stashed, joiners started), and a stopped slot idles
+  // until the check that sees it: on the 1024 mesh with 64 slots, 12 iterations between checks
+  // and refills at 6 free slots measured fastest among 6..16 and 2..8 (the iterates do not
+  // depend on it).
+  const int K = check_iters > 0 ? check_iters : 12;
   std::string err;
   std::vector<int32_t> inst(Bs, -1);  // instance in each slot (-1: free)
   std::vector<dlmpc::BCtl> fin(n);     // final control block of every instance
@@ -1274,6 +1276,10 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
   };
   int next = 0, active = 0, joins = 0, checks = 0;
   int64_t slot_iters = 0;  // slot-iterations launched (active or idle)
+  // Iterations that may still hold a CG step of the latest joiners (phases 1..cg_k fall in the
+  // 2nd..(cg_k+1)-th iteration after a join): those run the graphs with the CG kernels, the
+  // others the plain iteration graphs.
+  int cg_left = 0;
   // New instances next.. into the given slots: network inference, then the trajectory start.
   auto join = [&](std::vector<int32_t> slots, bool first) -> int {
     const int S = int(slots.size());
@@ -1295,6 +1301,7 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
     next += S;
     active += S;
     ++joins;
+    cg_left = p->cg_iters + 2;
     return DLMPC_OK;
   };
   {
@@ -1309,8 +1316,9 @@ int run_stream(dlmpc_problem *p, int32_t n, const double *x0_dev, double *u0_dev
   const int64_t guard = (int64_t(n) + 1) * (p->opt.max_iter + K);
   int64_t launched = 0;
   while (active > 0) {
-    rc = launch_graphs(p->sgexec, p->stream, K);
-    if (rc) return rc;
+    const int kc = std::min(K, cg_left);
+    if ((rc = launch_graphs(p->sgexec, p->stream, kc)) || (rc = launch_graphs(p->bgexec, p->stream, K - kc))) return rc;
+    cg_left -= kc;
     launched += K;
     slot_iters += int64_t(K) * Bs;
     ++checks;
