@@ -4,7 +4,9 @@
 With the learned start every per-instance step of the batched iteration is independent of the
 other instances and of the global iteration count, so an instance streamed into any slot at
 any moment follows exactly the iterates of the same instance in dlmpc_solve_batch_ex: u(0),
-iteration counts, convergence and fallbacks are compared for equality."""
+iteration counts, convergence, fallbacks and the FP64 check's values (run on a stash of the
+stopped instances' states, emptied whenever it fills: more instances than slots) are compared
+for equality."""
 import numpy as np
 import pytest
 
@@ -59,7 +61,7 @@ def _batched_reference(torch, pr, xd, B):
 
 @pytest.mark.parametrize("name,n,B,refill_min,check_iters,precision", [
     ("grid8", 57, 16, 4, 3, "fp32"),       # many joins, a few slots at a time
-    ("grid8", 40, 16, 0, 0, "fp32"),       # defaults: an eighth of the slots, checks every 16 iterations
+    ("grid8", 40, 16, 0, 0, "fp32"),       # defaults: a tenth of the slots, checks every 12 iterations
     ("grid16_box", 37, 8, 2, 5, "fp32"),   # active bounds
     ("grid8", 5, 16, 0, 0, "fp32"),        # fewer instances than slots: one fill, no join
     ("grid16_box", 37, 8, 2, 5, "fp32_bf16"),  # reduced-operator tier (eps 1e-3, above its floor)
@@ -80,6 +82,10 @@ def test_stream_equals_batched_learned_solves(torch, name, n, B, refill_min, che
     assert it_s == [s["iters"] for s in sb]
     assert [s["converged"] for s in ss] == [s["converged"] for s in sb]
     assert [s["fell_back"] for s in ss] == [s["fell_back"] for s in sb]
+    # the FP64 check of a streamed instance runs on its stashed stopping state (many instances per
+    # pass, whichever stash slot holds it): the same values as the batched solve's check
+    for f in ("objective", "kkt", "eq_resid", "u0_check"):
+        assert [s[f] for s in ss] == [s[f] for s in sb], f
     assert info["fell_back"] == sum(s["fell_back"] for s in ss)
     assert info["instance_iterations"] == sum(it_s)
     if n > B:
