@@ -962,42 +962,92 @@ __global__ __launch_bounds__(256) void bcheck_w_kernel(BArgs a, const double *x0
 template <int NX>
 __global__ __launch_bounds__(256) void bcheck_y_kernel(BArgs a, const double *x0, const int32_t *slots,
                                                        const int32_t *xsrc, int S) {
-  const int m = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // The product operand of each step (tile of m's row, 32 basis vectors) is staged once per
+  // block in LDS (two buffers, one barrier per step; the waves past rs only stage), and the
+  // next step's operand and basis rows are loaded while the current step's products run.
+  __shared__ __align__(16) double sW[2][32][kBMax];
+  __shared__ const double *s_nj[kMaxPatch];
+  __shared__ int64_t s_w[kMaxPatch];
+  __shared__ int s_ld[kMaxPatch], s_k[kMaxPatch];
+  const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int rs = a.rs;
-  if (16 * w >= rs) return;  // no barriers below
+  const bool act = 16 * w < rs;
   const int ntl = (S + 15) >> 4;  // instance tiles in use
+  const int64_t q0 = a.rt_ptr[m];
+  const int pm = int(a.rt_ptr[m + 1] - q0);
+  if (tid < pm) {
+    const int j = a.rt_col[q0 + tid];
+    const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
+    s_ld[tid] = (D + 3) & ~3;
+    s_k[tid] = a.kdim[j];
+    s_nj[tid] = a.nb64 + a.nb_off[j] + int64_t(a.rt_tile[q0 + tid] - a.tile_off[j]) * rs;
+    s_w[tid] = a.koff[j] * kBMax;  // rows koff_j .. of wchk (zero past k_j up to a multiple of 32)
+  }
+  __syncthreads();
   f64x4 acc[kNT];
 #pragma unroll
   for (int nt = 0; nt < kNT; ++nt) acc[nt] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int row = 16 * w + (lane & 15);  // A operand row of this lane
-  const bool rok = row < rs;
-  for (int64_t q = a.rt_ptr[m]; q < a.rt_ptr[m + 1]; ++q) {
-    const int j = a.rt_col[q];
-    const int D = int(a.tile_off[j + 1] - a.tile_off[j]) * rs;
-    const int ld = (D + 3) & ~3;
-    const int ro = int(a.rt_tile[q] - a.tile_off[j]) * rs;
-    const int k = a.kdim[j];
-    const double *Nj = a.nb64 + a.nb_off[j] + ro + row;
-    const double *Wj = a.wchk + a.koff[j] * kBMax + (lane & 15);
-    // s32 + 31 < k rounded up to 32 = the padded range of j in wchk (zeros past k)
-    for (int s32 = 0; s32 < k; s32 += 32) {
-      double av[8], bv[8][kNT];
+  const bool rok = act && row < rs;
+  // steps (tile t, first basis vector s) in the order of the tiles, 32 vectors per step
+  auto next = [&](int &t, int &s) {
+    s += 32;
+    while (t < pm && s >= s_k[t]) {
+      ++t;
+      s = 0;
+    }
+    return t < pm;
+  };
+  double wv[8], avc[8], avn[8];
+  auto load = [&](int t, int s, double *av) {
+    const double *src = a.wchk + s_w[t] + int64_t(s) * kBMax + tid * 8;  // 32 x 64 contiguous
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = s32 + 4 * u + (lane >> 4);
-        av[u] = (rok && i < k) ? Nj[int64_t(i) * ld] : 0.0;
+    for (int e = 0; e < 8; ++e) wv[e] = src[e];
+    const double *nj = s_nj[t] + row;
+    const int ld = s_ld[t], k = s_k[t];
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) bv[u][nt] = nt < ntl ? Wj[int64_t(i) * kBMax + 16 * nt] : 0.0;
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int i = s + 4 * u + (lane >> 4);
+      av[u] = (rok && i < k) ? nj[int64_t(i) * ld] : 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
+    double *d = &sW[buf][0][0] + tid * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = wv[e];
+  };
+  int ct = 0, cs = -32;
+  bool ok = next(ct, cs);
+  if (ok) {
+    load(ct, cs, avc);
+    stage(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  while (ok) {
+    int tn = ct, sn = cs;
+    const bool more = next(tn, sn);
+    if (more) load(tn, sn, avn);
+    if (act) {
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt) {
           if (nt >= ntl) break;
-          acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nt], acc[nt], 0, 0, 0);
+          const double bv = sW[buf][4 * u + (lane >> 4)][16 * nt + (lane & 15)];
+          acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(avc[u], bv, acc[nt], 0, 0, 0);
         }
     }
+    if (more) stage(buf ^ 1);  // read last in the previous step, before its barrier
+    __syncthreads();
+    buf ^= 1;
+    ct = tn;
+    cs = sn;
+    ok = more;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) avc[u] = avn[u];
   }
+  if (!act) return;  // no barriers below
   // epilogue: lane holds rows 16 w + lane / 16 + 4 v of instance 16 nt + lane % 16
   const int64_t plane = int64_t(a.Bmax) * a.N * rs;
 #pragma unroll
@@ -1033,18 +1083,20 @@ __global__ __launch_bounds__(256) void bcheck_y_kernel(BArgs a, const double *x0
 
 // Per instance from y64: largest |x_0 - x0| and |x_{t+1} - A x_t - B u_t| (Z_AB y - [x0; 0]),
 // largest bound violation, largest |u(0) returned (the FP32 row values) - u(0) of y64|, and
-// sum_r w_r y_r^2. One block per instance.
+// sum_r w_r y_r^2. Block (instance, part): the subsystems of part blockIdx.y of kParts; the
+// parts' maxima and partial sums are combined, the sums in part order, by bcheck_fin_kernel.
 template <int NX>
 __global__ __launch_bounds__(256) void bcheck_red_kernel(BArgs a, const double *x0, const int32_t *slots,
                                                          const int32_t *xsrc, int S) {
   __shared__ double r_eq[4], r_box[4], r_u[4], r_j[4];
-  const int bi = blockIdx.x, tid = threadIdx.x;
+  const int bi = blockIdx.x, tid = threadIdx.x, part = blockIdx.y;
   const int b = slots ? slots[bi] : bi;
   const double *xb = x0 + int64_t(xsrc ? xsrc[bi] : bi) * a.N * NX;
   const int rs = a.rs, nu = a.nu, T = a.T;
   const double *y = a.y64 + int64_t(b) * a.N * rs;
+  const int chunk = (a.N + kParts - 1) / kParts, m1 = min(a.N, (part + 1) * chunk);
   double eq = 0.0, box = 0.0, ud = 0.0, jv = 0.0;
-  for (int m = tid; m < a.N; m += 256) {
+  for (int m = part * chunk + tid; m < m1; m += 256) {
     const double *ym = y + int64_t(m) * rs;
 #pragma unroll
     for (int c = 0; c < NX; ++c) eq = fmax(eq, fabs(ym[c] - xb[m * NX + c]));
@@ -1093,11 +1145,30 @@ __global__ __launch_bounds__(256) void bcheck_red_kernel(BArgs a, const double *
   }
   __syncthreads();
   if (tid == 0) {
+    double *o = a.chkpart + (int64_t(b) * kParts + part) * 4;
+    o[0] = fmax(fmax(r_eq[0], r_eq[1]), fmax(r_eq[2], r_eq[3]));
+    o[1] = fmax(0.0, fmax(fmax(r_box[0], r_box[1]), fmax(r_box[2], r_box[3])));
+    o[2] = fmax(fmax(r_u[0], r_u[1]), fmax(r_u[2], r_u[3]));
+    o[3] = (r_j[0] + r_j[1]) + (r_j[2] + r_j[3]);
+  }
+}
+
+__global__ __launch_bounds__(64) void bcheck_fin_kernel(BArgs a, const int32_t *slots, int S) {
+  for (int bi = threadIdx.x; bi < S; bi += 64) {
+    const int b = slots ? slots[bi] : bi;
+    const double *o = a.chkpart + int64_t(b) * kParts * 4;
+    double eq = 0.0, box = 0.0, ud = 0.0, jv = 0.0;
+    for (int q = 0; q < kParts; ++q) {
+      eq = fmax(eq, o[4 * q]);
+      box = fmax(box, o[4 * q + 1]);
+      ud = fmax(ud, o[4 * q + 2]);
+      jv += o[4 * q + 3];
+    }
     BCtl &ic = a.ictl[b];
-    ic.eq_resid = fmax(fmax(r_eq[0], r_eq[1]), fmax(r_eq[2], r_eq[3]));
-    ic.box = fmax(0.0, fmax(fmax(r_box[0], r_box[1]), fmax(r_box[2], r_box[3])));
-    ic.u0dev = fmax(fmax(r_u[0], r_u[1]), fmax(r_u[2], r_u[3]));
-    ic.objective64 = (r_j[0] + r_j[1]) + (r_j[2] + r_j[3]);
+    ic.eq_resid = eq;
+    ic.box = box;
+    ic.u0dev = ud;
+    ic.objective64 = jv;
   }
 }
 
@@ -1775,7 +1846,8 @@ class BatchEngineT final : public BatchEngine {
         (rc = al(&a.cg_r, size_t(bmax) * ny, err)) || (rc = al(&a.cg_p, size_t(bmax) * ny, err)) ||
         (rc = al(&a.cg_q, size_t(bmax) * ny, err)) || (rc = al(&a.cg_rr, size_t(bmax), err)) ||
         (rc = al(&a.bpart, size_t(bmax) * 2 * kParts, err)) || (rc = al(&a.cg_rrn, size_t(bmax), err)) ||
-        (rc = al(&a.cgpart, size_t(bmax) * 2 * kCgParts, err)))
+        (rc = al(&a.cgpart, size_t(bmax) * 2 * kCgParts, err)) ||
+        (rc = al(&a.chkpart, size_t(bmax) * kParts * 4, err)))
       return rc;
     std::vector<float> ablk(hs.a_blocks.begin(), hs.a_blocks.end()), bblk(hs.b_blocks.begin(), hs.b_blocks.end());
     if ((rc = up(hs.a_rowptr, &a.a_rowptr, err)) || (rc = up(hs.a_colidx, &a.a_colidx, err)) ||
@@ -2034,8 +2106,10 @@ class BatchEngineT final : public BatchEngine {
     hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
                        B_);
     BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(B_), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
+    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(B_, kParts), dim3(256), 0, stream_, args_, x0_dev, nullptr, nullptr,
                        B_);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bcheck_fin_kernel, dim3(1), dim3(64), 0, stream_, args_, nullptr, B_);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }
@@ -2077,7 +2151,10 @@ class BatchEngineT final : public BatchEngine {
     BENG_CHECK(hipGetLastError());
     hipLaunchKernelGGL((bcheck_y_kernel<NX>), dim3(hs_->N), dim3(256), 0, stream_, sa, x0_dev, d_cslots_, d_cdst_, S);
     BENG_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(S), dim3(256), 0, stream_, sa, x0_dev, d_cslots_, d_cdst_, S);
+    hipLaunchKernelGGL((bcheck_red_kernel<NX>), dim3(S, kParts), dim3(256), 0, stream_, sa, x0_dev, d_cslots_, d_cdst_,
+                       S);
+    BENG_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bcheck_fin_kernel, dim3(1), dim3(64), 0, stream_, sa, d_cslots_, S);
     BENG_CHECK(hipGetLastError());
     return DLMPC_OK;
   }

@@ -258,6 +258,7 @@ struct BArgs {
   const int64_t *nb_off;
   double *y64;
   double *wchk;  // [Ktot][64] product operand of the check (W_j of each instance)
+  double *chkpart;  // [Bmax][parts][4] per-part maxima (eq, box, u0) and objective sums
 };
 
 class BatchEngine {
