@@ -48,6 +48,7 @@ constexpr int kPhiThreads = 512;  // bphi_kernel: 4 instance tiles x 2 halves of
 constexpr int kMaxPatch = 64;     // subsystems per d-hop patch (batched engine)
 constexpr int kSNs = 88;          // structured Psi-comp: patch states (p nx) at most
 constexpr int kSPnu = 64;         // structured Psi-comp: patch inputs per time step (p nu) at most
+constexpr int kSNnz = 512;        // structured Psi-comp: nonzeros of the patch dynamics at most
 
 __device__ __forceinline__ unsigned long long ord_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(v));
@@ -433,6 +434,10 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu((MT
   __shared__ __align__(16) __bf16 sh_hi[kBMax][kSH];
   __shared__ __align__(16) __bf16 sh_lo[kBMax][kSH];
   __shared__ float smu[STRUCT ? kBMax : 1][STRUCT ? kSNs + 1 : 1];
+  // structured: the patch's transposed dynamics (CSR) and input blocks, read by every step of
+  // the recursion (the same entries across a wave: staged once instead of loaded per step)
+  __shared__ int16_t s_srp[STRUCT ? kSNs + 1 : 1], s_scol[STRUCT ? kSNnz : 1];
+  __shared__ float s_sval[STRUCT ? kSNnz : 1], s_sbb[STRUCT ? kSPnu * NX : 1];
   __shared__ int s_rsub[kMaxPatch];
   __shared__ double red_e[kPsiWaves][kBMax], red_d[kPsiWaves][kBMax];
   __shared__ double red_od[kBMax][8][NX];
@@ -517,6 +522,15 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu((MT
       return jstage ? jsrc[int64_t(sb) * a.N * rs + row] : stage_src[int64_t(sb) * a.src_bs + row * a.src_rs];
     };
     for (int s0 = sub; s0 < kSNs + 1; s0 += 8) smu[sb][s0] = 0.f;  // mu_T = 0
+    for (int e = tid; e <= ns; e += kPsiThreads) s_srp[e] = static_cast<int16_t>(rpt[e]);
+    for (int e = tid; e < rpt[ns]; e += kPsiThreads) {
+      s_scol[e] = static_cast<int16_t>(colt[e]);
+      s_sval[e] = valt[e];
+    }
+    for (int e = tid; e < pnu * NX; e += kPsiThreads) {  // e = (member * nu + input) * NX + state
+      const int w = e / NX, sx = e - w * NX, ti = w / nu, kk = w - ti * nu;
+      s_sbb[e] = a.b_blk[int64_t(s_rsub[ti]) * NX * nu + sx * nu + kk];
+    }
     int fill = 0, chunk = 0;
     auto products = [&](int nrows) {  // chunk `chunk` of the K rows: sh rows [0, nrows)
       for (int ks = 0; ks < nrows / 32; ++ks) {
@@ -554,7 +568,7 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu((MT
         if (st < ns) {
           const int ti = st / NX, sx = st - ti * NX;
           v = src_at(int64_t(s_rsub[ti]) * rs + t * NX + sx);
-          for (int e = rpt[st]; e < rpt[st + 1]; ++e) v += valt[e] * smu[sb][colt[e]];
+          for (int e = s_srp[st]; e < s_srp[st + 1]; ++e) v += s_sval[e] * smu[sb][s_scol[e]];
         }
         mreg[i] = v;
       }
@@ -568,9 +582,8 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu((MT
         const int ti = w / nu, kk = w - ti * nu;
         const int m = s_rsub[ti];
         float gv = src_at(int64_t(m) * rs + nxT + (t - 1) * nu + kk);
-        const float *bb = a.b_blk + int64_t(m) * NX * nu;
 #pragma unroll
-        for (int sx = 0; sx < NX; ++sx) gv += bb[sx * nu + kk] * smu[sb][ti * NX + sx];
+        for (int sx = 0; sx < NX; ++sx) gv += s_sbb[w * NX + sx] * smu[sb][ti * NX + sx];
         const __bf16 gh = static_cast<__bf16>(gv);
         sh_hi[sb][fill + w] = gh;
         sh_lo[sb][fill + w] = static_cast<__bf16>(gv - static_cast<float>(gh));
@@ -1752,6 +1765,7 @@ class BatchEngineT final : public BatchEngine {
         pnu_max = std::max(pnu_max, int(hs.patch[j].size()) * hs.nu);
       }
       if (split && hs.d_nb && ns_max <= kSNs && pnu_max <= kSPnu && hs.T >= 2) {
+        int32_t nnz_max = 0;
         std::vector<int64_t> ntu_off(N + 1, 0), srp0(N), se0(N);
         std::vector<int32_t> srpt, scolt;
         std::vector<float> svalt;
@@ -1786,23 +1800,26 @@ class BatchEngineT final : public BatchEngine {
             c += int32_t(cols[r].size());
             srpt.push_back(c);
           }
+          nnz_max = std::max(nnz_max, c);
         }
         __bf16 *d_ntu = nullptr;
         const int64_t *d_nboff = nullptr, *d_ntuoff = nullptr, *d_toff = nullptr;
         const int32_t *d_k = nullptr;
-        if ((rc = al(&d_ntu, size_t(std::max<int64_t>(ntu_off[N], 1)), err)) || (rc = up(hs.nb_off, &d_nboff, err)) ||
-            (rc = up(ntu_off, &d_ntuoff, err)) || (rc = up(hs.tile_off, &d_toff, err)) || (rc = up(hs.kdim, &d_k, err)) ||
-            (rc = up(srp0, &a.srp0, err)) || (rc = up(se0, &a.se0, err)) || (rc = up(srpt, &a.srpt, err)) ||
-            (rc = up(scolt, &a.scolt, err)) || (rc = up(svalt, &a.svalt, err)))
-          return rc;
-        BENG_CHECK(hipMemset(d_ntu, 0, sizeof(__bf16) * std::max<int64_t>(ntu_off[N], 1)));
-        hipLaunchKernelGGL(bfragu_kernel, dim3(N, 16), dim3(256), 0, nullptr, hs.d_nb, d_nboff, d_k, d_toff, d_ntuoff,
-                           hs.rs, hs.nx, hs.nu, hs.T, d_ntu);
-        BENG_CHECK(hipGetLastError());
-        BENG_CHECK(hipDeviceSynchronize());
-        a.ntu = d_ntu;
-        a.ntu_off = d_ntuoff;
-        struct_ok_ = true;
+        if (nnz_max <= kSNnz) {  // otherwise the patch dynamics exceed the kernel's staging
+          if ((rc = al(&d_ntu, size_t(std::max<int64_t>(ntu_off[N], 1)), err)) || (rc = up(hs.nb_off, &d_nboff, err)) ||
+              (rc = up(ntu_off, &d_ntuoff, err)) || (rc = up(hs.tile_off, &d_toff, err)) || (rc = up(hs.kdim, &d_k, err)) ||
+              (rc = up(srp0, &a.srp0, err)) || (rc = up(se0, &a.se0, err)) || (rc = up(srpt, &a.srpt, err)) ||
+              (rc = up(scolt, &a.scolt, err)) || (rc = up(svalt, &a.svalt, err)))
+            return rc;
+          BENG_CHECK(hipMemset(d_ntu, 0, sizeof(__bf16) * std::max<int64_t>(ntu_off[N], 1)));
+          hipLaunchKernelGGL(bfragu_kernel, dim3(N, 16), dim3(256), 0, nullptr, hs.d_nb, d_nboff, d_k, d_toff, d_ntuoff,
+                             hs.rs, hs.nx, hs.nu, hs.T, d_ntu);
+          BENG_CHECK(hipGetLastError());
+          BENG_CHECK(hipDeviceSynchronize());
+          a.ntu = d_ntu;
+          a.ntu_off = d_ntuoff;
+          struct_ok_ = true;
+        }
       }
     }
     std::vector<float> offf(hs.off.begin(), hs.off.end()), wf(hs.w.begin(), hs.w.end()),
