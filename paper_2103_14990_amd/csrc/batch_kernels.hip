@@ -833,47 +833,59 @@ __global__ __launch_bounds__(kPsiThreads) __attribute__((amdgpu_waves_per_eu((MT
 // ------------------------------------------------------------------ decision, outputs
 
 __global__ __launch_bounds__(64) void bdecide_kernel(BArgs a) {
-  if (a.ctl->stop) return;
   __shared__ int n_stop;
   __shared__ unsigned long long worst_p, worst_d;
   const int b = threadIdx.x;
+  Ctl *c = a.ctl;
+  // every value the decision reads is loaded before the first use (independent addresses, one
+  // memory round trip instead of a chain of them)
+  const bool own = b < a.Bmax;
+  const int all_stop = c->stop, it = c->iters + 1, B = c->batch, cg_k = c->cg_k, max_iter = c->max_iter;
+  const double eps = c->eps;
+  const int i_stop = own ? a.ictl[b].stop : 1, i_it0 = own ? a.ictl[b].it0 : 0;
+  const int ph = own ? a.phase[b] : -1;
+  const unsigned long long sp = own ? a.slot[2 * b] : 0ull, sd = own ? a.slot[2 * b + 1] : 0ull;
+  if (all_stop) return;
   if (b == 0) {
     n_stop = 0;
     worst_p = worst_d = 0ull;
   }
   __syncthreads();
-  Ctl *c = a.ctl;
-  const int it = c->iters + 1;
-  const int B = c->batch;
   if (b < B) {
     BCtl &ic = a.ictl[b];
-    if (!ic.stop && a.phase[b] >= 0) {  // streamed join: its start runs; no decision yet
-      if (++a.phase[b] > a.ctl->cg_k + 1) {
+    bool stop = i_stop != 0;
+    if (!stop && ph >= 0) {  // streamed join: its start runs; no decision yet
+      if (ph + 1 > cg_k + 1) {
         a.phase[b] = -1;
         ic.it0 = it;  // its first ADMM iteration is the next one
+      } else {
+        a.phase[b] = ph + 1;
       }
-    } else if (!ic.stop) {
-      const double rp = __longlong_as_double(static_cast<long long>(a.slot[2 * b]));
-      const double rd = __longlong_as_double(static_cast<long long>(a.slot[2 * b + 1]));
-      ic.iters = it - ic.it0;
+    } else if (!stop) {
+      const double rp = __longlong_as_double(static_cast<long long>(sp));
+      const double rd = __longlong_as_double(static_cast<long long>(sd));
+      const int iters = it - i_it0;
+      ic.iters = iters;
       ic.last_rp = rp;
       ic.last_rd = rd;
       if (!(rp == rp) || !(rd == rd) || isinf(rp) || isinf(rd)) {
         ic.numeric = 1;
-        ic.stop = 1;
-      } else if (rp <= c->eps && rd <= c->eps) {
+        stop = true;
+      } else if (rp <= eps && rd <= eps) {
         ic.converged = 1;
-        ic.stop = 1;
-      } else if (ic.iters >= c->max_iter) {
-        ic.stop = 1;
+        stop = true;
+      } else if (iters >= max_iter) {
+        stop = true;
       }
-      if (!ic.stop) {
+      if (stop) {
+        ic.stop = 1;
+      } else {
         atomicMax(&worst_p, ord_bits(rp));
         atomicMax(&worst_d, ord_bits(rd));
       }
     }
     a.slot[2 * b] = a.slot[2 * b + 1] = 0ull;
-    if (ic.stop) atomicAdd(&n_stop, 1);
+    if (stop) atomicAdd(&n_stop, 1);
   }
   __syncthreads();
   if (b == 0) {
