@@ -101,7 +101,7 @@ __device__ __forceinline__ T wsum(T v) {
 // bpart_sum_kernel).
 constexpr int kPreY = 16;
 constexpr int kParts = 8;
-constexpr int kCgParts = 16;  // row ranges of one instance's CG step
+constexpr int kCgParts = 32;  // row ranges of one instance's CG step
 
 template <int NX>
 __global__ __launch_bounds__(256) void bprecompute_kernel(BArgs a, const double *x0, int B, int warm,
