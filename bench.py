@@ -297,8 +297,9 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-launch timing of the batched kernels (for profiler runs)")
-    ap.add_argument("--kernels-engine", default="batched", choices=["batched", "single"],
-                    help="--kernels-only: the batched kernels, or the single-instance kernels (one x0)")
+    ap.add_argument("--kernels-engine", default="batched", choices=["batched", "single", "single_structured"],
+                    help="--kernels-only: the batched kernels, or the single-instance kernels (one x0; dense or "
+                         "structured Psi-comp)")
     ap.add_argument("--kernels-precision", default="fp32", choices=["fp32", "fp32_bf16", "fp64"],
                     help="--kernels-only: split-operand kernels (fp32) or the reduced-operator tier")
     ap.add_argument("--setup-only", action="store_true",
@@ -353,18 +354,23 @@ def main() -> int:
             p.close()
         print(json.dumps({"workload": args.workload, "setup": rec}), flush=True)
         return 0
-    if args.kernels_only and args.kernels_engine == "single":
-        ps_ = make(args.kernels_precision if args.kernels_precision != "fp32_bf16" else "fp32", 0)
+    if args.kernels_only and args.kernels_engine in ("single", "single_structured"):
+        structured = args.kernels_engine == "single_structured"
+        ps_ = make(args.kernels_precision if args.kernels_precision != "fp32_bf16" else "fp32", 0,
+                   schedule="graph", structured_psi=structured)
         xk = torch.tensor(wl.x0(1000), dtype=torch.float64, device=dev)
         ku = ps_.time_kernels(xk.data_ptr(), 20)
-        nnz, dk = ps_.info["nnz"], ps_.info["sum_dcol_k"]
+        nnz = ps_.info["nnz"]
+        # the bases the Psi-comp passes read: N_j (dense), or their input rows N_u (structured: pass
+        # 1 is the adjoint recursion and N_u' g, pass 2 N_u t, the patch simulation and the epilogue)
+        dk = ps_.info["sum_du_k"] if structured else ps_.info["sum_dcol_k"]
         sz = 8 if args.kernels_precision == "fp64" else 4
         # algorithmic bytes per launch (every array once): Phi-comp reads Psi, Lambda (nnz each) and
         # the row data, writes Phi; pass 1 reads the bases and Phi + Lambda; pass 2 reads the bases,
         # Phi, Lambda, Psi and writes Psi, Lambda
         algo = {"phi_kernel": sz * (3 * nnz + 4 * R), "psi_pass1_kernel": sz * (dk + 2 * nnz),
                 "psi_pass2_kernel": sz * (dk + 6 * nnz), "conv_kernel": 0}
-        print(json.dumps({"kernels_us": ku, "engine": "single", "precision": args.kernels_precision,
+        print(json.dumps({"kernels_us": ku, "engine": args.kernels_engine, "precision": args.kernels_precision,
                           "timed_iterations": 20,
                           "GB/s": {k: round(algo[k] / (v * 1e-6) / 1e9, 1) if algo[k] else None
                                    for k, v in ku.items()},

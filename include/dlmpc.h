@@ -249,6 +249,8 @@ typedef struct {
   int32_t psi_structured;
   int32_t pad_info;
   double tune_structured_us;
+  int64_t sum_du_k;     /* sum over subsystems of mu_j * k_j, mu_j = p_j * nu * (T - 1) the input
+                           rows of column block j (entries of the structured Psi-comp's bases N_u) */
 } dlmpc_info;
 
 /* Offline precomputation (Algorithm 1, first step). Builds G_(A,B), the d-hop patches, the

@@ -784,6 +784,9 @@ int dlmpc_query(const dlmpc_problem *p, dlmpc_info *info) {
   info->tune_cached = p->tune_cached;
   info->psi_structured = p->psi_structured ? 1 : 0;
   info->tune_structured_us = p->tune_structured_us;
+  info->sum_du_k = 0;
+  for (int j = 0; j < h.N; ++j)
+    info->sum_du_k += int64_t(h.patch[j].size()) * h.nu * (h.T - 1) * h.kdim[j];
   return DLMPC_OK;
 }
 

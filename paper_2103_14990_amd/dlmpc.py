@@ -110,7 +110,8 @@ class Info(C.Structure):
                 ("factor_device", C.c_int32), ("factor_fallbacks", C.c_int32),
                 ("batch_phi_ntw", C.c_int32), ("batch_psi_capx", C.c_int32), ("batch_psi_units", C.c_int32),
                 ("tune_cached", C.c_int32), ("tune_phi_us", C.c_double * 2), ("tune_psi_us", C.c_double * 6),
-                ("psi_structured", C.c_int32), ("pad_info", C.c_int32), ("tune_structured_us", C.c_double)]
+                ("psi_structured", C.c_int32), ("pad_info", C.c_int32), ("tune_structured_us", C.c_double),
+                ("sum_du_k", C.c_int64)]
 
     def as_dict(self) -> dict:
         out = {}
