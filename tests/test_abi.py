@@ -77,6 +77,11 @@ def test_host_setup_matches_oracle(name):
     assert pr.info["sum_k"] == sum(kt)
     assert pr.info["sum_dcol_k"] == sum(len(b.rows) * k for b, k in zip(pb.blocks, kt))
     assert pr.info["sum_dcol2"] == sum(len(b.rows) ** 2 for b in pb.blocks)
+    # input rows of each column block (the structured Psi-comp's bases): p_j nu (T - 1), p_j the
+    # patch size, i.e. the support rows of j that are inputs
+    lay = pb.lay
+    n_u_rows = [int(np.sum(np.asarray(b.rows) >= lay.Nx * lay.T)) for b in pb.blocks]
+    assert pr.info["sum_du_k"] == sum(mu * k for mu, k in zip(n_u_rows, kt))
 
 
 @pytest.mark.parametrize("nx,nu,d,T,seed", [(1, 1, 1, 4, 0), (3, 2, 1, 3, 1), (2, 2, 2, 4, 2)])
