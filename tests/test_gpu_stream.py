@@ -64,6 +64,8 @@ def _batched_reference(torch, pr, xd, B):
     ("grid8", 40, 16, 0, 0, "fp32"),       # defaults: a tenth of the slots, checks every 12 iterations
     ("grid16_box", 37, 8, 2, 5, "fp32"),   # active bounds
     ("grid8", 5, 16, 0, 0, "fp32"),        # fewer instances than slots: one fill, no join
+    ("grid8", 6, 1, 0, 0, "fp32"),         # one slot: the stash holds one instance, checked at every stop
+    ("grid8", 30, 4, 1, 1, "fp32"),        # a check after every iteration, joins of single slots
     ("grid16_box", 37, 8, 2, 5, "fp32_bf16"),  # reduced-operator tier (eps 1e-3, above its floor)
 ])
 def test_stream_equals_batched_learned_solves(torch, name, n, B, refill_min, check_iters, precision):
